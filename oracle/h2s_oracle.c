@@ -1,0 +1,1027 @@
+/*
+ * h2s_oracle.c -- plain, slow FP64 CPU oracle for the H2* and (H2+H)* fast
+ * kernel matrix-vector product of Khan & Ambikasaran, "New algebraic fast
+ * algorithms for N-body problems in two and three dimensions"
+ * (arXiv 2309.14085).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this file.  It shares no code, header,
+ * table or helper with the library in paper_2309_14085_amd/; the two are
+ * independent implementations of the same published method.
+ *
+ * Every routine follows the paper's definitions in the paper's order, with
+ * no blocking, fusion or reordering:
+ *   - uniform 2^d tree, kappa = ceil(log_{2^d}(N / n_max))       (Sec. 3.1)
+ *   - weak admissibility, clan, near field N*, IL = IL_far + IL_ver
+ *                                           (Sec. 3.3, Table "HOD_notation",
+ *                                            Sec. 5.1 / Fig. "interaction_split")
+ *   - partially pivoted ACA and its stopping rule              (Sec. 3.4)
+ *   - B2T NCA on IL_far, levels kappa..2                       (Sec. 5.1.1 step 1, Alg. "b2t")
+ *   - T2B NCA on IL_ver, levels 1..kappa                       (Sec. 5.1.1 step 2, Alg. "t2b")
+ *   - per-pair ACA on IL_ver for (H2+H)*                       (Sec. 5.2.1, Alg. "pure_aca")
+ *   - L2P/P2M/L2L/M2M/M2L operators, symmetric-kernel transpose (Sec. 3.4.3)
+ *   - the MVP: upward, transverse, downward traversal plus the
+ *     direct near field                                        (Sec. 5.1.2, Sec. 5.2.2)
+ *   - the direct O(N^2) product used for t_direct and RE_MVP   (Sec. 6, Table "app_notations")
+ *
+ * Readings of points where the paper is silent or ambiguous (tie-breaks,
+ * bounding cube, clan definition, outgoing pivots, ...) are the ones listed
+ * in the repository's design notes; each is marked "reading:" below.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (see oracle/build.py).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Kernel functions (Sec. 6.1.1, 6.2.1, Appendix D; Gaussian RBF for solves) */
+/* ------------------------------------------------------------------------ */
+
+enum { ORC_LOG_R = 0, ORC_INV_R = 1, ORC_GAUSS = 2, ORC_EXP_R = 3 };
+
+typedef struct {
+    int kind;
+    double param; /* Gaussian length scale */
+    double diag;  /* K(x_i, x_i) */
+    double shift; /* adds shift * I to the matrix */
+} orc_kernel;
+
+/* K(x, y).  reading: the diagonal value is used whenever the two points
+ * coincide (r == 0), which covers i == j; for log r and 1/r the paper sets
+ * K_ii = 0 (Sec. 6.1.1, 6.2.1). */
+static double kernel_value(const orc_kernel *k, int d, const double *x, const double *y)
+{
+    double r2 = 0.0;
+    for (int c = 0; c < d; ++c) {
+        double t = x[c] - y[c];
+        r2 += t * t;
+    }
+    if (r2 == 0.0) return k->diag;
+    switch (k->kind) {
+    case ORC_LOG_R: return log(sqrt(r2));
+    case ORC_INV_R: return 1.0 / sqrt(r2);
+    case ORC_GAUSS: return exp(-r2 / (k->param * k->param));
+    case ORC_EXP_R: return exp(-sqrt(r2));
+    default: return NAN;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Direct product phi = (K + shift I) q, Neumaier-compensated (Sec. 6)       */
+/* ------------------------------------------------------------------------ */
+
+/* pts: user order, row-major n x d.  rows: the nrows row indices wanted
+ * (NULL means all rows 0..n-1).  out[r] = phi[rows[r]]. */
+void orc_direct(const double *pts, int64_t n, int d, int kind, double param, double diag,
+                double shift, const double *q, const int64_t *rows, int64_t nrows, double *out)
+{
+    orc_kernel k = {kind, param, diag, shift};
+    if (!rows) nrows = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        double s = 0.0, comp = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double term = kernel_value(&k, d, pts + i * d, pts + j * d) * q[j];
+            double t = s + term;
+            if (fabs(s) >= fabs(term)) comp += (s - t) + term;
+            else comp += (term - t) + s;
+            s = t;
+        }
+        out[r] = s + comp + shift * q[i];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Partially pivoted ACA (Sec. 3.4, eq. for K^(p) and its stopping rule)     */
+/* ------------------------------------------------------------------------ */
+
+typedef double (*entry_fn)(const void *ctx, int64_t i, int64_t j);
+
+/* Result of one cross approximation K(I, J) ~ sum_p u_p v_p^T. */
+typedef struct {
+    int64_t rank;
+    int64_t *prow; /* pivot positions in I, in selection order */
+    int64_t *pcol; /* pivot positions in J */
+    double *u;     /* rank vectors of length nI, stored one after another */
+    double *v;     /* rank vectors of length nJ */
+} aca_result;
+
+static void aca_free(aca_result *a)
+{
+    free(a->prow); free(a->pcol); free(a->u); free(a->v);
+    memset(a, 0, sizeof(*a));
+}
+
+static double dot(const double *a, const double *b, int64_t n)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/*
+ * reading (the paper states only the stopping rule):
+ *   - start with the first row of I; the approximant S starts at 0;
+ *   - residual row R_j = K(i*, J_j) - sum_{k<p} u_k(i*) v_k(j), subtracting
+ *     the terms in order k = 0, 1, ...;
+ *   - column pivot j* = argmax of |R_j| over unused columns, first on ties;
+ *   - a zero pivot marks the row used and moves to the next unused row of I
+ *     (in I order); with no rows left the approximation ends;
+ *   - v_p = R / R_{j*};  u_p(i) = K(I_i, j*) - sum_{k<p} u_k(i) v_k(j*);
+ *   - ||S||_F^2 += ||u_p||^2 ||v_p||^2 + 2 sum_{k<p} (u_k.u_p)(v_k.v_p);
+ *   - the term is accepted; stop if ||u_p|| ||v_p|| <= eps ||S||_F or the
+ *     rank reaches min(|I|, |J|);
+ *   - next row pivot = argmax of |u_p| over unused rows, first on ties.
+ * eps = 0 runs to full rank.
+ */
+static void aca(entry_fn f, const void *ctx, const int64_t *I, int64_t nI, const int64_t *J,
+                int64_t nJ, double eps, aca_result *res)
+{
+    memset(res, 0, sizeof(*res));
+    if (nI <= 0 || nJ <= 0) return;
+    int64_t maxr = nI < nJ ? nI : nJ;
+    int64_t cap = 8 < maxr ? 8 : maxr;
+    res->prow = malloc(sizeof(int64_t) * maxr);
+    res->pcol = malloc(sizeof(int64_t) * maxr);
+    res->u = malloc(sizeof(double) * cap * nI);
+    res->v = malloc(sizeof(double) * cap * nJ);
+    char *rowused = calloc(nI, 1), *colused = calloc(nJ, 1);
+    double *R = malloc(sizeof(double) * nJ);
+    double s2 = 0.0;
+    int64_t p = 0, istar = 0;
+
+    for (;;) {
+        /* residual row */
+        rowused[istar] = 1;
+        for (int64_t j = 0; j < nJ; ++j) {
+            double r = f(ctx, I[istar], J[j]);
+            for (int64_t k = 0; k < p; ++k) r -= res->u[k * nI + istar] * res->v[k * nJ + j];
+            R[j] = r;
+        }
+        int64_t jstar = -1;
+        double best = -1.0;
+        for (int64_t j = 0; j < nJ; ++j)
+            if (!colused[j] && fabs(R[j]) > best) { best = fabs(R[j]); jstar = j; }
+        if (jstar < 0) break;
+        if (R[jstar] == 0.0) {
+            int64_t next = -1;
+            for (int64_t i = 0; i < nI; ++i) if (!rowused[i]) { next = i; break; }
+            if (next < 0) break;
+            istar = next;
+            continue;
+        }
+        if (p == cap) {
+            cap = 2 * cap < maxr ? 2 * cap : maxr;
+            res->u = realloc(res->u, sizeof(double) * cap * nI);
+            res->v = realloc(res->v, sizeof(double) * cap * nJ);
+        }
+        double *up = res->u + p * nI, *vp = res->v + p * nJ;
+        for (int64_t j = 0; j < nJ; ++j) vp[j] = R[j] / R[jstar];
+        for (int64_t i = 0; i < nI; ++i) {
+            double r = f(ctx, I[i], J[jstar]);
+            for (int64_t k = 0; k < p; ++k) r -= res->u[k * nI + i] * res->v[k * nJ + jstar];
+            up[i] = r;
+        }
+        colused[jstar] = 1;
+        double nu2 = dot(up, up, nI), nv2 = dot(vp, vp, nJ);
+        double cross = 0.0;
+        for (int64_t k = 0; k < p; ++k)
+            cross += dot(res->u + k * nI, up, nI) * dot(res->v + k * nJ, vp, nJ);
+        s2 = s2 + (nu2 * nv2 + 2.0 * cross);
+        res->prow[p] = istar;
+        res->pcol[p] = jstar;
+        ++p;
+        if (sqrt(nu2 * nv2) <= eps * sqrt(s2) || p == maxr) break;
+        int64_t inext = -1;
+        best = -1.0;
+        for (int64_t i = 0; i < nI; ++i)
+            if (!rowused[i] && fabs(up[i]) > best) { best = fabs(up[i]); inext = i; }
+        if (inext < 0) break;
+        istar = inext;
+    }
+    res->rank = p;
+    free(rowused); free(colused); free(R);
+}
+
+/* ACA on an explicit row-major nI x nJ matrix (used to pin the ACA itself).
+ * U: nI x min(nI,nJ) column-major, V: nJ x min(nI,nJ) column-major. */
+typedef struct { const double *m; int64_t ld; } dense_ctx;
+static double dense_entry(const void *c, int64_t i, int64_t j)
+{
+    const dense_ctx *d = (const dense_ctx *)c;
+    return d->m[i * d->ld + j];
+}
+
+int64_t orc_aca_dense(const double *M, int64_t nI, int64_t nJ, double eps, int64_t *prow,
+                      int64_t *pcol, double *U, double *V)
+{
+    dense_ctx c = {M, nJ};
+    int64_t *I = malloc(sizeof(int64_t) * (nI > 0 ? nI : 1));
+    int64_t *J = malloc(sizeof(int64_t) * (nJ > 0 ? nJ : 1));
+    for (int64_t i = 0; i < nI; ++i) I[i] = i;
+    for (int64_t j = 0; j < nJ; ++j) J[j] = j;
+    aca_result a;
+    aca(dense_entry, &c, I, nI, J, nJ, eps, &a);
+    for (int64_t p = 0; p < a.rank; ++p) {
+        prow[p] = a.prow[p];
+        pcol[p] = a.pcol[p];
+        memcpy(U + p * nI, a.u + p * nI, sizeof(double) * nI);
+        memcpy(V + p * nJ, a.v + p * nJ, sizeof(double) * nJ);
+    }
+    int64_t r = a.rank;
+    aca_free(&a);
+    free(I); free(J);
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense LU with partial pivoting and the solve X A = B  (operators, Sec. 3.4.3) */
+/* ------------------------------------------------------------------------ */
+
+/* In-place LU of the r x r row-major A: P A = L U, unit L below the diagonal.
+ * Row k is swapped with piv[k].  Returns 0, or -1 on an exactly zero pivot. */
+static int lu_factor(double *A, int64_t r, int64_t *piv)
+{
+    int ok = 0;
+    for (int64_t k = 0; k < r; ++k) {
+        int64_t p = k;
+        double best = fabs(A[k * r + k]);
+        for (int64_t i = k + 1; i < r; ++i)
+            if (fabs(A[i * r + k]) > best) { best = fabs(A[i * r + k]); p = i; }
+        piv[k] = p;
+        if (p != k)
+            for (int64_t j = 0; j < r; ++j) {
+                double t = A[k * r + j]; A[k * r + j] = A[p * r + j]; A[p * r + j] = t;
+            }
+        if (A[k * r + k] == 0.0) { ok = -1; continue; }
+        for (int64_t i = k + 1; i < r; ++i) {
+            A[i * r + k] /= A[k * r + k];
+            for (int64_t j = k + 1; j < r; ++j) A[i * r + j] -= A[i * r + k] * A[k * r + j];
+        }
+    }
+    return ok;
+}
+
+/* x A = b for one row vector b (length r), overwriting b with x.
+ * With P A = L U:  A^T = U^T L^T P, so solve U^T y = b, L^T z = y, x = P^T z. */
+static void lu_solve_row(const double *LU, const int64_t *piv, int64_t r, double *b)
+{
+    for (int64_t j = 0; j < r; ++j) {
+        double s = b[j];
+        for (int64_t i = 0; i < j; ++i) s -= LU[i * r + j] * b[i];
+        b[j] = s / LU[j * r + j];
+    }
+    for (int64_t j = r - 1; j >= 0; --j) {
+        double s = b[j];
+        for (int64_t i = j + 1; i < r; ++i) s -= LU[i * r + j] * b[i];
+        b[j] = s;
+    }
+    for (int64_t k = r - 1; k >= 0; --k)
+        if (piv[k] != k) { double t = b[k]; b[k] = b[piv[k]]; b[piv[k]] = t; }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tree, lists, pivots, operators                                           */
+/* ------------------------------------------------------------------------ */
+
+enum { FAM_FAR = 0, FAM_VER = 1 };
+enum { LIST_NEAR = 0, LIST_FAR = 1, LIST_VER = 2 };
+
+typedef struct {
+    int64_t rank;
+    int64_t *row;  /* t^{X,i}: incoming row pivots (tree positions) */
+    int64_t *col;  /* s^{X,i}: incoming column pivots (tree positions) */
+    int64_t nrow_op, ncol_op;
+    double *op;    /* leaf: U_X (n_X x rank); non-leaf: stacked L2L (sum r_c x rank); column-major */
+} obasis;
+
+typedef struct {
+    int64_t x, y, rank;   /* box indices at the level, x < y */
+    double *ub, *vb;      /* K(t^X, t^Y) ~ ub vb^T; ub: n_X x rank, vb: n_Y x rank, column-major */
+} ohph;
+
+typedef struct {
+    int64_t nbox;
+    int64_t *morton, *begin, *end, *parent, *cbeg, *cend;
+    int32_t *coord;                 /* d per box */
+    int64_t *off[3], *idx[3];       /* CSR lists: near (leaf level only), far, ver */
+    obasis *fam[2];
+    int64_t npair;
+    ohph *pair;
+} olevel;
+
+typedef struct orc_tree {
+    int d, kappa, variant;
+    int64_t n, nmax;
+    orc_kernel ker;
+    double eps_far, eps_ver;
+    double ctr[3], half, origin[3];
+    int64_t *perm;  /* perm[t] = user index of tree position t */
+    double *pts;    /* tree-order points, row-major n x d */
+    olevel *lev;    /* kappa + 1 levels */
+} orc_tree;
+
+typedef struct { const orc_tree *t; } kctx;
+static double tree_entry(const void *c, int64_t i, int64_t j)
+{
+    const orc_tree *t = ((const kctx *)c)->t;
+    return kernel_value(&t->ker, t->d, t->pts + i * t->d, t->pts + j * t->d);
+}
+static double K(const orc_tree *t, int64_t i, int64_t j)
+{
+    return kernel_value(&t->ker, t->d, t->pts + i * t->d, t->pts + j * t->d);
+}
+
+/* Morton interleave: bit b of coordinate c goes to bit d*b + c. */
+static uint64_t interleave(const int32_t *a, int d, int bits)
+{
+    uint64_t key = 0;
+    for (int b = 0; b < bits; ++b)
+        for (int c = 0; c < d; ++c)
+            key |= (uint64_t)((a[c] >> b) & 1) << (d * b + c);
+    return key;
+}
+
+typedef struct { uint64_t key; int64_t idx; } keyidx;
+static int cmp_keyidx(const void *a, const void *b)
+{
+    const keyidx *x = a, *y = b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx);
+}
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return x < y ? -1 : (x > y);
+}
+
+static int64_t find_box(const olevel *L, uint64_t m)
+{
+    int64_t lo = 0, hi = L->nbox - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if ((uint64_t)L->morton[mid] == m) return mid;
+        if ((uint64_t)L->morton[mid] < m) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+/* Append src[0..ns) to a growable array. */
+static void append(int64_t **a, int64_t *n, int64_t *cap, const int64_t *src, int64_t ns)
+{
+    if (*n + ns > *cap) {
+        *cap = (*n + ns) * 2 + 16;
+        *a = realloc(*a, sizeof(int64_t) * (*cap));
+    }
+    memcpy(*a + *n, src, sizeof(int64_t) * ns);
+    *n += ns;
+}
+
+/* Sec. 3.1: the leaf level is kappa = ceil(log_{2^d}(N / n_max)), i.e. the
+ * smallest kappa >= 0 with N <= n_max 2^(d kappa). */
+int orc_depth(int64_t n, int d, int64_t nmax)
+{
+    int kappa = 0;
+    while (nmax * ((int64_t)1 << (d * kappa)) < n) ++kappa;
+    return kappa;
+}
+
+/* Sec. 3.1: bounding cube, kappa, leaf boxes, tree order.
+ * reading: C is the bounding cube (centre of the bounding box, half-width the
+ * largest half extent, 1 if all points coincide); kappa is the smallest
+ * kappa >= 0 with n_max 2^(d kappa) >= N; a point's leaf coordinate is
+ * floor((x - (c - h)) 2^kappa / (2h)) clamped to [0, 2^kappa - 1];
+ * tree order sorts by (leaf Morton key, user index). */
+static void build_tree(orc_tree *t, const double *user_pts)
+{
+    int d = t->d;
+    int64_t n = t->n;
+    double lo[3], hi[3];
+    for (int c = 0; c < d; ++c) { lo[c] = user_pts[c]; hi[c] = user_pts[c]; }
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < d; ++c) {
+            double x = user_pts[i * d + c];
+            if (x < lo[c]) lo[c] = x;
+            if (x > hi[c]) hi[c] = x;
+        }
+    t->half = 0.0;
+    for (int c = 0; c < d; ++c) {
+        t->ctr[c] = (lo[c] + hi[c]) * 0.5;
+        double h = (hi[c] - lo[c]) * 0.5;
+        if (h > t->half) t->half = h;
+    }
+    if (t->half == 0.0) t->half = 1.0;
+    for (int c = 0; c < d; ++c) t->origin[c] = t->ctr[c] - t->half;
+
+    int kappa = orc_depth(n, d, t->nmax);
+    t->kappa = kappa;
+    int64_t side = (int64_t)1 << kappa;
+
+    keyidx *ki = malloc(sizeof(keyidx) * (n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t a[3];
+        for (int c = 0; c < d; ++c) {
+            double s = (user_pts[i * d + c] - t->origin[c]) * (double)side / (2.0 * t->half);
+            double fl = floor(s);
+            int64_t v = (int64_t)fl;
+            if (fl < 0.0) v = 0;
+            if (v > side - 1) v = side - 1;
+            a[c] = (int32_t)v;
+        }
+        ki[i].key = interleave(a, d, kappa);
+        ki[i].idx = i;
+    }
+    qsort(ki, n, sizeof(keyidx), cmp_keyidx);
+    t->perm = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+    t->pts = malloc(sizeof(double) * (n > 0 ? n : 1) * d);
+    uint64_t *key = malloc(sizeof(uint64_t) * (n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        t->perm[i] = ki[i].idx;
+        key[i] = ki[i].key;
+        memcpy(t->pts + i * d, user_pts + ki[i].idx * d, sizeof(double) * d);
+    }
+    free(ki);
+
+    /* non-empty boxes per level, Morton order */
+    t->lev = calloc(kappa + 1, sizeof(olevel));
+    for (int l = 0; l <= kappa; ++l) {
+        olevel *L = &t->lev[l];
+        int shift = d * (kappa - l);
+        int64_t nb = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (i == 0 || (key[i] >> shift) != (key[i - 1] >> shift)) ++nb;
+        L->nbox = nb;
+        L->morton = malloc(sizeof(int64_t) * (nb ? nb : 1));
+        L->begin = malloc(sizeof(int64_t) * (nb ? nb : 1));
+        L->end = malloc(sizeof(int64_t) * (nb ? nb : 1));
+        L->coord = malloc(sizeof(int32_t) * (nb ? nb : 1) * d);
+        int64_t b = -1;
+        for (int64_t i = 0; i < n; ++i) {
+            if (i == 0 || (key[i] >> shift) != (key[i - 1] >> shift)) {
+                ++b;
+                L->morton[b] = (int64_t)(key[i] >> shift);
+                L->begin[b] = i;
+                for (int c = 0; c < d; ++c) {
+                    int32_t v = 0;
+                    for (int bit = 0; bit < l; ++bit)
+                        v |= (int32_t)((L->morton[b] >> (d * bit + c)) & 1) << bit;
+                    L->coord[b * d + c] = v;
+                }
+            }
+            L->end[b] = i + 1;
+        }
+    }
+    free(key);
+    for (int l = 0; l <= kappa; ++l) {
+        olevel *L = &t->lev[l];
+        L->parent = malloc(sizeof(int64_t) * (L->nbox ? L->nbox : 1));
+        L->cbeg = malloc(sizeof(int64_t) * (L->nbox ? L->nbox : 1));
+        L->cend = malloc(sizeof(int64_t) * (L->nbox ? L->nbox : 1));
+        for (int64_t b = 0; b < L->nbox; ++b) {
+            L->parent[b] = l > 0 ? find_box(&t->lev[l - 1], (uint64_t)L->morton[b] >> d) : -1;
+            L->cbeg[b] = L->cend[b] = 0;
+        }
+        if (l < kappa) {
+            olevel *C = &t->lev[l + 1];
+            for (int64_t c = 0; c < C->nbox; ++c) {
+                int64_t p = find_box(L, (uint64_t)C->morton[c] >> d);
+                if (L->cend[p] == 0) L->cbeg[p] = c;
+                L->cend[p] = c + 1;
+            }
+        }
+    }
+}
+
+/* Sec. 3.3 and Table "HOD_notation": at level l >= 1 the candidates for box X
+ * are the children of its parent P and of P's edge/face-sharing neighbours
+ * (reading: the clan uses the edge/face neighbours of the parent, which is
+ * the reading that reproduces |IL*| = 15 in 2D and 133 in 3D).  A candidate
+ * Y != X with offsets delta = |a_X - a_Y| is
+ *   near    if max delta <= 1 and fewer than d offsets equal 1,
+ *   IL_ver  if every offset equals 1 (shares only a vertex),
+ *   IL_far  if max delta >= 2.
+ * The near list (kept at the leaf level) also contains X.  Lists are sorted
+ * by Morton index; empty boxes do not exist. */
+static void build_lists(orc_tree *t)
+{
+    int d = t->d;
+    for (int l = 0; l <= t->kappa; ++l) {
+        olevel *L = &t->lev[l];
+        for (int w = 0; w < 3; ++w) {
+            L->off[w] = calloc(L->nbox + 1, sizeof(int64_t));
+            L->idx[w] = NULL;
+        }
+        int64_t cnt[3] = {0, 0, 0}, cap[3] = {0, 0, 0};
+        int64_t *tmp[3] = {malloc(sizeof(int64_t) * 512), malloc(sizeof(int64_t) * 512),
+                           malloc(sizeof(int64_t) * 512)};
+        for (int64_t x = 0; x < L->nbox; ++x) {
+            int64_t nt[3] = {0, 0, 0};
+            if (l == 0) {
+                tmp[LIST_NEAR][nt[LIST_NEAR]++] = x;
+            } else {
+                olevel *Pl = &t->lev[l - 1];
+                int64_t P = L->parent[x];
+                const int32_t *aP = Pl->coord + P * d;
+                int nofs = 1;
+                for (int c = 0; c < d; ++c) nofs *= 3;
+                for (int o = 0; o < nofs; ++o) {
+                    int32_t off[3], aq[3];
+                    int oo = o, nz = 0, inside = 1;
+                    for (int c = 0; c < d; ++c) { off[c] = oo % 3 - 1; oo /= 3; if (off[c]) ++nz; }
+                    if (nz == d) continue; /* vertex neighbours of P are not in the clan */
+                    for (int c = 0; c < d; ++c) {
+                        aq[c] = aP[c] + off[c];
+                        if (aq[c] < 0 || aq[c] >= (1 << (l - 1))) inside = 0;
+                    }
+                    if (!inside) continue;
+                    int64_t Q = find_box(Pl, interleave(aq, d, l - 1));
+                    if (Q < 0) continue;
+                    for (int64_t y = Pl->cbeg[Q]; y < Pl->cend[Q]; ++y) {
+                        const int32_t *ax = L->coord + x * d, *ay = L->coord + y * d;
+                        int maxd = 0, ones = 0;
+                        for (int c = 0; c < d; ++c) {
+                            int dl = abs(ax[c] - ay[c]);
+                            if (dl > maxd) maxd = dl;
+                            if (dl == 1) ++ones;
+                        }
+                        int w;
+                        if (y == x) w = LIST_NEAR;
+                        else if (maxd >= 2) w = LIST_FAR;
+                        else if (ones == d) w = LIST_VER;
+                        else w = LIST_NEAR;
+                        tmp[w][nt[w]++] = y;
+                    }
+                }
+            }
+            for (int w = 0; w < 3; ++w) {
+                qsort(tmp[w], nt[w], sizeof(int64_t), cmp_i64);
+                if (w == LIST_NEAR && l != t->kappa) nt[w] = 0;
+                append(&L->idx[w], &cnt[w], &cap[w], tmp[w], nt[w]);
+                L->off[w][x + 1] = cnt[w];
+            }
+        }
+        for (int w = 0; w < 3; ++w) free(tmp[w]);
+    }
+}
+
+/* B2T NCA on IL_far (Sec. 5.1.1 step 1, Alg. "b2t"), levels kappa down to 2.
+ * Leaf: I = t^X, J = union of t^Y over Y in IL_far(X).  Non-leaf: I = union
+ * of the children's row pivots, J = union over Y in IL_far(X) and over the
+ * children of Y of their outgoing column pivots.  reading: the kernel is
+ * symmetric, so the outgoing pivots are the incoming ones transposed
+ * (s^{Y,o} = t^{Y,i}, Sec. 3.4.3 remark). */
+static void far_pivots(orc_tree *t)
+{
+    kctx c = {t};
+    for (int l = t->kappa; l >= 2; --l) {
+        olevel *L = &t->lev[l];
+        L->fam[FAM_FAR] = calloc(L->nbox ? L->nbox : 1, sizeof(obasis));
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t x = 0; x < L->nbox; ++x) {
+            obasis *B = &L->fam[FAM_FAR][x];
+            int64_t *I = NULL, *J = NULL, nI = 0, nJ = 0, capI = 0, capJ = 0;
+            if (L->off[LIST_FAR][x + 1] == L->off[LIST_FAR][x]) continue;
+            if (l == t->kappa) {
+                for (int64_t i = L->begin[x]; i < L->end[x]; ++i) append(&I, &nI, &capI, &i, 1);
+                for (int64_t e = L->off[LIST_FAR][x]; e < L->off[LIST_FAR][x + 1]; ++e) {
+                    int64_t y = L->idx[LIST_FAR][e];
+                    for (int64_t j = L->begin[y]; j < L->end[y]; ++j) append(&J, &nJ, &capJ, &j, 1);
+                }
+            } else {
+                olevel *C = &t->lev[l + 1];
+                for (int64_t xc = L->cbeg[x]; xc < L->cend[x]; ++xc)
+                    append(&I, &nI, &capI, C->fam[FAM_FAR][xc].row, C->fam[FAM_FAR][xc].rank);
+                for (int64_t e = L->off[LIST_FAR][x]; e < L->off[LIST_FAR][x + 1]; ++e) {
+                    int64_t y = L->idx[LIST_FAR][e];
+                    for (int64_t yc = L->cbeg[y]; yc < L->cend[y]; ++yc)
+                        append(&J, &nJ, &capJ, C->fam[FAM_FAR][yc].row, C->fam[FAM_FAR][yc].rank);
+                }
+            }
+            aca_result a;
+            aca(tree_entry, &c, I, nI, J, nJ, t->eps_far, &a);
+            B->rank = a.rank;
+            B->row = malloc(sizeof(int64_t) * (a.rank ? a.rank : 1));
+            B->col = malloc(sizeof(int64_t) * (a.rank ? a.rank : 1));
+            for (int64_t p = 0; p < a.rank; ++p) { B->row[p] = I[a.prow[p]]; B->col[p] = J[a.pcol[p]]; }
+            aca_free(&a);
+            free(I); free(J);
+        }
+    }
+}
+
+/* T2B NCA on IL_ver (Sec. 5.1.1 step 2), levels 1 to kappa.
+ * I = t^X; J = union of t^Y over Y in IL_ver(X), then (l > 1) the parent's
+ * incoming column pivots s^{P,i}.  reading: J is the union over all Y of the
+ * set equations (the printed pseudocode overwrites J inside its loop);
+ * parent pivots already in J are not repeated. */
+static void ver_pivots(orc_tree *t)
+{
+    kctx c = {t};
+    for (int l = 1; l <= t->kappa; ++l) {
+        olevel *L = &t->lev[l];
+        L->fam[FAM_VER] = calloc(L->nbox ? L->nbox : 1, sizeof(obasis));
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t x = 0; x < L->nbox; ++x) {
+            obasis *B = &L->fam[FAM_VER][x];
+            int64_t *I = NULL, *J = NULL, nI = 0, nJ = 0, capI = 0, capJ = 0;
+            for (int64_t i = L->begin[x]; i < L->end[x]; ++i) append(&I, &nI, &capI, &i, 1);
+            for (int64_t e = L->off[LIST_VER][x]; e < L->off[LIST_VER][x + 1]; ++e) {
+                int64_t y = L->idx[LIST_VER][e];
+                for (int64_t j = L->begin[y]; j < L->end[y]; ++j) append(&J, &nJ, &capJ, &j, 1);
+            }
+            if (l > 1) {
+                const obasis *PB = &t->lev[l - 1].fam[FAM_VER][L->parent[x]];
+                int64_t nbase = nJ;
+                for (int64_t k = 0; k < PB->rank; ++k) {
+                    int dup = 0;
+                    for (int64_t j = 0; j < nbase; ++j) if (J[j] == PB->col[k]) { dup = 1; break; }
+                    if (!dup) append(&J, &nJ, &capJ, &PB->col[k], 1);
+                }
+            }
+            aca_result a;
+            aca(tree_entry, &c, I, nI, J, nJ, t->eps_ver, &a);
+            B->rank = a.rank;
+            B->row = malloc(sizeof(int64_t) * (a.rank ? a.rank : 1));
+            B->col = malloc(sizeof(int64_t) * (a.rank ? a.rank : 1));
+            for (int64_t p = 0; p < a.rank; ++p) { B->row[p] = I[a.prow[p]]; B->col[p] = J[a.pcol[p]]; }
+            aca_free(&a);
+            free(I); free(J);
+        }
+    }
+}
+
+/* (H2+H)*: ACA of K(t^X, t^Y) for every vertex-sharing pair at every level
+ * (Sec. 5.2.1, Alg. "pure_aca").  reading: each unordered pair is
+ * approximated once, with X the lower Morton index; the block K(t^Y, t^X)
+ * uses the transposed factors. */
+static void hph_pairs(orc_tree *t)
+{
+    kctx c = {t};
+    for (int l = 1; l <= t->kappa; ++l) {
+        olevel *L = &t->lev[l];
+        int64_t np = 0;
+        for (int64_t x = 0; x < L->nbox; ++x)
+            for (int64_t e = L->off[LIST_VER][x]; e < L->off[LIST_VER][x + 1]; ++e)
+                if (L->idx[LIST_VER][e] > x) ++np;
+        L->npair = np;
+        L->pair = calloc(np ? np : 1, sizeof(ohph));
+        np = 0;
+        for (int64_t x = 0; x < L->nbox; ++x)
+            for (int64_t e = L->off[LIST_VER][x]; e < L->off[LIST_VER][x + 1]; ++e)
+                if (L->idx[LIST_VER][e] > x) { L->pair[np].x = x; L->pair[np].y = L->idx[LIST_VER][e]; ++np; }
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t p = 0; p < np; ++p) {
+            ohph *H = &L->pair[p];
+            int64_t nx = L->end[H->x] - L->begin[H->x], ny = L->end[H->y] - L->begin[H->y];
+            int64_t *I = malloc(sizeof(int64_t) * nx), *J = malloc(sizeof(int64_t) * ny);
+            for (int64_t i = 0; i < nx; ++i) I[i] = L->begin[H->x] + i;
+            for (int64_t j = 0; j < ny; ++j) J[j] = L->begin[H->y] + j;
+            aca_result a;
+            aca(tree_entry, &c, I, nx, J, ny, t->eps_ver, &a);
+            H->rank = a.rank;
+            H->ub = a.u; a.u = NULL;
+            H->vb = a.v; a.v = NULL;
+            aca_free(&a);
+            free(I); free(J);
+        }
+    }
+}
+
+/* Operators (Sec. 3.4.3): with A = K(t^{X,i}, s^{X,i}),
+ *   leaf:     U_X = K(t^X, s^{X,i}) A^{-1}               (L2P; P2M = U_X^T)
+ *   non-leaf: U~_{X_c X} = K(t^{X_c,i}, s^{X,i}) A^{-1}  (L2L; M2M = transpose)
+ *   M2L:      T_{X,Y} = K(t^{X,i}, s^{Y,o}) = K(t^{X,i}, t^{Y,i})  (evaluated in the MVP)
+ * reading: A^{-1} is applied by LU with partial pivoting. */
+static void build_operators(orc_tree *t, int fam)
+{
+    for (int l = 1; l <= t->kappa; ++l) {
+        olevel *L = &t->lev[l];
+        if (!L->fam[fam]) continue;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t x = 0; x < L->nbox; ++x) {
+            obasis *B = &L->fam[fam][x];
+            int64_t r = B->rank;
+            if (r == 0) continue;
+            double *A = malloc(sizeof(double) * r * r);
+            int64_t *piv = malloc(sizeof(int64_t) * r);
+            for (int64_t a = 0; a < r; ++a)
+                for (int64_t b = 0; b < r; ++b) A[a * r + b] = K(t, B->row[a], B->col[b]);
+            lu_factor(A, r, piv);
+            int64_t nrows = 0;
+            if (l == t->kappa) {
+                nrows = L->end[x] - L->begin[x];
+            } else {
+                olevel *C = &t->lev[l + 1];
+                for (int64_t xc = L->cbeg[x]; xc < L->cend[x]; ++xc) nrows += C->fam[fam][xc].rank;
+            }
+            B->nrow_op = nrows;
+            B->ncol_op = r;
+            B->op = malloc(sizeof(double) * (nrows ? nrows : 1) * r);
+            double *row = malloc(sizeof(double) * r);
+            int64_t ir = 0;
+            if (l == t->kappa) {
+                for (int64_t i = L->begin[x]; i < L->end[x]; ++i, ++ir) {
+                    for (int64_t b = 0; b < r; ++b) row[b] = K(t, i, B->col[b]);
+                    lu_solve_row(A, piv, r, row);
+                    for (int64_t b = 0; b < r; ++b) B->op[b * nrows + ir] = row[b];
+                }
+            } else {
+                olevel *C = &t->lev[l + 1];
+                for (int64_t xc = L->cbeg[x]; xc < L->cend[x]; ++xc) {
+                    const obasis *CB = &C->fam[fam][xc];
+                    for (int64_t k = 0; k < CB->rank; ++k, ++ir) {
+                        for (int64_t b = 0; b < r; ++b) row[b] = K(t, CB->row[k], B->col[b]);
+                        lu_solve_row(A, piv, r, row);
+                        for (int64_t b = 0; b < r; ++b) B->op[b * nrows + ir] = row[b];
+                    }
+                }
+            }
+            free(row); free(A); free(piv);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public entry points                                                      */
+/* ------------------------------------------------------------------------ */
+
+void orc_free(orc_tree *t);
+
+/* variant 0: H2*(b+t);  variant 1: (H2+H)*. */
+orc_tree *orc_build(const double *pts, int64_t n, int d, int kind, double param, double diag,
+                    double shift, int64_t nmax, double eps_far, double eps_ver, int variant)
+{
+    if (n < 1 || (d != 2 && d != 3) || nmax < 1) return NULL;
+    orc_tree *t = calloc(1, sizeof(orc_tree));
+    t->d = d; t->n = n; t->nmax = nmax; t->variant = variant;
+    t->ker.kind = kind; t->ker.param = param; t->ker.diag = diag; t->ker.shift = shift;
+    t->eps_far = eps_far; t->eps_ver = eps_ver;
+    build_tree(t, pts);
+    build_lists(t);
+    far_pivots(t);
+    build_operators(t, FAM_FAR);
+    if (variant == 0) {
+        ver_pivots(t);
+        build_operators(t, FAM_VER);
+    } else {
+        hph_pairs(t);
+    }
+    return t;
+}
+
+void orc_free(orc_tree *t)
+{
+    if (!t) return;
+    for (int l = 0; l <= t->kappa; ++l) {
+        olevel *L = &t->lev[l];
+        for (int f = 0; f < 2; ++f) {
+            if (!L->fam[f]) continue;
+            for (int64_t x = 0; x < L->nbox; ++x) {
+                free(L->fam[f][x].row); free(L->fam[f][x].col); free(L->fam[f][x].op);
+            }
+            free(L->fam[f]);
+        }
+        for (int64_t p = 0; p < L->npair; ++p) { free(L->pair[p].ub); free(L->pair[p].vb); }
+        free(L->pair);
+        for (int w = 0; w < 3; ++w) { free(L->off[w]); free(L->idx[w]); }
+        free(L->morton); free(L->begin); free(L->end); free(L->parent);
+        free(L->cbeg); free(L->cend); free(L->coord);
+    }
+    free(t->lev); free(t->perm); free(t->pts);
+    free(t);
+}
+
+/* The MVP of Sec. 5.1.2 (H2*) / Sec. 5.2.2 ((H2+H)*).  q and the three
+ * outputs are in user order; near includes the shift * q term.  Any output
+ * pointer may be NULL to skip that part. */
+void orc_apply(const orc_tree *t, const double *q_user, double *near_out, double *far_out,
+               double *ver_out)
+{
+    int64_t n = t->n;
+    int kappa = t->kappa;
+    double *q = malloc(sizeof(double) * n);
+    double *phi = malloc(sizeof(double) * n);
+    for (int64_t i = 0; i < n; ++i) q[i] = q_user[t->perm[i]];
+
+    /* near field: phi_X = sum over X' in N*(X) of K(t^X, s^{X'}) q_{X'} */
+    if (near_out) {
+        const olevel *L = &t->lev[kappa];
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t x = 0; x < L->nbox; ++x)
+            for (int64_t i = L->begin[x]; i < L->end[x]; ++i) {
+                double s = 0.0;
+                for (int64_t e = L->off[LIST_NEAR][x]; e < L->off[LIST_NEAR][x + 1]; ++e) {
+                    int64_t y = L->idx[LIST_NEAR][e];
+                    for (int64_t j = L->begin[y]; j < L->end[y]; ++j) s += K(t, i, j) * q[j];
+                }
+                phi[i] = s + t->ker.shift * q[i];
+            }
+        for (int64_t i = 0; i < n; ++i) near_out[t->perm[i]] = phi[i];
+    }
+
+    for (int fam = 0; fam < 2; ++fam) {
+        double *out = fam == FAM_FAR ? far_out : ver_out;
+        if (!out) continue;
+        for (int64_t i = 0; i < n; ++i) phi[i] = 0.0;
+        if (fam == FAM_VER && t->variant == 1) {
+            /* (H2+H)* vertex potential: phi(X) += U (V^T q_Y) per pair */
+            for (int l = 1; l <= kappa; ++l) {
+                const olevel *L = &t->lev[l];
+                for (int64_t p = 0; p < L->npair; ++p) {
+                    const ohph *H = &L->pair[p];
+                    int64_t bx = L->begin[H->x], nx = L->end[H->x] - bx;
+                    int64_t by = L->begin[H->y], ny = L->end[H->y] - by;
+                    for (int64_t k = 0; k < H->rank; ++k) {
+                        double wy = dot(H->vb + k * ny, q + by, ny);
+                        double wx = dot(H->ub + k * nx, q + bx, nx);
+                        for (int64_t i = 0; i < nx; ++i) phi[bx + i] += H->ub[k * nx + i] * wy;
+                        for (int64_t j = 0; j < ny; ++j) phi[by + j] += H->vb[k * ny + j] * wx;
+                    }
+                }
+            }
+            for (int64_t i = 0; i < n; ++i) out[t->perm[i]] = phi[i];
+            continue;
+        }
+        int lmin = fam == FAM_FAR ? 2 : 1;
+        int wlist = fam == FAM_FAR ? LIST_FAR : LIST_VER;
+        if (kappa < lmin) {
+            for (int64_t i = 0; i < n; ++i) out[i] = 0.0;
+            continue;
+        }
+        double **v = calloc(kappa + 1, sizeof(double *)), **u = calloc(kappa + 1, sizeof(double *));
+        int64_t **co = calloc(kappa + 1, sizeof(int64_t *));
+        for (int l = lmin; l <= kappa; ++l) {
+            const olevel *L = &t->lev[l];
+            co[l] = calloc(L->nbox + 1, sizeof(int64_t));
+            for (int64_t x = 0; x < L->nbox; ++x) co[l][x + 1] = co[l][x] + L->fam[fam][x].rank;
+            v[l] = calloc(co[l][L->nbox] + 1, sizeof(double));
+            u[l] = calloc(co[l][L->nbox] + 1, sizeof(double));
+        }
+        /* P2M at the leaves: v_X = V_X^* q_X = U_X^T q_X */
+        {
+            const olevel *L = &t->lev[kappa];
+            for (int64_t x = 0; x < L->nbox; ++x) {
+                const obasis *B = &L->fam[fam][x];
+                int64_t nx = L->end[x] - L->begin[x];
+                for (int64_t k = 0; k < B->rank; ++k)
+                    v[kappa][co[kappa][x] + k] = dot(B->op + k * nx, q + L->begin[x], nx);
+            }
+        }
+        /* M2M: v_X = sum_c V~*_{X X_c} v_{X_c}, l = kappa-1 .. lmin */
+        for (int l = kappa - 1; l >= lmin; --l) {
+            const olevel *L = &t->lev[l], *C = &t->lev[l + 1];
+            for (int64_t x = 0; x < L->nbox; ++x) {
+                const obasis *B = &L->fam[fam][x];
+                if (B->rank == 0) continue;
+                int64_t c0 = co[l + 1][L->cbeg[x]];
+                for (int64_t k = 0; k < B->rank; ++k)
+                    v[l][co[l][x] + k] = dot(B->op + k * B->nrow_op, v[l + 1] + c0, B->nrow_op);
+                (void)C;
+            }
+        }
+        /* M2L: u_X = sum_{Y in IL(X)} T_{X,Y} v_Y, T_{X,Y} = K(t^{X,i}, t^{Y,i}) */
+        for (int l = lmin; l <= kappa; ++l) {
+            const olevel *L = &t->lev[l];
+            for (int64_t x = 0; x < L->nbox; ++x) {
+                const obasis *B = &L->fam[fam][x];
+                for (int64_t e = L->off[wlist][x]; e < L->off[wlist][x + 1]; ++e) {
+                    int64_t y = L->idx[wlist][e];
+                    const obasis *BY = &L->fam[fam][y];
+                    for (int64_t a = 0; a < B->rank; ++a) {
+                        double s = 0.0;
+                        for (int64_t b = 0; b < BY->rank; ++b)
+                            s += K(t, B->row[a], BY->row[b]) * v[l][co[l][y] + b];
+                        u[l][co[l][x] + a] += s;
+                    }
+                }
+            }
+        }
+        /* L2L: u_{X_c} += U~_{X_c X} u_X, l = lmin .. kappa-1 */
+        for (int l = lmin; l < kappa; ++l) {
+            const olevel *L = &t->lev[l];
+            for (int64_t x = 0; x < L->nbox; ++x) {
+                const obasis *B = &L->fam[fam][x];
+                if (B->rank == 0) continue;
+                int64_t c0 = co[l + 1][L->cbeg[x]];
+                for (int64_t j = 0; j < B->nrow_op; ++j) {
+                    double s = 0.0;
+                    for (int64_t k = 0; k < B->rank; ++k) s += B->op[k * B->nrow_op + j] * u[l][co[l][x] + k];
+                    u[l + 1][c0 + j] += s;
+                }
+            }
+        }
+        /* L2P: phi_X = U_X u_X */
+        {
+            const olevel *L = &t->lev[kappa];
+            for (int64_t x = 0; x < L->nbox; ++x) {
+                const obasis *B = &L->fam[fam][x];
+                int64_t nx = L->end[x] - L->begin[x];
+                for (int64_t i = 0; i < nx; ++i) {
+                    double s = 0.0;
+                    for (int64_t k = 0; k < B->rank; ++k) s += B->op[k * nx + i] * u[kappa][co[kappa][x] + k];
+                    phi[L->begin[x] + i] = s;
+                }
+            }
+        }
+        for (int64_t i = 0; i < n; ++i) out[t->perm[i]] = phi[i];
+        for (int l = lmin; l <= kappa; ++l) { free(v[l]); free(u[l]); free(co[l]); }
+        free(v); free(u); free(co);
+    }
+    free(q); free(phi);
+}
+
+/* ---- structure queries for the tests ---- */
+
+/* out: d, n, kappa, variant, nmax, total boxes; returns kappa. */
+int64_t orc_info(const orc_tree *t, int64_t *out)
+{
+    int64_t nb = 0;
+    for (int l = 0; l <= t->kappa; ++l) nb += t->lev[l].nbox;
+    out[0] = t->d; out[1] = t->n; out[2] = t->kappa; out[3] = t->variant; out[4] = t->nmax; out[5] = nb;
+    return t->kappa;
+}
+
+/* out: centre (3), half-width */
+void orc_cube(const orc_tree *t, double *out)
+{
+    for (int c = 0; c < 3; ++c) out[c] = c < t->d ? t->ctr[c] : 0.0;
+    out[3] = t->half;
+}
+
+void orc_perm(const orc_tree *t, int64_t *out) { memcpy(out, t->perm, sizeof(int64_t) * t->n); }
+
+int64_t orc_nbox(const orc_tree *t, int l) { return (l < 0 || l > t->kappa) ? -1 : t->lev[l].nbox; }
+
+void orc_boxes(const orc_tree *t, int l, int64_t *morton, int32_t *coord, int64_t *begin,
+               int64_t *end, int64_t *parent)
+{
+    const olevel *L = &t->lev[l];
+    memcpy(morton, L->morton, sizeof(int64_t) * L->nbox);
+    memcpy(coord, L->coord, sizeof(int32_t) * L->nbox * t->d);
+    memcpy(begin, L->begin, sizeof(int64_t) * L->nbox);
+    memcpy(end, L->end, sizeof(int64_t) * L->nbox);
+    memcpy(parent, L->parent, sizeof(int64_t) * L->nbox);
+}
+
+int64_t orc_list_len(const orc_tree *t, int which, int l) { return t->lev[l].off[which][t->lev[l].nbox]; }
+
+void orc_list(const orc_tree *t, int which, int l, int64_t *off, int64_t *idx)
+{
+    const olevel *L = &t->lev[l];
+    memcpy(off, L->off[which], sizeof(int64_t) * (L->nbox + 1));
+    memcpy(idx, L->idx[which], sizeof(int64_t) * L->off[which][L->nbox]);
+}
+
+/* rank of box x at level l in family fam (-1 if the family has no basis there) */
+int64_t orc_rank(const orc_tree *t, int fam, int l, int64_t x)
+{
+    if (l < 0 || l > t->kappa || !t->lev[l].fam[fam]) return -1;
+    return t->lev[l].fam[fam][x].rank;
+}
+
+void orc_pivots(const orc_tree *t, int fam, int l, int64_t x, int64_t *row, int64_t *col)
+{
+    const obasis *B = &t->lev[l].fam[fam][x];
+    memcpy(row, B->row, sizeof(int64_t) * B->rank);
+    memcpy(col, B->col, sizeof(int64_t) * B->rank);
+}
+
+/* operator of box x: leaf U_X or stacked transfer, column-major nrow x rank.
+ * Returns nrow (the caller passes out = NULL to query it). */
+int64_t orc_operator(const orc_tree *t, int fam, int l, int64_t x, double *out)
+{
+    const obasis *B = &t->lev[l].fam[fam][x];
+    if (out && B->rank) memcpy(out, B->op, sizeof(double) * B->nrow_op * B->rank);
+    return B->nrow_op;
+}
+
+int64_t orc_hph_npairs(const orc_tree *t, int l) { return t->lev[l].npair; }
+
+/* info: x, y, rank; factors column-major (n_X x rank, n_Y x rank) */
+void orc_hph_pair(const orc_tree *t, int l, int64_t p, int64_t *info, double *ub, double *vb)
+{
+    const olevel *L = &t->lev[l];
+    const ohph *H = &L->pair[p];
+    info[0] = H->x; info[1] = H->y; info[2] = H->rank;
+    int64_t nx = L->end[H->x] - L->begin[H->x], ny = L->end[H->y] - L->begin[H->y];
+    if (ub) memcpy(ub, H->ub, sizeof(double) * nx * H->rank);
+    if (vb) memcpy(vb, H->vb, sizeof(double) * ny * H->rank);
+}
+
+/* tree-order points (n x d) */
+void orc_tree_points(const orc_tree *t, double *out) { memcpy(out, t->pts, sizeof(double) * t->n * t->d); }
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,78 @@
+"""Seeded synthetic inputs shared by the library's tests, the oracle's tests and the benchmark.
+
+This module holds random-number generation only: no part of the method's
+arithmetic.  Every point set is uniform in [-1, 1]^d and every right-hand side
+is N(0, 1), the distributions of the paper's MVP experiments (Sec. 6.1.1,
+Sec. 6.2.1: uniformly distributed particles in [-1,1]^d, random vectors q).
+Generators are NumPy PCG64 (`numpy.random.default_rng(seed)`), so any seed
+reproduces the same arrays on every machine.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+LOG_R, INV_R, GAUSS, EXP_R = 0, 1, 2, 3
+
+
+def uniform_points(n: int, d: int, seed: int) -> np.ndarray:
+    """n points i.i.d. uniform in [-1, 1]^d, row-major (n, d) float64."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n, d))
+
+
+def normal_rhs(n: int, m: int, seed: int) -> np.ndarray:
+    """m right-hand sides of length n with N(0, 1) entries, column-major (n, m) float64."""
+    return np.asfortranarray(np.random.default_rng(seed).standard_normal(size=(n, m)))
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    d: int
+    n: int
+    kind: int
+    param: float
+    diag: float
+    shift: float
+    nmax: int
+    eps: float
+    nrhs: int
+    seed_points: int
+    seed_rhs: int
+    extra: dict = field(default_factory=dict)
+
+    def points(self) -> np.ndarray:
+        return uniform_points(self.n, self.d, self.seed_points)
+
+    def rhs(self) -> np.ndarray:
+        return normal_rhs(self.n, self.nrhs, self.seed_rhs)
+
+
+def _w(c, name, d, n, kind, eps, nrhs, param=0.0, diag=None, shift=0.0, nmax=64, **extra):
+    if diag is None:
+        diag = 0.0 if kind in (LOG_R, INV_R) else 1.0
+    return Workload(name, d, n, kind, param, diag, shift, nmax, eps, nrhs, 1000 + c, 2000 + c, extra)
+
+
+# The five workloads the project measures and tests (index = config number - 1).
+WORKLOADS = [
+    _w(0, "2d_log_n4096", 2, 4096, LOG_R, 1e-8, 1),
+    _w(1, "2d_log_n1048576", 2, 1 << 20, LOG_R, 1e-8, 1),
+    _w(2, "3d_invr_n262144_m32", 3, 1 << 18, INV_R, 1e-6, 32),
+    _w(3, "2d_gauss_rbf_n262144", 2, 1 << 18, GAUSS, 1e-8, 1, param=0.1, shift=1e-2),
+    _w(4, "serving_mixed", 0, 0, LOG_R, 1e-8, 1, requests=512),
+]
+
+
+def workload(name_or_index) -> Workload:
+    if isinstance(name_or_index, int):
+        return WORKLOADS[name_or_index]
+    for w in WORKLOADS:
+        if w.name == name_or_index:
+            return w
+    raise KeyError(name_or_index)
+
+
+def scaled(w: Workload, n: int, seed_offset: int = 0) -> Workload:
+    """The same workload recipe at another size (and optionally other seeds)."""
+    return Workload(w.name + f"_n{n}", w.d, n, w.kind, w.param, w.diag, w.shift, w.nmax, w.eps, w.nrhs,
+                    w.seed_points + seed_offset, w.seed_rhs + seed_offset, dict(w.extra))

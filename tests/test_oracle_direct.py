@@ -1,0 +1,68 @@
+"""Pins for the oracle's direct product phi = (K + shift I) q (Sec. 6, t_direct / RE_MVP).
+
+Each expected value is a closed form of classical geometry, not a retyping of
+the oracle's loop.
+"""
+import math
+
+import numpy as np
+
+
+def test_log_r_on_unit_circle(orc):
+    # N equally spaced points on the unit circle: prod_{j != i} |x_i - x_j| = N,
+    # so with q = 1 and K_ii = 0 every potential equals log N.
+    for n in (3, 7, 64, 257):
+        th = 2 * np.pi * np.arange(n) / n
+        pts = np.stack([np.cos(th), np.sin(th)], 1)
+        phi = orc.direct(pts, np.ones(n), orc.LOG_R)
+        assert np.allclose(phi, math.log(n), rtol=0, atol=1e-12 * max(1.0, math.log(n)))
+
+
+def test_log_r_scaled_circle(orc):
+    # radius rho: prod |x_i - x_j| = N rho^(N-1)
+    n, rho = 16, 0.37
+    th = 2 * np.pi * np.arange(n) / n
+    pts = rho * np.stack([np.cos(th), np.sin(th)], 1) + np.array([0.25, -0.5])
+    phi = orc.direct(pts, np.ones(n), orc.LOG_R)
+    assert np.allclose(phi, math.log(n) + (n - 1) * math.log(rho), rtol=1e-13)
+
+
+def test_inv_r_cube_vertices(orc):
+    # unit cube: every vertex has 3 neighbours at 1, 3 at sqrt 2, 1 at sqrt 3
+    pts = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], float) * 0.5
+    phi = orc.direct(pts, np.ones(8), orc.INV_R)
+    want = (3 + 3 / math.sqrt(2) + 1 / math.sqrt(3)) / 0.5
+    assert np.allclose(phi, want, rtol=1e-14)
+
+
+def test_gaussian_and_exp_two_points_with_diag_and_shift(orc):
+    pts = np.array([[0.0, 0.0], [0.3, 0.4]])  # distance 0.5
+    q = np.array([2.0, -3.0])
+    h = 0.7
+    phi = orc.direct(pts, q, orc.GAUSS, param=h, diag=1.0, shift=0.01)
+    g = math.exp(-0.25 / h**2)
+    assert np.allclose(phi, [2 * 1.0 + g * -3 + 0.02, g * 2 + -3 * 1.0 - 0.03], rtol=1e-14)
+    phi = orc.direct(pts, q, orc.EXP_R, diag=1.0)
+    e = math.exp(-0.5)
+    assert np.allclose(phi, [2 + e * -3, e * 2 - 3], rtol=1e-14)
+
+
+def test_diagonal_convention_and_rows_subset(orc):
+    # K_ii = 0 for log r (Sec. 6.1.1): a single point has zero potential
+    assert orc.direct(np.array([[0.1, 0.2]]), np.array([5.0]), orc.LOG_R)[0] == 0.0
+    rng = np.random.default_rng(0)
+    pts = rng.uniform(-1, 1, (50, 2))
+    q = rng.standard_normal(50)
+    full = orc.direct(pts, q, orc.LOG_R)
+    rows = np.array([3, 17, 49, 0])
+    assert np.array_equal(orc.direct(pts, q, orc.LOG_R, rows=rows), full[rows])
+
+
+def test_symmetric_matrix(orc):
+    # x^T K y = y^T K x for a symmetric kernel
+    rng = np.random.default_rng(1)
+    pts = rng.uniform(-1, 1, (200, 3))
+    x, y = rng.standard_normal(200), rng.standard_normal(200)
+    a = x @ orc.direct(pts, y, orc.INV_R)
+    b = y @ orc.direct(pts, x, orc.INV_R)
+    assert abs(a - b) <= 1e-12 * abs(a)

@@ -1,0 +1,151 @@
+"""Pins for the oracle's H2* and (H2+H)* MVP (Sec. 5.1.2, Sec. 5.2.2) against the direct sum.
+
+* kappa = 0 reduces to the direct product; kappa = 1 has no far field (Sec. 5.1.2).
+* At a near-zero tolerance the product equals the direct sum to 1e-12.
+* The error falls as the tolerance falls and stays within a bounded multiple of it.
+* Each part (near, far, vertex) matches the brute-force sum over exactly the
+  blocks its lists name, so a dropped term or a wrong index shows up in one part.
+* K~ is symmetric for symmetric kernels (Sec. 3.4.3 remark); the shift adds shift*q.
+* The paper's printed RE_MVP for 3D 1/r at N = 64000 (Tables smvp3d_lap_1) is matched within 10x.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+KINDS = {"log_r": (2, 0, 0.0), "inv_r": (3, 1, 0.0), "gauss": (2, 2, 0.3), "exp_r": (3, 3, 0.0)}
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("kname", list(KINDS))
+@pytest.mark.parametrize("variant", [0, 1])
+def test_kappa0_is_direct(orc, inputs, kname, variant):
+    d, kind, param = KINDS[kname]
+    pts = inputs.uniform_points(50, d, 3)
+    q = inputs.normal_rhs(50, 1, 4)[:, 0]
+    T = orc.Tree(pts, kind, 64, 1e-6, variant=variant, param=param, shift=0.25)
+    assert T.kappa == 0
+    near, far, ver = T.apply_parts(q)
+    assert np.all(far == 0) and np.all(ver == 0)
+    assert rel(near, orc.direct(pts, q, kind, param=param, shift=0.25)) <= 1e-15
+
+
+def test_kappa1_has_no_far_field(orc, inputs):
+    pts = inputs.uniform_points(200, 2, 5)
+    q = inputs.normal_rhs(200, 1, 6)[:, 0]
+    for variant in (0, 1):
+        T = orc.Tree(pts, orc.LOG_R, 64, 1e-10, variant=variant)
+        assert T.kappa == 1
+        near, far, ver = T.apply_parts(q)
+        assert np.all(far == 0) and np.abs(ver).max() > 0
+        assert rel(near + far + ver, orc.direct(pts, q, orc.LOG_R)) <= 1e-9
+
+
+@pytest.mark.parametrize("kname", list(KINDS))
+@pytest.mark.parametrize("variant", [0, 1])
+def test_near_zero_tolerance_matches_direct(orc, inputs, kname, variant):
+    d, kind, param = KINDS[kname]
+    n = 1024 if d == 2 else 1200
+    pts = inputs.uniform_points(n, d, 7)
+    q = inputs.normal_rhs(n, 1, 8)[:, 0]
+    T = orc.Tree(pts, kind, 16, 1e-15, variant=variant, param=param)
+    assert T.kappa >= 2
+    assert rel(T.apply(q), orc.direct(pts, q, kind, param=param)) <= 1e-12
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_error_falls_with_tolerance(orc, inputs, d):
+    n = 4096 if d == 2 else 8192
+    kind = orc.LOG_R if d == 2 else orc.INV_R
+    pts = inputs.uniform_points(n, d, 1000)
+    q = inputs.normal_rhs(n, 1, 2000)[:, 0]
+    ex = orc.direct(pts, q, kind)
+    for variant in (0, 1):
+        errs = []
+        epss = [1e-4, 1e-6, 1e-8, 1e-10] + ([1e-12] if d == 2 else [])
+        for eps in epss:
+            T = orc.Tree(pts, kind, 64, eps, variant=variant)
+            errs.append(rel(T.apply(q), ex))
+        assert all(b < a for a, b in zip(errs, errs[1:])), errs
+        assert all(e <= 100 * eps for e, eps in zip(errs, epss)), errs
+
+
+def _parts_brute_force(T, pts_tree, q_tree, kind):
+    """Near / far / vertex sums over exactly the listed blocks, for every point (tree order)."""
+    K = T.kappa
+    n = len(q_tree)
+    box_of = []
+    for l in range(K + 1):
+        b = T.boxes(l)
+        bo = np.empty(n, np.int64)
+        for i, (s, e) in enumerate(zip(b["begin"], b["end"])):
+            bo[s:e] = i
+        box_of.append(bo)
+    dd = pts_tree[:, None, :] - pts_tree[None, :, :]
+    r = np.sqrt((dd ** 2).sum(-1))
+    with np.errstate(divide="ignore"):
+        Kmat = np.log(r) if kind == 0 else 1.0 / r
+    Kmat[r == 0] = 0.0
+    out = []
+    for which, levels in ((0, [K]), (1, range(2, K + 1)), (2, range(1, K + 1))):
+        mask = np.zeros((n, n), bool)
+        for l in levels:
+            off, idx = T.lists(which, l)
+            for X in range(len(off) - 1):
+                rows = box_of[l] == X
+                cols = np.isin(box_of[l], idx[off[X]:off[X + 1]])
+                mask[np.ix_(rows, cols)] = True
+        out.append((Kmat * mask) @ q_tree)
+    return out
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_each_part_matches_its_blocks(orc, inputs, d, variant):
+    kind = orc.LOG_R if d == 2 else orc.INV_R
+    n = 2048 if d == 2 else 2600
+    pts = inputs.uniform_points(n, d, 31)
+    q = inputs.normal_rhs(n, 1, 32)[:, 0]
+    eps = 1e-10
+    T = orc.Tree(pts, kind, 16 if d == 2 else 8, eps, variant=variant)
+    assert T.kappa >= 3
+    perm = T.perm()
+    near, far, ver = T.apply_parts(q)
+    bn, bf, bv = _parts_brute_force(T, pts[perm], q[perm], kind)
+    total = np.linalg.norm(bn + bf + bv)
+    assert np.linalg.norm(near[perm] - bn) <= 1e-13 * total
+    assert np.linalg.norm(far[perm] - bf) <= 1e3 * eps * total
+    assert np.linalg.norm(ver[perm] - bv) <= 1e3 * eps * total
+    assert rel(far[perm], bf) <= 1e4 * eps and rel(ver[perm], bv) <= 1e4 * eps
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_symmetry_linearity_shift(orc, inputs, variant):
+    pts = inputs.uniform_points(4096, 2, 41)
+    rng = np.random.default_rng(42)
+    x, y = rng.standard_normal(4096), rng.standard_normal(4096)
+    T = orc.Tree(pts, orc.LOG_R, 64, 1e-6, variant=variant)
+    Kx, Ky = T.apply(x), T.apply(y)
+    assert abs(x @ Ky - y @ Kx) <= 1e-13 * np.linalg.norm(x) * np.linalg.norm(Ky)
+    assert rel(T.apply(2.0 * x - 3.0 * y), 2.0 * Kx - 3.0 * Ky) <= 1e-14
+    Ts = orc.Tree(pts, orc.LOG_R, 64, 1e-6, variant=variant, shift=0.5)
+    assert np.allclose(Ts.apply(x) - Kx, 0.5 * x, rtol=0, atol=1e-12 * np.abs(Kx).max())
+
+
+@pytest.mark.parametrize("case", json.load(open(os.path.join(GOLDEN, "paper_re_bands.json")))["cases"])
+def test_paper_re_band_3d(orc, inputs, case):
+    n, d = case["n"], case["d"]
+    pts = inputs.uniform_points(n, d, 1000)
+    rows = np.random.default_rng(0).choice(n, 300, replace=False)
+    T = orc.Tree(pts, orc.INV_R, case["nmax"], case["eps"], variant=0 if case["variant"] == "h2star" else 1)
+    res = []
+    for s in range(2):
+        q = inputs.normal_rhs(n, 1, 2000 + s)[:, 0]
+        res.append(rel(T.apply(q)[rows], orc.direct(pts, q, orc.INV_R, rows=rows)))
+    re = float(np.mean(res))
+    assert case["re"] / 10 <= re <= case["re"] * 10, (re, case["re"])

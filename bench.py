@@ -1,0 +1,208 @@
+"""Benchmark: H2* fast MVP throughput on one MI355X.
+
+Workload: 2D, N = 2^20 points i.i.d. uniform in [-1,1]^2 (seed 1001), kernel
+log|x-y| with K_ii = 0, leaf size 64, NCA tolerance 1e-8, one N(0,1)
+right-hand side (seed 2001).  A step is one complete product y = K~ x through
+h2s_apply (charges to tree order, P2M, M2M, M2L, L2L, L2P, near field,
+scatter) with x and y resident in HBM.  `value` is the FP64 H2* rate in
+points/s; the FP32 form and the (H2+H)* variant are timed beside it.
+
+Prints one JSON line (see the fields below).  --gpus N > 1 is not supported:
+this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks used for the roofline fraction.
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6
+FP32_VECTOR_TFLOPS = 157.3
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--profile-steps", type=int, default=3)
+    p.add_argument("--workload", default="2d_log_n1048576")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--only", default="", help="comma list of h2star_fp64,h2star_fp32,h2plush_fp64")
+    return p.parse_args()
+
+
+def time_variant(h2s, torch, pts, q, w, variant, prec, steps, warmup, prof_steps):
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    T = h2s.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps, variant=variant, prec=prec,
+                  param=w.param, shift=w.shift)
+    t_init = time.perf_counter() - t0
+    x = torch.from_numpy(q).to(dev)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        T.apply(x, y)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        T.apply(x, y)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / steps
+    T.set_profiling(True)
+    for _ in range(prof_steps):
+        T.apply(x, y)
+    prof = T.profile()
+    T.set_profiling(False)
+    torch.cuda.synchronize()
+    stats = T.stats()
+    out = y.cpu().numpy()
+    T.free()
+    return dict(ms=ms, wall_ms=1e3 * wall / steps, t_init=t_init, stats=stats,
+                kernels={k: {"avg_ms": v[0] / max(v[1], 1), "launches_per_step": v[1] / max(prof_steps, 1)}
+                         for k, v in prof.items() if v[1]}), out
+
+
+def algorithmic_work(stats, kernel, prec):
+    """Algorithmic bytes and kernel evaluations per launch of one kernel class."""
+    n = stats["n"]
+    b = 8
+    basis_b = 8 if prec == 0 else 4
+    leaf_rank = stats["leaf_basis_entries"]
+    if kernel == "leaf_down":
+        # x gather is in leaf_up; here: points, charges, U and u at the leaves, y and perm
+        byts = n * (2 * b + b + b + 4) + leaf_rank * basis_b
+        return byts, stats["p2p_evals"]
+    if kernel == "leaf_up":
+        return n * (b + 4 + b) + leaf_rank * basis_b, 0
+    if kernel == "m2l":
+        return 0, stats["m2l_evals"]
+    return 0, 0
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2309_14085_amd import h2s, inputs
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    h2s.load()
+    w = inputs.workload(a.workload)
+    pts, q = w.points(), np.ascontiguousarray(w.rhs()[:, 0])
+    todo = [("h2star_fp64", h2s.H2STAR, h2s.FP64), ("h2star_fp32", h2s.H2STAR, h2s.FP32),
+            ("h2plush_fp64", h2s.H2_PLUS_H, h2s.FP64)]
+    if a.only:
+        todo = [t for t in todo if t[0] in a.only.split(",")]
+    res, outs = {}, {}
+    for name, variant, prec in todo:
+        print(f"# building and timing {name}", file=sys.stderr, flush=True)
+        r, y = time_variant(h2s, torch, pts, q, w, variant, prec, a.steps, a.warmup, a.profile_steps)
+        r["points_per_s"] = w.n / (r["ms"] * 1e-3)
+        res[name], outs[name] = r, y
+        print(f"# {name}: {r['ms']:.3f} ms/step, {r['points_per_s']:.3e} points/s, init {r['t_init']:.1f}s",
+              file=sys.stderr, flush=True)
+    ref = outs.get("h2star_fp64")
+    for name in outs:
+        if ref is not None and name != "h2star_fp64":
+            res[name]["rel_err_vs_fp64_h2star"] = float(np.linalg.norm(outs[name] - ref) / np.linalg.norm(ref))
+
+    main_name = "h2star_fp64" if "h2star_fp64" in res else next(iter(res))
+    m = res[main_name]
+    kernels = m["kernels"]
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
+    roofline = roofline_entry(dom, kernels[dom], m["stats"], 0 if main_name.endswith("fp64") else 1)
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(pts, q, w)
+
+    line = {
+        "metric": "H2* MVP points/s (FP64, rel err vs FP64 oracle <= 1e-12)",
+        "value": m["points_per_s"],
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": m["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: uniform points in [-1,1]^2 (seed 1001), N(0,1) rhs (seed 2001)",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "kernel": "log r (K_ii = 0)", "leaf_size": w.nmax,
+                   "nca_tol": w.eps, "nrhs": 1, "variant": "H2*(b+t)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": {k: {kk: vv for kk, vv in v.items() if kk != "stats"} for k, v in res.items()},
+        "ranks": {"far_max_by_level": m["stats"]["rank_max_level"][0],
+                  "ver_max_by_level": m["stats"]["rank_max_level"][1],
+                  "far_avg_by_level": [round(x, 1) for x in m["stats"]["rank_avg_level"][0]],
+                  "ver_avg_by_level": [round(x, 1) for x in m["stats"]["rank_avg_level"][1]]},
+        "work": {k: m["stats"][k] for k in ("p2p_evals", "m2l_evals", "operator_bytes", "device_bytes",
+                                            "near_pairs", "far_pairs", "ver_pairs")},
+    }
+    print(json.dumps(line))
+
+
+def roofline_entry(name, k, stats, prec):
+    """Roofline of the dominant kernel; the accounting is described in the design notes."""
+    avg_s = k["avg_ms"] * 1e-3
+    byts, evals = algorithmic_work(stats, name, prec)
+    if evals:
+        # kernel evaluations: FP64 flops of the pair arithmetic (differences, squared
+        # distance, log via its evaluation, multiply-add), see FLOPS_PER_EVAL
+        flops = evals * FLOPS_PER_EVAL[prec]
+        peak = FP64_VECTOR_TFLOPS if prec == 0 else FP32_VECTOR_TFLOPS
+        ach = flops / avg_s / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None, "evals_per_launch": evals,
+                "flops_per_eval": FLOPS_PER_EVAL[prec], "avg_launch_ms": k["avg_ms"]}
+    ach = byts / avg_s / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": byts, "avg_launch_ms": k["avg_ms"]}
+
+
+# Floating-point operations charged per pairwise 2D log-kernel evaluation:
+# 2 subtractions, 1 multiply + 1 fused multiply-add for r^2 (3 flops), the
+# logarithm as the 20 flops of a degree-8 minimax polynomial in Horner form
+# after range reduction (frexp + 2 ops), and the multiply-add into the sum (2).
+FLOPS_PER_EVAL = {0: 2 + 3 + 22 + 2, 1: 2 + 3 + 22 + 2}
+
+
+def cpu_baseline(pts, q, w):
+    """The oracle's H2* MVP on the host cores (build untimed), same inputs."""
+    import numpy as np
+
+    import oracle
+    t0 = time.perf_counter()
+    T = oracle.Tree(pts, w.kind, w.nmax, w.eps)
+    t_build = time.perf_counter() - t0
+    times = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        T.apply(q)
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    return {"value": w.n / t, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"full workload {w.name}: oracle FP64 H2* build ({t_build:.1f} s, untimed) then "
+                      f"{len(times)} MVPs, median {t:.2f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * h2s.h -- C ABI of the MI355X H2* / (H2+H)* fast kernel matrix-vector product.
+ *
+ * Method: Khan & Ambikasaran, "New algebraic fast algorithms for N-body
+ * problems in two and three dimensions" (arXiv 2309.14085).
+ *   build  -- uniform 2^d tree (Sec. 3.1), weak-admissibility lists (Sec. 3.3,
+ *             Table "HOD_notation"), B2T NCA on the far field and T2B NCA on
+ *             the vertex-sharing field (Sec. 5.1.1, Algs. "b2t" / "t2b"), or
+ *             per-pair ACA on the vertex-sharing field for (H2+H)* (Sec. 5.2.1,
+ *             Alg. "pure_aca"), and the operators of Sec. 3.4.3.  Runs on the
+ *             host in C++; the operators are then copied to device memory.
+ *   apply  -- phi = K~ x (Sec. 5.1.2, Sec. 5.2.2): P2M, M2M, M2L, L2L, L2P and
+ *             the direct near field, all in HIP kernels on the caller's stream.
+ *
+ * Conventions
+ *   - Every call returns h2s_status; no C++ exception crosses the ABI.
+ *   - Arguments are validated before anything is allocated.  On failure an
+ *     output handle is set to NULL, nothing leaks, and h2s_last_error() gives a
+ *     thread-local description.
+ *   - Points are host memory, row-major n x d doubles.  x and y of apply are
+ *     DEVICE pointers, user (input) order, column-major n x nrhs doubles with
+ *     leading dimensions ldx, ldy >= n.  The library never frees or retains
+ *     caller memory.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  apply is
+ *     asynchronous with respect to the host and ordered on `stream`; a kernel
+ *     fault surfaces at the caller's next synchronisation of that stream.
+ *   - One handle may be used by one stream at a time (its device workspace is
+ *     shared by its calls); distinct handles may run concurrently.
+ */
+#ifndef H2S_H
+#define H2S_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    H2S_OK = 0,
+    H2S_ERR_INVALID_ARG = 1,
+    H2S_ERR_OUT_OF_MEMORY = 2,
+    H2S_ERR_DEVICE = 3,
+    H2S_ERR_NOT_CONVERGED = 4,
+    H2S_ERR_UNSUPPORTED = 5,
+    H2S_ERR_INTERNAL = 6
+} h2s_status;
+
+/* Kernel functions.  LOG_R: log|x-y| (2D single-layer Laplacian, Sec. 6.1.1);
+ * INV_R: 1/|x-y| (3D single-layer Laplacian, Sec. 6.2.1); GAUSSIAN:
+ * exp(-|x-y|^2 / param^2) (RBF interpolation); EXP_R: exp(-|x-y|) (Matern
+ * nu = 1/2, Appendix D).  The closed set is compiled into the device code. */
+typedef enum { H2S_K_LOG_R = 0, H2S_K_INV_R = 1, H2S_K_GAUSSIAN = 2, H2S_K_EXP_R = 3 } h2s_kernel_kind;
+
+typedef struct {
+    h2s_kernel_kind kind;
+    double param; /* GAUSSIAN length scale h > 0; unused otherwise */
+    double diag;  /* K(x, x), used whenever two points coincide: 0 for LOG_R / INV_R (Sec. 6.1.1, 6.2.1) */
+    double shift; /* the matrix is K + shift * I */
+} h2s_kernel;
+
+typedef enum { H2S_H2STAR = 0, H2S_H2_PLUS_H = 1 } h2s_variant;
+
+/* Internal arithmetic of apply.  FP64: everything in double.  FP32: operators,
+ * coefficients, kernel evaluations and accumulation in float (coordinates are
+ * taken relative to box centres so close pairs keep their accuracy); inputs
+ * and outputs stay double at the boundary. */
+typedef enum { H2S_FP64 = 0, H2S_FP32 = 1 } h2s_precision;
+
+typedef struct {
+    int32_t leaf_size;    /* n_max >= 1: leaf level kappa = ceil(log_{2^d}(n / n_max)) (Sec. 3.1) */
+    double eps_far;       /* ACA tolerance of the far-field NCA, >= 0 (Sec. 5.1.1) */
+    double eps_ver;       /* ACA tolerance of the vertex-sharing NCA / per-pair ACA, >= 0 */
+    h2s_variant variant;
+    h2s_precision prec;
+    int32_t host_threads; /* OpenMP threads for the host build; <= 0 = runtime default */
+    int32_t host_only;    /* 1: build the representation on the host only (export / stats; apply is rejected) */
+} h2s_build_opts;
+
+typedef struct h2s_tree_s *h2s_tree;
+
+/* Build the representation of the n x n kernel matrix of `points`.
+ * points: host, row-major n x d doubles (copied).  d in {2, 3}; n >= 1; all
+ * coordinates finite.  The handle owns all device memory until h2s_free.
+ * Errors: INVALID_ARG (bad argument), OUT_OF_MEMORY (host or device),
+ * DEVICE (no HIP device / HIP error), INTERNAL. */
+h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kernel *kernel,
+                     const h2s_build_opts *opts, void *stream, h2s_tree *out);
+
+/* y = (K~ + shift I) x for nrhs right-hand sides (Sec. 5.1.2 / 5.2.2).
+ * x, y: device, user order, column-major, ld >= n; x and y must not overlap.
+ * Errors: INVALID_ARG, UNSUPPORTED (host_only handle), DEVICE. */
+h2s_status h2s_apply(h2s_tree t, const double *x, double *y, int32_t nrhs, int64_t ldx, int64_t ldy,
+                     void *stream);
+
+/* Phase masks for h2s_apply_phases. */
+#define H2S_PHASE_NEAR 1u /* direct near field N* plus shift * x (Sec. 5.1.2, near-field potential) */
+#define H2S_PHASE_FAR 2u  /* far field through the nested far basis */
+#define H2S_PHASE_VER 4u  /* vertex-sharing field: nested basis (H2*) or per-pair low rank ((H2+H)*) */
+#define H2S_PHASE_ALL 7u
+
+/* As h2s_apply, restricted to the phases in `mask` (non-zero subset of
+ * H2S_PHASE_ALL); used to check each part of the product separately. */
+h2s_status h2s_apply_phases(h2s_tree t, uint32_t mask, const double *x, double *y, int32_t nrhs,
+                            int64_t ldx, int64_t ldy, void *stream);
+
+/* Release the handle and its device memory (NULL is accepted). */
+h2s_status h2s_free(h2s_tree t);
+
+typedef struct {
+    int32_t d, kappa, variant, prec;
+    int64_t n;
+    int64_t boxes;                /* non-empty boxes over all levels */
+    int64_t near_pairs;           /* ordered leaf pairs in the near lists (self included) */
+    int64_t far_pairs, ver_pairs; /* ordered box pairs over all levels */
+    int64_t rank_sum[2];          /* sum of ranks, far / vertex family */
+    int32_t rank_max[2];
+    int64_t p2p_evals;            /* kernel evaluations of the near field */
+    int64_t m2l_evals;            /* kernel evaluations of M2L (sum of r_X r_Y) */
+    int64_t leaf_basis_entries;   /* sum over leaves and families of n_X r_X (P2M / L2P operators) */
+    int64_t transfer_entries;     /* sum over non-leaf boxes and families of (sum_c r_c) r_X */
+    int64_t pair_entries;         /* (H2+H)*: sum over vertex pairs of (n_X + n_Y) r */
+    int64_t operator_bytes;       /* stored operators on the device */
+    int64_t device_bytes;         /* all device memory the handle owns */
+    double build_seconds;         /* host build wall time */
+    int32_t rank_max_level[2][32];
+    double rank_avg_level[2][32];
+} h2s_stats;
+
+/* Sizes, ranks per level and work counts of a handle. */
+h2s_status h2s_get_stats(h2s_tree t, h2s_stats *s);
+
+/* Write the tree, permutation, lists, pivots and FP64 operators to `path` as a
+ * container of named arrays: the bytes "H2SX", uint32 version (1), uint32
+ * array count, then per array a NUL-padded char name[32], uint32 dtype
+ * (1 = int32, 2 = int64, 3 = float64), uint32 ndim, int64 dims[ndim] and the
+ * little-endian data.  Arrays: meta (d, kappa, n, variant), cube (centre,
+ * half-width), perm, points (tree order), lev_off, box_begin / end / parent /
+ * coord / morton, {near,far,ver}_off / _idx, and per family fam_{far,ver}_
+ * rank / coef_off / piv_row / piv_col / op_off / op_rows / op (leaf U_X
+ * column-major, stacked L2L row-major), pairs (level, x, y, rank, off_u,
+ * off_v per (H2+H)* pair) and pair_data. */
+h2s_status h2s_export(h2s_tree t, const char *path);
+
+/* Kernel classes timed by the profiling hooks, in launch order. */
+#define H2S_PROF_LEAF_UP 0   /* charges to tree order + P2M */
+#define H2S_PROF_M2M 1       /* all M2M levels */
+#define H2S_PROF_M2L 2       /* M2L, every level and family in one launch */
+#define H2S_PROF_L2L 3       /* all L2L levels */
+#define H2S_PROF_PAIR_PART 4 /* (H2+H)* partial products */
+#define H2S_PROF_PAIR_SUM 5  /* (H2+H)* chunk sums */
+#define H2S_PROF_LEAF_DOWN 6 /* L2P + (H2+H)* vertex blocks + near field + scatter */
+#define H2S_NUM_PROF 7
+
+/* Profiling hooks for measurement: while enabled, every apply records a HIP
+ * event before and after each kernel class on the caller's stream (adding
+ * small gaps between kernels).  h2s_get_profile waits for the recorded
+ * events, writes per-class total milliseconds and launch counts (arrays of
+ * H2S_NUM_PROF entries, either may be NULL) and clears the record. */
+h2s_status h2s_set_profiling(h2s_tree t, int32_t enable);
+h2s_status h2s_get_profile(h2s_tree t, double *ms_total, int64_t *launches);
+
+/* Device memory hooks: alloc(ctx, bytes, &ptr) returns 0 on success.  NULL
+ * functions restore hipMalloc / hipFree.  Affects later builds only. */
+typedef int (*h2s_alloc_fn)(void *ctx, size_t bytes, void **ptr);
+typedef void (*h2s_free_fn)(void *ctx, void *ptr);
+h2s_status h2s_set_allocator(h2s_alloc_fn alloc_fn, h2s_free_fn free_fn, void *ctx);
+
+const char *h2s_status_string(h2s_status s);
+
+/* Copy the calling thread's last error text into buf (always NUL-terminated). */
+h2s_status h2s_last_error(char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2S_H */

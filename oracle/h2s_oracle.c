@@ -24,9 +24,9 @@
  *     direct near field                                        (Sec. 5.1.2, Sec. 5.2.2)
  *   - the direct O(N^2) product used for t_direct and RE_MVP   (Sec. 6, Table "app_notations")
  *
- * Readings of points where the paper is silent or ambiguous (tie-breaks,
- * bounding cube, clan definition, outgoing pivots, ...) are the ones listed
- * in the repository's design notes; each is marked "reading:" below.
+ * Where the paper is silent or ambiguous (tie-breaks, bounding cube, clan
+ * definition, outgoing pivots, ...) the interpretation taken is stated at the
+ * place it is used, marked "reading:".
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (see oracle/build.py).
  */

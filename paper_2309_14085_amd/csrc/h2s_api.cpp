@@ -1,0 +1,558 @@
+// h2s_api.cpp -- the C ABI declared in include/h2s.h.
+//
+// build: validate, construct the representation on the host
+// (h2s_host_build.cpp), pack it into the device layout of h2s_device.hpp in
+// the requested precision and copy it to HBM on the caller's stream.
+// apply: validate, then enqueue the MVP kernels (h2s_kernels.hip) once per
+// right-hand side.  Nothing here computes any part of the product.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "h2s.h"
+#include "h2s_device.hpp"
+#include "h2s_host.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+h2s_alloc_fn g_alloc = nullptr;
+h2s_free_fn g_free = nullptr;
+void *g_alloc_ctx = nullptr;
+
+h2s_status fail(h2s_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+int default_alloc(void *, size_t bytes, void **p) { return hipMalloc(p, bytes) == hipSuccess ? 0 : 1; }
+void default_free(void *, void *p) { (void)hipFree(p); }
+
+} // namespace
+
+struct h2s_tree_s {
+    h2s::HostRep rep;
+    h2s_build_opts opts{};
+    h2s_kernel ker{};
+    bool host_only = false;
+    int device = 0;
+    h2s_alloc_fn afn = default_alloc;
+    h2s_free_fn ffn = default_free;
+    void *actx = nullptr;
+    std::vector<void *> allocs;
+    size_t device_bytes = 0;
+    int64_t operator_bytes = 0;
+    std::vector<int32_t> lev_off;
+    h2s::DevTree<double> t64{};
+    h2s::DevTree<float> t32{};
+    // profiling: (class, start, stop) events recorded by apply while enabled
+    bool profiling = false;
+    hipStream_t prof_stream = nullptr;
+    struct Mark {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+
+    void clear_marks()
+    {
+        for (Mark &m : marks) {
+            (void)hipEventDestroy(m.a);
+            (void)hipEventDestroy(m.b);
+        }
+        marks.clear();
+    }
+
+    ~h2s_tree_s()
+    {
+        clear_marks();
+        for (void *p : allocs) ffn(actx, p);
+    }
+};
+
+namespace {
+void record_mark(void *ctx, int cls, int end)
+{
+    h2s_tree t = (h2s_tree)ctx;
+    if (!end) {
+        h2s_tree_s::Mark m{cls, nullptr, nullptr};
+        if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess) return;
+        (void)hipEventRecord(m.a, t->prof_stream);
+        t->marks.push_back(m);
+    } else if (!t->marks.empty() && t->marks.back().cls == cls) {
+        (void)hipEventRecord(t->marks.back().b, t->prof_stream);
+    }
+}
+} // namespace
+
+namespace {
+
+struct Uploader {
+    h2s_tree t;
+    hipStream_t s;
+    h2s_status st = H2S_OK;
+
+    void *raw(size_t bytes)
+    {
+        if (st != H2S_OK) return nullptr;
+        void *p = nullptr;
+        if (bytes == 0) bytes = 256;
+        if (t->afn(t->actx, bytes, &p) != 0 || !p) {
+            st = fail(H2S_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(bytes) + " bytes failed");
+            return nullptr;
+        }
+        t->allocs.push_back(p);
+        t->device_bytes += bytes;
+        return p;
+    }
+    template <class T> T *copy(const std::vector<T> &v)
+    {
+        // the host vectors are temporaries: wait for each copy before they go away
+        T *p = (T *)raw(sizeof(T) * v.size());
+        if (p && !v.empty() &&
+            (hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+             hipStreamSynchronize(s) != hipSuccess))
+            st = fail(H2S_ERR_DEVICE, "host-to-device copy failed during upload");
+        return p;
+    }
+    template <class T> T *zeros(size_t n)
+    {
+        T *p = (T *)raw(sizeof(T) * n);
+        if (p && n && hipMemsetAsync(p, 0, sizeof(T) * n, s) != hipSuccess)
+            st = fail(H2S_ERR_DEVICE, "hipMemsetAsync failed during upload");
+        return p;
+    }
+};
+
+// Centre of a global box from its integer coordinates.
+void box_centre(const h2s::HostRep &r, int32_t g, double *c)
+{
+    const int l = r.level_of(g);
+    const double w = 2.0 * r.half / (double)((int64_t)1 << l);
+    for (int k = 0; k < 3; ++k) c[k] = k < r.d ? r.origin[k] + (r.box_coord[(size_t)g * 3 + k] + 0.5) * w : 0.0;
+}
+
+template <typename T> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<T> &D)
+{
+    const h2s::HostRep &r = t->rep;
+    const int d = r.d, kappa = r.kappa;
+    const int32_t nbox = r.nbox(), leaf0 = r.leaf0(), nleaf = r.nleaf();
+    const int64_t n = r.n;
+    const bool local = sizeof(T) == 4; // FP32 stores coordinates relative to box centres
+    Uploader up{t, s};
+
+    D = h2s::DevTree<T>{};
+    D.n = (int32_t)n;
+    D.d = d;
+    D.kappa = kappa;
+    D.nleaf = nleaf;
+    D.leaf0 = leaf0;
+    D.nbox = nbox;
+    D.kind = r.ker.kind;
+    D.diag = r.ker.diag;
+    D.shift = r.ker.shift;
+    D.kparam = r.ker.kind == H2S_K_GAUSSIAN ? 1.0 / (r.ker.param * r.ker.param) : 0.0;
+    D.variant = r.variant;
+
+    std::vector<double> ctr((size_t)nbox * 3);
+    for (int32_t g = 0; g < nbox; ++g) box_centre(r, g, &ctr[(size_t)g * 3]);
+
+    D.perm = up.copy(r.perm);
+    {
+        std::vector<T> px(n), py(n), pz(d == 3 ? n : 1);
+        for (int32_t g = leaf0; g < nbox; ++g)
+            for (int32_t i = r.box_begin[g]; i < r.box_end[g]; ++i) {
+                const double *p = &r.pts[(size_t)i * d];
+                const double *c = &ctr[(size_t)g * 3];
+                px[i] = (T)(local ? p[0] - c[0] : p[0]);
+                py[i] = (T)(local ? p[1] - c[1] : p[1]);
+                if (d == 3) pz[i] = (T)(local ? p[2] - c[2] : p[2]);
+            }
+        D.px = up.copy(px);
+        D.py = up.copy(py);
+        D.pz = up.copy(pz);
+    }
+    D.box_begin = up.copy(r.box_begin);
+    D.box_end = up.copy(r.box_end);
+    D.box_cbeg = up.copy(r.box_cbeg);
+    D.box_cend = up.copy(r.box_cend);
+    D.box_ctr = up.copy(ctr);
+    {
+        std::vector<int32_t> anc((size_t)nleaf * (kappa + 1));
+        for (int32_t lf = 0; lf < nleaf; ++lf) {
+            int32_t g = leaf0 + lf;
+            for (int l = kappa; l >= 0; --l) {
+                anc[(size_t)lf * (kappa + 1) + l] = g;
+                g = l > 0 ? r.box_parent[g] : g;
+            }
+        }
+        D.leaf_anc = up.copy(anc);
+        std::vector<int32_t> noff(nleaf + 1, 0), nidx;
+        for (int32_t lf = 0; lf < nleaf; ++lf) {
+            const int32_t g = leaf0 + lf;
+            for (int64_t e = r.list_off[0][g]; e < r.list_off[0][g + 1]; ++e) nidx.push_back(r.list_idx[0][e] - leaf0);
+            noff[lf + 1] = (int32_t)nidx.size();
+        }
+        D.near_off = up.copy(noff);
+        D.near_idx = up.copy(nidx);
+    }
+    for (int f = 0; f < 2; ++f) {
+        const h2s::Family &F = r.fam[f];
+        h2s::DevFamily<T> &G = D.fam[f];
+        G.lmin = F.lmin;
+        std::vector<int32_t> co(nbox + 1);
+        for (int32_t g = 0; g <= nbox; ++g) co[g] = (int32_t)F.coef_off[g];
+        G.coef_off = up.copy(co);
+        const size_t nc = (size_t)F.coef_off[nbox];
+        std::vector<T> pvx(nc ? nc : 1), pvy(nc ? nc : 1), pvz(nc ? nc : 1);
+        for (int32_t g = 0; g < nbox; ++g)
+            for (int64_t c = F.coef_off[g]; c < F.coef_off[g + 1]; ++c) {
+                const double *p = &r.pts[(size_t)F.piv_row[c] * d];
+                const double *cc = &ctr[(size_t)g * 3];
+                pvx[c] = (T)(local ? p[0] - cc[0] : p[0]);
+                pvy[c] = (T)(local ? p[1] - cc[1] : p[1]);
+                pvz[c] = d == 3 ? (T)(local ? p[2] - cc[2] : p[2]) : T(0);
+            }
+        G.pvx = up.copy(pvx);
+        G.pvy = up.copy(pvy);
+        G.pvz = up.copy(pvz);
+        std::vector<T> op(F.op.size());
+        for (size_t i = 0; i < op.size(); ++i) op[i] = (T)F.op[i];
+        t->operator_bytes += (int64_t)(sizeof(T) * op.size());
+        const T *opd = up.copy(op);
+        G.U = opd;
+        G.Tr = opd;
+        const int64_t *ooff = up.copy(F.op_off);
+        G.troff = ooff;
+        G.uoff = ooff ? ooff + leaf0 : nullptr;
+        const int w = f == 0 ? 1 : 2;
+        std::vector<int32_t> ilo(nbox + 1);
+        for (int32_t g = 0; g <= nbox; ++g) ilo[g] = (int32_t)r.list_off[w][g];
+        G.il_off = up.copy(ilo);
+        G.il_idx = up.copy(r.list_idx[w]);
+        std::vector<int32_t> targets;
+        for (int32_t g = 0; g < nbox; ++g)
+            if (F.rank[g] > 0) targets.push_back(g);
+        G.ntargets = (int32_t)targets.size();
+        G.targets = up.copy(targets);
+        G.v = up.template zeros<T>(nc ? nc : 1);
+        G.u = up.template zeros<T>(nc ? nc : 1);
+    }
+    if (r.variant == H2S_H2_PLUS_H) {
+        h2s::DevPairs<T> &P = D.pairs;
+        const size_t np = r.pairs.size();
+        P.npairs = (int32_t)np;
+        std::vector<int32_t> px(np), py(np), pr(np);
+        std::vector<int64_t> pu(np), pv(np), pw(np);
+        int64_t woff = 0;
+        for (size_t p = 0; p < np; ++p) {
+            px[p] = r.pairs[p].x;
+            py[p] = r.pairs[p].y;
+            pr[p] = r.pairs[p].rank;
+            pu[p] = r.pairs[p].off_u;
+            pv[p] = r.pairs[p].off_v;
+            pw[p] = woff;
+            woff += 2 * (int64_t)r.pairs[p].rank;
+        }
+        P.px = up.copy(px);
+        P.py = up.copy(py);
+        P.prank = up.copy(pr);
+        P.pu = up.copy(pu);
+        P.pv = up.copy(pv);
+        P.pw = up.copy(pw);
+        std::vector<T> data(r.pair_data.size());
+        for (size_t i = 0; i < data.size(); ++i) data[i] = (T)r.pair_data[i];
+        t->operator_bytes += (int64_t)(sizeof(T) * data.size());
+        P.data = up.copy(data);
+        P.w = up.template zeros<T>(woff ? woff : 1);
+        // receivers: X gets (pair, side 0), Y gets (pair, side 1)
+        std::vector<std::vector<int32_t>> rec(nbox);
+        for (size_t p = 0; p < np; ++p) {
+            rec[px[p]].push_back((int32_t)(2 * p));
+            rec[py[p]].push_back((int32_t)(2 * p + 1));
+        }
+        std::vector<int32_t> roff(nbox + 1, 0), ridx;
+        for (int32_t g = 0; g < nbox; ++g) {
+            ridx.insert(ridx.end(), rec[g].begin(), rec[g].end());
+            roff[g + 1] = (int32_t)ridx.size();
+        }
+        P.recv_off = up.copy(roff);
+        P.recv = up.copy(ridx);
+        // row chunks of the two products of every pair
+        const int32_t CH = 2048;
+        std::vector<int32_t> cp, cs, cb, cl, sco(2 * np + 1, 0);
+        std::vector<int64_t> cpo;
+        int64_t poff = 0;
+        for (size_t p = 0; p < np; ++p)
+            for (int side = 0; side < 2; ++side) {
+                const int32_t box = side == 0 ? py[p] : px[p];
+                const int32_t rows = r.box_end[box] - r.box_begin[box];
+                if (pr[p] > 0)
+                    for (int32_t s0 = 0; s0 < rows; s0 += CH) {
+                        cp.push_back((int32_t)p);
+                        cs.push_back(side);
+                        cb.push_back(s0);
+                        cl.push_back(std::min(CH, rows - s0));
+                        cpo.push_back(poff);
+                        poff += pr[p];
+                    }
+                sco[2 * p + side + 1] = (int32_t)cp.size();
+            }
+        P.nchunks = (int32_t)cp.size();
+        P.chunk_pair = up.copy(cp);
+        P.chunk_side = up.copy(cs);
+        P.chunk_begin = up.copy(cb);
+        P.chunk_len = up.copy(cl);
+        P.chunk_poff = up.copy(cpo);
+        P.side_chunk_off = up.copy(sco);
+        P.partial = up.template zeros<T>(poff ? poff : 1);
+    }
+    D.qt = up.template zeros<T>(n);
+    D.phi = nullptr;
+    if (up.st != H2S_OK) return up.st;
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(H2S_ERR_DEVICE, "stream synchronisation failed after upload");
+    return H2S_OK;
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+} // namespace
+
+extern "C" {
+
+const char *h2s_status_string(h2s_status s)
+{
+    switch (s) {
+    case H2S_OK: return "ok";
+    case H2S_ERR_INVALID_ARG: return "invalid argument";
+    case H2S_ERR_OUT_OF_MEMORY: return "out of memory";
+    case H2S_ERR_DEVICE: return "device error";
+    case H2S_ERR_NOT_CONVERGED: return "not converged";
+    case H2S_ERR_UNSUPPORTED: return "unsupported";
+    case H2S_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+h2s_status h2s_last_error(char *buf, size_t len)
+{
+    if (!buf || len == 0) return H2S_ERR_INVALID_ARG;
+    std::strncpy(buf, g_last_error.c_str(), len - 1);
+    buf[len - 1] = '\0';
+    return H2S_OK;
+}
+
+h2s_status h2s_set_allocator(h2s_alloc_fn alloc_fn, h2s_free_fn free_fn, void *ctx)
+{
+    if ((alloc_fn == nullptr) != (free_fn == nullptr))
+        return fail(H2S_ERR_INVALID_ARG, "allocator and free function must be given together");
+    g_alloc = alloc_fn;
+    g_free = free_fn;
+    g_alloc_ctx = ctx;
+    return H2S_OK;
+}
+
+h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kernel *k, const h2s_build_opts *o,
+                     void *stream, h2s_tree *out)
+{
+    if (!out) return fail(H2S_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!points) return fail(H2S_ERR_INVALID_ARG, "points is NULL");
+    if (n < 1 || n > INT32_MAX) return fail(H2S_ERR_INVALID_ARG, "n must be in [1, 2^31 - 1]");
+    if (d != 2 && d != 3) return fail(H2S_ERR_INVALID_ARG, "d must be 2 or 3");
+    if (!k || !o) return fail(H2S_ERR_INVALID_ARG, "kernel or options is NULL");
+    if (k->kind < H2S_K_LOG_R || k->kind > H2S_K_EXP_R) return fail(H2S_ERR_INVALID_ARG, "unknown kernel kind");
+    if (k->kind == H2S_K_GAUSSIAN && !(is_finite(k->param) && k->param > 0))
+        return fail(H2S_ERR_INVALID_ARG, "Gaussian length scale must be finite and > 0");
+    if (!is_finite(k->diag) || !is_finite(k->shift)) return fail(H2S_ERR_INVALID_ARG, "diag and shift must be finite");
+    if (o->leaf_size < 1) return fail(H2S_ERR_INVALID_ARG, "leaf_size must be >= 1");
+    if (!(is_finite(o->eps_far) && o->eps_far >= 0 && is_finite(o->eps_ver) && o->eps_ver >= 0))
+        return fail(H2S_ERR_INVALID_ARG, "tolerances must be finite and >= 0");
+    if (o->variant != H2S_H2STAR && o->variant != H2S_H2_PLUS_H) return fail(H2S_ERR_INVALID_ARG, "unknown variant");
+    if (o->prec != H2S_FP64 && o->prec != H2S_FP32) return fail(H2S_ERR_INVALID_ARG, "unknown precision");
+    for (int64_t i = 0; i < n * d; ++i)
+        if (!is_finite(points[i])) return fail(H2S_ERR_INVALID_ARG, "points must be finite");
+
+    int dev = 0;
+    if (!o->host_only) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+            return fail(H2S_ERR_DEVICE, "no HIP device available (use host_only for a host-side build)");
+        if (hipGetDevice(&dev) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipGetDevice failed");
+    }
+
+    h2s_tree t = new (std::nothrow) h2s_tree_s();
+    if (!t) return fail(H2S_ERR_OUT_OF_MEMORY, "host allocation failed");
+    t->opts = *o;
+    t->ker = *k;
+    t->host_only = o->host_only != 0;
+    t->device = dev;
+    if (g_alloc) {
+        t->afn = g_alloc;
+        t->ffn = g_free;
+        t->actx = g_alloc_ctx;
+    }
+    std::string err;
+    const h2s::KernelSpec ks{k->kind, k->param, k->diag, k->shift};
+    h2s_status st = h2s::build_host(points, n, d, ks, o->leaf_size, o->eps_far, o->eps_ver, o->variant,
+                                    o->host_threads, t->rep, err);
+    if (st != H2S_OK) {
+        delete t;
+        return fail(st, err);
+    }
+    t->lev_off = t->rep.lev_off;
+    if (!t->host_only) {
+        st = o->prec == H2S_FP64 ? upload<double>(t, (hipStream_t)stream, t->t64)
+                                 : upload<float>(t, (hipStream_t)stream, t->t32);
+        if (st != H2S_OK) {
+            const std::string keep = g_last_error;
+            delete t;
+            g_last_error = keep;
+            return st;
+        }
+    }
+    *out = t;
+    return H2S_OK;
+}
+
+h2s_status h2s_apply_phases(h2s_tree t, uint32_t mask, const double *x, double *y, int32_t nrhs, int64_t ldx,
+                            int64_t ldy, void *stream)
+{
+    if (!t) return fail(H2S_ERR_INVALID_ARG, "tree is NULL");
+    if (t->host_only) return fail(H2S_ERR_UNSUPPORTED, "handle was built with host_only");
+    if (mask == 0 || (mask & ~(uint32_t)H2S_PHASE_ALL)) return fail(H2S_ERR_INVALID_ARG, "bad phase mask");
+    const int64_t n = t->rep.n;
+    if (!x || !y) return fail(H2S_ERR_INVALID_ARG, "x or y is NULL");
+    if (nrhs < 1) return fail(H2S_ERR_INVALID_ARG, "nrhs must be >= 1");
+    if (ldx < n || ldy < n) return fail(H2S_ERR_INVALID_ARG, "leading dimensions must be >= n");
+    const char *xb = (const char *)x, *xe = (const char *)(x + ldx * (nrhs - 1) + n);
+    const char *yb = (const char *)y, *ye = (const char *)(y + ldy * (nrhs - 1) + n);
+    if (xb < ye && yb < xe) return fail(H2S_ERR_INVALID_ARG, "x and y overlap");
+    if (hipSetDevice(t->device) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipSetDevice failed");
+    h2s::ProfileHook hook{t, record_mark};
+    const h2s::ProfileHook *prof = t->profiling ? &hook : nullptr;
+    t->prof_stream = (hipStream_t)stream;
+    for (int32_t c = 0; c < nrhs; ++c) {
+        const int rc = t->opts.prec == H2S_FP64
+                           ? h2s::launch_mvp<double>(t->t64, t->lev_off.data(), x + c * ldx, y + c * ldy, mask, stream, prof)
+                           : h2s::launch_mvp<float>(t->t32, t->lev_off.data(), x + c * ldx, y + c * ldy, mask, stream, prof);
+        if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
+    }
+    return H2S_OK;
+}
+
+h2s_status h2s_apply(h2s_tree t, const double *x, double *y, int32_t nrhs, int64_t ldx, int64_t ldy, void *stream)
+{
+    return h2s_apply_phases(t, H2S_PHASE_ALL, x, y, nrhs, ldx, ldy, stream);
+}
+
+h2s_status h2s_free(h2s_tree t)
+{
+    if (!t) return H2S_OK;
+    if (!t->host_only) (void)hipSetDevice(t->device);
+    delete t;
+    return H2S_OK;
+}
+
+h2s_status h2s_get_stats(h2s_tree t, h2s_stats *s)
+{
+    if (!t || !s) return fail(H2S_ERR_INVALID_ARG, "tree or stats is NULL");
+    const h2s::HostRep &r = t->rep;
+    std::memset(s, 0, sizeof(*s));
+    s->d = r.d;
+    s->kappa = r.kappa;
+    s->variant = r.variant;
+    s->prec = t->opts.prec;
+    s->n = r.n;
+    s->boxes = r.nbox();
+    s->near_pairs = (int64_t)r.list_idx[0].size();
+    s->far_pairs = (int64_t)r.list_idx[1].size();
+    s->ver_pairs = (int64_t)r.list_idx[2].size();
+    for (int32_t g = r.leaf0(); g < r.nbox(); ++g)
+        for (int64_t e = r.list_off[0][g]; e < r.list_off[0][g + 1]; ++e) {
+            const int32_t y = r.list_idx[0][e];
+            s->p2p_evals += (int64_t)(r.box_end[g] - r.box_begin[g]) * (r.box_end[y] - r.box_begin[y]);
+        }
+    for (int f = 0; f < 2; ++f) {
+        const h2s::Family &F = r.fam[f];
+        std::vector<int64_t> cnt(32, 0), sum(32, 0);
+        for (int32_t g = 0; g < r.nbox(); ++g) {
+            const int32_t rk = F.rank[g];
+            if (rk == 0) continue;
+            const int l = r.level_of(g);
+            s->rank_sum[f] += rk;
+            if (rk > s->rank_max[f]) s->rank_max[f] = rk;
+            if (l < 32) {
+                if (rk > s->rank_max_level[f][l]) s->rank_max_level[f][l] = rk;
+                cnt[l] += 1;
+                sum[l] += rk;
+            }
+            const int w = f == 0 ? 1 : 2;
+            for (int64_t e = r.list_off[w][g]; e < r.list_off[w][g + 1]; ++e)
+                s->m2l_evals += (int64_t)rk * F.rank[r.list_idx[w][e]];
+        }
+        for (int l = 0; l < 32; ++l) s->rank_avg_level[f][l] = cnt[l] ? (double)sum[l] / cnt[l] : 0.0;
+        for (int32_t g = 0; g < r.nbox(); ++g) {
+            const int64_t e = (int64_t)F.op_rows[g] * F.rank[g];
+            if (g >= r.leaf0()) s->leaf_basis_entries += e;
+            else s->transfer_entries += e;
+        }
+    }
+    for (const h2s::LowRankPair &P : r.pairs)
+        s->pair_entries += (int64_t)P.rank *
+                           ((r.box_end[P.x] - r.box_begin[P.x]) + (r.box_end[P.y] - r.box_begin[P.y]));
+    s->operator_bytes = t->operator_bytes;
+    s->device_bytes = (int64_t)t->device_bytes;
+    s->build_seconds = r.build_seconds;
+    return H2S_OK;
+}
+
+h2s_status h2s_set_profiling(h2s_tree t, int32_t enable)
+{
+    if (!t) return fail(H2S_ERR_INVALID_ARG, "tree is NULL");
+    if (t->host_only) return fail(H2S_ERR_UNSUPPORTED, "handle was built with host_only");
+    t->profiling = enable != 0;
+    return H2S_OK;
+}
+
+h2s_status h2s_get_profile(h2s_tree t, double *ms_total, int64_t *launches)
+{
+    if (!t) return fail(H2S_ERR_INVALID_ARG, "tree is NULL");
+    double ms[H2S_NUM_PROF] = {0};
+    int64_t cnt[H2S_NUM_PROF] = {0};
+    for (auto &m : t->marks) {
+        if (!m.b) continue;
+        if (hipEventSynchronize(m.b) != hipSuccess) {
+            t->clear_marks();
+            return fail(H2S_ERR_DEVICE, "event synchronisation failed");
+        }
+        float e = 0.f;
+        if (hipEventElapsedTime(&e, m.a, m.b) == hipSuccess) {
+            ms[m.cls] += e;
+            cnt[m.cls] += 1;
+        }
+    }
+    t->clear_marks();
+    for (int i = 0; i < H2S_NUM_PROF; ++i) {
+        if (ms_total) ms_total[i] = ms[i];
+        if (launches) launches[i] = cnt[i];
+    }
+    return H2S_OK;
+}
+
+h2s_status h2s_export(h2s_tree t, const char *path)
+{
+    if (!t || !path) return fail(H2S_ERR_INVALID_ARG, "tree or path is NULL");
+    std::string err;
+    const h2s_status st = h2s::export_host(t->rep, path, err);
+    if (st != H2S_OK) return fail(st, err);
+    return H2S_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,234 @@
+"""Python binding of the C ABI in include/h2s.h (argument marshalling only).
+
+Every step of the product runs in libh2s.so (host build in C++, MVP in HIP
+kernels).  PyTorch provides device memory and streams.  There is no fallback:
+if the library is missing, loading raises.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libh2s.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "h2s.h")
+
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED, ERR_UNSUPPORTED, ERR_INTERNAL = range(7)
+LOG_R, INV_R, GAUSSIAN, EXP_R = 0, 1, 2, 3
+H2STAR, H2_PLUS_H = 0, 1
+FP64, FP32 = 0, 1
+PHASE_NEAR, PHASE_FAR, PHASE_VER, PHASE_ALL = 1, 2, 4, 7
+PROF_NAMES = ("leaf_up", "m2m", "m2l", "l2l", "pair_part", "pair_sum", "leaf_down")
+
+
+class Kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("param", ctypes.c_double), ("diag", ctypes.c_double),
+                ("shift", ctypes.c_double)]
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("leaf_size", ctypes.c_int32), ("eps_far", ctypes.c_double), ("eps_ver", ctypes.c_double),
+                ("variant", ctypes.c_int), ("prec", ctypes.c_int), ("host_threads", ctypes.c_int32),
+                ("host_only", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("kappa", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("n", ctypes.c_int64), ("boxes", ctypes.c_int64),
+                ("near_pairs", ctypes.c_int64), ("far_pairs", ctypes.c_int64), ("ver_pairs", ctypes.c_int64),
+                ("rank_sum", ctypes.c_int64 * 2), ("rank_max", ctypes.c_int32 * 2),
+                ("p2p_evals", ctypes.c_int64), ("m2l_evals", ctypes.c_int64),
+                ("leaf_basis_entries", ctypes.c_int64), ("transfer_entries", ctypes.c_int64),
+                ("pair_entries", ctypes.c_int64),
+                ("operator_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("build_seconds", ctypes.c_double),
+                ("rank_max_level", (ctypes.c_int32 * 32) * 2), ("rank_avg_level", (ctypes.c_double * 32) * 2)]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            if name in ("rank_max_level", "rank_avg_level"):
+                v = [list(row)[: self.kappa + 1] for row in v]
+            elif hasattr(v, "__len__"):
+                v = list(v)
+            out[name] = v
+        return out
+
+
+_lib = None
+
+
+class H2SError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_string(status)}: {msg}")
+        self.status = status
+
+
+def load():
+    """Load libh2s.so (built by paper_2309_14085_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    f64p = ctypes.POINTER(ctypes.c_double)
+    lib.h2s_build.argtypes = [f64p, i64, i32, ctypes.POINTER(Kernel), ctypes.POINTER(BuildOpts), vp,
+                              ctypes.POINTER(vp)]
+    lib.h2s_apply.argtypes = [vp, vp, vp, i32, i64, i64, vp]
+    lib.h2s_apply_phases.argtypes = [vp, u32, vp, vp, i32, i64, i64, vp]
+    lib.h2s_free.argtypes = [vp]
+    lib.h2s_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.h2s_export.argtypes = [vp, ctypes.c_char_p]
+    lib.h2s_set_allocator.argtypes = [vp, vp, vp]
+    lib.h2s_set_profiling.argtypes = [vp, i32]
+    lib.h2s_get_profile.argtypes = [vp, f64p, ctypes.POINTER(i64)]
+    lib.h2s_status_string.restype = ctypes.c_char_p
+    lib.h2s_status_string.argtypes = [ctypes.c_int]
+    lib.h2s_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    for name in ("h2s_build", "h2s_apply", "h2s_apply_phases", "h2s_free", "h2s_get_stats", "h2s_export",
+                 "h2s_set_allocator", "h2s_last_error", "h2s_set_profiling", "h2s_get_profile"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def header_functions():
+    """Names of the functions include/h2s.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(h2s_\w+)\s*\(", text, re.M)))
+
+
+def status_string(s):
+    return load().h2s_status_string(int(s)).decode()
+
+
+def last_error():
+    buf = ctypes.create_string_buffer(512)
+    load().h2s_last_error(buf, 512)
+    return buf.value.decode()
+
+
+def check(status):
+    if status != OK:
+        raise H2SError(status, last_error())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return ctypes.c_void_p(0)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class Tree:
+    """Handle returned by h2s_build."""
+
+    def __init__(self, handle, n, d):
+        self._h = handle
+        self.n, self.d = n, d
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.h2s_free(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def apply(self, x, y=None, mask=PHASE_ALL, stream=None):
+        """y = K~ x for a CUDA float64 tensor x of shape (n,) or column-major (n, m)."""
+        import torch
+        if x.dtype != torch.float64 or not x.is_cuda:
+            raise TypeError("x must be a CUDA float64 tensor")
+        if x.dim() == 1:
+            xx = x.contiguous()
+            m, ldx = 1, self.n
+        else:
+            if x.stride(0) != 1:
+                x = x.t().contiguous().t()
+            xx, m, ldx = x, x.shape[1], x.stride(1) if x.shape[1] > 1 else self.n
+        if y is None:
+            y = torch.empty_strided(tuple(x.shape), (1,) if x.dim() == 1 else (1, self.n), dtype=torch.float64,
+                                    device=x.device)
+        ldy = self.n if y.dim() == 1 or y.shape[1] == 1 else y.stride(1)
+        check(load().h2s_apply_phases(self._h, mask, ctypes.c_void_p(xx.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                      m, ldx, ldy, _stream_ptr(stream)))
+        return y
+
+    def apply_ptr(self, x_ptr, y_ptr, nrhs=1, ldx=None, ldy=None, mask=PHASE_ALL, stream=None):
+        """Raw-pointer form of h2s_apply_phases (pointers as ints)."""
+        return load().h2s_apply_phases(self._h, mask, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr), nrhs,
+                                       ldx or self.n, ldy or self.n, _stream_ptr(stream))
+
+    def set_profiling(self, on=True):
+        check(load().h2s_set_profiling(self._h, int(bool(on))))
+
+    def profile(self):
+        """{kernel class: (total ms, launches)} since the last call; waits for the recorded events."""
+        ms = (ctypes.c_double * len(PROF_NAMES))()
+        cnt = (ctypes.c_int64 * len(PROF_NAMES))()
+        check(load().h2s_get_profile(self._h, ms, cnt))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(PROF_NAMES)}
+
+    def stats(self):
+        s = Stats()
+        check(load().h2s_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def export(self, path):
+        check(load().h2s_export(self._h, str(path).encode()))
+        return read_export(path)
+
+
+def build(points, kind=LOG_R, leaf_size=64, eps=1e-8, eps_ver=None, variant=H2STAR, prec=FP64, param=0.0,
+          diag=None, shift=0.0, host_threads=0, host_only=False, stream=None):
+    """h2s_build on host points (n, d) float64."""
+    lib = load()
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n, d = pts.shape
+    if diag is None:
+        diag = 0.0 if kind in (LOG_R, INV_R) else 1.0
+    k = Kernel(kind, param, diag, shift)
+    o = BuildOpts(leaf_size, eps, eps if eps_ver is None else eps_ver, variant, prec, host_threads, int(host_only))
+    h = ctypes.c_void_p()
+    check(lib.h2s_build(pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n, d, ctypes.byref(k), ctypes.byref(o),
+                        _stream_ptr(stream) if not host_only else ctypes.c_void_p(0), ctypes.byref(h)))
+    return Tree(h, n, d)
+
+
+_DT = {1: np.int32, 2: np.int64, 3: np.float64}
+
+
+def read_export(path):
+    """Parse the named-array container written by h2s_export."""
+    with open(path, "rb") as f:
+        buf = f.read()
+    if buf[:4] != b"H2SX":
+        raise ValueError("not an h2s export file")
+    count = int(np.frombuffer(buf, np.uint32, 1, 8)[0])
+    pos, out = 12, {}
+    for _ in range(count):
+        name = buf[pos:pos + 32].split(b"\0", 1)[0].decode()
+        dtype, ndim = np.frombuffer(buf, np.uint32, 2, pos + 32)
+        dims = np.frombuffer(buf, np.int64, int(ndim), pos + 40)
+        pos += 40 + 8 * int(ndim)
+        cnt = int(np.prod(dims)) if ndim else 1
+        dt = np.dtype(_DT[int(dtype)])
+        out[name] = np.frombuffer(buf, dt, cnt, pos).reshape(tuple(int(x) for x in dims)).copy()
+        pos += cnt * dt.itemsize
+    return out

@@ -1,0 +1,135 @@
+"""The C ABI on the CPU: library loads, exports every declared symbol, validates
+arguments before allocating, and its host build equals the oracle's bit for bit.
+
+No compute call reaches the GPU here (host_only handles only).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2309_14085_amd import h2s
+    h2s.load()
+    return h2s
+
+
+def test_exports_every_declared_symbol(lib):
+    names = lib.header_functions()
+    assert {"h2s_build", "h2s_apply", "h2s_apply_phases", "h2s_free", "h2s_get_stats", "h2s_export",
+            "h2s_set_allocator", "h2s_status_string", "h2s_last_error"} <= set(names)
+    so = lib.load()
+    for n in names:
+        assert hasattr(so, n), n
+
+
+def _raw_build(lib, pts, n, d, k, o):
+    h = ctypes.c_void_p(12345)
+    p = pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if pts is not None else None
+    st = lib.load().h2s_build(p, n, d, ctypes.byref(k) if k else None, ctypes.byref(o) if o else None, None,
+                              ctypes.byref(h))
+    return st, h.value
+
+
+def test_validation_before_allocation(lib):
+    pts = np.random.default_rng(0).uniform(-1, 1, (100, 2))
+    k = lib.Kernel(lib.LOG_R, 0.0, 0.0, 0.0)
+    o = lib.BuildOpts(64, 1e-8, 1e-8, 0, 0, 0, 1)
+    assert _raw_build(lib, pts, 100, 2, k, o)[0] == lib.OK
+    bad = [
+        (None, 100, 2, k, o),
+        (pts, 0, 2, k, o),
+        (pts, 100, 4, k, o),
+        (pts, 100, 2, None, o),
+        (pts, 100, 2, lib.Kernel(9, 0, 0, 0), o),
+        (pts, 100, 2, lib.Kernel(lib.GAUSSIAN, 0.0, 1.0, 0.0), o),
+        (pts, 100, 2, k, lib.BuildOpts(0, 1e-8, 1e-8, 0, 0, 0, 1)),
+        (pts, 100, 2, k, lib.BuildOpts(64, -1.0, 1e-8, 0, 0, 0, 1)),
+        (pts, 100, 2, k, lib.BuildOpts(64, float("nan"), 1e-8, 0, 0, 0, 1)),
+        (pts, 100, 2, k, lib.BuildOpts(64, 1e-8, 1e-8, 5, 0, 0, 1)),
+        (pts, 100, 2, k, lib.BuildOpts(64, 1e-8, 1e-8, 0, 7, 0, 1)),
+    ]
+    for args in bad:
+        st, h = _raw_build(lib, *args)
+        assert st == lib.ERR_INVALID_ARG and h is None, args
+    nanpts = pts.copy()
+    nanpts[5, 1] = np.inf
+    st, h = _raw_build(lib, nanpts, 100, 2, k, o)
+    assert st == lib.ERR_INVALID_ARG and h is None
+    assert "finite" in lib.last_error()
+
+
+def test_host_only_handle(lib, inputs):
+    pts = inputs.uniform_points(4096, 2, 1)
+    T = lib.build(pts, host_only=True)
+    s = T.stats()
+    assert s["kappa"] == 3 and s["n"] == 4096 and s["near_pairs"] == 288 and s["device_bytes"] == 0
+    assert s["far_pairs"] == 96 + 576 and s["ver_pairs"] == 4 + 32 + 160
+    st = T.apply_ptr(1 << 20, 2 << 20)
+    assert st == lib.ERR_UNSUPPORTED
+    assert lib.load().h2s_free(None) == lib.OK
+    assert lib.status_string(lib.ERR_DEVICE) == "device error"
+
+
+CASES = [
+    (2, 4096, 0, 64, 1e-8, 0, 0.0, 1000),
+    (2, 4096, 0, 64, 1e-8, 1, 0.0, 1000),
+    (3, 5000, 1, 64, 1e-6, 0, 0.0, 7),
+    (2, 3000, 2, 32, 1e-10, 0, 0.3, 8),
+    (3, 3000, 3, 20, 1e-12, 1, 0.0, 9),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_host_build_equals_oracle_bitwise(lib, orc, inputs, case, tmp_path):
+    d, n, kind, nmax, eps, variant, param, seed = case
+    pts = inputs.uniform_points(n, d, seed)
+    O = orc.Tree(pts, kind, nmax, eps, variant=variant, param=param)
+    L = lib.build(pts, kind=kind, leaf_size=nmax, eps=eps, variant=variant, param=param, host_only=True)
+    ex = L.export(tmp_path / "rep.bin")
+    assert np.array_equal(ex["perm"], O.perm())
+    lev = ex["lev_off"]
+    K = O.kappa
+    assert len(lev) == K + 2
+    for l in range(K + 1):
+        b = O.boxes(l)
+        g0, g1 = lev[l], lev[l + 1]
+        assert np.array_equal(ex["box_begin"][g0:g1], b["begin"])
+        for which, nm in ((0, "near"), (1, "far"), (2, "ver")):
+            if (which == 0 and l != K) or (which and l == 0):
+                continue
+            off, idx = O.lists(which, l)
+            eo, ei = ex[nm + "_off"], ex[nm + "_idx"]
+            for x in range(g1 - g0):
+                assert np.array_equal(ei[eo[g0 + x]:eo[g0 + x + 1]] - g0, idx[off[x]:off[x + 1]])
+        for f, fn in ((0, "far"), (1, "ver")):
+            if variant == 1 and f == 1:
+                continue
+            rk, co = ex[f"fam_{fn}_rank"], ex[f"fam_{fn}_coef_off"]
+            oo, orow = ex[f"fam_{fn}_op_off"], ex[f"fam_{fn}_op_rows"]
+            for x in range(g1 - g0):
+                g = g0 + x
+                r = max(O.rank(f, l, x), 0)
+                assert rk[g] == r
+                if r == 0:
+                    continue
+                pr, pc = O.pivots(f, l, x)
+                assert np.array_equal(ex[f"fam_{fn}_piv_row"][co[g]:co[g + 1]], pr)
+                assert np.array_equal(ex[f"fam_{fn}_piv_col"][co[g]:co[g + 1]], pc)
+                mine = ex[f"fam_{fn}_op"][oo[g]:oo[g + 1]]
+                mine = mine.reshape(r, orow[g]).T if l == K else mine.reshape(orow[g], r)
+                assert np.array_equal(mine, O.operator(f, l, x))
+    if variant == 1:
+        pairs = ex["pairs"].reshape(-1, 6)
+        data = ex["pair_data"]
+        for l in range(1, K + 1):
+            op = O.hph_pairs(l)
+            mine = pairs[pairs[:, 0] == l]
+            assert len(mine) == len(op)
+            for (lv, gx, gy, r, ou, ov), (x, y, ub, vb) in zip(mine, op):
+                assert (gx - lev[l], gy - lev[l], r) == (x, y, ub.shape[1])
+                nx, ny = ub.shape[0], vb.shape[0]
+                assert np.array_equal(data[ou:ou + r * nx].reshape(r, nx).T, ub)
+                assert np.array_equal(data[ov:ov + r * ny].reshape(r, ny).T, vb)

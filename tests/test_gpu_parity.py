@@ -1,0 +1,141 @@
+"""GPU parity: the HIP MVP (through the C ABI) against the FP64 oracle, element by element.
+
+Bars: FP64 <= 1e-12 relative 2-norm per phase and in total; FP32 <= 1e-5
+against the FP64 oracle product.  Inputs are the seeded synthetic workloads
+(uniform points in [-1,1]^d, N(0,1) right-hand sides).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2309_14085_amd import h2s
+    h2s.load()
+    return h2s
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def gpu_apply(T, q, mask=7):
+    x = torch.from_numpy(np.asfortranarray(q)).to(_dev())
+    y = T.apply(x, mask=mask)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+CASES = [
+    # name, d, n, kind, nmax, eps, param, shift, seed
+    ("cfg1_2d_log_4096", 2, 4096, 0, 64, 1e-8, 0.0, 0.0, 1000),
+    ("2d_log_ragged_5000", 2, 5000, 0, 40, 1e-10, 0.0, 0.0, 3),
+    ("3d_invr_ragged_5000", 3, 5000, 1, 64, 1e-6, 0.0, 0.0, 4),
+    ("2d_gauss_shift_3000", 2, 3000, 2, 32, 1e-10, 0.3, 1e-2, 5),
+    ("3d_expr_3000", 3, 3000, 3, 20, 1e-12, 0.0, 0.0, 6),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fp64_matches_oracle_per_phase(lib, orc, inputs, case, variant):
+    name, d, n, kind, nmax, eps, param, shift, seed = case
+    print(f"case {name} variant {variant}", flush=True)
+    pts = inputs.uniform_points(n, d, seed)
+    q = inputs.normal_rhs(n, 1, seed + 1)[:, 0]
+    O = orc.Tree(pts, kind, nmax, eps, variant=variant, param=param, shift=shift)
+    near, far, ver = O.apply_parts(q)
+    T = lib.build(pts, kind=kind, leaf_size=nmax, eps=eps, variant=variant, param=param, shift=shift)
+    total = near + far + ver
+    assert rel(gpu_apply(T, q, lib.PHASE_NEAR), near) <= 1e-12
+    if np.any(far):
+        assert rel(gpu_apply(T, q, lib.PHASE_FAR), far) <= 1e-12
+    assert rel(gpu_apply(T, q, lib.PHASE_VER), ver) <= 1e-12
+    assert rel(gpu_apply(T, q), total) <= 1e-12
+
+
+@pytest.mark.parametrize("n,nmax", [(1, 64), (50, 64), (200, 64), (257, 64)])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_degenerate_sizes(lib, orc, inputs, n, nmax, variant):
+    print(f"degenerate n={n} variant={variant}", flush=True)
+    pts = inputs.uniform_points(n, 2, 77)
+    q = inputs.normal_rhs(n, 1, 78)[:, 0]
+    O = orc.Tree(pts, 0, nmax, 1e-10, variant=variant)
+    T = lib.build(pts, kind=0, leaf_size=nmax, eps=1e-10, variant=variant)
+    want = O.apply(q)
+    got = gpu_apply(T, q)
+    if n == 1:
+        assert got[0] == want[0] == 0.0
+    else:
+        assert rel(got, want) <= 1e-12
+
+
+def test_multi_rhs_with_leading_dimension(lib, orc, inputs):
+    n, m, ld = 3000, 3, 3017
+    pts = inputs.uniform_points(n, 2, 90)
+    Q = inputs.normal_rhs(n, m, 91)
+    O = orc.Tree(pts, 0, 64, 1e-8)
+    T = lib.build(pts, kind=0, leaf_size=64, eps=1e-8)
+    dev = _dev()
+    xb = torch.zeros(m * ld, dtype=torch.float64, device=dev)
+    yb = torch.full((m * ld,), 7.0, dtype=torch.float64, device=dev)
+    for c in range(m):
+        xb[c * ld:c * ld + n] = torch.from_numpy(Q[:, c].copy()).to(dev)
+    assert T.apply_ptr(xb.data_ptr(), yb.data_ptr(), nrhs=m, ldx=ld, ldy=ld) == lib.OK
+    torch.cuda.synchronize()
+    y = yb.cpu().numpy()
+    for c in range(m):
+        assert rel(y[c * ld:c * ld + n], O.apply(Q[:, c])) <= 1e-12
+        assert np.all(y[c * ld + n:(c + 1) * ld] == 7.0)  # padding untouched
+
+
+@pytest.mark.parametrize("d,kind,eps", [(2, 0, 1e-8), (3, 1, 1e-6), (2, 2, 1e-8)])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fp32_within_1e5_of_fp64_oracle(lib, orc, inputs, d, kind, eps, variant):
+    n = 8192 if d == 2 else 6000
+    param = 0.1 if kind == 2 else 0.0
+    shift = 1e-2 if kind == 2 else 0.0
+    pts = inputs.uniform_points(n, d, 500 + d)
+    q = inputs.normal_rhs(n, 1, 600 + d)[:, 0]
+    O = orc.Tree(pts, kind, 64, eps, variant=variant, param=param, shift=shift)
+    T = lib.build(pts, kind=kind, leaf_size=64, eps=eps, variant=variant, prec=lib.FP32, param=param, shift=shift)
+    err = rel(gpu_apply(T, q), O.apply(q))
+    print(f"fp32 d={d} kind={kind} variant={variant}: rel err vs fp64 oracle {err:.2e}", flush=True)
+    assert err <= 1e-5
+
+
+def test_fp64_65536_matches_oracle(lib, orc, inputs):
+    n = 65536
+    pts = inputs.uniform_points(n, 2, 1001)
+    q = inputs.normal_rhs(n, 1, 2001)[:, 0]
+    O = orc.Tree(pts, 0, 64, 1e-8)
+    T = lib.build(pts, kind=0, leaf_size=64, eps=1e-8)
+    assert rel(gpu_apply(T, q), O.apply(q)) <= 1e-12
+
+
+@pytest.mark.timeout(600)
+def test_full_size_2d_config_matches_oracle(lib, orc, inputs):
+    """N = 2^20, 2D log r, n_max 64, eps 1e-8: the benchmarked launch configuration,
+    FP64 against the full oracle product and FP32 against the same."""
+    w = inputs.workload(1)
+    pts, q = w.points(), w.rhs()[:, 0]
+    print("building oracle at N=2^20", flush=True)
+    O = orc.Tree(pts, w.kind, w.nmax, w.eps)
+    want = O.apply(q)
+    del O
+    print("building library at N=2^20", flush=True)
+    T = lib.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps)
+    assert rel(gpu_apply(T, q), want) <= 1e-12
+    T32 = lib.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps, prec=lib.FP32)
+    assert rel(gpu_apply(T32, q), want) <= 1e-5

@@ -62,11 +62,16 @@ typedef struct {
 
 typedef enum { H2S_H2STAR = 0, H2S_H2_PLUS_H = 1 } h2s_variant;
 
-/* Internal arithmetic of apply.  FP64: everything in double.  FP32: operators,
- * coefficients, kernel evaluations and accumulation in float (coordinates are
- * taken relative to box centres so close pairs keep their accuracy); inputs
- * and outputs stay double at the boundary. */
-typedef enum { H2S_FP64 = 0, H2S_FP32 = 1 } h2s_precision;
+/* Internal arithmetic of apply; x and y stay double at the boundary.
+ *   FP64      everything in double.
+ *   FP32      near field (kernel evaluations with box-centred coordinates)
+ *             and leaf bases in float; M2L, transfers, multipole and local
+ *             coefficients and every accumulation in double.
+ *   FP32_M2L  as FP32, and the far-field M2L evaluated in float as well (for
+ *             log r as a per-pair constant in double plus a float remainder).
+ *             The interpolative operators amplify float M2L values, so its
+ *             error against FP64 is larger; it is reported, not bounded. */
+typedef enum { H2S_FP64 = 0, H2S_FP32 = 1, H2S_FP32_M2L = 2 } h2s_precision;
 
 typedef struct {
     int32_t leaf_size;    /* n_max >= 1: leaf level kappa = ceil(log_{2^d}(n / n_max)) (Sec. 3.1) */

@@ -7,6 +7,7 @@
 // right-hand side.  Nothing here computes any part of the product.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -49,8 +50,9 @@ struct h2s_tree_s {
     size_t device_bytes = 0;
     int64_t operator_bytes = 0;
     std::vector<int32_t> lev_off;
-    h2s::DevTree<double> t64{};
-    h2s::DevTree<float> t32{};
+    h2s::DevTree<h2s::P64> t64{};
+    h2s::DevTree<h2s::P32> t32{};
+    h2s::DevTree<h2s::P32M> t32m{};
     // profiling: (class, start, stop) events recorded by apply while enabled
     bool profiling = false;
     hipStream_t prof_stream = nullptr;
@@ -138,16 +140,93 @@ void box_centre(const h2s::HostRep &r, int32_t g, double *c)
     for (int k = 0; k < 3; ++k) c[k] = k < r.d ? r.origin[k] + (r.box_coord[(size_t)g * 3 + k] + 0.5) * w : 0.0;
 }
 
-template <typename T> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<T> &D)
+// Pack one family for the device: pivot coordinates (box-centred when
+// `local`), both copies of the leaf bases and transfers, lists, work list.
+template <typename CT, typename BT>
+void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector<double> &ctr, bool local,
+                   h2s::DevFamily<CT, BT> &G, int64_t &op_bytes)
 {
+    const h2s::Family &F = r.fam[f];
+    const int d = r.d, kappa = r.kappa;
+    const int32_t nbox = r.nbox(), leaf0 = r.leaf0();
+    G.lmin = F.lmin;
+    std::vector<int32_t> co(nbox + 1);
+    for (int32_t g = 0; g <= nbox; ++g) co[g] = (int32_t)F.coef_off[g];
+    G.coef_off = up.copy(co);
+    const size_t nc = (size_t)F.coef_off[nbox];
+    std::vector<CT> pvx(nc ? nc : 1), pvy(nc ? nc : 1), pvz(nc ? nc : 1);
+    for (int32_t g = 0; g < nbox; ++g)
+        for (int64_t c = F.coef_off[g]; c < F.coef_off[g + 1]; ++c) {
+            const double *p = &r.pts[(size_t)F.piv_row[c] * d];
+            const double *cc = &ctr[(size_t)g * 3];
+            pvx[c] = (CT)(local ? p[0] - cc[0] : p[0]);
+            pvy[c] = (CT)(local ? p[1] - cc[1] : p[1]);
+            pvz[c] = d == 3 ? (CT)(local ? p[2] - cc[2] : p[2]) : CT(0);
+        }
+    G.pvx = up.copy(pvx);
+    G.pvy = up.copy(pvy);
+    G.pvz = up.copy(pvz);
+    // leaf bases: the host keeps U_X column-major (n_X x r); add the row-major copy
+    std::vector<int64_t> uoff(r.nleaf() + 1, 0);
+    for (int32_t lf = 0; lf < r.nleaf(); ++lf) uoff[lf + 1] = uoff[lf] + F.op_off[leaf0 + lf + 1] - F.op_off[leaf0 + lf];
+    std::vector<BT> ucm(uoff.back() ? uoff.back() : 1), urm(uoff.back() ? uoff.back() : 1);
+    for (int32_t lf = 0; lf < r.nleaf(); ++lf) {
+        const int32_t g = leaf0 + lf;
+        const int64_t rk = F.rank[g], nx = F.op_rows[g];
+        const double *src = F.op.data() + F.op_off[g];
+        for (int64_t k = 0; k < rk; ++k)
+            for (int64_t i = 0; i < nx; ++i) {
+                ucm[uoff[lf] + k * nx + i] = (BT)src[k * nx + i];
+                urm[uoff[lf] + i * rk + k] = (BT)src[k * nx + i];
+            }
+    }
+    G.U_cm = up.copy(ucm);
+    G.U_rm = up.copy(urm);
+    G.uoff = up.copy(uoff);
+    op_bytes += (int64_t)(2 * sizeof(BT) * uoff.back());
+    // transfers: the host keeps them row-major ((sum r_c) x r); add the column-major copy
+    std::vector<int64_t> toff(nbox + 1, 0);
+    for (int32_t g = 0; g < nbox; ++g) toff[g + 1] = toff[g] + (g < leaf0 ? F.op_off[g + 1] - F.op_off[g] : 0);
+    std::vector<double> trm(toff.back() ? toff.back() : 1), tcm(toff.back() ? toff.back() : 1);
+    for (int32_t g = 0; g < leaf0; ++g) {
+        const int64_t rk = F.rank[g], rows = F.op_rows[g];
+        const double *src = F.op.data() + F.op_off[g];
+        for (int64_t j = 0; j < rows; ++j)
+            for (int64_t k = 0; k < rk; ++k) {
+                trm[toff[g] + j * rk + k] = src[j * rk + k];
+                tcm[toff[g] + k * rows + j] = src[j * rk + k];
+            }
+    }
+    G.Tr_rm = up.copy(trm);
+    G.Tr_cm = up.copy(tcm);
+    G.troff = up.copy(toff);
+    op_bytes += (int64_t)(2 * sizeof(double) * toff.back());
+    const int w = f == 0 ? 1 : 2;
+    std::vector<int32_t> ilo(nbox + 1);
+    for (int32_t g = 0; g <= nbox; ++g) ilo[g] = (int32_t)r.list_off[w][g];
+    G.il_off = up.copy(ilo);
+    G.il_idx = up.copy(r.list_idx[w]);
+    std::vector<int32_t> targets;
+    for (int32_t g = 0; g < nbox; ++g)
+        if (F.rank[g] > 0) targets.push_back(g);
+    G.ntargets = (int32_t)targets.size();
+    G.targets = up.copy(targets);
+    G.v = up.template zeros<double>(nc ? nc : 1);
+    G.u = up.template zeros<double>(nc ? nc : 1);
+    (void)kappa;
+}
+
+template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> &D)
+{
+    using PT = typename P::pt_t;
+    using BT = typename P::basis_t;
     const h2s::HostRep &r = t->rep;
     const int d = r.d, kappa = r.kappa;
     const int32_t nbox = r.nbox(), leaf0 = r.leaf0(), nleaf = r.nleaf();
     const int64_t n = r.n;
-    const bool local = sizeof(T) == 4; // FP32 stores coordinates relative to box centres
     Uploader up{t, s};
 
-    D = h2s::DevTree<T>{};
+    D = h2s::DevTree<P>{};
     D.n = (int32_t)n;
     D.d = d;
     D.kappa = kappa;
@@ -157,22 +236,41 @@ template <typename T> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<
     D.kind = r.ker.kind;
     D.diag = r.ker.diag;
     D.shift = r.ker.shift;
-    D.kparam = r.ker.kind == H2S_K_GAUSSIAN ? 1.0 / (r.ker.param * r.ker.param) : 0.0;
+    D.kparam = r.ker.kind == H2S_K_GAUSSIAN ? r.ker.param * r.ker.param : 0.0;
     D.variant = r.variant;
+    D.max_leaf = 1;
+    for (int32_t g = leaf0; g < nbox; ++g) D.max_leaf = std::max(D.max_leaf, r.box_end[g] - r.box_begin[g]);
+    D.max_rows = 1;
+    D.max_rank = 1;
+    for (int f = 0; f < 2; ++f)
+        for (int32_t g = 0; g < nbox; ++g) {
+            D.max_rank = std::max(D.max_rank, r.fam[f].rank[g]);
+            if (g < leaf0) D.max_rows = std::max(D.max_rows, r.fam[f].op_rows[g]);
+        }
+    // Leaves, stacked transfer rows (both families at once) and ranks are
+    // staged whole in LDS (64 KiB per block); an M2L source box must fit the
+    // kernel's staging group, which bounds the rank.
+    const int32_t lds_cap = 7680, rank_cap = 512;
+    if (D.max_leaf > lds_cap || 2 * D.max_rows > lds_cap)
+        return fail(H2S_ERR_UNSUPPORTED, "a leaf or stacked transfer exceeds " + std::to_string(lds_cap) +
+                                             " entries; use a smaller leaf_size");
+    if (D.max_rank > rank_cap)
+        return fail(H2S_ERR_UNSUPPORTED, "a basis rank exceeds " + std::to_string(rank_cap) +
+                                             "; use a larger tolerance or a smaller leaf_size");
 
     std::vector<double> ctr((size_t)nbox * 3);
     for (int32_t g = 0; g < nbox; ++g) box_centre(r, g, &ctr[(size_t)g * 3]);
 
     D.perm = up.copy(r.perm);
     {
-        std::vector<T> px(n), py(n), pz(d == 3 ? n : 1);
+        std::vector<PT> px(n), py(n), pz(d == 3 ? n : 1);
         for (int32_t g = leaf0; g < nbox; ++g)
             for (int32_t i = r.box_begin[g]; i < r.box_end[g]; ++i) {
                 const double *p = &r.pts[(size_t)i * d];
                 const double *c = &ctr[(size_t)g * 3];
-                px[i] = (T)(local ? p[0] - c[0] : p[0]);
-                py[i] = (T)(local ? p[1] - c[1] : p[1]);
-                if (d == 3) pz[i] = (T)(local ? p[2] - c[2] : p[2]);
+                px[i] = (PT)(P::local ? p[0] - c[0] : p[0]);
+                py[i] = (PT)(P::local ? p[1] - c[1] : p[1]);
+                if (d == 3) pz[i] = (PT)(P::local ? p[2] - c[2] : p[2]);
             }
         D.px = up.copy(px);
         D.py = up.copy(py);
@@ -202,52 +300,12 @@ template <typename T> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<
         D.near_off = up.copy(noff);
         D.near_idx = up.copy(nidx);
     }
-    for (int f = 0; f < 2; ++f) {
-        const h2s::Family &F = r.fam[f];
-        h2s::DevFamily<T> &G = D.fam[f];
-        G.lmin = F.lmin;
-        std::vector<int32_t> co(nbox + 1);
-        for (int32_t g = 0; g <= nbox; ++g) co[g] = (int32_t)F.coef_off[g];
-        G.coef_off = up.copy(co);
-        const size_t nc = (size_t)F.coef_off[nbox];
-        std::vector<T> pvx(nc ? nc : 1), pvy(nc ? nc : 1), pvz(nc ? nc : 1);
-        for (int32_t g = 0; g < nbox; ++g)
-            for (int64_t c = F.coef_off[g]; c < F.coef_off[g + 1]; ++c) {
-                const double *p = &r.pts[(size_t)F.piv_row[c] * d];
-                const double *cc = &ctr[(size_t)g * 3];
-                pvx[c] = (T)(local ? p[0] - cc[0] : p[0]);
-                pvy[c] = (T)(local ? p[1] - cc[1] : p[1]);
-                pvz[c] = d == 3 ? (T)(local ? p[2] - cc[2] : p[2]) : T(0);
-            }
-        G.pvx = up.copy(pvx);
-        G.pvy = up.copy(pvy);
-        G.pvz = up.copy(pvz);
-        std::vector<T> op(F.op.size());
-        for (size_t i = 0; i < op.size(); ++i) op[i] = (T)F.op[i];
-        t->operator_bytes += (int64_t)(sizeof(T) * op.size());
-        const T *opd = up.copy(op);
-        G.U = opd;
-        G.Tr = opd;
-        const int64_t *ooff = up.copy(F.op_off);
-        G.troff = ooff;
-        G.uoff = ooff ? ooff + leaf0 : nullptr;
-        const int w = f == 0 ? 1 : 2;
-        std::vector<int32_t> ilo(nbox + 1);
-        for (int32_t g = 0; g <= nbox; ++g) ilo[g] = (int32_t)r.list_off[w][g];
-        G.il_off = up.copy(ilo);
-        G.il_idx = up.copy(r.list_idx[w]);
-        std::vector<int32_t> targets;
-        for (int32_t g = 0; g < nbox; ++g)
-            if (F.rank[g] > 0) targets.push_back(g);
-        G.ntargets = (int32_t)targets.size();
-        G.targets = up.copy(targets);
-        G.v = up.template zeros<T>(nc ? nc : 1);
-        G.u = up.template zeros<T>(nc ? nc : 1);
-    }
+    upload_family(up, r, 0, ctr, sizeof(typename P::far_t) == 4, D.far, t->operator_bytes);
+    upload_family(up, r, 1, ctr, false, D.ver, t->operator_bytes);
     if (r.variant == H2S_H2_PLUS_H) {
-        h2s::DevPairs<T> &P = D.pairs;
+        auto &Pr = D.pairs;
         const size_t np = r.pairs.size();
-        P.npairs = (int32_t)np;
+        Pr.npairs = (int32_t)np;
         std::vector<int32_t> px(np), py(np), pr(np);
         std::vector<int64_t> pu(np), pv(np), pw(np);
         int64_t woff = 0;
@@ -260,18 +318,17 @@ template <typename T> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<
             pw[p] = woff;
             woff += 2 * (int64_t)r.pairs[p].rank;
         }
-        P.px = up.copy(px);
-        P.py = up.copy(py);
-        P.prank = up.copy(pr);
-        P.pu = up.copy(pu);
-        P.pv = up.copy(pv);
-        P.pw = up.copy(pw);
-        std::vector<T> data(r.pair_data.size());
-        for (size_t i = 0; i < data.size(); ++i) data[i] = (T)r.pair_data[i];
-        t->operator_bytes += (int64_t)(sizeof(T) * data.size());
-        P.data = up.copy(data);
-        P.w = up.template zeros<T>(woff ? woff : 1);
-        // receivers: X gets (pair, side 0), Y gets (pair, side 1)
+        Pr.px = up.copy(px);
+        Pr.py = up.copy(py);
+        Pr.prank = up.copy(pr);
+        Pr.pu = up.copy(pu);
+        Pr.pv = up.copy(pv);
+        Pr.pw = up.copy(pw);
+        std::vector<BT> data(r.pair_data.size());
+        for (size_t i = 0; i < data.size(); ++i) data[i] = (BT)r.pair_data[i];
+        t->operator_bytes += (int64_t)(sizeof(BT) * data.size());
+        Pr.data = up.copy(data);
+        Pr.w = up.template zeros<double>(woff ? woff : 1);
         std::vector<std::vector<int32_t>> rec(nbox);
         for (size_t p = 0; p < np; ++p) {
             rec[px[p]].push_back((int32_t)(2 * p));
@@ -282,10 +339,9 @@ template <typename T> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<
             ridx.insert(ridx.end(), rec[g].begin(), rec[g].end());
             roff[g + 1] = (int32_t)ridx.size();
         }
-        P.recv_off = up.copy(roff);
-        P.recv = up.copy(ridx);
-        // row chunks of the two products of every pair
-        const int32_t CH = 2048;
+        Pr.recv_off = up.copy(roff);
+        Pr.recv = up.copy(ridx);
+        const int32_t CHR = 2048; // rows per chunk (the partial-product kernel stages them in LDS)
         std::vector<int32_t> cp, cs, cb, cl, sco(2 * np + 1, 0);
         std::vector<int64_t> cpo;
         int64_t poff = 0;
@@ -294,27 +350,26 @@ template <typename T> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<
                 const int32_t box = side == 0 ? py[p] : px[p];
                 const int32_t rows = r.box_end[box] - r.box_begin[box];
                 if (pr[p] > 0)
-                    for (int32_t s0 = 0; s0 < rows; s0 += CH) {
+                    for (int32_t s0 = 0; s0 < rows; s0 += CHR) {
                         cp.push_back((int32_t)p);
                         cs.push_back(side);
                         cb.push_back(s0);
-                        cl.push_back(std::min(CH, rows - s0));
+                        cl.push_back(std::min(CHR, rows - s0));
                         cpo.push_back(poff);
                         poff += pr[p];
                     }
                 sco[2 * p + side + 1] = (int32_t)cp.size();
             }
-        P.nchunks = (int32_t)cp.size();
-        P.chunk_pair = up.copy(cp);
-        P.chunk_side = up.copy(cs);
-        P.chunk_begin = up.copy(cb);
-        P.chunk_len = up.copy(cl);
-        P.chunk_poff = up.copy(cpo);
-        P.side_chunk_off = up.copy(sco);
-        P.partial = up.template zeros<T>(poff ? poff : 1);
+        Pr.nchunks = (int32_t)cp.size();
+        Pr.chunk_pair = up.copy(cp);
+        Pr.chunk_side = up.copy(cs);
+        Pr.chunk_begin = up.copy(cb);
+        Pr.chunk_len = up.copy(cl);
+        Pr.chunk_poff = up.copy(cpo);
+        Pr.side_chunk_off = up.copy(sco);
+        Pr.partial = up.template zeros<double>(poff ? poff : 1);
     }
-    D.qt = up.template zeros<T>(n);
-    D.phi = nullptr;
+    D.qt = up.template zeros<double>(n);
     if (up.st != H2S_OK) return up.st;
     if (hipStreamSynchronize(s) != hipSuccess) return fail(H2S_ERR_DEVICE, "stream synchronisation failed after upload");
     return H2S_OK;
@@ -375,7 +430,8 @@ h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kerne
     if (!(is_finite(o->eps_far) && o->eps_far >= 0 && is_finite(o->eps_ver) && o->eps_ver >= 0))
         return fail(H2S_ERR_INVALID_ARG, "tolerances must be finite and >= 0");
     if (o->variant != H2S_H2STAR && o->variant != H2S_H2_PLUS_H) return fail(H2S_ERR_INVALID_ARG, "unknown variant");
-    if (o->prec != H2S_FP64 && o->prec != H2S_FP32) return fail(H2S_ERR_INVALID_ARG, "unknown precision");
+    if (o->prec != H2S_FP64 && o->prec != H2S_FP32 && o->prec != H2S_FP32_M2L)
+        return fail(H2S_ERR_INVALID_ARG, "unknown precision");
     for (int64_t i = 0; i < n * d; ++i)
         if (!is_finite(points[i])) return fail(H2S_ERR_INVALID_ARG, "points must be finite");
 
@@ -408,8 +464,9 @@ h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kerne
     }
     t->lev_off = t->rep.lev_off;
     if (!t->host_only) {
-        st = o->prec == H2S_FP64 ? upload<double>(t, (hipStream_t)stream, t->t64)
-                                 : upload<float>(t, (hipStream_t)stream, t->t32);
+        if (o->prec == H2S_FP64) st = upload<h2s::P64>(t, (hipStream_t)stream, t->t64);
+        else if (o->prec == H2S_FP32) st = upload<h2s::P32>(t, (hipStream_t)stream, t->t32);
+        else st = upload<h2s::P32M>(t, (hipStream_t)stream, t->t32m);
         if (st != H2S_OK) {
             const std::string keep = g_last_error;
             delete t;
@@ -439,9 +496,12 @@ h2s_status h2s_apply_phases(h2s_tree t, uint32_t mask, const double *x, double *
     const h2s::ProfileHook *prof = t->profiling ? &hook : nullptr;
     t->prof_stream = (hipStream_t)stream;
     for (int32_t c = 0; c < nrhs; ++c) {
-        const int rc = t->opts.prec == H2S_FP64
-                           ? h2s::launch_mvp<double>(t->t64, t->lev_off.data(), x + c * ldx, y + c * ldy, mask, stream, prof)
-                           : h2s::launch_mvp<float>(t->t32, t->lev_off.data(), x + c * ldx, y + c * ldy, mask, stream, prof);
+        const double *xc = x + c * ldx;
+        double *yc = y + c * ldy;
+        int rc;
+        if (t->opts.prec == H2S_FP64) rc = h2s::launch_mvp<h2s::P64>(t->t64, t->lev_off.data(), xc, yc, mask, stream, prof);
+        else if (t->opts.prec == H2S_FP32) rc = h2s::launch_mvp<h2s::P32>(t->t32, t->lev_off.data(), xc, yc, mask, stream, prof);
+        else rc = h2s::launch_mvp<h2s::P32M>(t->t32m, t->lev_off.data(), xc, yc, mask, stream, prof);
         if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
     }
     return H2S_OK;

@@ -115,6 +115,20 @@ def test_fp32_within_1e5_of_fp64_oracle(lib, orc, inputs, d, kind, eps, variant)
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("d,kind,eps", [(2, 0, 1e-8), (3, 1, 1e-6)])
+def test_fp32_m2l_error_reported(lib, orc, inputs, d, kind, eps):
+    """FP32_M2L also evaluates the far-field M2L in float; its error is larger than FP32's
+    (the interpolative operators amplify float M2L values) and is reported, with a sanity cap."""
+    n = 8192 if d == 2 else 6000
+    pts = inputs.uniform_points(n, d, 500 + d)
+    q = inputs.normal_rhs(n, 1, 600 + d)[:, 0]
+    O = orc.Tree(pts, kind, 64, eps)
+    T = lib.build(pts, kind=kind, leaf_size=64, eps=eps, prec=lib.FP32_M2L)
+    err = rel(gpu_apply(T, q), O.apply(q))
+    print(f"fp32_m2l d={d} kind={kind}: rel err vs fp64 oracle {err:.2e}", flush=True)
+    assert err <= 1e-4
+
+
 def test_fp64_65536_matches_oracle(lib, orc, inputs):
     n = 65536
     pts = inputs.uniform_points(n, 2, 1001)
@@ -136,6 +150,10 @@ def test_full_size_2d_config_matches_oracle(lib, orc, inputs):
     del O
     print("building library at N=2^20", flush=True)
     T = lib.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps)
-    assert rel(gpu_apply(T, q), want) <= 1e-12
+    err64 = rel(gpu_apply(T, q), want)
+    del T
     T32 = lib.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps, prec=lib.FP32)
-    assert rel(gpu_apply(T32, q), want) <= 1e-5
+    err32 = rel(gpu_apply(T32, q), want)
+    print(f"full size: fp64 {err64:.2e} fp32 {err32:.2e}", flush=True)
+    assert err64 <= 1e-12
+    assert err32 <= 1e-5

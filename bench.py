@@ -33,7 +33,9 @@ def parse():
     p.add_argument("--profile-steps", type=int, default=3)
     p.add_argument("--workload", default="2d_log_n1048576")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--only", default="", help="comma list of h2star_fp64,h2star_fp32,h2plush_fp64")
+    p.add_argument("--only", default="", help="comma list of h2star_fp64,h2star_fp32,h2star_fp32m2l,h2plush_fp64")
+    p.add_argument("--calib-copy", action="store_true",
+                   help="also run one plain 256 MiB device copy (reference for the HBM byte counters)")
     return p.parse_args()
 
 
@@ -73,19 +75,27 @@ def time_variant(h2s, torch, pts, q, w, variant, prec, steps, warmup, prof_steps
 
 
 def algorithmic_work(stats, kernel, prec):
-    """Algorithmic bytes and kernel evaluations per launch of one kernel class."""
-    n = stats["n"]
-    b = 8
+    """Algorithmic HBM bytes and kernel evaluations of one launch of a kernel class.
+
+    Bytes count each operator entry, coordinate, charge and output once:
+    leaf bases sum_X n_X r_X entries, transfers sum_X (sum_c r_c) r_X entries,
+    points d FP64 (FP32 in the FP32 policies) per point, charges, y and perm."""
+    n, d = stats["n"], stats["d"]
     basis_b = 8 if prec == 0 else 4
-    leaf_rank = stats["leaf_basis_entries"]
+    pt_b = 8 if prec == 0 else 4
+    leaf = stats["leaf_basis_entries"]
     if kernel == "leaf_down":
-        # x gather is in leaf_up; here: points, charges, U and u at the leaves, y and perm
-        byts = n * (2 * b + b + b + 4) + leaf_rank * basis_b
-        return byts, stats["p2p_evals"]
+        return n * (d * pt_b + 8 + 8 + 4) + leaf * basis_b, stats["p2p_evals"]
     if kernel == "leaf_up":
-        return n * (b + 4 + b) + leaf_rank * basis_b, 0
-    if kernel == "m2l":
-        return 0, stats["m2l_evals"]
+        return n * (8 + 4 + 8) + leaf * basis_b, 0
+    if kernel == "m2l_far":
+        return 0, stats["m2l_evals_family"][0]
+    if kernel == "m2l_ver":
+        return 0, stats["m2l_evals_family"][1]
+    if kernel in ("m2m", "l2l"):
+        return stats["transfer_entries"] * 8, 0
+    if kernel == "pair_part":
+        return stats["pair_entries"] * basis_b, 0
     return 0, 0
 
 
@@ -103,10 +113,16 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     h2s.load()
+    if a.calib_copy:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = inputs.workload(a.workload)
     pts, q = w.points(), np.ascontiguousarray(w.rhs()[:, 0])
     todo = [("h2star_fp64", h2s.H2STAR, h2s.FP64), ("h2star_fp32", h2s.H2STAR, h2s.FP32),
-            ("h2plush_fp64", h2s.H2_PLUS_H, h2s.FP64)]
+            ("h2star_fp32m2l", h2s.H2STAR, h2s.FP32_M2L), ("h2plush_fp64", h2s.H2_PLUS_H, h2s.FP64)]
     if a.only:
         todo = [t for t in todo if t[0] in a.only.split(",")]
     res, outs = {}, {}
@@ -125,8 +141,10 @@ def main():
     main_name = "h2star_fp64" if "h2star_fp64" in res else next(iter(res))
     m = res[main_name]
     kernels = m["kernels"]
-    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
-    roofline = roofline_entry(dom, kernels[dom], m["stats"], 0 if main_name.endswith("fp64") else 1)
+    roofline = None
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
+        roofline = roofline_entry(dom, kernels[dom], m["stats"], 0 if main_name.endswith("fp64") else 1)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -161,28 +179,44 @@ def main():
 
 
 def roofline_entry(name, k, stats, prec):
-    """Roofline of the dominant kernel; the accounting is described in the design notes."""
+    """Roofline of the dominant kernel class (one launch per step for the leaf and M2L classes)."""
     avg_s = k["avg_ms"] * 1e-3
     byts, evals = algorithmic_work(stats, name, prec)
+    traffic = measured_traffic(name)
     if evals:
-        # kernel evaluations: FP64 flops of the pair arithmetic (differences, squared
-        # distance, log via its evaluation, multiply-add), see FLOPS_PER_EVAL
-        flops = evals * FLOPS_PER_EVAL[prec]
-        peak = FP64_VECTOR_TFLOPS if prec == 0 else FP32_VECTOR_TFLOPS
+        flops = evals * FLOPS_PER_EVAL
         ach = flops / avg_s / 1e12
-        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None, "evals_per_launch": evals,
-                "flops_per_eval": FLOPS_PER_EVAL[prec], "avg_launch_ms": k["avg_ms"]}
+        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_VECTOR_TFLOPS, "traffic": traffic, "evals_per_launch": evals,
+                "flops_per_eval": FLOPS_PER_EVAL, "avg_launch_ms": k["avg_ms"],
+                "evals_per_s": evals / avg_s}
     ach = byts / avg_s / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": byts, "avg_launch_ms": k["avg_ms"]}
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": byts, "avg_launch_ms": k["avg_ms"]}
 
 
-# Floating-point operations charged per pairwise 2D log-kernel evaluation:
-# 2 subtractions, 1 multiply + 1 fused multiply-add for r^2 (3 flops), the
-# logarithm as the 20 flops of a degree-8 minimax polynomial in Horner form
-# after range reduction (frexp + 2 ops), and the multiply-add into the sum (2).
-FLOPS_PER_EVAL = {0: 2 + 3 + 22 + 2, 1: 2 + 3 + 22 + 2}
+# FP64 floating-point operations of one log-kernel evaluation as compiled for
+# gfx950 (FMA = 2, add / mul / rcp = 1): squared distance, the frexp + atanh-
+# series logarithm and the multiply-add into the sum, counted from the M2L
+# inner loop (the near-field loop performs the same evaluation).
+FLOPS_PER_EVAL = 44
+
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_2d_log_n1048576.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
+    or None if that summary was taken on other kernel sources."""
+    import hashlib
+    try:
+        c = json.load(open(COUNTERS))
+    except (OSError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_2309_14085_amd", "csrc", "h2s_kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != c.get("kernels_sha256"):
+        return None
+    k = c.get("per_launch_bytes", {}).get(kernel)
+    return None if k is None else k["fetch"] + k["write"]
 
 
 def cpu_baseline(pts, q, w):

@@ -123,6 +123,7 @@ typedef struct {
     int32_t rank_max[2];
     int64_t p2p_evals;            /* kernel evaluations of the near field */
     int64_t m2l_evals;            /* kernel evaluations of M2L (sum of r_X r_Y) */
+    int64_t m2l_evals_family[2];  /* the same for the far / vertex family */
     int64_t leaf_basis_entries;   /* sum over leaves and families of n_X r_X (P2M / L2P operators) */
     int64_t transfer_entries;     /* sum over non-leaf boxes and families of (sum_c r_c) r_X */
     int64_t pair_entries;         /* (H2+H)*: sum over vertex pairs of (n_X + n_Y) r */
@@ -151,12 +152,13 @@ h2s_status h2s_export(h2s_tree t, const char *path);
 /* Kernel classes timed by the profiling hooks, in launch order. */
 #define H2S_PROF_LEAF_UP 0   /* charges to tree order + P2M */
 #define H2S_PROF_M2M 1       /* all M2M levels */
-#define H2S_PROF_M2L 2       /* M2L, every level and family in one launch */
+#define H2S_PROF_M2L_FAR 2   /* far-field M2L, every level in one launch */
 #define H2S_PROF_L2L 3       /* all L2L levels */
 #define H2S_PROF_PAIR_PART 4 /* (H2+H)* partial products */
 #define H2S_PROF_PAIR_SUM 5  /* (H2+H)* chunk sums */
 #define H2S_PROF_LEAF_DOWN 6 /* L2P + (H2+H)* vertex blocks + near field + scatter */
-#define H2S_NUM_PROF 7
+#define H2S_PROF_M2L_VER 7   /* vertex-sharing M2L, every level in one launch */
+#define H2S_NUM_PROF 8
 
 /* Profiling hooks for measurement: while enabled, every apply records a HIP
  * event before and after each kernel class on the caller's stream (adding

@@ -50,6 +50,7 @@ struct h2s_tree_s {
     size_t device_bytes = 0;
     int64_t operator_bytes = 0;
     std::vector<int32_t> lev_off;
+    h2s::LaunchPlan plan{};
     h2s::DevTree<h2s::P64> t64{};
     h2s::DevTree<h2s::P32> t32{};
     h2s::DevTree<h2s::P32M> t32m{};
@@ -250,10 +251,12 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
     // Leaves, stacked transfer rows (both families at once) and ranks are
     // staged whole in LDS (64 KiB per block); an M2L source box must fit the
     // kernel's staging group, which bounds the rank.
-    const int32_t lds_cap = 7680, rank_cap = 512;
+    const int32_t lds_cap = 5120, rank_cap = 512;
     if (D.max_leaf > lds_cap || 2 * D.max_rows > lds_cap)
         return fail(H2S_ERR_UNSUPPORTED, "a leaf or stacked transfer exceeds " + std::to_string(lds_cap) +
                                              " entries; use a smaller leaf_size");
+    if (kappa > h2s::kMaxLevels)
+        return fail(H2S_ERR_UNSUPPORTED, "tree depth exceeds " + std::to_string(h2s::kMaxLevels) + " levels");
     if (D.max_rank > rank_cap)
         return fail(H2S_ERR_UNSUPPORTED, "a basis rank exceeds " + std::to_string(rank_cap) +
                                              "; use a larger tolerance or a smaller leaf_size");
@@ -370,6 +373,30 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
         Pr.partial = up.template zeros<double>(poff ? poff : 1);
     }
     D.qt = up.template zeros<double>(n);
+    {
+        // 0.5 ln x by table reduction: subinterval i of m in [1/2, 1) has centre
+        // z_i = 1/2 + (i + 1/2)/256; store c_i = 1/z_i and -0.5 ln c_i (extended precision)
+        std::vector<double> tab(2 * 128);
+        for (int i = 0; i < 128; ++i) {
+            const double c = 1.0 / (0.5 + (i + 0.5) / 256.0);
+            tab[2 * i] = c;
+            tab[2 * i + 1] = (double)(-0.5L * std::log((long double)c));
+        }
+        D.logtab = up.copy(tab);
+    }
+    // block sizes: one thread per output of a box (both families), whole wavefronts
+    auto threads = [](int32_t outputs) { return std::min(512, std::max(64, (outputs + 63) / 64 * 64)); };
+    t->plan = h2s::LaunchPlan{};
+    t->plan.lev_off = t->lev_off.data();
+    for (int l = 0; l <= kappa; ++l) {
+        int32_t cols = 0, rows = 0;
+        for (int32_t g = r.lev_off[l]; g < r.lev_off[l + 1]; ++g) {
+            cols = std::max(cols, r.fam[0].rank[g] + r.fam[1].rank[g]);
+            if (l < kappa) rows = std::max(rows, r.fam[0].op_rows[g] + r.fam[1].op_rows[g]);
+        }
+        t->plan.up_threads[l] = threads(cols);
+        t->plan.dn_threads[l] = threads(rows);
+    }
     if (up.st != H2S_OK) return up.st;
     if (hipStreamSynchronize(s) != hipSuccess) return fail(H2S_ERR_DEVICE, "stream synchronisation failed after upload");
     return H2S_OK;
@@ -499,9 +526,9 @@ h2s_status h2s_apply_phases(h2s_tree t, uint32_t mask, const double *x, double *
         const double *xc = x + c * ldx;
         double *yc = y + c * ldy;
         int rc;
-        if (t->opts.prec == H2S_FP64) rc = h2s::launch_mvp<h2s::P64>(t->t64, t->lev_off.data(), xc, yc, mask, stream, prof);
-        else if (t->opts.prec == H2S_FP32) rc = h2s::launch_mvp<h2s::P32>(t->t32, t->lev_off.data(), xc, yc, mask, stream, prof);
-        else rc = h2s::launch_mvp<h2s::P32M>(t->t32m, t->lev_off.data(), xc, yc, mask, stream, prof);
+        if (t->opts.prec == H2S_FP64) rc = h2s::launch_mvp<h2s::P64>(t->t64, t->plan, xc, yc, mask, stream, prof);
+        else if (t->opts.prec == H2S_FP32) rc = h2s::launch_mvp<h2s::P32>(t->t32, t->plan, xc, yc, mask, stream, prof);
+        else rc = h2s::launch_mvp<h2s::P32M>(t->t32m, t->plan, xc, yc, mask, stream, prof);
         if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
     }
     return H2S_OK;
@@ -554,8 +581,10 @@ h2s_status h2s_get_stats(h2s_tree t, h2s_stats *s)
                 sum[l] += rk;
             }
             const int w = f == 0 ? 1 : 2;
-            for (int64_t e = r.list_off[w][g]; e < r.list_off[w][g + 1]; ++e)
+            for (int64_t e = r.list_off[w][g]; e < r.list_off[w][g + 1]; ++e) {
                 s->m2l_evals += (int64_t)rk * F.rank[r.list_idx[w][e]];
+                s->m2l_evals_family[f] += (int64_t)rk * F.rank[r.list_idx[w][e]];
+            }
         }
         for (int l = 0; l < 32; ++l) s->rank_avg_level[f][l] = cnt[l] ? (double)sum[l] / cnt[l] : 0.0;
         for (int32_t g = 0; g < r.nbox(); ++g) {

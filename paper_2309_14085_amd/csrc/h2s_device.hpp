@@ -103,6 +103,15 @@ template <class P> struct DevTree {
     DevFamily<double, basis_t> ver;
     DevPairs<basis_t> pairs;
     double *qt;
+    const double *logtab; // log r: (c_i, -0.5 ln c_i) for 128 mantissa subintervals
+};
+
+// Host-side launch shapes, fixed at upload.
+constexpr int kMaxLevels = 32;
+struct LaunchPlan {
+    const int32_t *lev_off;              // global box range of every level (kappa + 2 entries)
+    int32_t up_threads[kMaxLevels + 1];  // block size of P2M (level kappa) and M2M (levels < kappa)
+    int32_t dn_threads[kMaxLevels + 1];  // block size of L2L per level
 };
 
 // Optional timing hook: mark(ctx, kernel class, 0 = before / 1 = after).
@@ -112,10 +121,9 @@ struct ProfileHook {
 };
 
 // Enqueue one product y = K~ x (single right-hand side) on `stream`.
-// lev_off: host copy of the global box range of every level (kappa + 2).
 // Returns a hipError_t as int.
 template <class P>
-int launch_mvp(const DevTree<P> &t, const int32_t *lev_off, const double *x, double *y, uint32_t mask, void *stream,
+int launch_mvp(const DevTree<P> &t, const LaunchPlan &plan, const double *x, double *y, uint32_t mask, void *stream,
                const ProfileHook *prof);
 
 } // namespace h2s

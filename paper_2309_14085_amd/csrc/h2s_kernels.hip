@@ -53,43 +53,39 @@ template <bool ORD> __device__ __forceinline__ double madd(double s, double a, d
     else return fma(a, b, s);
 }
 
-// 0.5 ln(x) for finite x > 0 in double, written from the mathematics:
-// x = m 2^e with m in [sqrt(1/2), sqrt(2)) (frexp), ln m = 2 atanh(s) with
-// s = (m - 1) / (m + 1), |s| <= 0.1716, and atanh(s) = s + s^3/3 + s^5/5 + ...
-// summed through s^21 by Horner in s^2 (the next term is below 1e-19 of the
-// result).  The quotient uses the hardware reciprocal refined by two Newton
-// steps.  Error: a few ulps.
-__device__ __forceinline__ double half_log(double x)
+// 0.5 ln(x) for finite x > 0 in double, table-driven (Tang's reduction):
+// x = m 2^e with m in [1/2, 1) (frexp); the top 7 fraction bits of m select
+// a subinterval i of width 1/256 with centre z_i, c_i ~ 1/z_i; then
+// r = m c_i - 1 (|r| < 2^-8, one rounding) and
+//   0.5 ln x = 0.5 e ln 2 - 0.5 ln c_i + 0.5 ln(1 + r),
+// the last term by its Taylor series through r^6 (truncation below 1e-18).
+// tab holds (c_i, -0.5 ln c_i) for the 128 subintervals (built on the host
+// in extended precision) and is staged in LDS by the caller.  Absolute
+// error about one ulp of the result.
+constexpr int kLogTab = 128;
+
+__device__ __forceinline__ double half_log(double x, const double2 *tab)
 {
     int e;
-    double m = frexp(x, &e);
-    if (m < 0.70710678118654752440) {
-        m += m;
-        e -= 1;
-    }
-    const double dn = m + 1.0;
-    double rc = __builtin_amdgcn_rcp(dn);
-    rc = fma(rc, fma(-dn, rc, 1.0), rc);
-    rc = fma(rc, fma(-dn, rc, 1.0), rc);
-    const double s = (m - 1.0) * rc;
-    const double z = s * s;
-    double p = 1.0 / 21;
-    p = fma(p, z, 1.0 / 19);
-    p = fma(p, z, 1.0 / 17);
-    p = fma(p, z, 1.0 / 15);
-    p = fma(p, z, 1.0 / 13);
-    p = fma(p, z, 1.0 / 11);
-    p = fma(p, z, 1.0 / 9);
-    p = fma(p, z, 1.0 / 7);
-    p = fma(p, z, 1.0 / 5);
-    p = fma(p, z, 1.0 / 3);
-    const double at = fma(s * z, p, s);
-    return fma((double)e, 0.34657359027997264, at); // ln 2 / 2
+    const double m = frexp(x, &e);
+    const int i = (__double2hiint(m) >> 13) & (kLogTab - 1);
+    const double2 c = tab[i];
+    const double r = fma(m, c.x, -1.0);
+    double p = -1.0 / 12;
+    p = fma(p, r, 1.0 / 10);
+    p = fma(p, r, -1.0 / 8);
+    p = fma(p, r, 1.0 / 6);
+    p = fma(p, r, -1.0 / 4);
+    p = fma(p, r, 1.0 / 2);
+    return fma((double)e, 0.34657359027997264, c.y) + r * p; // ln 2 / 2
 }
 
-// Which FP64 evaluation of log r the kernels use: the library's correctly
-// rounded log(sqrt(r^2)), or half_log above.
-constexpr bool kFastLog = true;
+// Stage the log table in LDS (whole block; the caller synchronises).
+template <int KIND> __device__ __forceinline__ void stage_log_table(const double *g, double2 *tab)
+{
+    if constexpr (KIND == H2S_K_LOG_R)
+        for (int i = threadIdx.x; i < kLogTab; i += blockDim.x) tab[i] = make_double2(g[2 * i], g[2 * i + 1]);
+}
 
 // Squared distance with products and sums rounded separately under ORD.
 template <bool ORD, int D, typename T> __device__ __forceinline__ T dist2(T dx, T dy, T dz)
@@ -105,15 +101,19 @@ template <bool ORD, int D, typename T> __device__ __forceinline__ T dist2(T dx, 
     }
 }
 
-// Kernel value from the squared distance; r2 == 0 means coincident points.
-// kp: h^2 for the Gaussian.
-template <int KIND> __device__ __forceinline__ double kval(double r2, double diag, double kp)
+// Kernel value from a squared distance r2 > 0.  kp: h^2 for the Gaussian.
+template <int KIND> __device__ __forceinline__ double kval_pos(double r2, double kp, const double2 *tab)
 {
-    double v;
-    if constexpr (KIND == H2S_K_LOG_R) v = kFastLog ? half_log(r2) : log(sqrt(r2));
-    else if constexpr (KIND == H2S_K_INV_R) v = 1.0 / sqrt(r2);
-    else if constexpr (KIND == H2S_K_GAUSSIAN) v = exp(-r2 / kp);
-    else v = exp(-sqrt(r2));
+    if constexpr (KIND == H2S_K_LOG_R) return half_log(r2, tab);
+    else if constexpr (KIND == H2S_K_INV_R) return 1.0 / sqrt(r2);
+    else if constexpr (KIND == H2S_K_GAUSSIAN) return exp(-r2 / kp);
+    else return exp(-sqrt(r2));
+}
+
+// Kernel value from the squared distance; r2 == 0 means coincident points.
+template <int KIND> __device__ __forceinline__ double kval(double r2, double diag, double kp, const double2 *tab)
+{
+    const double v = kval_pos<KIND>(r2, kp, tab);
     return r2 == 0.0 ? diag : v;
 }
 
@@ -135,26 +135,60 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v)
 }
 
 // ---------------------------------------------------------------------------
-// P2M, M2M, L2L: one output per thread, terms in index order.
+// P2M, M2M, L2L: one output per thread, terms in index order.  Blocks are
+// sized per level by the host to cover the outputs of a box (both families)
+// in one pass.
 // ---------------------------------------------------------------------------
-constexpr int NT_UP = 64; // P2M and M2M: ranks rarely exceed 64
+constexpr int NT_GEMV_MAX = 512;
 
-// out[k] = sum_j A[j r + k] x[j] (A row-major R x r), one column k.
+// Ordered dot product sum_j a(j) x[j], a(j) = A[j stride].  The sum itself is
+// sequential; the operator loads are software-pipelined two batches of UNR
+// deep so that a batch is in flight while the previous one is accumulated.
+constexpr int UNR = 8;
+
 template <bool ORD, typename AT>
-__device__ __forceinline__ void colsum(const AT *__restrict__ A, int R, int r, const double *xs, double *out, int k)
+__device__ __forceinline__ double ordered_dot(const AT *__restrict__ A, size_t stride, int R, const double *xs)
 {
     double s = 0.0;
-    for (int j = 0; j < R; ++j) s = madd<ORD>(s, (double)A[(size_t)j * r + k], xs[j]);
-    out[k] = s;
+    int j = 0;
+    if (R >= 2 * UNR) {
+        double a[UNR], b[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) a[u] = (double)A[(size_t)u * stride];
+        for (; j + 3 * UNR <= R; j += 2 * UNR) {
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) b[u] = (double)A[(size_t)(j + UNR + u) * stride];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) s = madd<ORD>(s, a[u], xs[j + u]);
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) a[u] = (double)A[(size_t)(j + 2 * UNR + u) * stride];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) s = madd<ORD>(s, b[u], xs[j + UNR + u]);
+        }
+        // a holds rows j .. j + UNR - 1 (fewer than 3 UNR rows were left)
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) s = madd<ORD>(s, a[u], xs[j + u]);
+        j += UNR;
+    }
+    // the remaining rows, one predicated batch of loads at a time
+    for (; j < R; j += UNR) {
+        double c[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) c[u] = j + u < R ? (double)A[(size_t)(j + u) * stride] : 0.0;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (j + u < R) s = madd<ORD>(s, c[u], xs[j + u]);
+    }
+    return s;
 }
 
 template <class P>
-__global__ __launch_bounds__(NT_UP) void k_up_leaf(DevTree<P> t, const double *__restrict__ x, uint32_t mask)
+__global__ __launch_bounds__(NT_GEMV_MAX) void k_up_leaf(DevTree<P> t, const double *__restrict__ x, uint32_t mask)
 {
     extern __shared__ double qs[]; // largest leaf
-    const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf, tid = threadIdx.x;
+    const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf, tid = threadIdx.x, nt = blockDim.x;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
-    for (int i = tid; i < n; i += NT_UP) {
+    for (int i = tid; i < n; i += nt) {
         const double v = x[t.perm[b + i]];
         qs[i] = v;
         t.qt[b + i] = v;
@@ -162,64 +196,66 @@ __global__ __launch_bounds__(NT_UP) void k_up_leaf(DevTree<P> t, const double *_
     __syncthreads();
     const int cf = t.far.coef_off[g], rf = (mask & kFar) && t.kappa >= t.far.lmin ? t.far.coef_off[g + 1] - cf : 0;
     const int cv = t.ver.coef_off[g], rv = (mask & kVer) && t.kappa >= t.ver.lmin ? t.ver.coef_off[g + 1] - cv : 0;
-    // one column of the two families per thread
-    for (int k = tid; k < rf + rv; k += NT_UP) {
-        if (k < rf) colsum<P::ordered>(t.far.U_rm + t.far.uoff[leaf], n, rf, qs, t.far.v + cf, k);
-        else colsum<P::ordered>(t.ver.U_rm + t.ver.uoff[leaf], n, rv, qs, t.ver.v + cv, k - rf);
+    // one column of the two families per thread (U row-major n x r: column k strided by r)
+    for (int k = tid; k < rf + rv; k += nt) {
+        if (k < rf) t.far.v[cf + k] = ordered_dot<P::ordered>(t.far.U_rm + t.far.uoff[leaf] + k, (size_t)rf, n, qs);
+        else t.ver.v[cv + k - rf] = ordered_dot<P::ordered>(t.ver.U_rm + t.ver.uoff[leaf] + (k - rf), (size_t)rv, n, qs);
     }
 }
 
-template <class P> __global__ __launch_bounds__(NT_UP) void k_m2m(DevTree<P> t, int32_t g0, uint32_t mask)
+template <class P> __global__ __launch_bounds__(NT_GEMV_MAX) void k_m2m(DevTree<P> t, int32_t g0, uint32_t mask)
 {
     extern __shared__ double xs[]; // both families' child coefficients
-    const int g = g0 + blockIdx.x, tid = threadIdx.x;
+    const int g = g0 + blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const auto &Fa = t.far;
     const auto &Ve = t.ver;
     const int cf = Fa.coef_off[g], rf = (mask & kFar) ? Fa.coef_off[g + 1] - cf : 0;
     const int cv = Ve.coef_off[g], rv = (mask & kVer) ? Ve.coef_off[g + 1] - cv : 0;
     const int bf = Fa.coef_off[t.box_cbeg[g]], Rf = rf ? Fa.coef_off[t.box_cend[g]] - bf : 0;
     const int bv = Ve.coef_off[t.box_cbeg[g]], Rv = rv ? Ve.coef_off[t.box_cend[g]] - bv : 0;
-    for (int j = tid; j < Rf; j += NT_UP) xs[j] = Fa.v[bf + j];
-    for (int j = tid; j < Rv; j += NT_UP) xs[Rf + j] = Ve.v[bv + j];
+    for (int j = tid; j < Rf; j += nt) xs[j] = Fa.v[bf + j];
+    for (int j = tid; j < Rv; j += nt) xs[Rf + j] = Ve.v[bv + j];
     __syncthreads();
-    for (int k = tid; k < rf + rv; k += NT_UP) {
-        if (k < rf) colsum<P::ordered>(Fa.Tr_rm + Fa.troff[g], Rf, rf, xs, Fa.v + cf, k);
-        else colsum<P::ordered>(Ve.Tr_rm + Ve.troff[g], Rv, rv, xs + Rf, Ve.v + cv, k - rf);
+    // stacked transfers row-major (sum r_c) x r: column k strided by r
+    for (int k = tid; k < rf + rv; k += nt) {
+        if (k < rf) Fa.v[cf + k] = ordered_dot<P::ordered>(Fa.Tr_rm + Fa.troff[g] + k, (size_t)rf, Rf, xs);
+        else Ve.v[cv + k - rf] = ordered_dot<P::ordered>(Ve.Tr_rm + Ve.troff[g] + (k - rf), (size_t)rv, Rv, xs + Rf);
     }
 }
 
-constexpr int NT_DN = 256; // L2L rows per box reach a few hundred
-
-template <bool ORD, typename F>
-__device__ __forceinline__ void l2l_family(const F &fam, const int32_t *cbeg, const int32_t *cend, int g, double *xs)
+template <class P> __global__ __launch_bounds__(NT_GEMV_MAX) void k_l2l(DevTree<P> t, int32_t g0, uint32_t mask)
 {
-    const int c0 = fam.coef_off[g], r = fam.coef_off[g + 1] - c0;
-    if (r == 0) return;
-    const int cb = fam.coef_off[cbeg[g]], R = fam.coef_off[cend[g]] - cb;
-    for (int k = threadIdx.x; k < r; k += NT_DN) xs[k] = fam.u[c0 + k];
+    extern __shared__ double xs[]; // both families' parent locals
+    constexpr bool ORD = P::ordered;
+    const int g = g0 + blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const auto &Fa = t.far;
+    const auto &Ve = t.ver;
+    const int cf = Fa.coef_off[g], rf = (mask & kFar) ? Fa.coef_off[g + 1] - cf : 0;
+    const int cv = Ve.coef_off[g], rv = (mask & kVer) ? Ve.coef_off[g + 1] - cv : 0;
+    const int bf = Fa.coef_off[t.box_cbeg[g]], Rf = rf ? Fa.coef_off[t.box_cend[g]] - bf : 0;
+    const int bv = Ve.coef_off[t.box_cbeg[g]], Rv = rv ? Ve.coef_off[t.box_cend[g]] - bv : 0;
+    for (int k = tid; k < rf; k += nt) xs[k] = Fa.u[cf + k];
+    for (int k = tid; k < rv; k += nt) xs[rf + k] = Ve.u[cv + k];
     __syncthreads();
-    const double *A = fam.Tr_cm + fam.troff[g];
-    for (int j = threadIdx.x; j < R; j += NT_DN) {
-        double s = 0.0;
-        for (int k = 0; k < r; ++k) s = madd<ORD>(s, A[(size_t)k * R + j], xs[k]);
-        fam.u[cb + j] = ORD ? __dadd_rn(fam.u[cb + j], s) : fam.u[cb + j] + s;
+    // stacked transfers column-major (sum r_c) x r: row j strided by the row count
+    for (int j = tid; j < Rf + Rv; j += nt) {
+        if (j < Rf) {
+            const double s = ordered_dot<ORD>(Fa.Tr_cm + Fa.troff[g] + j, (size_t)Rf, rf, xs);
+            Fa.u[bf + j] = ORD ? __dadd_rn(Fa.u[bf + j], s) : Fa.u[bf + j] + s;
+        } else {
+            const int jj = j - Rf;
+            const double s = ordered_dot<ORD>(Ve.Tr_cm + Ve.troff[g] + jj, (size_t)Rv, rv, xs + rf);
+            Ve.u[bv + jj] = ORD ? __dadd_rn(Ve.u[bv + jj], s) : Ve.u[bv + jj] + s;
+        }
     }
-    __syncthreads();
-}
-
-template <class P> __global__ __launch_bounds__(NT_DN) void k_l2l(DevTree<P> t, int32_t g0, uint32_t mask)
-{
-    extern __shared__ double xs[]; // largest rank
-    const int g = g0 + blockIdx.x;
-    if (mask & kFar) l2l_family<P::ordered>(t.far, t.box_cbeg, t.box_cend, g, xs);
-    if (mask & kVer) l2l_family<P::ordered>(t.ver, t.box_cbeg, t.box_cend, g, xs);
 }
 
 // ---------------------------------------------------------------------------
 // M2L: one target box per block.  Work item (a, Y): pivot a of X against
 // source box Y, s_{aY} = sum_b K(t^{X,i}_a, t^{Y,i}_b) v_Y[b] in b order;
 // then u_X[a] = sum_Y s_{aY} in list order.  Sources are staged in LDS a
-// group of whole boxes at a time.
+// group of whole boxes at a time.  X and Y are distinct boxes of one level,
+// and coincident points always fall in the same box, so r^2 > 0 here.
 // ---------------------------------------------------------------------------
 constexpr int NT_M2L = 128;
 constexpr int M2L_SRC = 512;   // staged pivots per group (>= the largest rank)
@@ -248,7 +284,9 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
     __shared__ int ybeg[M2L_BOX], ylen[M2L_BOX];
     __shared__ double ylc[CENTRED ? M2L_BOX : 1];
     __shared__ float yic[CENTRED ? M2L_BOX : 1];
+    __shared__ double2 ltab[KIND == H2S_K_LOG_R && !LOWP ? kLogTab : 1];
     const int tid = threadIdx.x;
+    if constexpr (!LOWP) stage_log_table<KIND>(t.logtab, ltab);
     const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
@@ -321,10 +359,22 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
                 }
                 s = (double)sf;
             } else {
-                for (int j = jb; j < je; ++j) {
+                int j = jb;
+                for (; j + 4 <= je; j += 4) {
+                    double kv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double r2 = dist2<ORD, D>((double)xa - (double)sx[j + u], (double)ya - (double)sy[j + u],
+                                                        D == 3 ? (double)za - (double)sz[j + u] : 0.0);
+                        kv[u] = kval_pos<KIND>(r2, (double)kp, ltab);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) s = madd<ORD>(s, kv[u], sv[j + u]);
+                }
+                for (; j < je; ++j) {
                     const double r2 = dist2<ORD, D>((double)xa - (double)sx[j], (double)ya - (double)sy[j],
                                                     D == 3 ? (double)za - (double)sz[j] : 0.0);
-                    s = madd<ORD>(s, kval<KIND>(r2, (double)diag, (double)kp), sv[j]);
+                    s = madd<ORD>(s, kval_pos<KIND>(r2, (double)kp, ltab), sv[j]);
                 }
             }
             part[yl * r + a] = s;
@@ -402,10 +452,7 @@ __device__ __forceinline__ double l2p_family(const F &fam, int g, int leaf, int 
     if (kappa < fam.lmin) return 0.0;
     const int c0 = fam.coef_off[g], r = fam.coef_off[g + 1] - c0;
     if (r == 0) return 0.0;
-    const auto *U = fam.U_cm + fam.uoff[leaf];
-    double s = 0.0;
-    for (int k = 0; k < r; ++k) s = madd<ORD>(s, (double)U[(size_t)k * n + i], fam.u[c0 + k]);
-    return s;
+    return ordered_dot<ORD>(fam.U_cm + fam.uoff[leaf] + i, (size_t)n, r, fam.u + c0);
 }
 
 template <class P, int KIND, int D>
@@ -413,31 +460,55 @@ __global__ __launch_bounds__(NT_LEAF) void k_down_leaf(DevTree<P> t, double *__r
 {
     using PT = typename P::pt_t;
     constexpr bool ORD = P::ordered;
+    constexpr bool TAB = KIND == H2S_K_LOG_R && sizeof(PT) == 8;
     __shared__ PT sx[P2P_SRC], sy[P2P_SRC], sz[D == 3 ? P2P_SRC : 1], sq[P2P_SRC];
     __shared__ double red[NT_LEAF];
+    __shared__ double2 ltab[TAB ? kLogTab : 1];
     const int tid = threadIdx.x;
     const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
     const PT diag = (PT)t.diag, kp = (PT)t.kparam;
     const double *cX = t.box_ctr + 3 * g;
+    if constexpr (TAB) stage_log_table<KIND>(t.logtab, ltab); // first used after a barrier
     for (int i0 = 0; i0 < n; i0 += NT_LEAF) {
         const int m = min(n - i0, NT_LEAF), S = NT_LEAF / m, s = tid / m, i = i0 + tid % m;
         const PT xi = t.px[b + i], yi = t.py[b + i], zi = D == 3 ? t.pz[b + i] : PT(0);
         double acc = 0.0;
         if (mask & kNear) {
-            int pos = 0;
+            int pos = 0, self0 = 0, self1 = 0; // staged positions of the target leaf's own points
+            // slice s takes the staged sources jb + s, jb + s + S, ... below je
+            auto slice_sum = [&](int jb, int je, auto check) {
+                constexpr bool CHECK = decltype(check)::value;
+                auto k = [&](PT r2) -> PT {
+                    if constexpr (sizeof(PT) == 8) {
+                        if constexpr (CHECK) return kval<KIND>(r2, diag, kp, ltab);
+                        else return kval_pos<KIND>(r2, kp, ltab);
+                    } else {
+                        return kval<KIND>(r2, diag, kp);
+                    }
+                };
+                PT part[4] = {0, 0, 0, 0};
+                int j = jb + s;
+                for (; j + 3 * S < je; j += 4 * S) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int jj = j + u * S;
+                        part[u] += k(dist2<false, D>(xi - sx[jj], yi - sy[jj], zi - sz[D == 3 ? jj : 0])) * sq[jj];
+                    }
+                }
+                for (; j < je; j += S) part[0] += k(dist2<false, D>(xi - sx[j], yi - sy[j], zi - sz[D == 3 ? j : 0])) * sq[j];
+                return (double)((part[0] + part[1]) + (part[2] + part[3]));
+            };
             auto flush = [&]() {
                 __syncthreads();
                 if (s < S) {
-                    PT part = 0;
-                    for (int j = s; j < pos; j += S) {
-                        const PT r2 = dist2<false, D>(xi - sx[j], yi - sy[j], zi - sz[D == 3 ? j : 0]);
-                        part += kval<KIND>(r2, diag, kp) * sq[j];
-                    }
-                    acc += (double)part;
+                    // only the target leaf's own points can coincide with a target
+                    acc += slice_sum(0, self0, std::false_type{});
+                    acc += slice_sum(self0, self1, std::true_type{});
+                    acc += slice_sum(self1, pos, std::false_type{});
                 }
                 __syncthreads();
-                pos = 0;
+                pos = self0 = self1 = 0;
             };
             for (int e = t.near_off[leaf]; e < t.near_off[leaf + 1]; ++e) {
                 const int gs = t.leaf0 + t.near_idx[e];
@@ -462,6 +533,10 @@ __global__ __launch_bounds__(NT_LEAF) void k_down_leaf(DevTree<P> t, double *__r
                             if constexpr (D == 3) sz[pos + j] = t.pz[src];
                         }
                         sq[pos + j] = (PT)t.qt[src];
+                    }
+                    if (gs == g) {
+                        self0 = pos;
+                        self1 = pos + take;
                     }
                     pos += take;
                     j0 += take;
@@ -493,7 +568,8 @@ __global__ __launch_bounds__(NT_LEAF) void k_down_leaf(DevTree<P> t, double *__r
                             const int r = Pr.prank[p];
                             const auto *G = Pr.data + (side == 0 ? Pr.pu[p] : Pr.pv[p]);
                             const double *w = Pr.w + Pr.pw[p] + (size_t)side * r;
-                            for (int k = 0; k < r; ++k) v = madd<ORD>(v, (double)G[(size_t)k * nX + off], w[k]);
+                            const double d = ordered_dot<ORD>(G + off, (size_t)nX, r, w);
+                            v = ORD ? __dadd_rn(v, d) : v + d;
                         }
                     }
                 }
@@ -506,36 +582,43 @@ __global__ __launch_bounds__(NT_LEAF) void k_down_leaf(DevTree<P> t, double *__r
 }
 
 template <class P, int KIND, int D>
-hipError_t enqueue(const DevTree<P> &t, const int32_t *lev_off, const double *x, double *y, uint32_t mask,
+hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x, double *y, uint32_t mask,
                    hipStream_t s, const ProfileHook *prof)
 {
     auto mark = [&](int cls, int end) {
         if (prof) prof->mark(prof->ctx, cls, end);
     };
+    const int32_t *lev_off = plan.lev_off;
     const size_t lds_leaf = sizeof(double) * (size_t)t.max_leaf;
     const size_t lds_rows = sizeof(double) * (size_t)(2 * t.max_rows);
-    const size_t lds_rank = sizeof(double) * (size_t)t.max_rank;
+    const size_t lds_rank = sizeof(double) * (size_t)(2 * t.max_rank);
     mark(H2S_PROF_LEAF_UP, 0);
-    hipLaunchKernelGGL(k_up_leaf<P>, dim3(t.nleaf), dim3(NT_UP), lds_leaf, s, t, x, mask);
+    hipLaunchKernelGGL(k_up_leaf<P>, dim3(t.nleaf), dim3(plan.up_threads[t.kappa]), lds_leaf, s, t, x, mask);
     mark(H2S_PROF_LEAF_UP, 1);
     const bool fam_on = (mask & (kFar | kVer)) && t.kappa >= 1;
     if (fam_on) {
         mark(H2S_PROF_M2M, 0);
         for (int l = t.kappa - 1; l >= 1; --l) {
             const int nb = lev_off[l + 1] - lev_off[l];
-            if (nb) hipLaunchKernelGGL(k_m2m<P>, dim3(nb), dim3(NT_UP), lds_rows, s, t, lev_off[l], mask);
+            if (nb)
+                hipLaunchKernelGGL(k_m2m<P>, dim3(nb), dim3(plan.up_threads[l]), lds_rows, s, t, lev_off[l], mask);
         }
         mark(H2S_PROF_M2M, 1);
-        mark(H2S_PROF_M2L, 0);
-        if ((mask & kFar) && t.far.ntargets)
+        if ((mask & kFar) && t.far.ntargets) {
+            mark(H2S_PROF_M2L_FAR, 0);
             hipLaunchKernelGGL((k_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_M2L), 0, s, t);
-        if ((mask & kVer) && t.ver.ntargets)
+            mark(H2S_PROF_M2L_FAR, 1);
+        }
+        if ((mask & kVer) && t.ver.ntargets) {
+            mark(H2S_PROF_M2L_VER, 0);
             hipLaunchKernelGGL((k_m2l<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_M2L), 0, s, t);
-        mark(H2S_PROF_M2L, 1);
+            mark(H2S_PROF_M2L_VER, 1);
+        }
         mark(H2S_PROF_L2L, 0);
         for (int l = 1; l <= t.kappa - 1; ++l) {
             const int nb = lev_off[l + 1] - lev_off[l];
-            if (nb) hipLaunchKernelGGL(k_l2l<P>, dim3(nb), dim3(NT_DN), lds_rank, s, t, lev_off[l], mask);
+            if (nb)
+                hipLaunchKernelGGL(k_l2l<P>, dim3(nb), dim3(plan.dn_threads[l]), lds_rank, s, t, lev_off[l], mask);
         }
         mark(H2S_PROF_L2L, 1);
     }
@@ -556,28 +639,28 @@ hipError_t enqueue(const DevTree<P> &t, const int32_t *lev_off, const double *x,
 } // namespace
 
 template <class P>
-int launch_mvp(const DevTree<P> &t, const int32_t *lev_off, const double *x, double *y, uint32_t mask, void *stream,
+int launch_mvp(const DevTree<P> &t, const LaunchPlan &plan, const double *x, double *y, uint32_t mask, void *stream,
                const ProfileHook *prof)
 {
     hipStream_t s = (hipStream_t)stream;
     const int key = t.kind * 2 + (t.d == 3);
     switch (key) {
-    case 0: return (int)enqueue<P, H2S_K_LOG_R, 2>(t, lev_off, x, y, mask, s, prof);
-    case 1: return (int)enqueue<P, H2S_K_LOG_R, 3>(t, lev_off, x, y, mask, s, prof);
-    case 2: return (int)enqueue<P, H2S_K_INV_R, 2>(t, lev_off, x, y, mask, s, prof);
-    case 3: return (int)enqueue<P, H2S_K_INV_R, 3>(t, lev_off, x, y, mask, s, prof);
-    case 4: return (int)enqueue<P, H2S_K_GAUSSIAN, 2>(t, lev_off, x, y, mask, s, prof);
-    case 5: return (int)enqueue<P, H2S_K_GAUSSIAN, 3>(t, lev_off, x, y, mask, s, prof);
-    case 6: return (int)enqueue<P, H2S_K_EXP_R, 2>(t, lev_off, x, y, mask, s, prof);
-    default: return (int)enqueue<P, H2S_K_EXP_R, 3>(t, lev_off, x, y, mask, s, prof);
+    case 0: return (int)enqueue<P, H2S_K_LOG_R, 2>(t, plan, x, y, mask, s, prof);
+    case 1: return (int)enqueue<P, H2S_K_LOG_R, 3>(t, plan, x, y, mask, s, prof);
+    case 2: return (int)enqueue<P, H2S_K_INV_R, 2>(t, plan, x, y, mask, s, prof);
+    case 3: return (int)enqueue<P, H2S_K_INV_R, 3>(t, plan, x, y, mask, s, prof);
+    case 4: return (int)enqueue<P, H2S_K_GAUSSIAN, 2>(t, plan, x, y, mask, s, prof);
+    case 5: return (int)enqueue<P, H2S_K_GAUSSIAN, 3>(t, plan, x, y, mask, s, prof);
+    case 6: return (int)enqueue<P, H2S_K_EXP_R, 2>(t, plan, x, y, mask, s, prof);
+    default: return (int)enqueue<P, H2S_K_EXP_R, 3>(t, plan, x, y, mask, s, prof);
     }
 }
 
-template int launch_mvp<P64>(const DevTree<P64> &, const int32_t *, const double *, double *, uint32_t, void *,
+template int launch_mvp<P64>(const DevTree<P64> &, const LaunchPlan &, const double *, double *, uint32_t, void *,
                              const ProfileHook *);
-template int launch_mvp<P32>(const DevTree<P32> &, const int32_t *, const double *, double *, uint32_t, void *,
+template int launch_mvp<P32>(const DevTree<P32> &, const LaunchPlan &, const double *, double *, uint32_t, void *,
                              const ProfileHook *);
-template int launch_mvp<P32M>(const DevTree<P32M> &, const int32_t *, const double *, double *, uint32_t, void *,
+template int launch_mvp<P32M>(const DevTree<P32M> &, const LaunchPlan &, const double *, double *, uint32_t, void *,
                               const ProfileHook *);
 
 } // namespace h2s

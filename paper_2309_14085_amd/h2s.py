@@ -19,7 +19,7 @@ LOG_R, INV_R, GAUSSIAN, EXP_R = 0, 1, 2, 3
 H2STAR, H2_PLUS_H = 0, 1
 FP64, FP32, FP32_M2L = 0, 1, 2
 PHASE_NEAR, PHASE_FAR, PHASE_VER, PHASE_ALL = 1, 2, 4, 7
-PROF_NAMES = ("leaf_up", "m2m", "m2l", "l2l", "pair_part", "pair_sum", "leaf_down")
+PROF_NAMES = ("leaf_up", "m2m", "m2l_far", "l2l", "pair_part", "pair_sum", "leaf_down", "m2l_ver")
 
 
 class Kernel(ctypes.Structure):
@@ -38,7 +38,7 @@ class Stats(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("n", ctypes.c_int64), ("boxes", ctypes.c_int64),
                 ("near_pairs", ctypes.c_int64), ("far_pairs", ctypes.c_int64), ("ver_pairs", ctypes.c_int64),
                 ("rank_sum", ctypes.c_int64 * 2), ("rank_max", ctypes.c_int32 * 2),
-                ("p2p_evals", ctypes.c_int64), ("m2l_evals", ctypes.c_int64),
+                ("p2p_evals", ctypes.c_int64), ("m2l_evals", ctypes.c_int64), ("m2l_evals_family", ctypes.c_int64 * 2),
                 ("leaf_basis_entries", ctypes.c_int64), ("transfer_entries", ctypes.c_int64),
                 ("pair_entries", ctypes.c_int64),
                 ("operator_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),

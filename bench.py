@@ -79,13 +79,16 @@ def algorithmic_work(stats, kernel, prec):
 
     Bytes count each operator entry, coordinate, charge and output once:
     leaf bases sum_X n_X r_X entries, transfers sum_X (sum_c r_c) r_X entries,
-    points d FP64 (FP32 in the FP32 policies) per point, charges, y and perm."""
+    points d FP64 (FP32 in the FP32 policies) per point, charges, near-field
+    potentials, y and perm."""
     n, d = stats["n"], stats["d"]
     basis_b = 8 if prec == 0 else 4
     pt_b = 8 if prec == 0 else 4
     leaf = stats["leaf_basis_entries"]
+    if kernel == "near":
+        return n * (d * pt_b + 8 + 8), stats["p2p_evals"]
     if kernel == "leaf_down":
-        return n * (d * pt_b + 8 + 8 + 4) + leaf * basis_b, stats["p2p_evals"]
+        return n * (8 + 8 + 4 + 8) + leaf * basis_b, 0
     if kernel == "leaf_up":
         return n * (8 + 4 + 8) + leaf * basis_b, 0
     if kernel == "m2l_far":

@@ -95,6 +95,10 @@ h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kerne
 
 /* y = (K~ + shift I) x for nrhs right-hand sides (Sec. 5.1.2 / 5.2.2).
  * x, y: device, user order, column-major, ld >= n; x and y must not overlap.
+ * Asynchronous and ordered on `stream`: the direct near field runs on a
+ * second stream owned by the handle, forked from and joined back into
+ * `stream` with events, so the caller sees one stream-ordered operation.
+ * One handle serves one stream at a time.
  * Errors: INVALID_ARG, UNSUPPORTED (host_only handle), DEVICE. */
 h2s_status h2s_apply(h2s_tree t, const double *x, double *y, int32_t nrhs, int64_t ldx, int64_t ldy,
                      void *stream);
@@ -156,13 +160,14 @@ h2s_status h2s_export(h2s_tree t, const char *path);
 #define H2S_PROF_L2L 3       /* all L2L levels */
 #define H2S_PROF_PAIR_PART 4 /* (H2+H)* partial products */
 #define H2S_PROF_PAIR_SUM 5  /* (H2+H)* chunk sums */
-#define H2S_PROF_LEAF_DOWN 6 /* L2P + (H2+H)* vertex blocks + near field + scatter */
+#define H2S_PROF_LEAF_DOWN 6 /* L2P + (H2+H)* vertex blocks + sum + scatter */
 #define H2S_PROF_M2L_VER 7   /* vertex-sharing M2L, every level in one launch */
-#define H2S_NUM_PROF 8
+#define H2S_PROF_NEAR 8      /* direct near field, on a second stream beside the sweeps */
+#define H2S_NUM_PROF 9
 
 /* Profiling hooks for measurement: while enabled, every apply records a HIP
- * event before and after each kernel class on the caller's stream (adding
- * small gaps between kernels).  h2s_get_profile waits for the recorded
+ * event before and after each kernel class on the stream that runs it
+ * (adding small gaps between kernels).  h2s_get_profile waits for the recorded
  * events, writes per-class total milliseconds and launch counts (arrays of
  * H2S_NUM_PROF entries, either may be NULL) and clears the record. */
 h2s_status h2s_set_profiling(h2s_tree t, int32_t enable);

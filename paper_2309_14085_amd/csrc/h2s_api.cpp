@@ -56,12 +56,14 @@ struct h2s_tree_s {
     h2s::DevTree<h2s::P32M> t32m{};
     // profiling: (class, start, stop) events recorded by apply while enabled
     bool profiling = false;
-    hipStream_t prof_stream = nullptr;
     struct Mark {
         int cls;
         hipEvent_t a, b;
     };
     std::vector<Mark> marks;
+    // second stream for the near field and the events that fork / join it
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     void clear_marks()
     {
@@ -75,21 +77,32 @@ struct h2s_tree_s {
     ~h2s_tree_s()
     {
         clear_marks();
+        if (aux) {
+            (void)hipStreamSynchronize(aux);
+            (void)hipStreamDestroy(aux);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         for (void *p : allocs) ffn(actx, p);
     }
 };
 
 namespace {
-void record_mark(void *ctx, int cls, int end)
+void record_mark(void *ctx, int cls, int end, void *stream)
 {
     h2s_tree t = (h2s_tree)ctx;
     if (!end) {
         h2s_tree_s::Mark m{cls, nullptr, nullptr};
         if (hipEventCreate(&m.a) != hipSuccess || hipEventCreate(&m.b) != hipSuccess) return;
-        (void)hipEventRecord(m.a, t->prof_stream);
+        (void)hipEventRecord(m.a, (hipStream_t)stream);
         t->marks.push_back(m);
-    } else if (!t->marks.empty() && t->marks.back().cls == cls) {
-        (void)hipEventRecord(t->marks.back().b, t->prof_stream);
+    } else {
+        // the most recent open mark of this class (marks of the two streams interleave)
+        for (auto it = t->marks.rbegin(); it != t->marks.rend(); ++it)
+            if (it->cls == cls) {
+                (void)hipEventRecord(it->b, (hipStream_t)stream);
+                break;
+            }
     }
 }
 } // namespace
@@ -373,6 +386,7 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
         Pr.partial = up.template zeros<double>(poff ? poff : 1);
     }
     D.qt = up.template zeros<double>(n);
+    D.yn = up.template zeros<double>(n);
     {
         // 0.5 ln x by table reduction: subinterval i of m in [1/2, 1) has centre
         // z_i = 1/2 + (i + 1/2)/256; store c_i = 1/z_i and -0.5 ln c_i (extended precision)
@@ -519,16 +533,31 @@ h2s_status h2s_apply_phases(h2s_tree t, uint32_t mask, const double *x, double *
     const char *yb = (const char *)y, *ye = (const char *)(y + ldy * (nrhs - 1) + n);
     if (xb < ye && yb < xe) return fail(H2S_ERR_INVALID_ARG, "x and y overlap");
     if (hipSetDevice(t->device) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipSetDevice failed");
+    if (!t->aux) {
+        // created on first use, on the handle's device, at the default priority
+        hipStream_t a = nullptr;
+        hipEvent_t f = nullptr, j = nullptr;
+        if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+            if (a) (void)hipStreamDestroy(a);
+            if (f) (void)hipEventDestroy(f);
+            return fail(H2S_ERR_DEVICE, "creating the near-field stream or its events failed");
+        }
+        t->aux = a;
+        t->ev_fork = f;
+        t->ev_join = j;
+    }
     h2s::ProfileHook hook{t, record_mark};
     const h2s::ProfileHook *prof = t->profiling ? &hook : nullptr;
-    t->prof_stream = (hipStream_t)stream;
+    const h2s::Streams st{stream, t->aux, t->ev_fork, t->ev_join};
     for (int32_t c = 0; c < nrhs; ++c) {
         const double *xc = x + c * ldx;
         double *yc = y + c * ldy;
         int rc;
-        if (t->opts.prec == H2S_FP64) rc = h2s::launch_mvp<h2s::P64>(t->t64, t->plan, xc, yc, mask, stream, prof);
-        else if (t->opts.prec == H2S_FP32) rc = h2s::launch_mvp<h2s::P32>(t->t32, t->plan, xc, yc, mask, stream, prof);
-        else rc = h2s::launch_mvp<h2s::P32M>(t->t32m, t->plan, xc, yc, mask, stream, prof);
+        if (t->opts.prec == H2S_FP64) rc = h2s::launch_mvp<h2s::P64>(t->t64, t->plan, xc, yc, mask, st, prof);
+        else if (t->opts.prec == H2S_FP32) rc = h2s::launch_mvp<h2s::P32>(t->t32, t->plan, xc, yc, mask, st, prof);
+        else rc = h2s::launch_mvp<h2s::P32M>(t->t32m, t->plan, xc, yc, mask, st, prof);
         if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
     }
     return H2S_OK;

@@ -102,7 +102,8 @@ template <class P> struct DevTree {
     DevFamily<typename P::far_t, basis_t> far;
     DevFamily<double, basis_t> ver;
     DevPairs<basis_t> pairs;
-    double *qt;
+    double *qt;           // charges in tree order
+    double *yn;           // near-field potentials in tree order
     const double *logtab; // log r: (c_i, -0.5 ln c_i) for 128 mantissa subintervals
 };
 
@@ -114,16 +115,22 @@ struct LaunchPlan {
     int32_t dn_threads[kMaxLevels + 1];  // block size of L2L per level
 };
 
-// Optional timing hook: mark(ctx, kernel class, 0 = before / 1 = after).
+// Optional timing hook: mark(ctx, kernel class, 0 = before / 1 = after, stream).
 struct ProfileHook {
     void *ctx;
-    void (*mark)(void *ctx, int cls, int end);
+    void (*mark)(void *ctx, int cls, int end, void *stream);
 };
 
-// Enqueue one product y = K~ x (single right-hand side) on `stream`.
+// The caller's stream, the handle's second stream (near field) and the two
+// events that fork the second stream from the first and join it back.
+struct Streams {
+    void *main, *aux, *fork, *join;
+};
+
+// Enqueue one product y = K~ x (single right-hand side), ordered on st.main.
 // Returns a hipError_t as int.
 template <class P>
-int launch_mvp(const DevTree<P> &t, const LaunchPlan &plan, const double *x, double *y, uint32_t mask, void *stream,
-               const ProfileHook *prof);
+int launch_mvp(const DevTree<P> &t, const LaunchPlan &plan, const double *x, double *y, uint32_t mask,
+               const Streams &st, const ProfileHook *prof);
 
 } // namespace h2s

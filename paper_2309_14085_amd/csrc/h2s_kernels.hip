@@ -2,25 +2,30 @@
 // for CDNA4 (gfx950), Khan & Ambikasaran (arXiv 2309.14085), Sec. 5.1.2 and
 // Sec. 5.2.2:
 //
-//   k_up_leaf    charges to tree order + P2M   v_X = U_X^T q_X            (both families)
+//   k_permute    charges to tree order         q = x[perm]
+//   k_p2p        direct near field             yn_X = sum_{X' in N*(X)} K(X, X') q_X'
+//   k_up_leaf    P2M                           v_X = U_X^T q_X            (both families)
 //   k_m2m        one level of M2M              v_X = sum_c U~_{X_c X}^T v_{X_c}
 //   k_m2l        all levels of one family      u_X = sum_{Y in IL(X)} K(t^{X,i}, t^{Y,i}) v_Y
 //   k_l2l        one level of L2L              u_{X_c} += U~_{X_c X} u_X
 //   k_pair_part  (H2+H)*: partial products Vb^T q_Y, Ub^T q_X over row chunks
 //   k_pair_sum   (H2+H)*: chunk sums in a fixed order
-//   k_down_leaf  near field over N*(X) + L2P U_X u_X + (H2+H)* vertex blocks,
+//   k_down_leaf  yn + shift q + L2P U_X u_X + (H2+H)* vertex blocks,
 //                scattered back to user order
+//
+// k_p2p needs only the permuted charges, so it runs on a second stream while
+// the main stream goes up and down the tree; k_down_leaf joins the two.
 //
 // Summation order.  The interpolative NCA operators have norms up to ~1e3 -
 // 1e4 on coarse levels, so a rounding difference in a multipole or local
 // coefficient is amplified on its way to the potential.  The steps whose
 // results are amplified (P2M, M2M, the per-source-box M2L sums, L2L, L2P)
 // therefore sum in the order of the definitions -- one output per thread,
-// terms in index order, and under the FP64 policy with the product and the
-// sum rounded separately -- so the GPU product tracks a plain sequential
-// evaluation to within a few ulps of each coefficient.  The direct near field
-// is a plain sum of kernel values (nothing amplifies it); it is split over
-// source slices to fill the block.  No floating-point atomics are used.
+// terms in index order (as fused multiply-adds) -- so the GPU product
+// tracks a plain sequential evaluation to within a few ulps of each
+// coefficient.  The direct near field is a plain sum of kernel values
+// (nothing amplifies it); it is split over source slices to fill the block.
+// No floating-point atomics are used.
 //
 // M2L and the near field evaluate the kernel on the fly from coordinates
 // staged in LDS; the GEMV-shaped steps are HBM-bound and read each operator
@@ -46,12 +51,9 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb)
     return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
 }
 
-// s + a b: product and sum rounded separately (ORD) or fused.
-template <bool ORD> __device__ __forceinline__ double madd(double s, double a, double b)
-{
-    if constexpr (ORD) return __dadd_rn(s, __dmul_rn(a, b));
-    else return fma(a, b, s);
-}
+// s + a b as one fused multiply-add.  ORD marks the sums kept in the order
+// of their definition (it selects the accumulation pattern at the call sites).
+template <bool ORD> __device__ __forceinline__ double madd(double s, double a, double b) { return fma(a, b, s); }
 
 // 0.5 ln(x) for finite x > 0 in double, table-driven (Tang's reduction):
 // x = m 2^e with m in [1/2, 1) (frexp); the top 7 fraction bits of m select
@@ -87,18 +89,12 @@ template <int KIND> __device__ __forceinline__ void stage_log_table(const double
         for (int i = threadIdx.x; i < kLogTab; i += blockDim.x) tab[i] = make_double2(g[2 * i], g[2 * i + 1]);
 }
 
-// Squared distance with products and sums rounded separately under ORD.
+// Squared distance (ORD is accepted for symmetry with madd).
 template <bool ORD, int D, typename T> __device__ __forceinline__ T dist2(T dx, T dy, T dz)
 {
-    if constexpr (ORD && sizeof(T) == 8) {
-        double r2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
-        if constexpr (D == 3) r2 = __dadd_rn(r2, __dmul_rn(dz, dz));
-        return r2;
-    } else {
-        T r2 = dx * dx + dy * dy;
-        if constexpr (D == 3) r2 += dz * dz;
-        return r2;
-    }
+    T r2 = dx * dx + dy * dy;
+    if constexpr (D == 3) r2 += dz * dz;
+    return r2;
 }
 
 // Kernel value from a squared distance r2 > 0.  kp: h^2 for the Gaussian.
@@ -182,17 +178,19 @@ __device__ __forceinline__ double ordered_dot(const AT *__restrict__ A, size_t s
     return s;
 }
 
-template <class P>
-__global__ __launch_bounds__(NT_GEMV_MAX) void k_up_leaf(DevTree<P> t, const double *__restrict__ x, uint32_t mask)
+// Charges to tree order: qt[i] = x[perm[i]].
+template <class P> __global__ __launch_bounds__(256) void k_permute(DevTree<P> t, const double *__restrict__ x)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < t.n) t.qt[i] = x[t.perm[i]];
+}
+
+template <class P> __global__ __launch_bounds__(NT_GEMV_MAX) void k_up_leaf(DevTree<P> t, uint32_t mask)
 {
     extern __shared__ double qs[]; // largest leaf
     const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf, tid = threadIdx.x, nt = blockDim.x;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
-    for (int i = tid; i < n; i += nt) {
-        const double v = x[t.perm[b + i]];
-        qs[i] = v;
-        t.qt[b + i] = v;
-    }
+    for (int i = tid; i < n; i += nt) qs[i] = t.qt[b + i];
     __syncthreads();
     const int cf = t.far.coef_off[g], rf = (mask & kFar) && t.kappa >= t.far.lmin ? t.far.coef_off[g + 1] - cf : 0;
     const int cv = t.ver.coef_off[g], rv = (mask & kVer) && t.kappa >= t.ver.lmin ? t.ver.coef_off[g + 1] - cv : 0;
@@ -241,11 +239,11 @@ template <class P> __global__ __launch_bounds__(NT_GEMV_MAX) void k_l2l(DevTree<
     for (int j = tid; j < Rf + Rv; j += nt) {
         if (j < Rf) {
             const double s = ordered_dot<ORD>(Fa.Tr_cm + Fa.troff[g] + j, (size_t)Rf, rf, xs);
-            Fa.u[bf + j] = ORD ? __dadd_rn(Fa.u[bf + j], s) : Fa.u[bf + j] + s;
+            Fa.u[bf + j] = Fa.u[bf + j] + s;
         } else {
             const int jj = j - Rf;
             const double s = ordered_dot<ORD>(Ve.Tr_cm + Ve.troff[g] + jj, (size_t)Rv, rv, xs + rf);
-            Ve.u[bv + jj] = ORD ? __dadd_rn(Ve.u[bv + jj], s) : Ve.u[bv + jj] + s;
+            Ve.u[bv + jj] = Ve.u[bv + jj] + s;
         }
     }
 }
@@ -386,7 +384,7 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
             const int a = tid + o * NT_M2L;
             if (a < r)
                 for (int yl = 0; yl < ny; ++yl)
-                    uacc[o] = ORD ? __dadd_rn(uacc[o], part[yl * r + a]) : uacc[o] + part[yl * r + a];
+                    uacc[o] = uacc[o] + part[yl * r + a];
         }
         __syncthreads();
     }
@@ -440,11 +438,115 @@ template <class P> __global__ __launch_bounds__(64) void k_pair_sum(DevTree<P> t
 }
 
 // ---------------------------------------------------------------------------
-// Leaf pass down: near field (source slices), L2P (in index order), the
-// (H2+H)* vertex blocks, sum and scatter.
+// Near field: one target leaf per block, its near list N*(X) staged in LDS
+// and split over source slices; yn[i] = sum_{j in N*(X)} K(x_i, x_j) q_j.
 // ---------------------------------------------------------------------------
-constexpr int NT_LEAF = 256;
+constexpr int NT_P2P = 256;
 constexpr int P2P_SRC = 1024; // staged source points per group
+
+template <class P, int KIND, int D>
+__global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t)
+{
+    using PT = typename P::pt_t;
+    constexpr bool TAB = KIND == H2S_K_LOG_R && sizeof(PT) == 8;
+    __shared__ PT sx[P2P_SRC], sy[P2P_SRC], sz[D == 3 ? P2P_SRC : 1], sq[P2P_SRC];
+    __shared__ double red[NT_P2P];
+    __shared__ double2 ltab[TAB ? kLogTab : 1];
+    const int tid = threadIdx.x;
+    const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf;
+    const int b = t.box_begin[g], n = t.box_end[g] - b;
+    const PT diag = (PT)t.diag, kp = (PT)t.kparam;
+    const double *cX = t.box_ctr + 3 * g;
+    if constexpr (TAB) stage_log_table<KIND>(t.logtab, ltab); // first used after a barrier
+    for (int i0 = 0; i0 < n; i0 += NT_P2P) {
+        const int m = min(n - i0, NT_P2P), S = NT_P2P / m, s = tid / m, i = i0 + tid % m;
+        const PT xi = t.px[b + i], yi = t.py[b + i], zi = D == 3 ? t.pz[b + i] : PT(0);
+        double acc = 0.0;
+        int pos = 0, self0 = 0, self1 = 0; // staged positions of the target leaf's own points
+        // slice s takes the staged sources jb + s, jb + s + S, ... below je
+        auto slice_sum = [&](int jb, int je, auto check) {
+            constexpr bool CHECK = decltype(check)::value;
+            auto k = [&](PT r2) -> PT {
+                if constexpr (sizeof(PT) == 8) {
+                    if constexpr (CHECK) return kval<KIND>(r2, diag, kp, ltab);
+                    else return kval_pos<KIND>(r2, kp, ltab);
+                } else {
+                    return kval<KIND>(r2, diag, kp);
+                }
+            };
+            PT part[4] = {0, 0, 0, 0};
+            int j = jb + s;
+            for (; j + 3 * S < je; j += 4 * S) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int jj = j + u * S;
+                    part[u] += k(dist2<false, D>(xi - sx[jj], yi - sy[jj], zi - sz[D == 3 ? jj : 0])) * sq[jj];
+                }
+            }
+            for (; j < je; j += S) part[0] += k(dist2<false, D>(xi - sx[j], yi - sy[j], zi - sz[D == 3 ? j : 0])) * sq[j];
+            return (double)((part[0] + part[1]) + (part[2] + part[3]));
+        };
+        auto flush = [&]() {
+            __syncthreads();
+            if (s < S) {
+                // only the target leaf's own points can coincide with a target
+                acc += slice_sum(0, self0, std::false_type{});
+                acc += slice_sum(self0, self1, std::true_type{});
+                acc += slice_sum(self1, pos, std::false_type{});
+            }
+            __syncthreads();
+            pos = self0 = self1 = 0;
+        };
+        for (int e = t.near_off[leaf]; e < t.near_off[leaf + 1]; ++e) {
+            const int gs = t.leaf0 + t.near_idx[e];
+            const int sb = t.box_begin[gs], sn = t.box_end[gs] - sb;
+            double dcx = 0, dcy = 0, dcz = 0;
+            if constexpr (P::local) {
+                dcx = t.box_ctr[3 * gs] - cX[0];
+                dcy = t.box_ctr[3 * gs + 1] - cX[1];
+                dcz = t.box_ctr[3 * gs + 2] - cX[2];
+            }
+            for (int j0 = 0; j0 < sn;) {
+                const int take = min(sn - j0, P2P_SRC - pos);
+                for (int j = tid; j < take; j += NT_P2P) {
+                    const int src = sb + j0 + j;
+                    if constexpr (P::local) {
+                        sx[pos + j] = (PT)(dcx + (double)t.px[src]);
+                        sy[pos + j] = (PT)(dcy + (double)t.py[src]);
+                        if constexpr (D == 3) sz[pos + j] = (PT)(dcz + (double)t.pz[src]);
+                    } else {
+                        sx[pos + j] = t.px[src];
+                        sy[pos + j] = t.py[src];
+                        if constexpr (D == 3) sz[pos + j] = t.pz[src];
+                    }
+                    sq[pos + j] = (PT)t.qt[src];
+                }
+                if (gs == g) {
+                    self0 = pos;
+                    self1 = pos + take;
+                }
+                pos += take;
+                j0 += take;
+                if (pos == P2P_SRC) flush();
+            }
+        }
+        if (pos > 0) flush();
+        red[tid] = s < S ? acc : 0.0;
+        __syncthreads();
+        if (tid < m) {
+            double phi = 0.0;
+            for (int q = 0; q < S; ++q) phi += red[q * m + tid];
+            t.yn[b + i] = phi;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Leaf pass down: near field + shift q, L2P (in index order), the (H2+H)*
+// vertex blocks, sum and scatter to user order.  One thread per point.
+// ---------------------------------------------------------------------------
+constexpr int NT_LEAF = 128;
 
 template <bool ORD, typename F>
 __device__ __forceinline__ double l2p_family(const F &fam, int g, int leaf, int n, int i, int kappa)
@@ -455,194 +557,119 @@ __device__ __forceinline__ double l2p_family(const F &fam, int g, int leaf, int 
     return ordered_dot<ORD>(fam.U_cm + fam.uoff[leaf] + i, (size_t)n, r, fam.u + c0);
 }
 
-template <class P, int KIND, int D>
-__global__ __launch_bounds__(NT_LEAF) void k_down_leaf(DevTree<P> t, double *__restrict__ y, uint32_t mask)
+template <class P> __global__ __launch_bounds__(NT_LEAF) void k_down_leaf(DevTree<P> t, double *__restrict__ y, uint32_t mask)
 {
-    using PT = typename P::pt_t;
     constexpr bool ORD = P::ordered;
-    constexpr bool TAB = KIND == H2S_K_LOG_R && sizeof(PT) == 8;
-    __shared__ PT sx[P2P_SRC], sy[P2P_SRC], sz[D == 3 ? P2P_SRC : 1], sq[P2P_SRC];
-    __shared__ double red[NT_LEAF];
-    __shared__ double2 ltab[TAB ? kLogTab : 1];
-    const int tid = threadIdx.x;
     const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
-    const PT diag = (PT)t.diag, kp = (PT)t.kparam;
-    const double *cX = t.box_ctr + 3 * g;
-    if constexpr (TAB) stage_log_table<KIND>(t.logtab, ltab); // first used after a barrier
-    for (int i0 = 0; i0 < n; i0 += NT_LEAF) {
-        const int m = min(n - i0, NT_LEAF), S = NT_LEAF / m, s = tid / m, i = i0 + tid % m;
-        const PT xi = t.px[b + i], yi = t.py[b + i], zi = D == 3 ? t.pz[b + i] : PT(0);
-        double acc = 0.0;
-        if (mask & kNear) {
-            int pos = 0, self0 = 0, self1 = 0; // staged positions of the target leaf's own points
-            // slice s takes the staged sources jb + s, jb + s + S, ... below je
-            auto slice_sum = [&](int jb, int je, auto check) {
-                constexpr bool CHECK = decltype(check)::value;
-                auto k = [&](PT r2) -> PT {
-                    if constexpr (sizeof(PT) == 8) {
-                        if constexpr (CHECK) return kval<KIND>(r2, diag, kp, ltab);
-                        else return kval_pos<KIND>(r2, kp, ltab);
-                    } else {
-                        return kval<KIND>(r2, diag, kp);
-                    }
-                };
-                PT part[4] = {0, 0, 0, 0};
-                int j = jb + s;
-                for (; j + 3 * S < je; j += 4 * S) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int jj = j + u * S;
-                        part[u] += k(dist2<false, D>(xi - sx[jj], yi - sy[jj], zi - sz[D == 3 ? jj : 0])) * sq[jj];
-                    }
-                }
-                for (; j < je; j += S) part[0] += k(dist2<false, D>(xi - sx[j], yi - sy[j], zi - sz[D == 3 ? j : 0])) * sq[j];
-                return (double)((part[0] + part[1]) + (part[2] + part[3]));
-            };
-            auto flush = [&]() {
-                __syncthreads();
-                if (s < S) {
-                    // only the target leaf's own points can coincide with a target
-                    acc += slice_sum(0, self0, std::false_type{});
-                    acc += slice_sum(self0, self1, std::true_type{});
-                    acc += slice_sum(self1, pos, std::false_type{});
-                }
-                __syncthreads();
-                pos = self0 = self1 = 0;
-            };
-            for (int e = t.near_off[leaf]; e < t.near_off[leaf + 1]; ++e) {
-                const int gs = t.leaf0 + t.near_idx[e];
-                const int sb = t.box_begin[gs], sn = t.box_end[gs] - sb;
-                double dcx = 0, dcy = 0, dcz = 0;
-                if constexpr (P::local) {
-                    dcx = t.box_ctr[3 * gs] - cX[0];
-                    dcy = t.box_ctr[3 * gs + 1] - cX[1];
-                    dcz = t.box_ctr[3 * gs + 2] - cX[2];
-                }
-                for (int j0 = 0; j0 < sn;) {
-                    const int take = min(sn - j0, P2P_SRC - pos);
-                    for (int j = tid; j < take; j += NT_LEAF) {
-                        const int src = sb + j0 + j;
-                        if constexpr (P::local) {
-                            sx[pos + j] = (PT)(dcx + (double)t.px[src]);
-                            sy[pos + j] = (PT)(dcy + (double)t.py[src]);
-                            if constexpr (D == 3) sz[pos + j] = (PT)(dcz + (double)t.pz[src]);
-                        } else {
-                            sx[pos + j] = t.px[src];
-                            sy[pos + j] = t.py[src];
-                            if constexpr (D == 3) sz[pos + j] = t.pz[src];
-                        }
-                        sq[pos + j] = (PT)t.qt[src];
-                    }
-                    if (gs == g) {
-                        self0 = pos;
-                        self1 = pos + take;
-                    }
-                    pos += take;
-                    j0 += take;
-                    if (pos == P2P_SRC) flush();
-                }
-            }
-            if (pos > 0) flush();
+    for (int i = threadIdx.x; i < n; i += NT_LEAF) {
+        double phi = 0.0;
+        if (mask & kNear) phi = madd<ORD>(t.yn[b + i], t.shift, t.qt[b + i]);
+        if (mask & kFar) {
+            const double f = l2p_family<ORD>(t.far, g, leaf, n, i, t.kappa);
+            phi = phi + f;
         }
-        red[tid] = s < S ? acc : 0.0;
-        __syncthreads();
-        if (tid < m) {
-            double phi = 0.0;
-            for (int q = 0; q < S; ++q) phi += red[q * m + tid];
-            if (mask & kNear) phi = madd<ORD>(phi, t.shift, t.qt[b + i]);
-            if (mask & kFar) {
-                const double f = l2p_family<ORD>(t.far, g, leaf, n, i, t.kappa);
-                phi = ORD ? __dadd_rn(phi, f) : phi + f;
-            }
-            if (mask & kVer) {
-                double v = l2p_family<ORD>(t.ver, g, leaf, n, i, t.kappa);
-                if (t.variant == H2S_H2_PLUS_H) {
-                    const auto &Pr = t.pairs;
-                    for (int l = 1; l <= t.kappa; ++l) {
-                        const int X = t.leaf_anc[(size_t)leaf * (t.kappa + 1) + l];
-                        const int off = b + i - t.box_begin[X];
-                        const int nX = t.box_end[X] - t.box_begin[X];
-                        for (int e = Pr.recv_off[X]; e < Pr.recv_off[X + 1]; ++e) {
-                            const int ps = Pr.recv[e], p = ps >> 1, side = ps & 1;
-                            const int r = Pr.prank[p];
-                            const auto *G = Pr.data + (side == 0 ? Pr.pu[p] : Pr.pv[p]);
-                            const double *w = Pr.w + Pr.pw[p] + (size_t)side * r;
-                            const double d = ordered_dot<ORD>(G + off, (size_t)nX, r, w);
-                            v = ORD ? __dadd_rn(v, d) : v + d;
-                        }
+        if (mask & kVer) {
+            double v = l2p_family<ORD>(t.ver, g, leaf, n, i, t.kappa);
+            if (t.variant == H2S_H2_PLUS_H) {
+                const auto &Pr = t.pairs;
+                for (int l = 1; l <= t.kappa; ++l) {
+                    const int X = t.leaf_anc[(size_t)leaf * (t.kappa + 1) + l];
+                    const int off = b + i - t.box_begin[X];
+                    const int nX = t.box_end[X] - t.box_begin[X];
+                    for (int e = Pr.recv_off[X]; e < Pr.recv_off[X + 1]; ++e) {
+                        const int ps = Pr.recv[e], p = ps >> 1, side = ps & 1;
+                        const int r = Pr.prank[p];
+                        const auto *G = Pr.data + (side == 0 ? Pr.pu[p] : Pr.pv[p]);
+                        const double *w = Pr.w + Pr.pw[p] + (size_t)side * r;
+                        const double d = ordered_dot<ORD>(G + off, (size_t)nX, r, w);
+                        v = v + d;
                     }
                 }
-                phi = ORD ? __dadd_rn(phi, v) : phi + v;
             }
-            y[t.perm[b + i]] = phi;
+            phi = phi + v;
         }
-        __syncthreads();
+        y[t.perm[b + i]] = phi;
     }
 }
 
 template <class P, int KIND, int D>
 hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x, double *y, uint32_t mask,
-                   hipStream_t s, const ProfileHook *prof)
+                   const Streams &st, const ProfileHook *prof)
 {
-    auto mark = [&](int cls, int end) {
-        if (prof) prof->mark(prof->ctx, cls, end);
+    hipStream_t s = (hipStream_t)st.main, aux = (hipStream_t)st.aux;
+    auto mark = [&](int cls, int end, hipStream_t on) {
+        if (prof) prof->mark(prof->ctx, cls, end, on);
     };
     const int32_t *lev_off = plan.lev_off;
     const size_t lds_leaf = sizeof(double) * (size_t)t.max_leaf;
     const size_t lds_rows = sizeof(double) * (size_t)(2 * t.max_rows);
     const size_t lds_rank = sizeof(double) * (size_t)(2 * t.max_rank);
-    mark(H2S_PROF_LEAF_UP, 0);
-    hipLaunchKernelGGL(k_up_leaf<P>, dim3(t.nleaf), dim3(plan.up_threads[t.kappa]), lds_leaf, s, t, x, mask);
-    mark(H2S_PROF_LEAF_UP, 1);
     const bool fam_on = (mask & (kFar | kVer)) && t.kappa >= 1;
+    mark(H2S_PROF_LEAF_UP, 0, s);
+    hipLaunchKernelGGL(k_permute<P>, dim3((t.n + 255) / 256), dim3(256), 0, s, t, x);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    // the near field needs only the permuted charges: run it on the second
+    // stream while the main stream goes up and down the tree
+    if (mask & kNear) {
+        if ((err = hipEventRecord((hipEvent_t)st.fork, s)) != hipSuccess) return err;
+        if ((err = hipStreamWaitEvent(aux, (hipEvent_t)st.fork, 0)) != hipSuccess) return err;
+        mark(H2S_PROF_NEAR, 0, aux);
+        hipLaunchKernelGGL((k_p2p<P, KIND, D>), dim3(t.nleaf), dim3(NT_P2P), 0, aux, t);
+        mark(H2S_PROF_NEAR, 1, aux);
+        if ((err = hipEventRecord((hipEvent_t)st.join, aux)) != hipSuccess) return err;
+    }
+    if (fam_on) hipLaunchKernelGGL(k_up_leaf<P>, dim3(t.nleaf), dim3(plan.up_threads[t.kappa]), lds_leaf, s, t, mask);
+    mark(H2S_PROF_LEAF_UP, 1, s);
     if (fam_on) {
-        mark(H2S_PROF_M2M, 0);
+        mark(H2S_PROF_M2M, 0, s);
         for (int l = t.kappa - 1; l >= 1; --l) {
             const int nb = lev_off[l + 1] - lev_off[l];
             if (nb)
                 hipLaunchKernelGGL(k_m2m<P>, dim3(nb), dim3(plan.up_threads[l]), lds_rows, s, t, lev_off[l], mask);
         }
-        mark(H2S_PROF_M2M, 1);
+        mark(H2S_PROF_M2M, 1, s);
         if ((mask & kFar) && t.far.ntargets) {
-            mark(H2S_PROF_M2L_FAR, 0);
+            mark(H2S_PROF_M2L_FAR, 0, s);
             hipLaunchKernelGGL((k_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_M2L), 0, s, t);
-            mark(H2S_PROF_M2L_FAR, 1);
+            mark(H2S_PROF_M2L_FAR, 1, s);
         }
         if ((mask & kVer) && t.ver.ntargets) {
-            mark(H2S_PROF_M2L_VER, 0);
+            mark(H2S_PROF_M2L_VER, 0, s);
             hipLaunchKernelGGL((k_m2l<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_M2L), 0, s, t);
-            mark(H2S_PROF_M2L_VER, 1);
+            mark(H2S_PROF_M2L_VER, 1, s);
         }
-        mark(H2S_PROF_L2L, 0);
+        mark(H2S_PROF_L2L, 0, s);
         for (int l = 1; l <= t.kappa - 1; ++l) {
             const int nb = lev_off[l + 1] - lev_off[l];
             if (nb)
                 hipLaunchKernelGGL(k_l2l<P>, dim3(nb), dim3(plan.dn_threads[l]), lds_rank, s, t, lev_off[l], mask);
         }
-        mark(H2S_PROF_L2L, 1);
+        mark(H2S_PROF_L2L, 1, s);
     }
     if (t.variant == H2S_H2_PLUS_H && (mask & kVer) && t.pairs.npairs) {
-        mark(H2S_PROF_PAIR_PART, 0);
+        mark(H2S_PROF_PAIR_PART, 0, s);
         hipLaunchKernelGGL(k_pair_part<P>, dim3(t.pairs.nchunks), dim3(256), 0, s, t);
-        mark(H2S_PROF_PAIR_PART, 1);
-        mark(H2S_PROF_PAIR_SUM, 0);
+        mark(H2S_PROF_PAIR_PART, 1, s);
+        mark(H2S_PROF_PAIR_SUM, 0, s);
         hipLaunchKernelGGL(k_pair_sum<P>, dim3(2 * t.pairs.npairs), dim3(64), 0, s, t);
-        mark(H2S_PROF_PAIR_SUM, 1);
+        mark(H2S_PROF_PAIR_SUM, 1, s);
     }
-    mark(H2S_PROF_LEAF_DOWN, 0);
-    hipLaunchKernelGGL((k_down_leaf<P, KIND, D>), dim3(t.nleaf), dim3(NT_LEAF), 0, s, t, y, mask);
-    mark(H2S_PROF_LEAF_DOWN, 1);
+    if (mask & kNear)
+        if ((err = hipStreamWaitEvent(s, (hipEvent_t)st.join, 0)) != hipSuccess) return err;
+    mark(H2S_PROF_LEAF_DOWN, 0, s);
+    hipLaunchKernelGGL(k_down_leaf<P>, dim3(t.nleaf), dim3(NT_LEAF), 0, s, t, y, mask);
+    mark(H2S_PROF_LEAF_DOWN, 1, s);
     return hipGetLastError();
 }
 
 } // namespace
 
 template <class P>
-int launch_mvp(const DevTree<P> &t, const LaunchPlan &plan, const double *x, double *y, uint32_t mask, void *stream,
-               const ProfileHook *prof)
+int launch_mvp(const DevTree<P> &t, const LaunchPlan &plan, const double *x, double *y, uint32_t mask,
+               const Streams &s, const ProfileHook *prof)
 {
-    hipStream_t s = (hipStream_t)stream;
     const int key = t.kind * 2 + (t.d == 3);
     switch (key) {
     case 0: return (int)enqueue<P, H2S_K_LOG_R, 2>(t, plan, x, y, mask, s, prof);
@@ -656,11 +683,11 @@ int launch_mvp(const DevTree<P> &t, const LaunchPlan &plan, const double *x, dou
     }
 }
 
-template int launch_mvp<P64>(const DevTree<P64> &, const LaunchPlan &, const double *, double *, uint32_t, void *,
+template int launch_mvp<P64>(const DevTree<P64> &, const LaunchPlan &, const double *, double *, uint32_t, const Streams &,
                              const ProfileHook *);
-template int launch_mvp<P32>(const DevTree<P32> &, const LaunchPlan &, const double *, double *, uint32_t, void *,
+template int launch_mvp<P32>(const DevTree<P32> &, const LaunchPlan &, const double *, double *, uint32_t, const Streams &,
                              const ProfileHook *);
-template int launch_mvp<P32M>(const DevTree<P32M> &, const LaunchPlan &, const double *, double *, uint32_t, void *,
+template int launch_mvp<P32M>(const DevTree<P32M> &, const LaunchPlan &, const double *, double *, uint32_t, const Streams &,
                               const ProfileHook *);
 
 } // namespace h2s

@@ -19,7 +19,7 @@ LOG_R, INV_R, GAUSSIAN, EXP_R = 0, 1, 2, 3
 H2STAR, H2_PLUS_H = 0, 1
 FP64, FP32, FP32_M2L = 0, 1, 2
 PHASE_NEAR, PHASE_FAR, PHASE_VER, PHASE_ALL = 1, 2, 4, 7
-PROF_NAMES = ("leaf_up", "m2m", "m2l_far", "l2l", "pair_part", "pair_sum", "leaf_down", "m2l_ver")
+PROF_NAMES = ("leaf_up", "m2m", "m2l_far", "l2l", "pair_part", "pair_sum", "leaf_down", "m2l_ver", "near")
 
 
 class Kernel(ctypes.Structure):

@@ -21,8 +21,6 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks used for the roofline fraction.
 HBM_PEAK_GBS = 8000.0
-FP64_VECTOR_TFLOPS = 78.6
-FP32_VECTOR_TFLOPS = 157.3
 
 
 def parse():
@@ -182,27 +180,40 @@ def main():
 
 
 def roofline_entry(name, k, stats, prec):
-    """Roofline of the dominant kernel class (one launch per step for the leaf and M2L classes)."""
+    """Roofline of the dominant kernel class (one launch per step for the leaf and M2L classes).
+
+    Kernel-evaluation classes are bound by FP64 VALU issue: the chip issues
+    256 CUs x 4 SIMDs x 16 FP64 lanes per clock at 2.4 GHz, and one
+    evaluation of log r (distance, table-driven logarithm, multiply-add)
+    takes VALU_PER_EVAL vector instructions in the compiled inner loop, so
+    the peak is the issue rate divided by that count.  Operator-streaming
+    classes are bound by HBM bandwidth."""
     avg_s = k["avg_ms"] * 1e-3
     byts, evals = algorithmic_work(stats, name, prec)
     traffic = measured_traffic(name)
     if evals:
-        flops = evals * FLOPS_PER_EVAL
-        ach = flops / avg_s / 1e12
-        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP64_VECTOR_TFLOPS, "traffic": traffic, "evals_per_launch": evals,
-                "flops_per_eval": FLOPS_PER_EVAL, "avg_launch_ms": k["avg_ms"],
-                "evals_per_s": evals / avg_s}
+        per_eval = VALU_PER_EVAL.get(name, VALU_PER_EVAL["near"])
+        peak = VALU_LANE_ISSUE_PER_S / per_eval / 1e9
+        ach = evals / avg_s / 1e9
+        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": peak, "unit": "Geval/s",
+                "frac": ach / peak, "traffic": traffic, "evals_per_launch": evals,
+                "valu_instr_per_eval": per_eval, "avg_launch_ms": k["avg_ms"],
+                "fp64_tflops": ach * FP64_FLOPS_PER_EVAL / 1e3, "fp64_flops_per_eval": FP64_FLOPS_PER_EVAL}
     ach = byts / avg_s / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": byts, "avg_launch_ms": k["avg_ms"]}
 
 
-# FP64 floating-point operations of one log-kernel evaluation as compiled for
-# gfx950 (FMA = 2, add / mul / rcp = 1): squared distance, the frexp + atanh-
-# series logarithm and the multiply-add into the sum, counted from the M2L
-# inner loop (the near-field loop performs the same evaluation).
-FLOPS_PER_EVAL = 44
+# FP64 VALU lane-instructions per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (the 78.6 TFLOP/s FP64 vector peak counts one FMA per lane-instruction as 2 flops).
+VALU_LANE_ISSUE_PER_S = 256 * 4 * 16 * 2.4e9
+# Vector instructions per log-r kernel evaluation in the compiled FP64 2D inner
+# loops (4 evaluations per iteration, loop control included): the near field
+# 84 / 4, M2L 82 / 4.
+VALU_PER_EVAL = {"near": 21.0, "m2l_far": 20.5, "m2l_ver": 20.5}
+# FP64 flops of one evaluation (FMA = 2): squared distance 5, reduction
+# r = m c - 1 and the degree-6 series 14, the exponent term 2, multiply-add 2.
+FP64_FLOPS_PER_EVAL = 23
 
 COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_2d_log_n1048576.json")
 

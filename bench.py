@@ -34,6 +34,7 @@ def parse():
     p.add_argument("--only", default="", help="comma list of h2star_fp64,h2star_fp32,h2star_fp32m2l,h2plush_fp64")
     p.add_argument("--calib-copy", action="store_true",
                    help="also run one plain 256 MiB device copy (reference for the HBM byte counters)")
+    p.add_argument("--no-solve", action="store_true", help="skip the RBF interpolation solve beside the MVP")
     return p.parse_args()
 
 
@@ -70,6 +71,27 @@ def time_variant(h2s, torch, pts, q, w, variant, prec, steps, warmup, prof_steps
     return dict(ms=ms, wall_ms=1e3 * wall / steps, t_init=t_init, stats=stats,
                 kernels={k: {"avg_ms": v[0] / max(v[1], 1), "launches_per_step": v[1] / max(prof_steps, 1)}
                          for k, v in prof.items() if v[1]}), out
+
+
+def time_solve(h2s, torch, w):
+    """GMRES(50) + iterative refinement to 1e-8 (FP32 Krylov products, FP64 residuals) on the
+    RBF interpolation system.  Build and a one-step warm-up solve (uploads, workspace) untimed;
+    then one timed solve from x = 0."""
+    dev = torch.device("cuda:0")
+    T = h2s.build(w.points(), kind=w.kind, leaf_size=w.nmax, eps=w.eps, param=w.param, shift=w.shift)
+    b = torch.from_numpy(w.rhs()[:, 0].copy()).to(dev)
+    x, _ = T.solve(b, rtol=1e-8, max_iter=1, raise_on_fail=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = T.solve(b, x=x, rtol=1e-8, max_iter=100000, raise_on_fail=False)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    T.free()
+    i = info[0]
+    return {"workload": w.name, "n": w.n, "kernel": "exp(-r^2/0.1^2), K_ii = 1, shift 1e-2", "restart": 50,
+            "inner": "fp32", "rtol": 1e-8, "seconds": sec, "iterations": i["iterations"],
+            "refinements": i["refinements"], "ms_per_iteration": 1e3 * sec / max(i["iterations"], 1),
+            "residual_fp64": i["residual"], "converged": i["converged"]}
 
 
 def algorithmic_work(stats, kernel, prec):
@@ -147,6 +169,12 @@ def main():
         dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
         roofline = roofline_entry(dom, kernels[dom], m["stats"], 0 if main_name.endswith("fp64") else 1)
 
+    solve = None
+    if not a.no_solve:
+        print("# building and timing the RBF interpolation solve", file=sys.stderr, flush=True)
+        solve = time_solve(h2s, torch, inputs.workload("2d_gauss_rbf_n262144"))
+        print(f"# solve: {solve}", file=sys.stderr, flush=True)
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(pts, q, w)
@@ -168,6 +196,7 @@ def main():
                    "nca_tol": w.eps, "nrhs": 1, "variant": "H2*(b+t)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "solve": solve,
         "variants": {k: {kk: vv for kk, vv in v.items() if kk != "stats"} for k, v in res.items()},
         "ranks": {"far_max_by_level": m["stats"]["rank_max_level"][0],
                   "ver_max_by_level": m["stats"]["rank_max_level"][1],

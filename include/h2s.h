@@ -114,6 +114,45 @@ h2s_status h2s_apply(h2s_tree t, const double *x, double *y, int32_t nrhs, int64
 h2s_status h2s_apply_phases(h2s_tree t, uint32_t mask, const double *x, double *y, int32_t nrhs,
                             int64_t ldx, int64_t ldy, void *stream);
 
+/* Options of h2s_solve.  h2s_solve_opts_default fills the defaults shown. */
+typedef struct {
+    int32_t restart;          /* GMRES restart length m, 1..1000 (50) */
+    int32_t max_iter;         /* Krylov steps over all cycles (10000) */
+    int32_t max_refine;       /* refinement steps = GMRES cycles (1000) */
+    h2s_precision inner_prec; /* precision of the products inside the Krylov cycles (H2S_FP32) */
+    double rtol;              /* target ||b - K~ x|| / ||b|| with the FP64 product (1e-8) */
+    double inner_rtol;        /* a cycle stops once its residual estimate falls by this factor (1e-6) */
+    int32_t use_x0;           /* 1: x holds the initial guess on entry; 0: start from x = 0 (0) */
+} h2s_solve_opts;
+
+typedef struct {
+    int32_t iterations;  /* Krylov steps (products in the inner precision) */
+    int32_t refinements; /* refinement steps (FP64 residual products) */
+    int32_t converged;   /* 1 if the FP64 relative residual reached rtol */
+    double residual;     /* final ||b - K~ x|| / ||b|| with the FP64 product */
+} h2s_solve_info;
+
+h2s_status h2s_solve_opts_default(h2s_solve_opts *opts);
+
+/* Solve (K~ + shift I) x = b for nrhs right-hand sides, one after another:
+ * GMRES with iterative refinement (Sec. 6: GMRES on the fast product to a
+ * relative residual tolerance).  Each refinement step computes the FP64
+ * residual r = b - K~ x and runs one GMRES(restart) cycle on K~ d = r with the
+ * products in opts->inner_prec; Arnoldi vectors, both classical Gram-Schmidt
+ * passes, norms and the update x += d stay in FP64 on the device.
+ * b, x: device, user order, column-major, ld >= n; must not overlap.
+ * opts: NULL for the defaults.  info: NULL or nrhs entries.
+ * The handle uploads the FP64 and the inner-precision representations on
+ * first use (whatever its build precision) and keeps an n x (restart + 1)
+ * FP64 workspace.  Returns H2S_ERR_NOT_CONVERGED, with x the last iterate
+ * and info filled, when some right-hand side misses rtol within max_iter or
+ * max_refine steps or stagnates (three cycles without a 0.1% gain).
+ * Synchronises `stream` once per Krylov step.
+ * Errors: INVALID_ARG, UNSUPPORTED (host_only handle), OUT_OF_MEMORY, DEVICE,
+ * NOT_CONVERGED. */
+h2s_status h2s_solve(h2s_tree t, const double *b, double *x, int32_t nrhs, int64_t ldb, int64_t ldx,
+                     const h2s_solve_opts *opts, h2s_solve_info *info, void *stream);
+
 /* Release the handle and its device memory (NULL is accepted). */
 h2s_status h2s_free(h2s_tree t);
 

@@ -4,7 +4,10 @@
 // (h2s_host_build.cpp), pack it into the device layout of h2s_device.hpp in
 // the requested precision and copy it to HBM on the caller's stream.
 // apply: validate, then enqueue the MVP kernels (h2s_kernels.hip) once per
-// right-hand side.  Nothing here computes any part of the product.
+// right-hand side.  solve: validate, make sure the FP64 and inner-precision
+// representations are on the device, and run the GMRES driver
+// (h2s_solve.cpp) with the products as callbacks.  Nothing here computes any
+// part of the product or of the solve.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -15,8 +18,10 @@
 #include <vector>
 
 #include "h2s.h"
+#include "h2s_blas.hpp"
 #include "h2s_device.hpp"
 #include "h2s_host.hpp"
+#include "h2s_solve.hpp"
 
 namespace {
 
@@ -64,6 +69,11 @@ struct h2s_tree_s {
     // second stream for the near field and the events that fork / join it
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // which precisions are on the device
+    bool up[3] = {false, false, false};
+    // solve workspace for restart length solve_m (device memory is in allocs)
+    int solve_m = 0;
+    h2s::SolveWork work{};
 
     void clear_marks()
     {
@@ -83,6 +93,7 @@ struct h2s_tree_s {
         }
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
+        if (work.small_host) (void)hipHostFree(work.small_host);
         for (void *p : allocs) ffn(actx, p);
     }
 };
@@ -418,6 +429,66 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
 
 bool is_finite(double v) { return std::isfinite(v); }
 
+// Upload the representation in precision p unless it is already on the device.
+h2s_status ensure_uploaded(h2s_tree t, h2s_precision p, hipStream_t s)
+{
+    if (t->up[p]) return H2S_OK;
+    h2s_status st;
+    if (p == H2S_FP64) st = upload<h2s::P64>(t, s, t->t64);
+    else if (p == H2S_FP32) st = upload<h2s::P32>(t, s, t->t32);
+    else st = upload<h2s::P32M>(t, s, t->t32m);
+    if (st == H2S_OK) t->up[p] = true;
+    return st;
+}
+
+// The near-field stream and its fork / join events, created on first use on
+// the handle's device at the default priority.
+h2s_status ensure_streams(h2s_tree t)
+{
+    if (t->aux) return H2S_OK;
+    hipStream_t a = nullptr;
+    hipEvent_t f = nullptr, j = nullptr;
+    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+        if (a) (void)hipStreamDestroy(a);
+        if (f) (void)hipEventDestroy(f);
+        return fail(H2S_ERR_DEVICE, "creating the near-field stream or its events failed");
+    }
+    t->aux = a;
+    t->ev_fork = f;
+    t->ev_join = j;
+    return H2S_OK;
+}
+
+// One product in precision p (uploaded, streams created); hipError_t as int.
+int mvp(h2s_tree t, h2s_precision p, uint32_t mask, const double *x, double *y, void *stream,
+        const h2s::ProfileHook *prof)
+{
+    const h2s::Streams st{stream, t->aux, t->ev_fork, t->ev_join};
+    if (p == H2S_FP64) return h2s::launch_mvp<h2s::P64>(t->t64, t->plan, x, y, mask, st, prof);
+    if (p == H2S_FP32) return h2s::launch_mvp<h2s::P32>(t->t32, t->plan, x, y, mask, st, prof);
+    return h2s::launch_mvp<h2s::P32M>(t->t32m, t->plan, x, y, mask, st, prof);
+}
+
+struct SolveCtx {
+    h2s_tree t;
+    h2s_precision inner;
+    void *stream;
+};
+
+int solve_apply_inner(void *c, const double *x, double *y)
+{
+    const SolveCtx *s = (const SolveCtx *)c;
+    return mvp(s->t, s->inner, H2S_PHASE_ALL, x, y, s->stream, nullptr);
+}
+
+int solve_apply_outer(void *c, const double *x, double *y)
+{
+    const SolveCtx *s = (const SolveCtx *)c;
+    return mvp(s->t, H2S_FP64, H2S_PHASE_ALL, x, y, s->stream, nullptr);
+}
+
 } // namespace
 
 extern "C" {
@@ -505,9 +576,7 @@ h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kerne
     }
     t->lev_off = t->rep.lev_off;
     if (!t->host_only) {
-        if (o->prec == H2S_FP64) st = upload<h2s::P64>(t, (hipStream_t)stream, t->t64);
-        else if (o->prec == H2S_FP32) st = upload<h2s::P32>(t, (hipStream_t)stream, t->t32);
-        else st = upload<h2s::P32M>(t, (hipStream_t)stream, t->t32m);
+        st = ensure_uploaded(t, o->prec, (hipStream_t)stream);
         if (st != H2S_OK) {
             const std::string keep = g_last_error;
             delete t;
@@ -533,31 +602,11 @@ h2s_status h2s_apply_phases(h2s_tree t, uint32_t mask, const double *x, double *
     const char *yb = (const char *)y, *ye = (const char *)(y + ldy * (nrhs - 1) + n);
     if (xb < ye && yb < xe) return fail(H2S_ERR_INVALID_ARG, "x and y overlap");
     if (hipSetDevice(t->device) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipSetDevice failed");
-    if (!t->aux) {
-        // created on first use, on the handle's device, at the default priority
-        hipStream_t a = nullptr;
-        hipEvent_t f = nullptr, j = nullptr;
-        if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
-            if (a) (void)hipStreamDestroy(a);
-            if (f) (void)hipEventDestroy(f);
-            return fail(H2S_ERR_DEVICE, "creating the near-field stream or its events failed");
-        }
-        t->aux = a;
-        t->ev_fork = f;
-        t->ev_join = j;
-    }
+    if (ensure_streams(t) != H2S_OK) return H2S_ERR_DEVICE;
     h2s::ProfileHook hook{t, record_mark};
     const h2s::ProfileHook *prof = t->profiling ? &hook : nullptr;
-    const h2s::Streams st{stream, t->aux, t->ev_fork, t->ev_join};
     for (int32_t c = 0; c < nrhs; ++c) {
-        const double *xc = x + c * ldx;
-        double *yc = y + c * ldy;
-        int rc;
-        if (t->opts.prec == H2S_FP64) rc = h2s::launch_mvp<h2s::P64>(t->t64, t->plan, xc, yc, mask, st, prof);
-        else if (t->opts.prec == H2S_FP32) rc = h2s::launch_mvp<h2s::P32>(t->t32, t->plan, xc, yc, mask, st, prof);
-        else rc = h2s::launch_mvp<h2s::P32M>(t->t32m, t->plan, xc, yc, mask, st, prof);
+        const int rc = mvp(t, t->opts.prec, mask, x + c * ldx, y + c * ldy, stream, prof);
         if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
     }
     return H2S_OK;
@@ -566,6 +615,81 @@ h2s_status h2s_apply_phases(h2s_tree t, uint32_t mask, const double *x, double *
 h2s_status h2s_apply(h2s_tree t, const double *x, double *y, int32_t nrhs, int64_t ldx, int64_t ldy, void *stream)
 {
     return h2s_apply_phases(t, H2S_PHASE_ALL, x, y, nrhs, ldx, ldy, stream);
+}
+
+h2s_status h2s_solve_opts_default(h2s_solve_opts *o)
+{
+    if (!o) return fail(H2S_ERR_INVALID_ARG, "opts is NULL");
+    o->restart = 50;
+    o->max_iter = 10000;
+    o->max_refine = 1000;
+    o->inner_prec = H2S_FP32;
+    o->rtol = 1e-8;
+    o->inner_rtol = 1e-6;
+    o->use_x0 = 0;
+    return H2S_OK;
+}
+
+h2s_status h2s_solve(h2s_tree t, const double *b, double *x, int32_t nrhs, int64_t ldb, int64_t ldx,
+                     const h2s_solve_opts *opts, h2s_solve_info *info, void *stream)
+{
+    if (!t) return fail(H2S_ERR_INVALID_ARG, "tree is NULL");
+    if (t->host_only) return fail(H2S_ERR_UNSUPPORTED, "handle was built with host_only");
+    h2s_solve_opts o;
+    h2s_solve_opts_default(&o);
+    if (opts) o = *opts;
+    const int64_t n = t->rep.n;
+    if (!b || !x) return fail(H2S_ERR_INVALID_ARG, "b or x is NULL");
+    if (nrhs < 1) return fail(H2S_ERR_INVALID_ARG, "nrhs must be >= 1");
+    if (ldb < n || ldx < n) return fail(H2S_ERR_INVALID_ARG, "leading dimensions must be >= n");
+    if (o.restart < 1 || o.restart > 1000) return fail(H2S_ERR_INVALID_ARG, "restart must be in 1..1000");
+    if (o.max_iter < 0 || o.max_refine < 0) return fail(H2S_ERR_INVALID_ARG, "max_iter and max_refine must be >= 0");
+    if (!(o.rtol >= 0.0) || !is_finite(o.rtol) || !(o.inner_rtol >= 0.0) || !is_finite(o.inner_rtol))
+        return fail(H2S_ERR_INVALID_ARG, "rtol and inner_rtol must be finite and >= 0");
+    if (o.inner_prec != H2S_FP64 && o.inner_prec != H2S_FP32 && o.inner_prec != H2S_FP32_M2L)
+        return fail(H2S_ERR_INVALID_ARG, "bad inner precision");
+    const char *bb = (const char *)b, *be = (const char *)(b + ldb * (nrhs - 1) + n);
+    const char *xb = (const char *)x, *xe = (const char *)(x + ldx * (nrhs - 1) + n);
+    if (bb < xe && xb < be) return fail(H2S_ERR_INVALID_ARG, "b and x overlap");
+    if (hipSetDevice(t->device) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipSetDevice failed");
+    if (ensure_streams(t) != H2S_OK) return H2S_ERR_DEVICE;
+    h2s_status st = ensure_uploaded(t, H2S_FP64, (hipStream_t)stream);
+    if (st == H2S_OK) st = ensure_uploaded(t, o.inner_prec, (hipStream_t)stream);
+    if (st != H2S_OK) return st;
+    if (t->solve_m < o.restart) {
+        // workspace for this restart length (a shorter restart reuses a larger one)
+        Uploader up{t, (hipStream_t)stream};
+        const int m = o.restart;
+        h2s::SolveWork w{};
+        w.V = (double *)up.raw(sizeof(double) * (size_t)n * (m + 1));
+        w.w = (double *)up.raw(sizeof(double) * (size_t)n);
+        w.r = (double *)up.raw(sizeof(double) * (size_t)n);
+        w.y = (double *)up.raw(sizeof(double) * (size_t)n);
+        w.part = (double *)up.raw(sizeof(double) * (size_t)h2s::blas_dots_blocks(n) * (m + 1));
+        w.small = (double *)up.raw(sizeof(double) * (size_t)(2 * (m + 1) + 2));
+        if (up.st != H2S_OK) return up.st;
+        if (hipHostMalloc((void **)&w.small_host, sizeof(double) * (size_t)(2 * (m + 1) + 2), hipHostMallocDefault) !=
+            hipSuccess)
+            return fail(H2S_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
+        if (t->work.small_host) (void)hipHostFree(t->work.small_host);
+        t->work = w;
+        t->solve_m = m;
+    }
+    // the kernels index V with ld = n; a larger workspace is used with the same n
+    h2s::SolveWork w = t->work;
+    const h2s::SolveParams prm{o.restart, o.max_iter, o.max_refine, o.rtol, o.inner_rtol, o.use_x0};
+    SolveCtx ctx{t, o.inner_prec, stream};
+    const h2s::SolveOps ops{&ctx, solve_apply_inner, solve_apply_outer};
+    bool all = true;
+    for (int32_t c = 0; c < nrhs; ++c) {
+        h2s::SolveResult r{};
+        const int rc = h2s::gmres_ir(ops, w, prm, n, b + c * ldb, x + c * ldx, stream, &r);
+        if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("solve failed: ") + hipGetErrorString((hipError_t)rc));
+        if (info) info[c] = h2s_solve_info{r.iterations, r.refinements, r.converged, r.residual};
+        all = all && r.converged;
+    }
+    if (!all) return fail(H2S_ERR_NOT_CONVERGED, "a right-hand side did not reach rtol");
+    return H2S_OK;
 }
 
 h2s_status h2s_free(h2s_tree t)

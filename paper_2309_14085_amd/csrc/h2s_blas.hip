@@ -1,0 +1,173 @@
+// h2s_blas.hip -- FP64 vector kernels of the GMRES solve (Arnoldi with
+// classical Gram-Schmidt applied twice, the correction x += V y and the
+// residual b - K~ x).  Every reduction runs in a fixed order (per-block
+// partial sums, then one ordered pass over the blocks), so a solve is
+// bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "h2s_blas.hpp"
+
+namespace h2s {
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int ROWS_PER_THREAD = 8;
+constexpr int ROWS_PER_BLOCK = NT * ROWS_PER_THREAD;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// part[blk * ncols + k] = sum over the block's rows i of V[i + k ldv] w[i].
+__global__ __launch_bounds__(NT) void k_dots_part(const double *__restrict__ V, int64_t ldv, int ncols,
+                                                  const double *__restrict__ w, int64_t n, double *__restrict__ part)
+{
+    __shared__ double red[NT / 64];
+    const int64_t base = (int64_t)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x;
+    double wr[ROWS_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < ROWS_PER_THREAD; ++u) {
+        const int64_t i = base + (int64_t)u * NT;
+        wr[u] = i < n ? w[i] : 0.0;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k = 0; k < ncols; ++k) {
+        const double *col = V + (int64_t)k * ldv;
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < ROWS_PER_THREAD; ++u) {
+            const int64_t i = base + (int64_t)u * NT;
+            if (i < n) s = fma(col[i], wr[u], s);
+        }
+        s = wave_sum(s);
+        if (lane == 0) red[wave] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int q = 0; q < NT / 64; ++q) t += red[q];
+            part[(int64_t)blockIdx.x * ncols + k] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// out[k] = sum_blk part[blk * ncols + k], blocks in order.
+__global__ __launch_bounds__(64) void k_dots_final(const double *__restrict__ part, int nblk, int ncols,
+                                                   double *__restrict__ out)
+{
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= ncols) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * ncols + k];
+    out[k] = s;
+}
+
+// y[i] += alpha sum_k V[i + k ldv] c[k]   (c in device memory, ncols <= kMaxCols)
+__global__ __launch_bounds__(NT) void k_gemv_acc(const double *__restrict__ V, int64_t ldv, int ncols,
+                                                 const double *__restrict__ c, double alpha, double *__restrict__ y,
+                                                 int64_t n)
+{
+    __shared__ double cs[kMaxCols];
+    for (int k = threadIdx.x; k < ncols; k += NT) cs[k] = c[k];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < ncols; ++k) s = fma(V[i + (int64_t)k * ldv], cs[k], s);
+    y[i] = fma(alpha, s, y[i]);
+}
+
+// v = w / sqrt(nrm2[0]), or 0 when the norm is zero (breakdown).
+__global__ __launch_bounds__(NT) void k_normalise(const double *__restrict__ w, const double *__restrict__ nrm2,
+                                                  double *__restrict__ v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    const double s = nrm2[0];
+    v[i] = s > 0.0 ? w[i] / sqrt(s) : 0.0;
+}
+
+// v = w / beta (beta a host scalar > 0).
+__global__ __launch_bounds__(NT) void k_scale(const double *__restrict__ w, double beta, double *__restrict__ v,
+                                              int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) v[i] = w[i] / beta;
+}
+
+// r = b - y
+__global__ __launch_bounds__(NT) void k_sub(const double *__restrict__ b, const double *__restrict__ y,
+                                            double *__restrict__ r, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) r[i] = b[i] - y[i];
+}
+
+// v = c (fill)
+__global__ __launch_bounds__(NT) void k_fill(double *__restrict__ v, double c, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) v[i] = c;
+}
+
+inline unsigned grid(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
+
+} // namespace
+
+int64_t blas_dots_blocks(int64_t n) { return (n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK; }
+
+int blas_dots(const double *V, int64_t ldv, int ncols, const double *w, int64_t n, double *part, double *out,
+              void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nb = blas_dots_blocks(n);
+    if (ncols <= 0 || n <= 0) return 0;
+    hipLaunchKernelGGL(k_dots_part, dim3((unsigned)nb), dim3(NT), 0, s, V, ldv, ncols, w, n, part);
+    hipLaunchKernelGGL(k_dots_final, dim3(grid(ncols, 64)), dim3(64), 0, s, part, (int)nb, ncols, out);
+    return (int)hipGetLastError();
+}
+
+int blas_gemv_acc(const double *V, int64_t ldv, int ncols, const double *c, double alpha, double *y, int64_t n,
+                  void *stream)
+{
+    if (ncols <= 0 || n <= 0) return 0;
+    if (ncols > kMaxCols) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gemv_acc, dim3(grid(n, NT)), dim3(NT), 0, (hipStream_t)stream, V, ldv, ncols, c, alpha, y, n);
+    return (int)hipGetLastError();
+}
+
+int blas_normalise(const double *w, const double *nrm2, double *v, int64_t n, void *stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_normalise, dim3(grid(n, NT)), dim3(NT), 0, (hipStream_t)stream, w, nrm2, v, n);
+    return (int)hipGetLastError();
+}
+
+int blas_scale(const double *w, double beta, double *v, int64_t n, void *stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_scale, dim3(grid(n, NT)), dim3(NT), 0, (hipStream_t)stream, w, beta, v, n);
+    return (int)hipGetLastError();
+}
+
+int blas_sub(const double *b, const double *y, double *r, int64_t n, void *stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_sub, dim3(grid(n, NT)), dim3(NT), 0, (hipStream_t)stream, b, y, r, n);
+    return (int)hipGetLastError();
+}
+
+int blas_fill(double *v, double c, int64_t n, void *stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_fill, dim3(grid(n, NT)), dim3(NT), 0, (hipStream_t)stream, v, c, n);
+    return (int)hipGetLastError();
+}
+
+} // namespace h2s

@@ -1,0 +1,41 @@
+// h2s_solve.hpp -- mixed-precision GMRES with iterative refinement on the
+// device (h2s_solve.cpp).  The driver knows nothing about trees: the two
+// products come in as callbacks.
+#pragma once
+
+#include <cstdint>
+
+namespace h2s {
+
+struct SolveOps {
+    void *ctx;
+    // y = K~ x with x, y device vectors of length n, ordered on the solve's stream
+    int (*apply_inner)(void *ctx, const double *x, double *y); // precision of the Krylov iterations
+    int (*apply_outer)(void *ctx, const double *x, double *y); // FP64: residuals of the refinement
+};
+
+// Device workspace (owned by the caller) for restart length m.
+struct SolveWork {
+    double *V;          // n x (m + 1), column-major, ld = n
+    double *w, *r, *y;  // n each
+    double *part;       // blas_dots_blocks(n) * (m + 1)
+    double *small;      // device, 2 (m + 1) + 2
+    double *small_host; // pinned host mirror of `small`
+};
+
+struct SolveParams {
+    int restart, max_iter, max_refine;
+    double rtol, inner_rtol;
+    int use_x0;
+};
+
+struct SolveResult {
+    int iterations, refinements, converged;
+    double residual; // ||b - K~ x|| / ||b|| with the FP64 product
+};
+
+// Solve K~ x = b (b, x device, length n).  Returns 0 or a hipError_t.
+int gmres_ir(const SolveOps &ops, const SolveWork &wk, const SolveParams &prm, int64_t n, const double *b, double *x,
+             void *stream, SolveResult *res);
+
+} // namespace h2s

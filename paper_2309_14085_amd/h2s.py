@@ -66,6 +66,17 @@ class H2SError(RuntimeError):
         self.status = status
 
 
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("inner_prec", ctypes.c_int), ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
+                ("use_x0", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("refinements", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("residual", ctypes.c_double)]
+
+
 def load():
     """Load libh2s.so (built by paper_2309_14085_amd/build.py)."""
     global _lib
@@ -89,8 +100,11 @@ def load():
     lib.h2s_status_string.restype = ctypes.c_char_p
     lib.h2s_status_string.argtypes = [ctypes.c_int]
     lib.h2s_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    lib.h2s_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
+    lib.h2s_solve.argtypes = [vp, vp, vp, i32, i64, i64, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
     for name in ("h2s_build", "h2s_apply", "h2s_apply_phases", "h2s_free", "h2s_get_stats", "h2s_export",
-                 "h2s_set_allocator", "h2s_last_error", "h2s_set_profiling", "h2s_get_profile"):
+                 "h2s_set_allocator", "h2s_last_error", "h2s_set_profiling", "h2s_get_profile",
+                 "h2s_solve_opts_default", "h2s_solve"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -174,6 +188,42 @@ class Tree:
         """Raw-pointer form of h2s_apply_phases (pointers as ints)."""
         return load().h2s_apply_phases(self._h, mask, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr), nrhs,
                                        ldx or self.n, ldy or self.n, _stream_ptr(stream))
+
+    def solve(self, b, x=None, restart=50, rtol=1e-8, inner_prec=FP32, inner_rtol=1e-6, max_iter=10000,
+              max_refine=1000, use_x0=False, stream=None, raise_on_fail=True):
+        """Solve K~ x = b (h2s_solve) for a CUDA float64 b of shape (n,) or column-major (n, m).
+
+        Returns (x, [info dict per right-hand side]).  NOT_CONVERGED raises unless raise_on_fail is False."""
+        import torch
+        if b.dtype != torch.float64 or not b.is_cuda:
+            raise TypeError("b must be a CUDA float64 tensor")
+        if b.dim() == 1:
+            bb, m, ldb = b.contiguous(), 1, self.n
+        else:
+            if b.stride(0) != 1:
+                b = b.t().contiguous().t()
+            bb, m, ldb = b, b.shape[1], b.stride(1) if b.shape[1] > 1 else self.n
+        if x is None:
+            x = torch.zeros_like(bb) if bb.dim() == 1 else torch.zeros(
+                (m, self.n), dtype=torch.float64, device=b.device).t()
+        ldx = self.n if x.dim() == 1 or x.shape[1] == 1 else x.stride(1)
+        o = SolveOpts()
+        check(load().h2s_solve_opts_default(ctypes.byref(o)))
+        o.restart, o.rtol, o.inner_prec, o.inner_rtol = restart, rtol, inner_prec, inner_rtol
+        o.max_iter, o.max_refine, o.use_x0 = max_iter, max_refine, int(bool(use_x0))
+        infos = (SolveInfo * m)()
+        rc = load().h2s_solve(self._h, ctypes.c_void_p(bb.data_ptr()), ctypes.c_void_p(x.data_ptr()), m, ldb, ldx,
+                              ctypes.byref(o), infos, _stream_ptr(stream))
+        if rc != OK and (rc != ERR_NOT_CONVERGED or raise_on_fail):
+            check(rc)
+        return x, [{"iterations": i.iterations, "refinements": i.refinements, "converged": bool(i.converged),
+                    "residual": i.residual, "status": rc} for i in infos]
+
+    def solve_ptr(self, b_ptr, x_ptr, nrhs=1, ldb=None, ldx=None, opts=None, infos=None, stream=None):
+        """Raw-pointer form of h2s_solve (pointers as ints); returns the status."""
+        return load().h2s_solve(self._h, ctypes.c_void_p(b_ptr), ctypes.c_void_p(x_ptr), nrhs, ldb or self.n,
+                                ldx or self.n, None if opts is None else ctypes.byref(opts), infos,
+                                _stream_ptr(stream))
 
     def set_profiling(self, on=True):
         check(load().h2s_set_profiling(self._h, int(bool(on))))

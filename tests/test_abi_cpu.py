@@ -71,6 +71,24 @@ def test_host_only_handle(lib, inputs):
     assert st == lib.ERR_UNSUPPORTED
     assert lib.load().h2s_free(None) == lib.OK
     assert lib.status_string(lib.ERR_DEVICE) == "device error"
+    assert T.solve_ptr(1 << 20, 2 << 20) == lib.ERR_UNSUPPORTED
+
+
+def test_solve_defaults_and_validation(lib, inputs):
+    import ctypes
+    o = lib.SolveOpts()
+    assert lib.load().h2s_solve_opts_default(ctypes.byref(o)) == lib.OK
+    assert (o.restart, o.max_iter, o.max_refine, o.inner_prec, o.use_x0) == (50, 10000, 1000, lib.FP32, 0)
+    assert (o.rtol, o.inner_rtol) == (1e-8, 1e-6)
+    assert lib.load().h2s_solve_opts_default(None) == lib.ERR_INVALID_ARG
+    T = lib.build(inputs.uniform_points(300, 2, 5), host_only=True)
+    assert lib.load().h2s_solve(None, ctypes.c_void_p(8), ctypes.c_void_p(16), 1, 1, 1, None, None, None) == \
+        lib.ERR_INVALID_ARG
+    # the host-only handle is rejected before any argument reaches the device
+    bad = lib.SolveOpts()
+    lib.load().h2s_solve_opts_default(ctypes.byref(bad))
+    bad.restart = 0
+    assert T.solve_ptr(1 << 20, 2 << 20, opts=bad) == lib.ERR_UNSUPPORTED
 
 
 CASES = [

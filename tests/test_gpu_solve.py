@@ -1,0 +1,141 @@
+"""GPU solve (h2s_solve through the C ABI) against the FP64 oracle.
+
+Bar: the refined solution's relative residual ||b - K~ x|| / ||b|| <= 1e-8,
+measured with the oracle's own FP64 H2* product (independent of the library);
+where the system is well conditioned, x also agrees with the oracle's GMRES
+solution to within cond(K~) times the tolerances.  The Krylov products run in
+FP32 (the default) unless stated.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2309_14085_amd import h2s
+    h2s.load()
+    return h2s
+
+
+def oracle_residual(O, x, b):
+    return np.linalg.norm(b - O.apply(x)) / np.linalg.norm(b)
+
+
+def test_solve_well_conditioned_matches_oracle_solution(lib, orc, inputs):
+    from oracle.gmres import gmres
+    n, h, shift = 4096, 0.1, 1.0
+    print(f"solve gauss n={n} shift={shift}", flush=True)
+    pts = inputs.uniform_points(n, 2, 41)
+    b = inputs.normal_rhs(n, 1, 42)[:, 0]
+    O = orc.Tree(pts, orc.GAUSS, 64, 1e-10, param=h, shift=shift)
+    T = lib.build(pts, kind=lib.GAUSSIAN, leaf_size=64, eps=1e-10, param=h, shift=shift)
+    x, info = T.solve(torch.from_numpy(b).to(_dev()), rtol=1e-8)
+    torch.cuda.synchronize()
+    xg = x.cpu().numpy()
+    assert info[0]["converged"] and info[0]["residual"] <= 1e-8
+    assert oracle_residual(O, xg, b) <= 1.01e-8
+    want, oi = gmres(O.apply, b, restart=50, rtol=1e-12)
+    assert oi["converged"]
+    # cond(K~ + I) <= 1 + lambda_max ~ 1 + n pi h^2 / 4 ~ 33 here
+    assert np.linalg.norm(xg - want) / np.linalg.norm(want) <= 2e-6
+
+
+@pytest.mark.parametrize("inner", ["fp32", "fp64", "fp32_m2l"])
+def test_solve_rbf_shape_reaches_1e8(lib, orc, inputs, inner):
+    """The RBF interpolation system (Gaussian h = 0.1, K_ii = 1, shift 1e-2) at N = 16384."""
+    prec = {"fp32": lib.FP32, "fp64": lib.FP64, "fp32_m2l": lib.FP32_M2L}[inner]
+    n = 16384
+    print(f"solve rbf n={n} inner={inner}", flush=True)
+    pts = inputs.uniform_points(n, 2, 43)
+    b = inputs.normal_rhs(n, 1, 44)[:, 0]
+    O = orc.Tree(pts, orc.GAUSS, 64, 1e-8, param=0.1, shift=1e-2)
+    T = lib.build(pts, kind=lib.GAUSSIAN, leaf_size=64, eps=1e-8, param=0.1, shift=1e-2)
+    x, info = T.solve(torch.from_numpy(b).to(_dev()), rtol=1e-8, inner_prec=prec)
+    torch.cuda.synchronize()
+    print(f"  {inner}: {info[0]}", flush=True)
+    assert info[0]["converged"]
+    assert oracle_residual(O, x.cpu().numpy(), b) <= 1.01e-8
+
+
+def test_solve_multi_rhs_with_leading_dimension(lib, orc, inputs):
+    n, m, ld = 3000, 2, 3011
+    print("solve multi-rhs", flush=True)
+    pts = inputs.uniform_points(n, 2, 45)
+    B = inputs.normal_rhs(n, m, 46)
+    O = orc.Tree(pts, orc.GAUSS, 32, 1e-10, param=0.1, shift=0.1)
+    T = lib.build(pts, kind=lib.GAUSSIAN, leaf_size=32, eps=1e-10, param=0.1, shift=0.1)
+    dev = _dev()
+    bb = torch.zeros(m * ld, dtype=torch.float64, device=dev)
+    xb = torch.full((m * ld,), 5.0, dtype=torch.float64, device=dev)
+    for c in range(m):
+        bb[c * ld:c * ld + n] = torch.from_numpy(B[:, c].copy()).to(dev)
+    infos = (lib.SolveInfo * m)()
+    assert T.solve_ptr(bb.data_ptr(), xb.data_ptr(), nrhs=m, ldb=ld, ldx=ld, infos=infos) == lib.OK
+    torch.cuda.synchronize()
+    X = xb.cpu().numpy()
+    for c in range(m):
+        assert infos[c].converged == 1 and infos[c].residual <= 1e-8
+        assert oracle_residual(O, X[c * ld:c * ld + n], B[:, c]) <= 1.01e-8
+        assert np.all(X[c * ld + n:(c + 1) * ld] == 5.0)  # padding untouched
+
+
+def test_solve_iteration_limit_reports_not_converged(lib, inputs):
+    n = 4096
+    print("solve iteration limit", flush=True)
+    pts = inputs.uniform_points(n, 2, 47)
+    b = inputs.normal_rhs(n, 1, 48)[:, 0]
+    T = lib.build(pts, kind=lib.GAUSSIAN, leaf_size=64, eps=1e-8, param=0.1, shift=1e-2)
+    x, info = T.solve(torch.from_numpy(b).to(_dev()), rtol=1e-8, max_iter=3, raise_on_fail=False)
+    torch.cuda.synchronize()
+    assert info[0]["status"] == lib.ERR_NOT_CONVERGED and not info[0]["converged"]
+    assert info[0]["iterations"] == 3 and info[0]["refinements"] == 1
+    assert 0.0 < info[0]["residual"] < 1.0
+    assert torch.isfinite(x).all()
+
+
+def test_solve_zero_rhs_and_initial_guess(lib, inputs):
+    n = 2000
+    print("solve zero rhs / x0", flush=True)
+    pts = inputs.uniform_points(n, 2, 49)
+    T = lib.build(pts, kind=lib.GAUSSIAN, leaf_size=32, eps=1e-8, param=0.1, shift=0.5)
+    dev = _dev()
+    x, info = T.solve(torch.zeros(n, dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+    assert info[0]["converged"] and info[0]["iterations"] == 0 and float(x.abs().max()) == 0.0
+    b = torch.from_numpy(inputs.normal_rhs(n, 1, 50)[:, 0]).to(dev)
+    x1, i1 = T.solve(b, rtol=1e-9)
+    # restarting from the converged solution needs no Krylov step
+    x2, i2 = T.solve(b, x=x1.clone(), rtol=1e-9, use_x0=True)
+    torch.cuda.synchronize()
+    assert i1[0]["converged"] and i2[0]["converged"] and i2[0]["iterations"] == 0
+    assert torch.equal(x1, x2)
+
+
+@pytest.mark.timeout(600)
+def test_solve_rbf_full_size(lib, orc, inputs):
+    """N = 2^18 RBF interpolation solve to 1e-8, residual checked with the oracle product."""
+    w = inputs.workload("2d_gauss_rbf_n262144")
+    pts, b = w.points(), w.rhs()[:, 0]
+    print("solve full size: library build", flush=True)
+    T = lib.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps, param=w.param, shift=w.shift)
+    x, info = T.solve(torch.from_numpy(b).to(_dev()), rtol=1e-8, max_iter=100000, raise_on_fail=False)
+    torch.cuda.synchronize()
+    print(f"  {info[0]}", flush=True)
+    xg = x.cpu().numpy()
+    del T
+    print("solve full size: oracle residual", flush=True)
+    O = orc.Tree(pts, w.kind, w.nmax, w.eps, param=w.param, shift=w.shift)
+    res = oracle_residual(O, xg, b)
+    print(f"  oracle residual {res:.3e}", flush=True)
+    assert info[0]["converged"]
+    assert res <= 1.01e-8

@@ -261,7 +261,7 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
     D.kind = r.ker.kind;
     D.diag = r.ker.diag;
     D.shift = r.ker.shift;
-    D.kparam = r.ker.kind == H2S_K_GAUSSIAN ? r.ker.param * r.ker.param : 0.0;
+    D.kparam = r.ker.kind == H2S_K_GAUSSIAN ? -1.0 / (r.ker.param * r.ker.param) : 0.0;
     D.variant = r.variant;
     D.max_leaf = 1;
     for (int32_t g = leaf0; g < nbox; ++g) D.max_leaf = std::max(D.max_leaf, r.box_end[g] - r.box_begin[g]);
@@ -399,15 +399,22 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
     D.qt = up.template zeros<double>(n);
     D.yn = up.template zeros<double>(n);
     {
-        // 0.5 ln x by table reduction: subinterval i of m in [1/2, 1) has centre
-        // z_i = 1/2 + (i + 1/2)/256; store c_i = 1/z_i and -0.5 ln c_i (extended precision)
-        std::vector<double> tab(2 * 128);
-        for (int i = 0; i < 128; ++i) {
-            const double c = 1.0 / (0.5 + (i + 0.5) / 256.0);
-            tab[2 * i] = c;
-            tab[2 * i + 1] = (double)(-0.5L * std::log((long double)c));
+        // tables of the kernel functions (extended precision, rounded once)
+        std::vector<double> tab;
+        if (r.ker.kind == H2S_K_LOG_R) {
+            // 0.5 ln x by table reduction: subinterval i of m in [1/2, 1) has centre
+            // z_i = 1/2 + (i + 1/2)/256; store c_i = 1/z_i and -0.5 ln c_i
+            for (int i = 0; i < 128; ++i) {
+                const double c = 1.0 / (0.5 + (i + 0.5) / 256.0);
+                tab.push_back(c);
+                tab.push_back((double)(-0.5L * std::log((long double)c)));
+            }
+        } else if (r.ker.kind == H2S_K_GAUSSIAN || r.ker.kind == H2S_K_EXP_R) {
+            for (int j = 0; j < 64; ++j) tab.push_back((double)std::exp2((long double)j / 64.0L)); // 2^(j/64)
+        } else {
+            tab.assign(2, 0.0);
         }
-        D.logtab = up.copy(tab);
+        D.ktab = up.copy(tab);
     }
     // block sizes: one thread per output of a box (both families), whole wavefronts
     auto threads = [](int32_t outputs) { return std::min(512, std::max(64, (outputs + 63) / 64 * 64)); };

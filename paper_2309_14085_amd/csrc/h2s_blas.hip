@@ -1,8 +1,8 @@
 // h2s_blas.hip -- FP64 vector kernels of the GMRES solve (Arnoldi with
 // classical Gram-Schmidt applied twice, the correction x += V y and the
-// residual b - K~ x).  Every reduction runs in a fixed order (per-block
-// partial sums, then one ordered pass over the blocks), so a solve is
-// bitwise reproducible run to run.
+// residual b - K~ x).  Every reduction runs in a fixed order (partial sums
+// per wavefront, then a fixed tree over them), so a solve is bitwise
+// reproducible run to run.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -14,7 +14,7 @@ namespace h2s {
 namespace {
 
 constexpr int NT = 256;
-constexpr int ROWS_PER_THREAD = 8;
+constexpr int ROWS_PER_THREAD = 2;
 constexpr int ROWS_PER_BLOCK = NT * ROWS_PER_THREAD;
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -24,11 +24,13 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// part[blk * ncols + k] = sum over the block's rows i of V[i + k ldv] w[i].
+constexpr int WAVES = NT / 64;
+
+// part[(blk WAVES + wave) ncols + k] = sum over the wave's rows i of
+// V[i + k ldv] w[i]: wave-level reductions only, no block barriers.
 __global__ __launch_bounds__(NT) void k_dots_part(const double *__restrict__ V, int64_t ldv, int ncols,
                                                   const double *__restrict__ w, int64_t n, double *__restrict__ part)
 {
-    __shared__ double red[NT / 64];
     const int64_t base = (int64_t)blockIdx.x * ROWS_PER_BLOCK + threadIdx.x;
     double wr[ROWS_PER_THREAD];
 #pragma unroll
@@ -37,35 +39,49 @@ __global__ __launch_bounds__(NT) void k_dots_part(const double *__restrict__ V, 
         wr[u] = i < n ? w[i] : 0.0;
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int k = 0; k < ncols; ++k) {
-        const double *col = V + (int64_t)k * ldv;
-        double s = 0.0;
+    double *out = part + ((int64_t)blockIdx.x * WAVES + wave) * ncols;
+    // KB columns at a time keep KB x ROWS_PER_THREAD loads in flight per thread
+    constexpr int KB = 8;
+    for (int k0 = 0; k0 < ncols; k0 += KB) {
+        double s[KB];
 #pragma unroll
-        for (int u = 0; u < ROWS_PER_THREAD; ++u) {
-            const int64_t i = base + (int64_t)u * NT;
-            if (i < n) s = fma(col[i], wr[u], s);
+        for (int c = 0; c < KB; ++c) {
+            s[c] = 0.0;
+            if (k0 + c < ncols) {
+                const double *col = V + (int64_t)(k0 + c) * ldv;
+#pragma unroll
+                for (int u = 0; u < ROWS_PER_THREAD; ++u) {
+                    const int64_t i = base + (int64_t)u * NT;
+                    if (i < n) s[c] = fma(col[i], wr[u], s[c]);
+                }
+            }
         }
-        s = wave_sum(s);
-        if (lane == 0) red[wave] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int q = 0; q < NT / 64; ++q) t += red[q];
-            part[(int64_t)blockIdx.x * ncols + k] = t;
+#pragma unroll
+        for (int c = 0; c < KB; ++c) {
+            const double t = wave_sum(s[c]);
+            if (lane == 0 && k0 + c < ncols) out[k0 + c] = t;
         }
-        __syncthreads();
     }
 }
 
-// out[k] = sum_blk part[blk * ncols + k], blocks in order.
-__global__ __launch_bounds__(64) void k_dots_final(const double *__restrict__ part, int nblk, int ncols,
+// out[k] = sum_p part[p ncols + k] over the np partial rows: one block per k,
+// thread t sums rows t, t + NT, ... in order, then a fixed reduction tree.
+__global__ __launch_bounds__(NT) void k_dots_final(const double *__restrict__ part, int np, int ncols,
                                                    double *__restrict__ out)
 {
-    const int k = blockIdx.x * 64 + threadIdx.x;
-    if (k >= ncols) return;
+    __shared__ double red[WAVES];
+    const int k = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * ncols + k];
-    out[k] = s;
+    for (int p = threadIdx.x; p < np; p += NT) s += part[(int64_t)p * ncols + k];
+    s = wave_sum(s);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < WAVES; ++q) t += red[q];
+        out[k] = t;
+    }
 }
 
 // y[i] += alpha sum_k V[i + k ldv] c[k]   (c in device memory, ncols <= kMaxCols)
@@ -120,16 +136,16 @@ inline unsigned grid(int64_t n, int64_t per) { return (unsigned)((n + per - 1) /
 
 } // namespace
 
-int64_t blas_dots_blocks(int64_t n) { return (n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK; }
+int64_t blas_dots_blocks(int64_t n) { return WAVES * ((n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK); }
 
 int blas_dots(const double *V, int64_t ldv, int ncols, const double *w, int64_t n, double *part, double *out,
               void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    const int64_t nb = blas_dots_blocks(n);
+    const int64_t nb = (n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
     if (ncols <= 0 || n <= 0) return 0;
     hipLaunchKernelGGL(k_dots_part, dim3((unsigned)nb), dim3(NT), 0, s, V, ldv, ncols, w, n, part);
-    hipLaunchKernelGGL(k_dots_final, dim3(grid(ncols, 64)), dim3(64), 0, s, part, (int)nb, ncols, out);
+    hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ncols), dim3(NT), 0, s, part, (int)(nb * WAVES), ncols, out);
     return (int)hipGetLastError();
 }
 

@@ -9,7 +9,7 @@ namespace h2s {
 
 constexpr int kMaxCols = 1024; // columns of V in one GEMV (restart + 1)
 
-// Blocks (hence partial-sum rows) used by blas_dots for n rows.
+// Partial-sum rows used by blas_dots for n rows (one per wavefront).
 int64_t blas_dots_blocks(int64_t n);
 // out[k] = sum_i V[i + k ldv] w[i], k < ncols; part holds blas_dots_blocks(n) * ncols doubles.
 int blas_dots(const double *V, int64_t ldv, int ncols, const double *w, int64_t n, double *part, double *out,

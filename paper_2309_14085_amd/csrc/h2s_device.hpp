@@ -92,7 +92,7 @@ template <class P> struct DevTree {
     using basis_t = typename P::basis_t;
     int32_t n, d, kappa, nleaf, leaf0, nbox, kind, variant;
     int32_t max_leaf, max_rows, max_rank; // LDS sizing: largest leaf, stacked transfer rows, rank
-    double diag, shift, kparam; // K(x,x); shift * I; h^2 for the Gaussian
+    double diag, shift, kparam; // K(x,x); shift * I; -1/h^2 for the Gaussian (exponent r^2 kparam)
     const int32_t *perm;        // tree position -> user index
     const pt_t *px, *py, *pz;
     const int32_t *box_begin, *box_end, *box_cbeg, *box_cend;
@@ -104,7 +104,7 @@ template <class P> struct DevTree {
     DevPairs<basis_t> pairs;
     double *qt;           // charges in tree order
     double *yn;           // near-field potentials in tree order
-    const double *logtab; // log r: (c_i, -0.5 ln c_i) for 128 mantissa subintervals
+    const double *ktab;   // kernel-function table: log r (c_i, -0.5 ln c_i) x 128; exponentials 2^(j/64) x 64
 };
 
 // Host-side launch shapes, fixed at upload.

@@ -62,15 +62,12 @@ template <bool ORD> __device__ __forceinline__ double madd(double s, double a, d
 //   0.5 ln x = 0.5 e ln 2 - 0.5 ln c_i + 0.5 ln(1 + r),
 // the last term by its Taylor series through r^6 (truncation below 1e-18).
 // tab holds (c_i, -0.5 ln c_i) for the 128 subintervals (built on the host
-// in extended precision) and is staged in LDS by the caller.  Absolute
-// error about one ulp of the result.
-constexpr int kLogTab = 128;
-
+// in extended precision).  Absolute error about one ulp of the result.
 __device__ __forceinline__ double half_log(double x, const double2 *tab)
 {
     int e;
     const double m = frexp(x, &e);
-    const int i = (__double2hiint(m) >> 13) & (kLogTab - 1);
+    const int i = (__double2hiint(m) >> 13) & 127;
     const double2 c = tab[i];
     const double r = fma(m, c.x, -1.0);
     double p = -1.0 / 12;
@@ -82,11 +79,55 @@ __device__ __forceinline__ double half_log(double x, const double2 *tab)
     return fma((double)e, 0.34657359027997264, c.y) + r * p; // ln 2 / 2
 }
 
-// Stage the log table in LDS (whole block; the caller synchronises).
-template <int KIND> __device__ __forceinline__ void stage_log_table(const double *g, double2 *tab)
+// exp(x) in double, table-driven (Tang's reduction): k = nearest integer to
+// 64 x / ln 2, r = x - k ln2/64 (|r| <= ln2/128, with ln2/64 split into an
+// exactly multipliable head and a tail), k = 64 m + j, and
+//   exp(x) = 2^m 2^(j/64) exp(r),
+// exp(r) by its Taylor series through r^6 (truncation below 3e-20).  tab
+// holds 2^(j/64), j < 64 (extended precision on the host).  Arguments below
+// -1000 are clamped (the result is 0 in double either way).  Relative error
+// about two ulps.
+__device__ __forceinline__ double exp_tab(double x, const double *tab)
 {
-    if constexpr (KIND == H2S_K_LOG_R)
-        for (int i = threadIdx.x; i < kLogTab; i += blockDim.x) tab[i] = make_double2(g[2 * i], g[2 * i + 1]);
+    x = fmax(x, -1000.0);
+    const double kd = rint(x * 92.332482616893656877); // 64 / ln 2
+    const int k = (int)kd;
+    double r = fma(-kd, 0.010830417275428772, x);     // head of ln2/64
+    r = fma(-kd, 7.420820373487167e-09, r);           // tail of ln2/64
+    double p = 1.0 / 720;
+    p = fma(p, r, 1.0 / 120);
+    p = fma(p, r, 1.0 / 24);
+    p = fma(p, r, 1.0 / 6);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(tab[k & 63] * p, k >> 6);
+}
+
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y^2) / 2.  Relative error about one ulp.
+__device__ __forceinline__ double inv_sqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double t = x * y;
+        const double e = fma(-t, y, 1.0);
+        y = fma(y * 0.5, e, y);
+    }
+    return y;
+}
+
+// Lookup tables of the kernel functions, in doubles: log r (c_i, -0.5 ln c_i)
+// pairs, the exponential kernels 2^(j/64).  Staged in LDS per block.
+template <int KIND>
+constexpr int kTabLen = KIND == H2S_K_LOG_R ? 256 : (KIND == H2S_K_GAUSSIAN || KIND == H2S_K_EXP_R ? 64 : 2);
+
+// Stage the table in LDS (whole block; the caller synchronises).
+template <int KIND> __device__ __forceinline__ void stage_table(const double *g, double *tab)
+{
+    if constexpr (KIND != H2S_K_INV_R)
+        for (int i = threadIdx.x; i < kTabLen<KIND>; i += blockDim.x) tab[i] = g[i];
 }
 
 // Squared distance (ORD is accepted for symmetry with madd).
@@ -97,17 +138,17 @@ template <bool ORD, int D, typename T> __device__ __forceinline__ T dist2(T dx, 
     return r2;
 }
 
-// Kernel value from a squared distance r2 > 0.  kp: h^2 for the Gaussian.
-template <int KIND> __device__ __forceinline__ double kval_pos(double r2, double kp, const double2 *tab)
+// Kernel value from a squared distance r2 > 0.  kp: -1/h^2 for the Gaussian.
+template <int KIND> __device__ __forceinline__ double kval_pos(double r2, double kp, const double *tab)
 {
-    if constexpr (KIND == H2S_K_LOG_R) return half_log(r2, tab);
-    else if constexpr (KIND == H2S_K_INV_R) return 1.0 / sqrt(r2);
-    else if constexpr (KIND == H2S_K_GAUSSIAN) return exp(-r2 / kp);
-    else return exp(-sqrt(r2));
+    if constexpr (KIND == H2S_K_LOG_R) return half_log(r2, (const double2 *)tab);
+    else if constexpr (KIND == H2S_K_INV_R) return inv_sqrt(r2);
+    else if constexpr (KIND == H2S_K_GAUSSIAN) return exp_tab(r2 * kp, tab);
+    else return exp_tab(-sqrt(r2), tab);
 }
 
 // Kernel value from the squared distance; r2 == 0 means coincident points.
-template <int KIND> __device__ __forceinline__ double kval(double r2, double diag, double kp, const double2 *tab)
+template <int KIND> __device__ __forceinline__ double kval(double r2, double diag, double kp, const double *tab)
 {
     const double v = kval_pos<KIND>(r2, kp, tab);
     return r2 == 0.0 ? diag : v;
@@ -118,7 +159,7 @@ template <int KIND> __device__ __forceinline__ float kval(float r2, float diag, 
     float v;
     if constexpr (KIND == H2S_K_LOG_R) v = __log2f(r2) * 0.34657359027997264f; // ln 2 / 2
     else if constexpr (KIND == H2S_K_INV_R) v = __frsqrt_rn(r2);
-    else if constexpr (KIND == H2S_K_GAUSSIAN) v = __expf(-r2 / kp);
+    else if constexpr (KIND == H2S_K_GAUSSIAN) v = __expf(r2 * kp);
     else v = __expf(-__fsqrt_rn(r2));
     return r2 == 0.0f ? diag : v;
 }
@@ -282,9 +323,9 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
     __shared__ int ybeg[M2L_BOX], ylen[M2L_BOX];
     __shared__ double ylc[CENTRED ? M2L_BOX : 1];
     __shared__ float yic[CENTRED ? M2L_BOX : 1];
-    __shared__ double2 ltab[KIND == H2S_K_LOG_R && !LOWP ? kLogTab : 1];
+    __shared__ __align__(16) double ktab[kTabLen<KIND>];
     const int tid = threadIdx.x;
-    if constexpr (!LOWP) stage_log_table<KIND>(t.logtab, ltab);
+    if constexpr (!LOWP) stage_table<KIND>(t.ktab, ktab);
     const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
@@ -364,7 +405,7 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
                     for (int u = 0; u < 4; ++u) {
                         const double r2 = dist2<ORD, D>((double)xa - (double)sx[j + u], (double)ya - (double)sy[j + u],
                                                         D == 3 ? (double)za - (double)sz[j + u] : 0.0);
-                        kv[u] = kval_pos<KIND>(r2, (double)kp, ltab);
+                        kv[u] = kval_pos<KIND>(r2, (double)kp, ktab);
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) s = madd<ORD>(s, kv[u], sv[j + u]);
@@ -372,7 +413,7 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
                 for (; j < je; ++j) {
                     const double r2 = dist2<ORD, D>((double)xa - (double)sx[j], (double)ya - (double)sy[j],
                                                     D == 3 ? (double)za - (double)sz[j] : 0.0);
-                    s = madd<ORD>(s, kval_pos<KIND>(r2, (double)kp, ltab), sv[j]);
+                    s = madd<ORD>(s, kval_pos<KIND>(r2, (double)kp, ktab), sv[j]);
                 }
             }
             part[yl * r + a] = s;
@@ -448,16 +489,16 @@ template <class P, int KIND, int D>
 __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t)
 {
     using PT = typename P::pt_t;
-    constexpr bool TAB = KIND == H2S_K_LOG_R && sizeof(PT) == 8;
+    constexpr bool TAB = sizeof(PT) == 8;
     __shared__ PT sx[P2P_SRC], sy[P2P_SRC], sz[D == 3 ? P2P_SRC : 1], sq[P2P_SRC];
     __shared__ double red[NT_P2P];
-    __shared__ double2 ltab[TAB ? kLogTab : 1];
+    __shared__ __align__(16) double ktab[TAB ? kTabLen<KIND> : 2];
     const int tid = threadIdx.x;
     const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
     const PT diag = (PT)t.diag, kp = (PT)t.kparam;
     const double *cX = t.box_ctr + 3 * g;
-    if constexpr (TAB) stage_log_table<KIND>(t.logtab, ltab); // first used after a barrier
+    if constexpr (TAB) stage_table<KIND>(t.ktab, ktab); // first used after a barrier
     for (int i0 = 0; i0 < n; i0 += NT_P2P) {
         const int m = min(n - i0, NT_P2P), S = NT_P2P / m, s = tid / m, i = i0 + tid % m;
         const PT xi = t.px[b + i], yi = t.py[b + i], zi = D == 3 ? t.pz[b + i] : PT(0);
@@ -468,8 +509,8 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t)
             constexpr bool CHECK = decltype(check)::value;
             auto k = [&](PT r2) -> PT {
                 if constexpr (sizeof(PT) == 8) {
-                    if constexpr (CHECK) return kval<KIND>(r2, diag, kp, ltab);
-                    else return kval_pos<KIND>(r2, kp, ltab);
+                    if constexpr (CHECK) return kval<KIND>(r2, diag, kp, ktab);
+                    else return kval_pos<KIND>(r2, kp, ktab);
                 } else {
                     return kval<KIND>(r2, diag, kp);
                 }

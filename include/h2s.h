@@ -201,12 +201,13 @@ h2s_status h2s_export(h2s_tree t, const char *path);
 #define H2S_PROF_PAIR_SUM 5  /* (H2+H)* chunk sums */
 #define H2S_PROF_LEAF_DOWN 6 /* L2P + (H2+H)* vertex blocks + sum + scatter */
 #define H2S_PROF_M2L_VER 7   /* vertex-sharing M2L, every level in one launch */
-#define H2S_PROF_NEAR 8      /* direct near field, on a second stream beside the sweeps */
+#define H2S_PROF_NEAR 8      /* direct near field (beside the sweeps on a second stream when not profiling) */
 #define H2S_NUM_PROF 9
 
-/* Profiling hooks for measurement: while enabled, every apply records a HIP
- * event before and after each kernel class on the stream that runs it
- * (adding small gaps between kernels).  h2s_get_profile waits for the recorded
+/* Profiling hooks for measurement: while enabled, every apply runs all its
+ * kernels on the caller's stream (the near field does not overlap the tree
+ * sweeps) and records a HIP event before and after each kernel class, so
+ * each class is timed alone (adding small gaps between kernels).  h2s_get_profile waits for the recorded
  * events, writes per-class total milliseconds and launch counts (arrays of
  * H2S_NUM_PROF entries, either may be NULL) and clears the record. */
 h2s_status h2s_set_profiling(h2s_tree t, int32_t enable);

@@ -403,9 +403,9 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
         std::vector<double> tab;
         if (r.ker.kind == H2S_K_LOG_R) {
             // 0.5 ln x by table reduction: subinterval i of m in [1/2, 1) has centre
-            // z_i = 1/2 + (i + 1/2)/256; store c_i = 1/z_i and -0.5 ln c_i
-            for (int i = 0; i < 128; ++i) {
-                const double c = 1.0 / (0.5 + (i + 0.5) / 256.0);
+            // z_i = 1/2 + (i + 1/2)/512; store c_i = 1/z_i and -0.5 ln c_i
+            for (int i = 0; i < 256; ++i) {
+                const double c = 1.0 / (0.5 + (i + 0.5) / 512.0);
                 tab.push_back(c);
                 tab.push_back((double)(-0.5L * std::log((long double)c)));
             }

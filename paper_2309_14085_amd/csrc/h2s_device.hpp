@@ -104,7 +104,7 @@ template <class P> struct DevTree {
     DevPairs<basis_t> pairs;
     double *qt;           // charges in tree order
     double *yn;           // near-field potentials in tree order
-    const double *ktab;   // kernel-function table: log r (c_i, -0.5 ln c_i) x 128; exponentials 2^(j/64) x 64
+    const double *ktab;   // kernel-function table: log r (c_i, -0.5 ln c_i) x 256; exponentials 2^(j/64) x 64
 };
 
 // Host-side launch shapes, fixed at upload.

@@ -14,7 +14,9 @@
 //                scattered back to user order
 //
 // k_p2p needs only the permuted charges, so it runs on a second stream while
-// the main stream goes up and down the tree; k_down_leaf joins the two.
+// the main stream goes up and down the tree; k_down_leaf joins the two
+// (under the profiling hook everything runs on the main stream, one class
+// at a time).
 //
 // Summation order.  The interpolative NCA operators have norms up to ~1e3 -
 // 1e4 on coarse levels, so a rounding difference in a multipole or local
@@ -51,32 +53,41 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb)
     return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
 }
 
-// s + a b as one fused multiply-add.  ORD marks the sums kept in the order
-// of their definition (it selects the accumulation pattern at the call sites).
-template <bool ORD> __device__ __forceinline__ double madd(double s, double a, double b) { return fma(a, b, s); }
+// s + a b.  ORD: the product and the sum rounded separately, as a plain
+// sequential evaluation does (the HBM-bound sums can afford it); otherwise
+// one fused multiply-add.
+template <bool ORD> __device__ __forceinline__ double madd(double s, double a, double b)
+{
+    if constexpr (ORD) {
+#pragma clang fp contract(off)
+        const double p = a * b;
+        return s + p;
+    } else {
+        return fma(a, b, s);
+    }
+}
 
 // 0.5 ln(x) for finite x > 0 in double, table-driven (Tang's reduction):
-// x = m 2^e with m in [1/2, 1) (frexp); the top 7 fraction bits of m select
-// a subinterval i of width 1/256 with centre z_i, c_i ~ 1/z_i; then
-// r = m c_i - 1 (|r| < 2^-8, one rounding) and
+// x = m 2^e with m in [1/2, 1) (frexp); the top 8 fraction bits of m select
+// a subinterval i of width 1/512 with centre z_i, c_i ~ 1/z_i; then
+// r = m c_i - 1 (|r| < 2^-9, one rounding) and
 //   0.5 ln x = 0.5 e ln 2 - 0.5 ln c_i + 0.5 ln(1 + r),
-// the last term by its Taylor series through r^6 (truncation below 1e-18).
-// tab holds (c_i, -0.5 ln c_i) for the 128 subintervals (built on the host
+// the last term by its Taylor series through r^5 (truncation below 1e-17).
+// tab holds (c_i, -0.5 ln c_i) for the 256 subintervals (built on the host
 // in extended precision).  Absolute error about one ulp of the result.
 __device__ __forceinline__ double half_log(double x, const double2 *tab)
 {
     int e;
     const double m = frexp(x, &e);
-    const int i = (__double2hiint(m) >> 13) & 127;
+    const int i = (__double2hiint(m) >> 12) & 255;
     const double2 c = tab[i];
     const double r = fma(m, c.x, -1.0);
-    double p = -1.0 / 12;
-    p = fma(p, r, 1.0 / 10);
+    double p = 1.0 / 10;
     p = fma(p, r, -1.0 / 8);
     p = fma(p, r, 1.0 / 6);
     p = fma(p, r, -1.0 / 4);
     p = fma(p, r, 1.0 / 2);
-    return fma((double)e, 0.34657359027997264, c.y) + r * p; // ln 2 / 2
+    return fma(r, p, fma((double)e, 0.34657359027997264, c.y)); // ln 2 / 2
 }
 
 // exp(x) in double, table-driven (Tang's reduction): k = nearest integer to
@@ -118,10 +129,10 @@ __device__ __forceinline__ double inv_sqrt(double x)
     return y;
 }
 
-// Lookup tables of the kernel functions, in doubles: log r (c_i, -0.5 ln c_i)
+// Lookup tables of the kernel functions, in doubles: log r 256 (c_i, -0.5 ln c_i)
 // pairs, the exponential kernels 2^(j/64).  Staged in LDS per block.
 template <int KIND>
-constexpr int kTabLen = KIND == H2S_K_LOG_R ? 256 : (KIND == H2S_K_GAUSSIAN || KIND == H2S_K_EXP_R ? 64 : 2);
+constexpr int kTabLen = KIND == H2S_K_LOG_R ? 512 : (KIND == H2S_K_GAUSSIAN || KIND == H2S_K_EXP_R ? 64 : 2);
 
 // Stage the table in LDS (whole block; the caller synchronises).
 template <int KIND> __device__ __forceinline__ void stage_table(const double *g, double *tab)
@@ -437,6 +448,99 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
 }
 
 // ---------------------------------------------------------------------------
+// M2L in double, slice form: one target box X per block.  The pivots and
+// multipoles of every box of IL(X) are staged in LDS (a group at a time) and
+// split into source slices; each thread takes two target pivots (a and
+// a + NP) against one slice, so every staged source serves two evaluations.
+// u_X[a] = sum over slices (in slice order) of the slice's partial sums.
+// X and its list boxes are distinct boxes of one level, so r^2 > 0.
+// ---------------------------------------------------------------------------
+constexpr int NT_M2LS = 256;
+constexpr int M2LS_SRC = 512; // staged source pivots per group
+
+template <class P, bool FAR, int KIND, int D>
+__global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t)
+{
+    const auto &F = [&]() -> const auto & {
+        if constexpr (FAR) return t.far;
+        else return t.ver;
+    }();
+    __shared__ double sx[M2LS_SRC], sy[M2LS_SRC], sz[D == 3 ? M2LS_SRC : 1], sv[M2LS_SRC];
+    __shared__ double red[2 * NT_M2LS];
+    __shared__ __align__(16) double ktab[kTabLen<KIND>];
+    const int tid = threadIdx.x;
+    stage_table<KIND>(t.ktab, ktab); // first used after a barrier
+    const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
+    const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
+    const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
+    const double kp = t.kparam;
+    for (int a0 = 0; a0 < r; a0 += 2 * NT_M2LS) {
+        const int MT = min(r - a0, 2 * NT_M2LS), NP = (MT + 1) / 2, NS = NT_M2LS / NP;
+        const int s = tid / NP, pa = tid % NP;
+        const int ia = a0 + pa, ib = pa + NP < MT ? ia + NP : ia; // a lone last target is paired with itself
+        const double xa = F.pvx[c0 + ia], ya = F.pvy[c0 + ia], za = D == 3 ? (double)F.pvz[c0 + ia] : 0.0;
+        const double xb = F.pvx[c0 + ib], yb = F.pvy[c0 + ib], zb = D == 3 ? (double)F.pvz[c0 + ib] : 0.0;
+        double acc_a = 0.0, acc_b = 0.0;
+        int pos = 0;
+        auto flush = [&]() {
+            __syncthreads();
+            if (s < NS) {
+                double a0s = 0, a1s = 0, b0s = 0, b1s = 0;
+                int j = s;
+                for (; j + NS < pos; j += 2 * NS) {
+                    const int j1 = j + NS;
+                    const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, v0 = sv[j];
+                    const double x1 = sx[j1], y1 = sy[j1], z1 = D == 3 ? sz[j1] : 0.0, v1 = sv[j1];
+                    a0s = fma(kval_pos<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), kp, ktab), v0, a0s);
+                    b0s = fma(kval_pos<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), kp, ktab), v0, b0s);
+                    a1s = fma(kval_pos<KIND>(dist2<false, D>(xa - x1, ya - y1, za - z1), kp, ktab), v1, a1s);
+                    b1s = fma(kval_pos<KIND>(dist2<false, D>(xb - x1, yb - y1, zb - z1), kp, ktab), v1, b1s);
+                }
+                if (j < pos) {
+                    const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, v0 = sv[j];
+                    a0s = fma(kval_pos<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), kp, ktab), v0, a0s);
+                    b0s = fma(kval_pos<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), kp, ktab), v0, b0s);
+                }
+                acc_a += a0s + a1s;
+                acc_b += b0s + b1s;
+            }
+            __syncthreads();
+            pos = 0;
+        };
+        for (int e = e0; e < e1; ++e) {
+            const int y = F.il_idx[e];
+            const int cy = F.coef_off[y], ry = F.coef_off[y + 1] - cy;
+            for (int j0 = 0; j0 < ry;) {
+                const int take = min(ry - j0, M2LS_SRC - pos);
+                for (int j = tid; j < take; j += NT_M2LS) {
+                    sx[pos + j] = F.pvx[cy + j0 + j];
+                    sy[pos + j] = F.pvy[cy + j0 + j];
+                    if constexpr (D == 3) sz[pos + j] = F.pvz[cy + j0 + j];
+                    sv[pos + j] = F.v[cy + j0 + j];
+                }
+                pos += take;
+                j0 += take;
+                if (pos == M2LS_SRC) flush();
+            }
+        }
+        if (pos > 0) flush();
+        red[tid] = s < NS ? acc_a : 0.0;
+        red[NT_M2LS + tid] = s < NS ? acc_b : 0.0;
+        __syncthreads();
+        if (tid < NP) {
+            double ua = 0.0, ub = 0.0;
+            for (int q = 0; q < NS; ++q) {
+                ua += red[q * NP + tid];
+                ub += red[NT_M2LS + q * NP + tid];
+            }
+            F.u[c0 + ia] = ua;
+            if (ib != ia) F.u[c0 + ib] = ub;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // (H2+H)*: partial sums over one row chunk of G^T q, G = Vb over the rows of
 // Y (side 0: w = Vb^T q_Y) or Ub over the rows of X (side 1: w' = Ub^T q_X).
 // ---------------------------------------------------------------------------
@@ -479,8 +583,10 @@ template <class P> __global__ __launch_bounds__(64) void k_pair_sum(DevTree<P> t
 }
 
 // ---------------------------------------------------------------------------
-// Near field: one target leaf per block, its near list N*(X) staged in LDS
-// and split over source slices; yn[i] = sum_{j in N*(X)} K(x_i, x_j) q_j.
+// Near field: one target leaf per block, its near list N*(X) staged in LDS;
+// yn[i] = sum_{j in N*(X)} K(x_i, x_j) q_j.  Each thread takes two targets
+// (a and a + P) against one slice of the staged sources, so every source it
+// loads serves two evaluations.
 // ---------------------------------------------------------------------------
 constexpr int NT_P2P = 256;
 constexpr int P2P_SRC = 1024; // staged source points per group
@@ -491,7 +597,7 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t)
     using PT = typename P::pt_t;
     constexpr bool TAB = sizeof(PT) == 8;
     __shared__ PT sx[P2P_SRC], sy[P2P_SRC], sz[D == 3 ? P2P_SRC : 1], sq[P2P_SRC];
-    __shared__ double red[NT_P2P];
+    __shared__ double red[2 * NT_P2P];
     __shared__ __align__(16) double ktab[TAB ? kTabLen<KIND> : 2];
     const int tid = threadIdx.x;
     const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf;
@@ -499,12 +605,16 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t)
     const PT diag = (PT)t.diag, kp = (PT)t.kparam;
     const double *cX = t.box_ctr + 3 * g;
     if constexpr (TAB) stage_table<KIND>(t.ktab, ktab); // first used after a barrier
-    for (int i0 = 0; i0 < n; i0 += NT_P2P) {
-        const int m = min(n - i0, NT_P2P), S = NT_P2P / m, s = tid / m, i = i0 + tid % m;
-        const PT xi = t.px[b + i], yi = t.py[b + i], zi = D == 3 ? t.pz[b + i] : PT(0);
-        double acc = 0.0;
+    for (int i0 = 0; i0 < n; i0 += 2 * NT_P2P) {
+        // MT targets this pass as NP pairs (a, a + NP); NS source slices
+        const int MT = min(n - i0, 2 * NT_P2P), NP = (MT + 1) / 2, NS = NT_P2P / NP;
+        const int s = tid / NP, pa = tid % NP;
+        const int ia = i0 + pa, ib = pa + NP < MT ? ia + NP : ia; // a lone last target is paired with itself
+        const PT xa = t.px[b + ia], ya = t.py[b + ia], za = D == 3 ? t.pz[b + ia] : PT(0);
+        const PT xb = t.px[b + ib], yb = t.py[b + ib], zb = D == 3 ? t.pz[b + ib] : PT(0);
+        double acc_a = 0.0, acc_b = 0.0;
         int pos = 0, self0 = 0, self1 = 0; // staged positions of the target leaf's own points
-        // slice s takes the staged sources jb + s, jb + s + S, ... below je
+        // slice s takes the staged sources jb + s, jb + s + NS, ... below je
         auto slice_sum = [&](int jb, int je, auto check) {
             constexpr bool CHECK = decltype(check)::value;
             auto k = [&](PT r2) -> PT {
@@ -515,25 +625,32 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t)
                     return kval<KIND>(r2, diag, kp);
                 }
             };
-            PT part[4] = {0, 0, 0, 0};
+            PT a0 = 0, a1 = 0, b0 = 0, b1 = 0;
             int j = jb + s;
-            for (; j + 3 * S < je; j += 4 * S) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int jj = j + u * S;
-                    part[u] += k(dist2<false, D>(xi - sx[jj], yi - sy[jj], zi - sz[D == 3 ? jj : 0])) * sq[jj];
-                }
+            for (; j + NS < je; j += 2 * NS) {
+                const int j1 = j + NS;
+                const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
+                const PT x1 = sx[j1], y1 = sy[j1], z1 = D == 3 ? sz[j1] : PT(0), q1 = sq[j1];
+                a0 += k(dist2<false, D>(xa - x0, ya - y0, za - z0)) * q0;
+                b0 += k(dist2<false, D>(xb - x0, yb - y0, zb - z0)) * q0;
+                a1 += k(dist2<false, D>(xa - x1, ya - y1, za - z1)) * q1;
+                b1 += k(dist2<false, D>(xb - x1, yb - y1, zb - z1)) * q1;
             }
-            for (; j < je; j += S) part[0] += k(dist2<false, D>(xi - sx[j], yi - sy[j], zi - sz[D == 3 ? j : 0])) * sq[j];
-            return (double)((part[0] + part[1]) + (part[2] + part[3]));
+            if (j < je) {
+                const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
+                a0 += k(dist2<false, D>(xa - x0, ya - y0, za - z0)) * q0;
+                b0 += k(dist2<false, D>(xb - x0, yb - y0, zb - z0)) * q0;
+            }
+            acc_a += (double)(a0 + a1);
+            acc_b += (double)(b0 + b1);
         };
         auto flush = [&]() {
             __syncthreads();
-            if (s < S) {
+            if (s < NS) {
                 // only the target leaf's own points can coincide with a target
-                acc += slice_sum(0, self0, std::false_type{});
-                acc += slice_sum(self0, self1, std::true_type{});
-                acc += slice_sum(self1, pos, std::false_type{});
+                slice_sum(0, self0, std::false_type{});
+                slice_sum(self0, self1, std::true_type{});
+                slice_sum(self1, pos, std::false_type{});
             }
             __syncthreads();
             pos = self0 = self1 = 0;
@@ -572,12 +689,17 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t)
             }
         }
         if (pos > 0) flush();
-        red[tid] = s < S ? acc : 0.0;
+        red[tid] = s < NS ? acc_a : 0.0;
+        red[NT_P2P + tid] = s < NS ? acc_b : 0.0;
         __syncthreads();
-        if (tid < m) {
-            double phi = 0.0;
-            for (int q = 0; q < S; ++q) phi += red[q * m + tid];
-            t.yn[b + i] = phi;
+        if (tid < NP) {
+            double phi_a = 0.0, phi_b = 0.0;
+            for (int q = 0; q < NS; ++q) {
+                phi_a += red[q * NP + tid];
+                phi_b += red[NT_P2P + q * NP + tid];
+            }
+            t.yn[b + ia] = phi_a;
+            if (ib != ia) t.yn[b + ib] = phi_b;
         }
         __syncthreads();
     }
@@ -652,17 +774,23 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     // the near field needs only the permuted charges: run it on the second
-    // stream while the main stream goes up and down the tree
-    if (mask & kNear) {
+    // stream while the main stream goes up and down the tree.  Under the
+    // profiling hook it runs on the main stream instead, so that every kernel
+    // class is timed alone.
+    const bool overlap = (mask & kNear) && !prof;
+    if (overlap) {
         if ((err = hipEventRecord((hipEvent_t)st.fork, s)) != hipSuccess) return err;
         if ((err = hipStreamWaitEvent(aux, (hipEvent_t)st.fork, 0)) != hipSuccess) return err;
-        mark(H2S_PROF_NEAR, 0, aux);
         hipLaunchKernelGGL((k_p2p<P, KIND, D>), dim3(t.nleaf), dim3(NT_P2P), 0, aux, t);
-        mark(H2S_PROF_NEAR, 1, aux);
         if ((err = hipEventRecord((hipEvent_t)st.join, aux)) != hipSuccess) return err;
     }
     if (fam_on) hipLaunchKernelGGL(k_up_leaf<P>, dim3(t.nleaf), dim3(plan.up_threads[t.kappa]), lds_leaf, s, t, mask);
     mark(H2S_PROF_LEAF_UP, 1, s);
+    if ((mask & kNear) && !overlap) {
+        mark(H2S_PROF_NEAR, 0, s);
+        hipLaunchKernelGGL((k_p2p<P, KIND, D>), dim3(t.nleaf), dim3(NT_P2P), 0, s, t);
+        mark(H2S_PROF_NEAR, 1, s);
+    }
     if (fam_on) {
         mark(H2S_PROF_M2M, 0, s);
         for (int l = t.kappa - 1; l >= 1; --l) {
@@ -673,12 +801,15 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
         mark(H2S_PROF_M2M, 1, s);
         if ((mask & kFar) && t.far.ntargets) {
             mark(H2S_PROF_M2L_FAR, 0, s);
-            hipLaunchKernelGGL((k_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_M2L), 0, s, t);
+            if constexpr (sizeof(typename P::far_t) == 4)
+                hipLaunchKernelGGL((k_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_M2L), 0, s, t);
+            else
+                hipLaunchKernelGGL((k_m2l_slices<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_M2LS), 0, s, t);
             mark(H2S_PROF_M2L_FAR, 1, s);
         }
         if ((mask & kVer) && t.ver.ntargets) {
             mark(H2S_PROF_M2L_VER, 0, s);
-            hipLaunchKernelGGL((k_m2l<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_M2L), 0, s, t);
+            hipLaunchKernelGGL((k_m2l_slices<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_M2LS), 0, s, t);
             mark(H2S_PROF_M2L_VER, 1, s);
         }
         mark(H2S_PROF_L2L, 0, s);
@@ -697,7 +828,7 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
         hipLaunchKernelGGL(k_pair_sum<P>, dim3(2 * t.pairs.npairs), dim3(64), 0, s, t);
         mark(H2S_PROF_PAIR_SUM, 1, s);
     }
-    if (mask & kNear)
+    if (overlap)
         if ((err = hipStreamWaitEvent(s, (hipEvent_t)st.join, 0)) != hipSuccess) return err;
     mark(H2S_PROF_LEAF_DOWN, 0, s);
     hipLaunchKernelGGL(k_down_leaf<P>, dim3(t.nleaf), dim3(NT_LEAF), 0, s, t, y, mask);

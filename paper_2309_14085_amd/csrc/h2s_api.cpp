@@ -68,7 +68,7 @@ struct h2s_tree_s {
     std::vector<Mark> marks;
     // second stream for the near field and the events that fork / join it
     hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_fork2 = nullptr, ev_join = nullptr;
     // which precisions are on the device
     bool up[3] = {false, false, false};
     // solve workspace for restart length solve_m (device memory is in allocs)
@@ -92,6 +92,7 @@ struct h2s_tree_s {
             (void)hipStreamDestroy(aux);
         }
         if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_fork2) (void)hipEventDestroy(ev_fork2);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (work.small_host) (void)hipHostFree(work.small_host);
         for (void *p : allocs) ffn(actx, p);
@@ -454,16 +455,19 @@ h2s_status ensure_streams(h2s_tree t)
 {
     if (t->aux) return H2S_OK;
     hipStream_t a = nullptr;
-    hipEvent_t f = nullptr, j = nullptr;
+    hipEvent_t f = nullptr, f2 = nullptr, j = nullptr;
     if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&f2, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
         if (a) (void)hipStreamDestroy(a);
         if (f) (void)hipEventDestroy(f);
+        if (f2) (void)hipEventDestroy(f2);
         return fail(H2S_ERR_DEVICE, "creating the near-field stream or its events failed");
     }
     t->aux = a;
     t->ev_fork = f;
+    t->ev_fork2 = f2;
     t->ev_join = j;
     return H2S_OK;
 }
@@ -472,7 +476,7 @@ h2s_status ensure_streams(h2s_tree t)
 int mvp(h2s_tree t, h2s_precision p, uint32_t mask, const double *x, double *y, void *stream,
         const h2s::ProfileHook *prof)
 {
-    const h2s::Streams st{stream, t->aux, t->ev_fork, t->ev_join};
+    const h2s::Streams st{stream, t->aux, t->ev_fork, t->ev_fork2, t->ev_join};
     if (p == H2S_FP64) return h2s::launch_mvp<h2s::P64>(t->t64, t->plan, x, y, mask, st, prof);
     if (p == H2S_FP32) return h2s::launch_mvp<h2s::P32>(t->t32, t->plan, x, y, mask, st, prof);
     return h2s::launch_mvp<h2s::P32M>(t->t32m, t->plan, x, y, mask, st, prof);

@@ -121,10 +121,11 @@ struct ProfileHook {
     void (*mark)(void *ctx, int cls, int end, void *stream);
 };
 
-// The caller's stream, the handle's second stream (near field) and the two
-// events that fork the second stream from the first and join it back.
+// The caller's stream, the handle's second stream (near field) and the
+// events that fork the second stream from the first (twice per product) and
+// join it back.
 struct Streams {
-    void *main, *aux, *fork, *join;
+    void *main, *aux, *fork, *fork2, *join;
 };
 
 // Enqueue one product y = K~ x (single right-hand side), ordered on st.main.

@@ -188,6 +188,7 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v)
 // in one pass.
 // ---------------------------------------------------------------------------
 constexpr int NT_GEMV_MAX = 512;
+constexpr int GEMV_WAVES = 5; // waves per SIMD asked of the compiler (bytes in flight)
 
 // Ordered dot product sum_j a(j) x[j], a(j) = A[j stride].  The sum itself is
 // sequential; the operator loads are software-pipelined two batches of UNR
@@ -237,7 +238,7 @@ template <class P> __global__ __launch_bounds__(256) void k_permute(DevTree<P> t
     if (i < t.n) t.qt[i] = x[t.perm[i]];
 }
 
-template <class P> __global__ __launch_bounds__(NT_GEMV_MAX) void k_up_leaf(DevTree<P> t, uint32_t mask)
+template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_up_leaf(DevTree<P> t, uint32_t mask)
 {
     extern __shared__ double qs[]; // largest leaf
     const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf, tid = threadIdx.x, nt = blockDim.x;
@@ -248,12 +249,15 @@ template <class P> __global__ __launch_bounds__(NT_GEMV_MAX) void k_up_leaf(DevT
     const int cv = t.ver.coef_off[g], rv = (mask & kVer) && t.kappa >= t.ver.lmin ? t.ver.coef_off[g + 1] - cv : 0;
     // one column of the two families per thread (U row-major n x r: column k strided by r)
     for (int k = tid; k < rf + rv; k += nt) {
-        if (k < rf) t.far.v[cf + k] = ordered_dot<P::ordered>(t.far.U_rm + t.far.uoff[leaf] + k, (size_t)rf, n, qs);
-        else t.ver.v[cv + k - rf] = ordered_dot<P::ordered>(t.ver.U_rm + t.ver.uoff[leaf] + (k - rf), (size_t)rv, n, qs);
+        const bool f = k < rf;
+        const int kk = f ? k : k - rf;
+        const auto *A = f ? t.far.U_rm + t.far.uoff[leaf] + kk : t.ver.U_rm + t.ver.uoff[leaf] + kk;
+        double *out = f ? t.far.v + cf + kk : t.ver.v + cv + kk;
+        *out = ordered_dot<P::ordered>(A, (size_t)(f ? rf : rv), n, qs);
     }
 }
 
-template <class P> __global__ __launch_bounds__(NT_GEMV_MAX) void k_m2m(DevTree<P> t, int32_t g0, uint32_t mask)
+template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_m2m(DevTree<P> t, int32_t g0, uint32_t mask)
 {
     extern __shared__ double xs[]; // both families' child coefficients
     const int g = g0 + blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
@@ -268,12 +272,15 @@ template <class P> __global__ __launch_bounds__(NT_GEMV_MAX) void k_m2m(DevTree<
     __syncthreads();
     // stacked transfers row-major (sum r_c) x r: column k strided by r
     for (int k = tid; k < rf + rv; k += nt) {
-        if (k < rf) Fa.v[cf + k] = ordered_dot<P::ordered>(Fa.Tr_rm + Fa.troff[g] + k, (size_t)rf, Rf, xs);
-        else Ve.v[cv + k - rf] = ordered_dot<P::ordered>(Ve.Tr_rm + Ve.troff[g] + (k - rf), (size_t)rv, Rv, xs + Rf);
+        const bool f = k < rf;
+        const int kk = f ? k : k - rf;
+        const double *A = f ? Fa.Tr_rm + Fa.troff[g] + kk : Ve.Tr_rm + Ve.troff[g] + kk;
+        double *out = f ? Fa.v + cf + kk : Ve.v + cv + kk;
+        *out = ordered_dot<P::ordered>(A, (size_t)(f ? rf : rv), f ? Rf : Rv, f ? xs : xs + Rf);
     }
 }
 
-template <class P> __global__ __launch_bounds__(NT_GEMV_MAX) void k_l2l(DevTree<P> t, int32_t g0, uint32_t mask)
+template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_l2l(DevTree<P> t, int32_t g0, uint32_t mask)
 {
     extern __shared__ double xs[]; // both families' parent locals
     constexpr bool ORD = P::ordered;
@@ -289,14 +296,12 @@ template <class P> __global__ __launch_bounds__(NT_GEMV_MAX) void k_l2l(DevTree<
     __syncthreads();
     // stacked transfers column-major (sum r_c) x r: row j strided by the row count
     for (int j = tid; j < Rf + Rv; j += nt) {
-        if (j < Rf) {
-            const double s = ordered_dot<ORD>(Fa.Tr_cm + Fa.troff[g] + j, (size_t)Rf, rf, xs);
-            Fa.u[bf + j] = Fa.u[bf + j] + s;
-        } else {
-            const int jj = j - Rf;
-            const double s = ordered_dot<ORD>(Ve.Tr_cm + Ve.troff[g] + jj, (size_t)Rv, rv, xs + rf);
-            Ve.u[bv + jj] = Ve.u[bv + jj] + s;
-        }
+        const bool f = j < Rf;
+        const int jj = f ? j : j - Rf;
+        const double *A = f ? Fa.Tr_cm + Fa.troff[g] + jj : Ve.Tr_cm + Ve.troff[g] + jj;
+        double *out = f ? Fa.u + bf + jj : Ve.u + bv + jj;
+        const double s = ordered_dot<ORD>(A, (size_t)(f ? Rf : Rv), f ? rf : rv, f ? xs : xs + rf);
+        *out = *out + s;
     }
 }
 
@@ -589,10 +594,11 @@ template <class P> __global__ __launch_bounds__(64) void k_pair_sum(DevTree<P> t
 // loads serves two evaluations.
 // ---------------------------------------------------------------------------
 constexpr int NT_P2P = 256;
-constexpr int P2P_SRC = 1024; // staged source points per group
+constexpr int P2P_SRC = 1024;     // staged source points per group
+constexpr double kNearFirst = 0.6; // share of the leaves whose near field overlaps P2M and M2M
 
 template <class P, int KIND, int D>
-__global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t)
+__global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin, int32_t leaf_count)
 {
     using PT = typename P::pt_t;
     constexpr bool TAB = sizeof(PT) == 8;
@@ -600,108 +606,113 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t)
     __shared__ double red[2 * NT_P2P];
     __shared__ __align__(16) double ktab[TAB ? kTabLen<KIND> : 2];
     const int tid = threadIdx.x;
-    const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf;
-    const int b = t.box_begin[g], n = t.box_end[g] - b;
     const PT diag = (PT)t.diag, kp = (PT)t.kparam;
-    const double *cX = t.box_ctr + 3 * g;
     if constexpr (TAB) stage_table<KIND>(t.ktab, ktab); // first used after a barrier
-    for (int i0 = 0; i0 < n; i0 += 2 * NT_P2P) {
-        // MT targets this pass as NP pairs (a, a + NP); NS source slices
-        const int MT = min(n - i0, 2 * NT_P2P), NP = (MT + 1) / 2, NS = NT_P2P / NP;
-        const int s = tid / NP, pa = tid % NP;
-        const int ia = i0 + pa, ib = pa + NP < MT ? ia + NP : ia; // a lone last target is paired with itself
-        const PT xa = t.px[b + ia], ya = t.py[b + ia], za = D == 3 ? t.pz[b + ia] : PT(0);
-        const PT xb = t.px[b + ib], yb = t.py[b + ib], zb = D == 3 ? t.pz[b + ib] : PT(0);
-        double acc_a = 0.0, acc_b = 0.0;
-        int pos = 0, self0 = 0, self1 = 0; // staged positions of the target leaf's own points
-        // slice s takes the staged sources jb + s, jb + s + NS, ... below je
-        auto slice_sum = [&](int jb, int je, auto check) {
-            constexpr bool CHECK = decltype(check)::value;
-            auto k = [&](PT r2) -> PT {
-                if constexpr (sizeof(PT) == 8) {
-                    if constexpr (CHECK) return kval<KIND>(r2, diag, kp, ktab);
-                    else return kval_pos<KIND>(r2, kp, ktab);
-                } else {
-                    return kval<KIND>(r2, diag, kp);
-                }
-            };
-            PT a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-            int j = jb + s;
-            for (; j + NS < je; j += 2 * NS) {
-                const int j1 = j + NS;
-                const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
-                const PT x1 = sx[j1], y1 = sy[j1], z1 = D == 3 ? sz[j1] : PT(0), q1 = sq[j1];
-                a0 += k(dist2<false, D>(xa - x0, ya - y0, za - z0)) * q0;
-                b0 += k(dist2<false, D>(xb - x0, yb - y0, zb - z0)) * q0;
-                a1 += k(dist2<false, D>(xa - x1, ya - y1, za - z1)) * q1;
-                b1 += k(dist2<false, D>(xb - x1, yb - y1, zb - z1)) * q1;
-            }
-            if (j < je) {
-                const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
-                a0 += k(dist2<false, D>(xa - x0, ya - y0, za - z0)) * q0;
-                b0 += k(dist2<false, D>(xb - x0, yb - y0, zb - z0)) * q0;
-            }
-            acc_a += (double)(a0 + a1);
-            acc_b += (double)(b0 + b1);
-        };
-        auto flush = [&]() {
-            __syncthreads();
-            if (s < NS) {
-                // only the target leaf's own points can coincide with a target
-                slice_sum(0, self0, std::false_type{});
-                slice_sum(self0, self1, std::true_type{});
-                slice_sum(self1, pos, std::false_type{});
-            }
-            __syncthreads();
-            pos = self0 = self1 = 0;
-        };
-        for (int e = t.near_off[leaf]; e < t.near_off[leaf + 1]; ++e) {
-            const int gs = t.leaf0 + t.near_idx[e];
-            const int sb = t.box_begin[gs], sn = t.box_end[gs] - sb;
-            double dcx = 0, dcy = 0, dcz = 0;
-            if constexpr (P::local) {
-                dcx = t.box_ctr[3 * gs] - cX[0];
-                dcy = t.box_ctr[3 * gs + 1] - cX[1];
-                dcz = t.box_ctr[3 * gs + 2] - cX[2];
-            }
-            for (int j0 = 0; j0 < sn;) {
-                const int take = min(sn - j0, P2P_SRC - pos);
-                for (int j = tid; j < take; j += NT_P2P) {
-                    const int src = sb + j0 + j;
-                    if constexpr (P::local) {
-                        sx[pos + j] = (PT)(dcx + (double)t.px[src]);
-                        sy[pos + j] = (PT)(dcy + (double)t.py[src]);
-                        if constexpr (D == 3) sz[pos + j] = (PT)(dcz + (double)t.pz[src]);
+    // each block takes a contiguous chunk of leaves (one leaf when the grid covers them all)
+    const int chunk = (leaf_count + gridDim.x - 1) / gridDim.x, blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int l_end = min(leaf_count, (blk + 1) * chunk);
+    for (int lf = blk * chunk; lf < l_end; ++lf) {
+        const int leaf = leaf_begin + lf, g = t.leaf0 + leaf;
+        const int b = t.box_begin[g], n = t.box_end[g] - b;
+        const double *cX = t.box_ctr + 3 * g;
+        for (int i0 = 0; i0 < n; i0 += 2 * NT_P2P) {
+            // MT targets this pass as NP pairs (a, a + NP); NS source slices
+            const int MT = min(n - i0, 2 * NT_P2P), NP = (MT + 1) / 2, NS = NT_P2P / NP;
+            const int s = tid / NP, pa = tid % NP;
+            const int ia = i0 + pa, ib = pa + NP < MT ? ia + NP : ia; // a lone last target is paired with itself
+            const PT xa = t.px[b + ia], ya = t.py[b + ia], za = D == 3 ? t.pz[b + ia] : PT(0);
+            const PT xb = t.px[b + ib], yb = t.py[b + ib], zb = D == 3 ? t.pz[b + ib] : PT(0);
+            double acc_a = 0.0, acc_b = 0.0;
+            int pos = 0, self0 = 0, self1 = 0; // staged positions of the target leaf's own points
+            // slice s takes the staged sources jb + s, jb + s + NS, ... below je
+            auto slice_sum = [&](int jb, int je, auto check) {
+                constexpr bool CHECK = decltype(check)::value;
+                auto k = [&](PT r2) -> PT {
+                    if constexpr (sizeof(PT) == 8) {
+                        if constexpr (CHECK) return kval<KIND>(r2, diag, kp, ktab);
+                        else return kval_pos<KIND>(r2, kp, ktab);
                     } else {
-                        sx[pos + j] = t.px[src];
-                        sy[pos + j] = t.py[src];
-                        if constexpr (D == 3) sz[pos + j] = t.pz[src];
+                        return kval<KIND>(r2, diag, kp);
                     }
-                    sq[pos + j] = (PT)t.qt[src];
+                };
+                PT a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+                int j = jb + s;
+                for (; j + NS < je; j += 2 * NS) {
+                    const int j1 = j + NS;
+                    const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
+                    const PT x1 = sx[j1], y1 = sy[j1], z1 = D == 3 ? sz[j1] : PT(0), q1 = sq[j1];
+                    a0 += k(dist2<false, D>(xa - x0, ya - y0, za - z0)) * q0;
+                    b0 += k(dist2<false, D>(xb - x0, yb - y0, zb - z0)) * q0;
+                    a1 += k(dist2<false, D>(xa - x1, ya - y1, za - z1)) * q1;
+                    b1 += k(dist2<false, D>(xb - x1, yb - y1, zb - z1)) * q1;
                 }
-                if (gs == g) {
-                    self0 = pos;
-                    self1 = pos + take;
+                if (j < je) {
+                    const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
+                    a0 += k(dist2<false, D>(xa - x0, ya - y0, za - z0)) * q0;
+                    b0 += k(dist2<false, D>(xb - x0, yb - y0, zb - z0)) * q0;
                 }
-                pos += take;
-                j0 += take;
-                if (pos == P2P_SRC) flush();
+                acc_a += (double)(a0 + a1);
+                acc_b += (double)(b0 + b1);
+            };
+            auto flush = [&]() {
+                __syncthreads();
+                if (s < NS) {
+                    // only the target leaf's own points can coincide with a target
+                    slice_sum(0, self0, std::false_type{});
+                    slice_sum(self0, self1, std::true_type{});
+                    slice_sum(self1, pos, std::false_type{});
+                }
+                __syncthreads();
+                pos = self0 = self1 = 0;
+            };
+            for (int e = t.near_off[leaf]; e < t.near_off[leaf + 1]; ++e) {
+                const int gs = t.leaf0 + t.near_idx[e];
+                const int sb = t.box_begin[gs], sn = t.box_end[gs] - sb;
+                double dcx = 0, dcy = 0, dcz = 0;
+                if constexpr (P::local) {
+                    dcx = t.box_ctr[3 * gs] - cX[0];
+                    dcy = t.box_ctr[3 * gs + 1] - cX[1];
+                    dcz = t.box_ctr[3 * gs + 2] - cX[2];
+                }
+                for (int j0 = 0; j0 < sn;) {
+                    const int take = min(sn - j0, P2P_SRC - pos);
+                    for (int j = tid; j < take; j += NT_P2P) {
+                        const int src = sb + j0 + j;
+                        if constexpr (P::local) {
+                            sx[pos + j] = (PT)(dcx + (double)t.px[src]);
+                            sy[pos + j] = (PT)(dcy + (double)t.py[src]);
+                            if constexpr (D == 3) sz[pos + j] = (PT)(dcz + (double)t.pz[src]);
+                        } else {
+                            sx[pos + j] = t.px[src];
+                            sy[pos + j] = t.py[src];
+                            if constexpr (D == 3) sz[pos + j] = t.pz[src];
+                        }
+                        sq[pos + j] = (PT)t.qt[src];
+                    }
+                    if (gs == g) {
+                        self0 = pos;
+                        self1 = pos + take;
+                    }
+                    pos += take;
+                    j0 += take;
+                    if (pos == P2P_SRC) flush();
+                }
             }
-        }
-        if (pos > 0) flush();
-        red[tid] = s < NS ? acc_a : 0.0;
-        red[NT_P2P + tid] = s < NS ? acc_b : 0.0;
-        __syncthreads();
-        if (tid < NP) {
-            double phi_a = 0.0, phi_b = 0.0;
-            for (int q = 0; q < NS; ++q) {
-                phi_a += red[q * NP + tid];
-                phi_b += red[NT_P2P + q * NP + tid];
+            if (pos > 0) flush();
+            red[tid] = s < NS ? acc_a : 0.0;
+            red[NT_P2P + tid] = s < NS ? acc_b : 0.0;
+            __syncthreads();
+            if (tid < NP) {
+                double phi_a = 0.0, phi_b = 0.0;
+                for (int q = 0; q < NS; ++q) {
+                    phi_a += red[q * NP + tid];
+                    phi_b += red[NT_P2P + q * NP + tid];
+                }
+                t.yn[b + ia] = phi_a;
+                if (ib != ia) t.yn[b + ib] = phi_b;
             }
-            t.yn[b + ia] = phi_a;
-            if (ib != ia) t.yn[b + ib] = phi_b;
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -711,30 +722,29 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t)
 // ---------------------------------------------------------------------------
 constexpr int NT_LEAF = 128;
 
-template <bool ORD, typename F>
-__device__ __forceinline__ double l2p_family(const F &fam, int g, int leaf, int n, int i, int kappa)
-{
-    if (kappa < fam.lmin) return 0.0;
-    const int c0 = fam.coef_off[g], r = fam.coef_off[g + 1] - c0;
-    if (r == 0) return 0.0;
-    return ordered_dot<ORD>(fam.U_cm + fam.uoff[leaf] + i, (size_t)n, r, fam.u + c0);
-}
-
-template <class P> __global__ __launch_bounds__(NT_LEAF) void k_down_leaf(DevTree<P> t, double *__restrict__ y, uint32_t mask)
+template <class P>
+__global__ __launch_bounds__(NT_LEAF, GEMV_WAVES) void k_down_leaf(DevTree<P> t, double *__restrict__ y, uint32_t mask)
 {
     constexpr bool ORD = P::ordered;
+    constexpr int HALF = NT_LEAF / 2;
+    using BT = typename P::basis_t;
+    __shared__ double ver_part[HALF];
     const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
-    for (int i = threadIdx.x; i < n; i += NT_LEAF) {
-        double phi = 0.0;
-        if (mask & kNear) phi = madd<ORD>(t.yn[b + i], t.shift, t.qt[b + i]);
-        if (mask & kFar) {
-            const double f = l2p_family<ORD>(t.far, g, leaf, n, i, t.kappa);
-            phi = phi + f;
-        }
-        if (mask & kVer) {
-            double v = l2p_family<ORD>(t.ver, g, leaf, n, i, t.kappa);
-            if (t.variant == H2S_H2_PLUS_H) {
+    // threads [0, HALF) take the far family of point i, [HALF, NT_LEAF) the vertex family
+    const int f = threadIdx.x < HALF ? 0 : 1, il = threadIdx.x - f * HALF;
+    const bool on = f == 0 ? (mask & kFar) && t.kappa >= t.far.lmin : (mask & kVer) && t.kappa >= t.ver.lmin;
+    const int c0 = f == 0 ? t.far.coef_off[g] : t.ver.coef_off[g];
+    const int r = on ? (f == 0 ? t.far.coef_off[g + 1] : t.ver.coef_off[g + 1]) - c0 : 0;
+    const BT *U = f == 0 ? t.far.U_cm + t.far.uoff[leaf] : t.ver.U_cm + t.ver.uoff[leaf];
+    const double *uc = (f == 0 ? t.far.u : t.ver.u) + c0;
+    for (int i0 = 0; i0 < n; i0 += HALF) {
+        const int i = i0 + il;
+        double fam = 0.0;
+        if (i < n && r) fam = ordered_dot<ORD>(U + i, (size_t)n, r, uc);
+        if (f == 1 && i < n) {
+            double v = fam;
+            if (t.variant == H2S_H2_PLUS_H && (mask & kVer)) {
                 const auto &Pr = t.pairs;
                 for (int l = 1; l <= t.kappa; ++l) {
                     const int X = t.leaf_anc[(size_t)leaf * (t.kappa + 1) + l];
@@ -742,17 +752,24 @@ template <class P> __global__ __launch_bounds__(NT_LEAF) void k_down_leaf(DevTre
                     const int nX = t.box_end[X] - t.box_begin[X];
                     for (int e = Pr.recv_off[X]; e < Pr.recv_off[X + 1]; ++e) {
                         const int ps = Pr.recv[e], p = ps >> 1, side = ps & 1;
-                        const int r = Pr.prank[p];
+                        const int rp = Pr.prank[p];
                         const auto *G = Pr.data + (side == 0 ? Pr.pu[p] : Pr.pv[p]);
-                        const double *w = Pr.w + Pr.pw[p] + (size_t)side * r;
-                        const double d = ordered_dot<ORD>(G + off, (size_t)nX, r, w);
-                        v = v + d;
+                        const double *w = Pr.w + Pr.pw[p] + (size_t)side * rp;
+                        v = v + ordered_dot<ORD>(G + off, (size_t)nX, rp, w);
                     }
                 }
             }
-            phi = phi + v;
+            ver_part[il] = v;
         }
-        y[t.perm[b + i]] = phi;
+        __syncthreads();
+        if (f == 0 && i < n) {
+            double phi = 0.0;
+            if (mask & kNear) phi = madd<ORD>(t.yn[b + i], t.shift, t.qt[b + i]);
+            if (mask & kFar) phi = phi + fam;
+            if (mask & kVer) phi = phi + ver_part[il];
+            y[t.perm[b + i]] = phi;
+        }
+        __syncthreads();
     }
 }
 
@@ -773,22 +790,27 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
     hipLaunchKernelGGL(k_permute<P>, dim3((t.n + 255) / 256), dim3(256), 0, s, t, x);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    // the near field needs only the permuted charges: run it on the second
-    // stream while the main stream goes up and down the tree.  Under the
-    // profiling hook it runs on the main stream instead, so that every kernel
-    // class is timed alone.
+    // The near field needs only the permuted charges.  It runs on the second
+    // stream in two pieces: the first kNearFirst of the leaves beside P2P and
+    // M2M (HBM- and latency-bound), the rest beside L2L, so that it shares
+    // the GPU with the memory-bound sweeps rather than with the ALU-bound
+    // M2L.  Under the profiling hook it runs on the main stream instead, so
+    // that every kernel class is timed alone.
     const bool overlap = (mask & kNear) && !prof;
-    if (overlap) {
-        if ((err = hipEventRecord((hipEvent_t)st.fork, s)) != hipSuccess) return err;
-        if ((err = hipStreamWaitEvent(aux, (hipEvent_t)st.fork, 0)) != hipSuccess) return err;
-        hipLaunchKernelGGL((k_p2p<P, KIND, D>), dim3(t.nleaf), dim3(NT_P2P), 0, aux, t);
-        if ((err = hipEventRecord((hipEvent_t)st.join, aux)) != hipSuccess) return err;
-    }
+    const int near1 = overlap && fam_on ? (int)(kNearFirst * t.nleaf) : t.nleaf;
+    auto fork_near = [&](hipEvent_t ev, int lb, int le) -> hipError_t {
+        hipError_t e2;
+        if ((e2 = hipEventRecord(ev, s)) != hipSuccess) return e2;
+        if ((e2 = hipStreamWaitEvent(aux, ev, 0)) != hipSuccess) return e2;
+        if (le > lb) hipLaunchKernelGGL((k_p2p<P, KIND, D>), dim3(le - lb), dim3(NT_P2P), 0, aux, t, lb, le - lb);
+        return hipEventRecord((hipEvent_t)st.join, aux);
+    };
+    if (overlap && (err = fork_near((hipEvent_t)st.fork, 0, near1)) != hipSuccess) return err;
     if (fam_on) hipLaunchKernelGGL(k_up_leaf<P>, dim3(t.nleaf), dim3(plan.up_threads[t.kappa]), lds_leaf, s, t, mask);
     mark(H2S_PROF_LEAF_UP, 1, s);
     if ((mask & kNear) && !overlap) {
         mark(H2S_PROF_NEAR, 0, s);
-        hipLaunchKernelGGL((k_p2p<P, KIND, D>), dim3(t.nleaf), dim3(NT_P2P), 0, s, t);
+        hipLaunchKernelGGL((k_p2p<P, KIND, D>), dim3(t.nleaf), dim3(NT_P2P), 0, s, t, 0, t.nleaf);
         mark(H2S_PROF_NEAR, 1, s);
     }
     if (fam_on) {
@@ -812,6 +834,7 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
             hipLaunchKernelGGL((k_m2l_slices<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_M2LS), 0, s, t);
             mark(H2S_PROF_M2L_VER, 1, s);
         }
+        if (overlap && (err = fork_near((hipEvent_t)st.fork2, near1, t.nleaf)) != hipSuccess) return err;
         mark(H2S_PROF_L2L, 0, s);
         for (int l = 1; l <= t.kappa - 1; ++l) {
             const int nb = lev_off[l + 1] - lev_off[l];

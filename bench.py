@@ -35,6 +35,7 @@ def parse():
     p.add_argument("--calib-copy", action="store_true",
                    help="also run one plain 256 MiB device copy (reference for the HBM byte counters)")
     p.add_argument("--no-solve", action="store_true", help="skip the RBF interpolation solve beside the MVP")
+    p.add_argument("--no-multi-rhs", action="store_true", help="skip the 3D 32-RHS batched product beside the MVP")
     p.add_argument("--profile-only", action="store_true",
                    help="skip the timed steps: warm-up and the per-class profiled steps only (for rocprofv3 runs)")
     return p.parse_args()
@@ -98,6 +99,50 @@ def time_solve(h2s, torch, w):
             "inner": "fp32", "rtol": 1e-8, "seconds": sec, "iterations": i["iterations"],
             "refinements": i["refinements"], "ms_per_iteration": 1e3 * sec / max(i["iterations"], 1),
             "residual_fp64": i["residual"], "converged": i["converged"]}
+
+
+def time_multi_rhs(h2s, torch, w, reps=3):
+    """FP64 H2* product of 32 right-hand sides: one h2s_apply with nrhs = 32 (blocks of 8 columns
+    through the batched kernels) against 32 single-column applies; build untimed."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    T = h2s.build(w.points(), kind=w.kind, leaf_size=w.nmax, eps=w.eps)
+    t_init = time.perf_counter() - t0
+    Q = np.asfortranarray(w.rhs())
+    X = torch.from_numpy(Q).to(dev)                      # (n, m), column-major
+    X = X.t().contiguous().t() if X.stride(0) != 1 else X
+    Yb = torch.empty((w.nrhs, w.n), dtype=torch.float64, device=dev).t()
+    Ys = torch.empty_like(Yb)
+    T.apply(X, Yb)
+    for c in range(w.nrhs):
+        T.apply(X[:, c].contiguous(), Ys[:, c])
+    torch.cuda.synchronize()
+    cols = [X[:, c].contiguous() for c in range(w.nrhs)]
+    outs = [torch.empty(w.n, dtype=torch.float64, device=dev) for _ in range(w.nrhs)]
+
+    def timed(fn):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    ms_b = timed(lambda: T.apply(X, Yb))
+    ms_s = timed(lambda: [T.apply(cols[c], outs[c]) for c in range(w.nrhs)])
+    for c in range(w.nrhs):
+        Ys[:, c] = outs[c]
+    diff = float(((Yb - Ys).norm(dim=0) / Ys.norm(dim=0)).max())
+    st = T.stats()
+    T.free()
+    return {"workload": w.name, "n": w.n, "d": w.d, "kernel": "1/r (K_ii = 0)", "nca_tol": w.eps, "nrhs": w.nrhs,
+            "dtype": "f64", "batched_ms": ms_b, "per_vector_ms": ms_s, "speedup": ms_s / ms_b,
+            "points_x_rhs_per_s_batched": w.n * w.nrhs / (ms_b * 1e-3),
+            "points_x_rhs_per_s_per_vector": w.n * w.nrhs / (ms_s * 1e-3),
+            "max_rel_diff_batched_vs_per_vector": diff, "t_init_s": t_init,
+            "m2l_evals_per_rhs": st["m2l_evals"], "p2p_evals_per_rhs": st["p2p_evals"]}
 
 
 def algorithmic_work(stats, kernel, prec):
@@ -182,6 +227,12 @@ def main():
         solve = time_solve(h2s, torch, inputs.workload("2d_gauss_rbf_n262144"))
         print(f"# solve: {solve}", file=sys.stderr, flush=True)
 
+    multi = None
+    if not a.no_multi_rhs:
+        print("# building and timing the 32-RHS batched product", file=sys.stderr, flush=True)
+        multi = time_multi_rhs(h2s, torch, inputs.workload("3d_invr_n262144_m32"))
+        print(f"# multi-rhs: {multi}", file=sys.stderr, flush=True)
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(pts, q, w)
@@ -204,6 +255,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "solve": solve,
+        "multi_rhs": multi,
         "variants": {k: {kk: vv for kk, vv in v.items() if kk != "stats"} for k, v in res.items()},
         "ranks": {"far_max_by_level": m["stats"]["rank_max_level"][0],
                   "ver_max_by_level": m["stats"]["rank_max_level"][1],

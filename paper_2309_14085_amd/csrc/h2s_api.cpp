@@ -71,6 +71,8 @@ struct h2s_tree_s {
     hipEvent_t ev_fork = nullptr, ev_fork2 = nullptr, ev_join = nullptr;
     // which precisions are on the device
     bool up[3] = {false, false, false};
+    // multi-RHS block buffers allocated for these precisions
+    bool batch[3] = {false, false, false};
     // solve workspace for restart length solve_m (device memory is in allocs)
     int solve_m = 0;
     h2s::SolveWork work{};
@@ -482,6 +484,58 @@ int mvp(h2s_tree t, h2s_precision p, uint32_t mask, const double *x, double *y, 
     return h2s::launch_mvp<h2s::P32M>(t->t32m, t->plan, x, y, mask, st, prof);
 }
 
+// The batched product serves H2* with a double far field.
+template <class P> bool batch_supported(h2s_tree t, const h2s::DevTree<P> &)
+{
+    return t->rep.variant == H2S_H2STAR && sizeof(typename P::far_t) == 8;
+}
+
+// Allocate the multi-RHS block buffers of precision p on first use.
+template <class P> h2s_status ensure_batch(h2s_tree t, h2s::DevTree<P> &D, int p, hipStream_t s)
+{
+    if (t->batch[p]) return H2S_OK;
+    Uploader up{t, s};
+    const size_t nb = h2s::kBatch;
+    D.qb = up.template zeros<double>((size_t)D.n * nb);
+    D.ynb = up.template zeros<double>((size_t)D.n * nb);
+    const size_t nf = (size_t)t->rep.fam[0].coef_off.back(), nv = (size_t)t->rep.fam[1].coef_off.back();
+    D.far.vb = up.template zeros<double>((nf ? nf : 1) * nb);
+    D.far.ub = up.template zeros<double>((nf ? nf : 1) * nb);
+    D.ver.vb = up.template zeros<double>((nv ? nv : 1) * nb);
+    D.ver.ub = up.template zeros<double>((nv ? nv : 1) * nb);
+    if (up.st != H2S_OK) return up.st;
+    t->batch[p] = true;
+    return H2S_OK;
+}
+
+// y = K~ x for nrhs columns: blocks of kBatch through the batched product when
+// it applies, otherwise one column at a time.
+template <class P>
+h2s_status apply_columns(h2s_tree t, h2s::DevTree<P> &D, int p, uint32_t mask, const double *x, double *y,
+                         int32_t nrhs, int64_t ldx, int64_t ldy, void *stream, const h2s::ProfileHook *prof)
+{
+    const h2s::Streams st{stream, t->aux, t->ev_fork, t->ev_fork2, t->ev_join};
+    int32_t c = 0;
+    if constexpr (sizeof(typename P::far_t) == 8) { // the batched kernels exist for a double far field only
+        if (nrhs > 1 && !prof && batch_supported(t, D)) {
+            const h2s_status bs = ensure_batch(t, D, p, (hipStream_t)stream);
+            if (bs != H2S_OK) return bs;
+            for (; c + 1 < nrhs; c += h2s::kBatch) {
+                const int na = std::min<int32_t>(h2s::kBatch, nrhs - c);
+                const int rc = h2s::launch_mvp_batch<P>(D, t->plan, x + c * ldx, ldx, y + c * ldy, ldy, na, mask, st);
+                if (rc != 0)
+                    return fail(H2S_ERR_DEVICE,
+                                std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
+            }
+        }
+    }
+    for (; c < nrhs; ++c) {
+        const int rc = h2s::launch_mvp<P>(D, t->plan, x + c * ldx, y + c * ldy, mask, st, prof);
+        if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
+    }
+    return H2S_OK;
+}
+
 struct SolveCtx {
     h2s_tree t;
     h2s_precision inner;
@@ -616,11 +670,9 @@ h2s_status h2s_apply_phases(h2s_tree t, uint32_t mask, const double *x, double *
     if (ensure_streams(t) != H2S_OK) return H2S_ERR_DEVICE;
     h2s::ProfileHook hook{t, record_mark};
     const h2s::ProfileHook *prof = t->profiling ? &hook : nullptr;
-    for (int32_t c = 0; c < nrhs; ++c) {
-        const int rc = mvp(t, t->opts.prec, mask, x + c * ldx, y + c * ldy, stream, prof);
-        if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
-    }
-    return H2S_OK;
+    if (t->opts.prec == H2S_FP64) return apply_columns(t, t->t64, H2S_FP64, mask, x, y, nrhs, ldx, ldy, stream, prof);
+    if (t->opts.prec == H2S_FP32) return apply_columns(t, t->t32, H2S_FP32, mask, x, y, nrhs, ldx, ldy, stream, prof);
+    return apply_columns(t, t->t32m, H2S_FP32_M2L, mask, x, y, nrhs, ldx, ldy, stream, prof);
 }
 
 h2s_status h2s_apply(h2s_tree t, const double *x, double *y, int32_t nrhs, int64_t ldx, int64_t ldy, void *stream)

@@ -68,6 +68,7 @@ template <typename CT, typename BT> struct DevFamily {
     const int32_t *targets;      // boxes with rank > 0 at levels >= lmin
     int32_t ntargets;
     double *v, *u;
+    double *vb, *ub;             // multi-RHS blocks: kBatch entries per coefficient (allocated on first use)
 };
 
 // (H2+H)* vertex-sharing low-rank blocks.
@@ -104,6 +105,7 @@ template <class P> struct DevTree {
     DevPairs<basis_t> pairs;
     double *qt;           // charges in tree order
     double *yn;           // near-field potentials in tree order
+    double *qb, *ynb;     // multi-RHS blocks of both: kBatch entries per point (allocated on first use)
     const double *ktab;   // kernel-function table: log r (c_i, -0.5 ln c_i) x 256; exponentials 2^(j/64) x 64
 };
 
@@ -127,6 +129,16 @@ struct ProfileHook {
 struct Streams {
     void *main, *aux, *fork, *fork2, *join;
 };
+
+// Right-hand sides per block of the batched product.
+constexpr int kBatch = 8;
+
+// Enqueue the product for na <= kBatch right-hand sides at once (x, y
+// column-major with leading dimensions ldx, ldy), ordered on st.main.  H2*
+// with a double far field only; the block buffers must be allocated.
+template <class P>
+int launch_mvp_batch(const DevTree<P> &t, const LaunchPlan &plan, const double *x, int64_t ldx, double *y,
+                     int64_t ldy, int na, uint32_t mask, const Streams &st);
 
 // Enqueue one product y = K~ x (single right-hand side), ordered on st.main.
 // Returns a hipError_t as int.

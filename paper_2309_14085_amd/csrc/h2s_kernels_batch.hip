@@ -1,0 +1,431 @@
+// h2s_kernels_batch.hip -- the H2* product for a block of kBatch right-hand
+// sides at once (Sec. 5.1.2 applied column by column).  Every operator entry
+// read from HBM and every kernel value evaluated serves all kBatch columns:
+// the transfer and basis GEMVs become skinny GEMMs and the near field and M2L
+// evaluate K(x_i, x_j) once per pair.  Per column, the GEMV sums (P2M, M2M,
+// L2L, L2P) are those of the single-column kernels (h2s_kernels.hip): index
+// order, separately rounded products and sums.  The kernel sums (near field,
+// M2L) run in slice order with their own slicing, so they agree with the
+// single-column results to rounding.
+//
+// Layout: charges, near-field potentials and coefficients of a block are
+// row-major with the kBatch columns contiguous (qb[i kBatch + c]); columns
+// past the block's active count are zero.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "h2s.h"
+#include "h2s_device.hpp"
+#include "h2s_kfun.hpp"
+
+namespace h2s {
+
+namespace {
+
+constexpr int NB = kBatch;
+constexpr int NT_BG = 256; // GEMV blocks (one output of a box per thread, looping if needed)
+
+// qb[i][c] = x[c ldx + perm[i]] for the block's active columns, 0 beyond.
+template <class P>
+__global__ __launch_bounds__(256) void kb_permute(DevTree<P> t, const double *__restrict__ x, int64_t ldx, int na)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= t.n) return;
+    const int src = t.perm[i];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) t.qb[(size_t)i * NB + c] = c < na ? x[(size_t)c * ldx + src] : 0.0;
+}
+
+// acc[c] = sum_j A[j stride] xs[j NB + c], j in index order, for every column c.
+template <bool ORD, typename AT>
+__device__ __forceinline__ void ordered_dot_b(const AT *__restrict__ A, size_t stride, int R, const double *xs,
+                                              double (&acc)[NB])
+{
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[c] = 0.0;
+    int j = 0;
+    for (; j + 4 <= R; j += 4) {
+        double a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = (double)A[(size_t)(j + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) acc[c] = madd<ORD>(acc[c], a[u], xs[(j + u) * NB + c]);
+    }
+    for (; j < R; ++j) {
+        const double a = (double)A[(size_t)j * stride];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[c] = madd<ORD>(acc[c], a, xs[j * NB + c]);
+    }
+}
+
+// The vectors a block multiplies (a leaf's charges, the children's multipoles,
+// the parent's locals) are read by every thread at the same index, so they
+// are read in place through the caches rather than staged.
+template <class P> __global__ __launch_bounds__(NT_BG) void kb_up_leaf(DevTree<P> t, uint32_t mask)
+{
+    const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf, tid = threadIdx.x;
+    const int b = t.box_begin[g], n = t.box_end[g] - b;
+    const double *qs = t.qb + (size_t)b * NB;
+    const int cf = t.far.coef_off[g], rf = (mask & kFar) && t.kappa >= t.far.lmin ? t.far.coef_off[g + 1] - cf : 0;
+    const int cv = t.ver.coef_off[g], rv = (mask & kVer) && t.kappa >= t.ver.lmin ? t.ver.coef_off[g + 1] - cv : 0;
+    for (int k = tid; k < rf + rv; k += NT_BG) {
+        const bool f = k < rf;
+        const int kk = f ? k : k - rf;
+        const auto *A = f ? t.far.U_rm + t.far.uoff[leaf] + kk : t.ver.U_rm + t.ver.uoff[leaf] + kk;
+        double *out = (f ? t.far.vb + (size_t)(cf + kk) * NB : t.ver.vb + (size_t)(cv + kk) * NB);
+        double acc[NB];
+        ordered_dot_b<P::ordered>(A, (size_t)(f ? rf : rv), n, qs, acc);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) out[c] = acc[c];
+    }
+}
+
+template <class P> __global__ __launch_bounds__(NT_BG) void kb_m2m(DevTree<P> t, int32_t g0, uint32_t mask)
+{
+    const int g = g0 + blockIdx.x, tid = threadIdx.x;
+    const auto &Fa = t.far;
+    const auto &Ve = t.ver;
+    const int cf = Fa.coef_off[g], rf = (mask & kFar) ? Fa.coef_off[g + 1] - cf : 0;
+    const int cv = Ve.coef_off[g], rv = (mask & kVer) ? Ve.coef_off[g + 1] - cv : 0;
+    const int bf = Fa.coef_off[t.box_cbeg[g]], Rf = rf ? Fa.coef_off[t.box_cend[g]] - bf : 0;
+    const int bv = Ve.coef_off[t.box_cbeg[g]], Rv = rv ? Ve.coef_off[t.box_cend[g]] - bv : 0;
+    for (int k = tid; k < rf + rv; k += NT_BG) {
+        const bool f = k < rf;
+        const int kk = f ? k : k - rf;
+        const double *A = f ? Fa.Tr_rm + Fa.troff[g] + kk : Ve.Tr_rm + Ve.troff[g] + kk;
+        double *out = f ? Fa.vb + (size_t)(cf + kk) * NB : Ve.vb + (size_t)(cv + kk) * NB;
+        const double *xs = f ? Fa.vb + (size_t)bf * NB : Ve.vb + (size_t)bv * NB; // the children's multipoles
+        double acc[NB];
+        ordered_dot_b<P::ordered>(A, (size_t)(f ? rf : rv), f ? Rf : Rv, xs, acc);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) out[c] = acc[c];
+    }
+}
+
+template <class P> __global__ __launch_bounds__(NT_BG) void kb_l2l(DevTree<P> t, int32_t g0, uint32_t mask)
+{
+    const int g = g0 + blockIdx.x, tid = threadIdx.x;
+    const auto &Fa = t.far;
+    const auto &Ve = t.ver;
+    const int cf = Fa.coef_off[g], rf = (mask & kFar) ? Fa.coef_off[g + 1] - cf : 0;
+    const int cv = Ve.coef_off[g], rv = (mask & kVer) ? Ve.coef_off[g + 1] - cv : 0;
+    const int bf = Fa.coef_off[t.box_cbeg[g]], Rf = rf ? Fa.coef_off[t.box_cend[g]] - bf : 0;
+    const int bv = Ve.coef_off[t.box_cbeg[g]], Rv = rv ? Ve.coef_off[t.box_cend[g]] - bv : 0;
+    for (int j = tid; j < Rf + Rv; j += NT_BG) {
+        const bool f = j < Rf;
+        const int jj = f ? j : j - Rf;
+        const double *A = f ? Fa.Tr_cm + Fa.troff[g] + jj : Ve.Tr_cm + Ve.troff[g] + jj;
+        double *out = f ? Fa.ub + (size_t)(bf + jj) * NB : Ve.ub + (size_t)(bv + jj) * NB;
+        const double *xs = f ? Fa.ub + (size_t)cf * NB : Ve.ub + (size_t)cv * NB; // the parent's locals
+        double acc[NB];
+        ordered_dot_b<P::ordered>(A, (size_t)(f ? Rf : Rv), f ? rf : rv, xs, acc);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) out[c] = out[c] + acc[c];
+    }
+}
+
+// M2L in double, slice form (as k_m2l_slices), kBatch columns per evaluation.
+constexpr int NT_BM = 256;
+constexpr int BM_SRC = 512;
+
+template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM) void kb_m2l(DevTree<P> t)
+{
+    const auto &F = [&]() -> const auto & {
+        if constexpr (FAR) return t.far;
+        else return t.ver;
+    }();
+    __shared__ double sx[BM_SRC], sy[BM_SRC], sz[D == 3 ? BM_SRC : 1];
+    __shared__ double sv[BM_SRC * NB];
+    __shared__ double red[2 * NT_BM];
+    __shared__ __align__(16) double ktab[kTabLen<KIND>];
+    const int tid = threadIdx.x;
+    stage_table<KIND>(t.ktab, ktab); // first used after a barrier
+    const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
+    const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
+    const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
+    const double kp = t.kparam;
+    for (int a0 = 0; a0 < r; a0 += 2 * NT_BM) {
+        const int MT = min(r - a0, 2 * NT_BM), NP = (MT + 1) / 2, NS = NT_BM / NP;
+        const int s = tid / NP, pa = tid % NP;
+        const int ia = a0 + pa, ib = pa + NP < MT ? ia + NP : ia;
+        const double xa = F.pvx[c0 + ia], ya = F.pvy[c0 + ia], za = D == 3 ? (double)F.pvz[c0 + ia] : 0.0;
+        const double xb = F.pvx[c0 + ib], yb = F.pvy[c0 + ib], zb = D == 3 ? (double)F.pvz[c0 + ib] : 0.0;
+        double acc_a[NB], acc_b[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc_a[c] = acc_b[c] = 0.0;
+        int pos = 0;
+        auto flush = [&]() {
+            __syncthreads();
+            if (s < NS) {
+                double pa0[NB], pb0[NB];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) pa0[c] = pb0[c] = 0.0;
+                for (int j = s; j < pos; j += NS) {
+                    const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0;
+                    const double ka = kval_pos<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), kp, ktab);
+                    const double kb = kval_pos<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), kp, ktab);
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) {
+                        const double v = sv[j * NB + c];
+                        pa0[c] = fma(ka, v, pa0[c]);
+                        pb0[c] = fma(kb, v, pb0[c]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    acc_a[c] += pa0[c];
+                    acc_b[c] += pb0[c];
+                }
+            }
+            __syncthreads();
+            pos = 0;
+        };
+        for (int e = e0; e < e1; ++e) {
+            const int y = F.il_idx[e];
+            const int cy = F.coef_off[y], ry = F.coef_off[y + 1] - cy;
+            for (int j0 = 0; j0 < ry;) {
+                const int take = min(ry - j0, BM_SRC - pos);
+                for (int j = tid; j < take; j += NT_BM) {
+                    sx[pos + j] = F.pvx[cy + j0 + j];
+                    sy[pos + j] = F.pvy[cy + j0 + j];
+                    if constexpr (D == 3) sz[pos + j] = F.pvz[cy + j0 + j];
+                }
+                for (int e2 = tid; e2 < take * NB; e2 += NT_BM) sv[pos * NB + e2] = F.vb[(size_t)(cy + j0) * NB + e2];
+                pos += take;
+                j0 += take;
+                if (pos == BM_SRC) flush();
+            }
+        }
+        if (pos > 0) flush();
+        // slice partials, one column at a time
+        for (int c = 0; c < NB; ++c) {
+            red[tid] = s < NS ? acc_a[c] : 0.0;
+            red[NT_BM + tid] = s < NS ? acc_b[c] : 0.0;
+            __syncthreads();
+            if (tid < NP) {
+                double ua = 0.0, ub = 0.0;
+                for (int q = 0; q < NS; ++q) {
+                    ua += red[q * NP + tid];
+                    ub += red[NT_BM + q * NP + tid];
+                }
+                F.ub[(size_t)(c0 + ia) * NB + c] = ua;
+                if (ib != ia) F.ub[(size_t)(c0 + ib) * NB + c] = ub;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Near field (as k_p2p), kBatch columns per evaluation; one target per thread.
+constexpr int NT_BP = 256;
+constexpr int BP_SRC = 512;
+
+template <class P, int KIND, int D>
+__global__ __launch_bounds__(NT_BP) void kb_p2p(DevTree<P> t, int32_t leaf_begin)
+{
+    using PT = typename P::pt_t;
+    constexpr bool TAB = sizeof(PT) == 8;
+    __shared__ PT sx[BP_SRC], sy[BP_SRC], sz[D == 3 ? BP_SRC : 1];
+    __shared__ PT sq[BP_SRC * NB];
+    __shared__ double red[NT_BP];
+    __shared__ __align__(16) double ktab[TAB ? kTabLen<KIND> : 2];
+    const int tid = threadIdx.x;
+    const int leaf = leaf_begin + xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf;
+    const int b = t.box_begin[g], n = t.box_end[g] - b;
+    const PT diag = (PT)t.diag, kp = (PT)t.kparam;
+    const double *cX = t.box_ctr + 3 * g;
+    if constexpr (TAB) stage_table<KIND>(t.ktab, ktab); // first used after a barrier
+    for (int i0 = 0; i0 < n; i0 += NT_BP) {
+        const int m = min(n - i0, NT_BP), S = NT_BP / m, s = tid / m, i = i0 + tid % m;
+        const PT xi = t.px[b + i], yi = t.py[b + i], zi = D == 3 ? t.pz[b + i] : PT(0);
+        double acc[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[c] = 0.0;
+        int pos = 0, self0 = 0, self1 = 0;
+        auto slice_sum = [&](int jb, int je, auto check) {
+            constexpr bool CHECK = decltype(check)::value;
+            PT part[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) part[c] = 0;
+            for (int j = jb + s; j < je; j += S) {
+                const PT r2 = dist2<false, D>(xi - sx[j], yi - sy[j], zi - sz[D == 3 ? j : 0]);
+                PT k;
+                if constexpr (sizeof(PT) == 8) k = CHECK ? kval<KIND>(r2, diag, kp, ktab) : kval_pos<KIND>(r2, kp, ktab);
+                else k = kval<KIND>(r2, diag, kp);
+#pragma unroll
+                for (int c = 0; c < NB; ++c) part[c] += k * sq[j * NB + c];
+            }
+#pragma unroll
+            for (int c = 0; c < NB; ++c) acc[c] += (double)part[c];
+        };
+        auto flush = [&]() {
+            __syncthreads();
+            if (s < S) {
+                slice_sum(0, self0, std::false_type{});
+                slice_sum(self0, self1, std::true_type{});
+                slice_sum(self1, pos, std::false_type{});
+            }
+            __syncthreads();
+            pos = self0 = self1 = 0;
+        };
+        for (int e = t.near_off[leaf]; e < t.near_off[leaf + 1]; ++e) {
+            const int gs = t.leaf0 + t.near_idx[e];
+            const int sb = t.box_begin[gs], sn = t.box_end[gs] - sb;
+            double dcx = 0, dcy = 0, dcz = 0;
+            if constexpr (P::local) {
+                dcx = t.box_ctr[3 * gs] - cX[0];
+                dcy = t.box_ctr[3 * gs + 1] - cX[1];
+                dcz = t.box_ctr[3 * gs + 2] - cX[2];
+            }
+            for (int j0 = 0; j0 < sn;) {
+                const int take = min(sn - j0, BP_SRC - pos);
+                for (int j = tid; j < take; j += NT_BP) {
+                    const int src = sb + j0 + j;
+                    if constexpr (P::local) {
+                        sx[pos + j] = (PT)(dcx + (double)t.px[src]);
+                        sy[pos + j] = (PT)(dcy + (double)t.py[src]);
+                        if constexpr (D == 3) sz[pos + j] = (PT)(dcz + (double)t.pz[src]);
+                    } else {
+                        sx[pos + j] = t.px[src];
+                        sy[pos + j] = t.py[src];
+                        if constexpr (D == 3) sz[pos + j] = t.pz[src];
+                    }
+                }
+                for (int e2 = tid; e2 < take * NB; e2 += NT_BP)
+                    sq[pos * NB + e2] = (PT)t.qb[(size_t)(sb + j0) * NB + e2];
+                if (gs == g) {
+                    self0 = pos;
+                    self1 = pos + take;
+                }
+                pos += take;
+                j0 += take;
+                if (pos == BP_SRC) flush();
+            }
+        }
+        if (pos > 0) flush();
+        for (int c = 0; c < NB; ++c) {
+            red[tid] = s < S ? acc[c] : 0.0;
+            __syncthreads();
+            if (tid < m) {
+                double phi = 0.0;
+                for (int q = 0; q < S; ++q) phi += red[q * m + tid];
+                t.ynb[(size_t)(b + i) * NB + c] = phi;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// yn + shift q + L2P of both families, scattered to user order for the
+// block's active columns; threads [0, HALF) far, [HALF, NT) vertex family.
+constexpr int NT_BL = 128;
+
+template <class P>
+__global__ __launch_bounds__(NT_BL) void kb_down_leaf(DevTree<P> t, double *__restrict__ y, int64_t ldy, int na,
+                                                      uint32_t mask)
+{
+    constexpr bool ORD = P::ordered;
+    constexpr int HALF = NT_BL / 2;
+    using BT = typename P::basis_t;
+    __shared__ double ver_part[HALF * NB];
+    const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf;
+    const int b = t.box_begin[g], n = t.box_end[g] - b;
+    const int f = threadIdx.x < HALF ? 0 : 1, il = threadIdx.x - f * HALF;
+    const bool on = f == 0 ? (mask & kFar) && t.kappa >= t.far.lmin : (mask & kVer) && t.kappa >= t.ver.lmin;
+    const int c0 = f == 0 ? t.far.coef_off[g] : t.ver.coef_off[g];
+    const int r = on ? (f == 0 ? t.far.coef_off[g + 1] : t.ver.coef_off[g + 1]) - c0 : 0;
+    const BT *U = f == 0 ? t.far.U_cm + t.far.uoff[leaf] : t.ver.U_cm + t.ver.uoff[leaf];
+    const double *uc = (f == 0 ? t.far.ub : t.ver.ub) + (size_t)c0 * NB;
+    for (int i0 = 0; i0 < n; i0 += HALF) {
+        const int i = i0 + il;
+        double fam[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) fam[c] = 0.0;
+        if (i < n && r) ordered_dot_b<ORD>(U + i, (size_t)n, r, uc, fam);
+        if (f == 1 && i < n)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) ver_part[il * NB + c] = fam[c];
+        __syncthreads();
+        if (f == 0 && i < n) {
+            const int dst = t.perm[b + i];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                if (c >= na) continue;
+                double phi = 0.0;
+                if (mask & kNear)
+                    phi = madd<ORD>(t.ynb[(size_t)(b + i) * NB + c], t.shift, t.qb[(size_t)(b + i) * NB + c]);
+                if (mask & kFar) phi = phi + fam[c];
+                if (mask & kVer) phi = phi + ver_part[il * NB + c];
+                y[(size_t)c * ldy + dst] = phi;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <class P, int KIND, int D>
+hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *x, int64_t ldx, double *y,
+                     int64_t ldy, int na, uint32_t mask, const Streams &st)
+{
+    hipStream_t s = (hipStream_t)st.main, aux = (hipStream_t)st.aux;
+    const int32_t *lev_off = plan.lev_off;
+    const bool fam_on = (mask & (kFar | kVer)) && t.kappa >= 1;
+    hipLaunchKernelGGL(kb_permute<P>, dim3((t.n + 255) / 256), dim3(256), 0, s, t, x, ldx, na);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    // the near field on the second stream, beside the whole sweep
+    const bool near = (mask & kNear) != 0;
+    if (near) {
+        if ((err = hipEventRecord((hipEvent_t)st.fork, s)) != hipSuccess) return err;
+        if ((err = hipStreamWaitEvent(aux, (hipEvent_t)st.fork, 0)) != hipSuccess) return err;
+        hipLaunchKernelGGL((kb_p2p<P, KIND, D>), dim3(t.nleaf), dim3(NT_BP), 0, aux, t, 0);
+        if ((err = hipEventRecord((hipEvent_t)st.join, aux)) != hipSuccess) return err;
+    }
+    if (fam_on) {
+        hipLaunchKernelGGL(kb_up_leaf<P>, dim3(t.nleaf), dim3(NT_BG), 0, s, t, mask);
+        for (int l = t.kappa - 1; l >= 1; --l) {
+            const int nb = lev_off[l + 1] - lev_off[l];
+            if (nb) hipLaunchKernelGGL(kb_m2m<P>, dim3(nb), dim3(NT_BG), 0, s, t, lev_off[l], mask);
+        }
+        if ((mask & kFar) && t.far.ntargets)
+            hipLaunchKernelGGL((kb_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_BM), 0, s, t);
+        if ((mask & kVer) && t.ver.ntargets)
+            hipLaunchKernelGGL((kb_m2l<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_BM), 0, s, t);
+        for (int l = 1; l <= t.kappa - 1; ++l) {
+            const int nb = lev_off[l + 1] - lev_off[l];
+            if (nb) hipLaunchKernelGGL(kb_l2l<P>, dim3(nb), dim3(NT_BG), 0, s, t, lev_off[l], mask);
+        }
+    }
+    if (near && (err = hipStreamWaitEvent(s, (hipEvent_t)st.join, 0)) != hipSuccess) return err;
+    hipLaunchKernelGGL(kb_down_leaf<P>, dim3(t.nleaf), dim3(NT_BL), 0, s, t, y, ldy, na, mask);
+    return hipGetLastError();
+}
+
+} // namespace
+
+template <class P>
+int launch_mvp_batch(const DevTree<P> &t, const LaunchPlan &plan, const double *x, int64_t ldx, double *y,
+                     int64_t ldy, int na, uint32_t mask, const Streams &s)
+{
+    const int key = t.kind * 2 + (t.d == 3);
+    switch (key) {
+    case 0: return (int)enqueue_b<P, H2S_K_LOG_R, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 1: return (int)enqueue_b<P, H2S_K_LOG_R, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 2: return (int)enqueue_b<P, H2S_K_INV_R, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 3: return (int)enqueue_b<P, H2S_K_INV_R, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 4: return (int)enqueue_b<P, H2S_K_GAUSSIAN, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 5: return (int)enqueue_b<P, H2S_K_GAUSSIAN, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 6: return (int)enqueue_b<P, H2S_K_EXP_R, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
+    default: return (int)enqueue_b<P, H2S_K_EXP_R, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
+    }
+}
+
+template int launch_mvp_batch<P64>(const DevTree<P64> &, const LaunchPlan &, const double *, int64_t, double *,
+                                   int64_t, int, uint32_t, const Streams &);
+template int launch_mvp_batch<P32>(const DevTree<P32> &, const LaunchPlan &, const double *, int64_t, double *,
+                                   int64_t, int, uint32_t, const Streams &);
+
+} // namespace h2s

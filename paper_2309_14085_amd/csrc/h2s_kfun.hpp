@@ -1,0 +1,198 @@
+// h2s_kfun.hpp -- device helpers shared by the product kernels
+// (h2s_kernels.hip, h2s_kernels_batch.hip): phase masks, the XCD block
+// remap, separately rounded multiply-add, the FP64 kernel functions (table-
+// driven log and exp, Newton-refined 1/sqrt), the kernel value from a squared
+// distance, wavefront sums and the pipelined ordered dot product.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "h2s.h"
+
+namespace h2s {
+namespace {
+
+constexpr unsigned kNear = 1u, kFar = 2u, kVer = 4u;
+
+// Work items are dealt to the 8 XCDs round-robin by block index; remap so
+// each XCD gets a contiguous (Morton-local, so L2-sharing) range of items.
+__device__ __forceinline__ int xcd_remap(int bid, int nb)
+{
+    const int q = nb >> 3, rem = nb & 7, xcd = bid & 7, slot = bid >> 3;
+    return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
+}
+
+// s + a b.  ORD: the product and the sum rounded separately, as a plain
+// sequential evaluation does (the HBM-bound sums can afford it); otherwise
+// one fused multiply-add.
+template <bool ORD> __device__ __forceinline__ double madd(double s, double a, double b)
+{
+    if constexpr (ORD) {
+#pragma clang fp contract(off)
+        const double p = a * b;
+        return s + p;
+    } else {
+        return fma(a, b, s);
+    }
+}
+
+// 0.5 ln(x) for finite x > 0 in double, table-driven (Tang's reduction):
+// x = m 2^e with m in [1/2, 1) (frexp); the top 8 fraction bits of m select
+// a subinterval i of width 1/512 with centre z_i, c_i ~ 1/z_i; then
+// r = m c_i - 1 (|r| < 2^-9, one rounding) and
+//   0.5 ln x = 0.5 e ln 2 - 0.5 ln c_i + 0.5 ln(1 + r),
+// the last term by its Taylor series through r^5 (truncation below 1e-17).
+// tab holds (c_i, -0.5 ln c_i) for the 256 subintervals (built on the host
+// in extended precision).  Absolute error about one ulp of the result.
+__device__ __forceinline__ double half_log(double x, const double2 *tab)
+{
+    int e;
+    const double m = frexp(x, &e);
+    const int i = (__double2hiint(m) >> 12) & 255;
+    const double2 c = tab[i];
+    const double r = fma(m, c.x, -1.0);
+    double p = 1.0 / 10;
+    p = fma(p, r, -1.0 / 8);
+    p = fma(p, r, 1.0 / 6);
+    p = fma(p, r, -1.0 / 4);
+    p = fma(p, r, 1.0 / 2);
+    return fma(r, p, fma((double)e, 0.34657359027997264, c.y)); // ln 2 / 2
+}
+
+// exp(x) in double, table-driven (Tang's reduction): k = nearest integer to
+// 64 x / ln 2, r = x - k ln2/64 (|r| <= ln2/128, with ln2/64 split into an
+// exactly multipliable head and a tail), k = 64 m + j, and
+//   exp(x) = 2^m 2^(j/64) exp(r),
+// exp(r) by its Taylor series through r^6 (truncation below 3e-20).  tab
+// holds 2^(j/64), j < 64 (extended precision on the host).  Arguments below
+// -1000 are clamped (the result is 0 in double either way).  Relative error
+// about two ulps.
+__device__ __forceinline__ double exp_tab(double x, const double *tab)
+{
+    x = fmax(x, -1000.0);
+    const double kd = rint(x * 92.332482616893656877); // 64 / ln 2
+    const int k = (int)kd;
+    double r = fma(-kd, 0.010830417275428772, x);     // head of ln2/64
+    r = fma(-kd, 7.420820373487167e-09, r);           // tail of ln2/64
+    double p = 1.0 / 720;
+    p = fma(p, r, 1.0 / 120);
+    p = fma(p, r, 1.0 / 24);
+    p = fma(p, r, 1.0 / 6);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(tab[k & 63] * p, k >> 6);
+}
+
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y^2) / 2.  Relative error about one ulp.
+__device__ __forceinline__ double inv_sqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double t = x * y;
+        const double e = fma(-t, y, 1.0);
+        y = fma(y * 0.5, e, y);
+    }
+    return y;
+}
+
+// Lookup tables of the kernel functions, in doubles: log r 256 (c_i, -0.5 ln c_i)
+// pairs, the exponential kernels 2^(j/64).  Staged in LDS per block.
+template <int KIND>
+constexpr int kTabLen = KIND == H2S_K_LOG_R ? 512 : (KIND == H2S_K_GAUSSIAN || KIND == H2S_K_EXP_R ? 64 : 2);
+
+// Stage the table in LDS (whole block; the caller synchronises).
+template <int KIND> __device__ __forceinline__ void stage_table(const double *g, double *tab)
+{
+    if constexpr (KIND != H2S_K_INV_R)
+        for (int i = threadIdx.x; i < kTabLen<KIND>; i += blockDim.x) tab[i] = g[i];
+}
+
+// Squared distance (ORD is accepted for symmetry with madd).
+template <bool ORD, int D, typename T> __device__ __forceinline__ T dist2(T dx, T dy, T dz)
+{
+    T r2 = dx * dx + dy * dy;
+    if constexpr (D == 3) r2 += dz * dz;
+    return r2;
+}
+
+// Kernel value from a squared distance r2 > 0.  kp: -1/h^2 for the Gaussian.
+template <int KIND> __device__ __forceinline__ double kval_pos(double r2, double kp, const double *tab)
+{
+    if constexpr (KIND == H2S_K_LOG_R) return half_log(r2, (const double2 *)tab);
+    else if constexpr (KIND == H2S_K_INV_R) return inv_sqrt(r2);
+    else if constexpr (KIND == H2S_K_GAUSSIAN) return exp_tab(r2 * kp, tab);
+    else return exp_tab(-sqrt(r2), tab);
+}
+
+// Kernel value from the squared distance; r2 == 0 means coincident points.
+template <int KIND> __device__ __forceinline__ double kval(double r2, double diag, double kp, const double *tab)
+{
+    const double v = kval_pos<KIND>(r2, kp, tab);
+    return r2 == 0.0 ? diag : v;
+}
+
+template <int KIND> __device__ __forceinline__ float kval(float r2, float diag, float kp)
+{
+    float v;
+    if constexpr (KIND == H2S_K_LOG_R) v = __log2f(r2) * 0.34657359027997264f; // ln 2 / 2
+    else if constexpr (KIND == H2S_K_INV_R) v = __frsqrt_rn(r2);
+    else if constexpr (KIND == H2S_K_GAUSSIAN) v = __expf(r2 * kp);
+    else v = __expf(-__fsqrt_rn(r2));
+    return r2 == 0.0f ? diag : v;
+}
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Ordered dot product sum_j a(j) x[j], a(j) = A[j stride].  The sum itself is
+// sequential; the operator loads are software-pipelined two batches of UNR
+// deep so that a batch is in flight while the previous one is accumulated.
+constexpr int UNR = 8;
+
+template <bool ORD, typename AT>
+__device__ __forceinline__ double ordered_dot(const AT *__restrict__ A, size_t stride, int R, const double *xs)
+{
+    double s = 0.0;
+    int j = 0;
+    if (R >= 2 * UNR) {
+        double a[UNR], b[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) a[u] = (double)A[(size_t)u * stride];
+        for (; j + 3 * UNR <= R; j += 2 * UNR) {
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) b[u] = (double)A[(size_t)(j + UNR + u) * stride];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) s = madd<ORD>(s, a[u], xs[j + u]);
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) a[u] = (double)A[(size_t)(j + 2 * UNR + u) * stride];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) s = madd<ORD>(s, b[u], xs[j + UNR + u]);
+        }
+        // a holds rows j .. j + UNR - 1 (fewer than 3 UNR rows were left)
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) s = madd<ORD>(s, a[u], xs[j + u]);
+        j += UNR;
+    }
+    // the remaining rows, one predicated batch of loads at a time
+    for (; j < R; j += UNR) {
+        double c[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) c[u] = j + u < R ? (double)A[(size_t)(j + u) * stride] : 0.0;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (j + u < R) s = madd<ORD>(s, c[u], xs[j + u]);
+    }
+    return s;
+}
+
+} // namespace
+} // namespace h2s

@@ -1,0 +1,130 @@
+"""Batched multi-RHS product (blocks of 8 right-hand sides, h2s_apply with nrhs > 1)
+against the FP64 oracle column by column, and against the single-column path.
+
+Bars: FP64 <= 1e-12 relative 2-norm per column and per phase; FP32 <= 1e-5;
+batched and single-column FP64 products agree to 1e-13 (their near-field and
+M2L sums are sliced differently, so they agree to rounding, not bit for bit).
+Columns beyond the block's active count, and the padding rows of ld > n, are
+never written.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2309_14085_amd import h2s
+    h2s.load()
+    return h2s
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def apply_block(T, lib, Q, ld, mask=7):
+    """Q (n, m) host; returns the (n, m) result of one h2s_apply_phases call with leading dimension ld."""
+    n, m = Q.shape
+    dev = _dev()
+    xb = torch.zeros(m * ld, dtype=torch.float64, device=dev)
+    yb = torch.full((m * ld,), 3.0, dtype=torch.float64, device=dev)
+    for c in range(m):
+        xb[c * ld:c * ld + n] = torch.from_numpy(Q[:, c].copy()).to(dev)
+    assert T.apply_ptr(xb.data_ptr(), yb.data_ptr(), nrhs=m, ldx=ld, ldy=ld, mask=mask) == lib.OK
+    torch.cuda.synchronize()
+    y = yb.cpu().numpy()
+    for c in range(m):
+        assert np.all(y[c * ld + n:(c + 1) * ld] == 3.0)  # padding untouched
+    return np.stack([y[c * ld:c * ld + n] for c in range(m)], axis=1)
+
+
+CASES = [
+    # name, d, n, kind, nmax, eps, param, shift, seed
+    ("2d_log_5000", 2, 5000, 0, 48, 1e-10, 0.0, 0.0, 61),
+    ("3d_invr_6000", 3, 6000, 1, 64, 1e-6, 0.0, 0.0, 62),
+    ("2d_gauss_4000", 2, 4000, 2, 32, 1e-10, 0.2, 1e-2, 63),
+    ("3d_expr_3000", 3, 3000, 3, 32, 1e-10, 0.0, 0.0, 64),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("m", [3, 8, 11])
+def test_batched_fp64_matches_oracle_per_column(lib, orc, inputs, case, m):
+    name, d, n, kind, nmax, eps, param, shift, seed = case
+    print(f"batched {name} m={m}", flush=True)
+    pts = inputs.uniform_points(n, d, seed)
+    Q = inputs.normal_rhs(n, m, seed + 100)
+    O = orc.Tree(pts, kind, nmax, eps, param=param, shift=shift)
+    T = lib.build(pts, kind=kind, leaf_size=nmax, eps=eps, param=param, shift=shift)
+    Y = apply_block(T, lib, Q, n + 5)
+    for c in range(m):
+        assert rel(Y[:, c], O.apply(Q[:, c])) <= 1e-12, c
+
+
+def test_batched_phases_match_oracle_parts(lib, orc, inputs):
+    n, m = 5000, 8
+    print("batched phases", flush=True)
+    pts = inputs.uniform_points(n, 2, 65)
+    Q = inputs.normal_rhs(n, m, 66)
+    O = orc.Tree(pts, 0, 48, 1e-10)
+    T = lib.build(pts, kind=0, leaf_size=48, eps=1e-10)
+    parts = [O.apply_parts(Q[:, c]) for c in range(m)]
+    for mask, idx in ((lib.PHASE_NEAR, 0), (lib.PHASE_FAR, 1), (lib.PHASE_VER, 2)):
+        Y = apply_block(T, lib, Q, n, mask=mask)
+        for c in range(m):
+            assert rel(Y[:, c], parts[c][idx]) <= 1e-12, (mask, c)
+
+
+def test_batched_agrees_with_single_column_path(lib, inputs):
+    n, m = 20000, 8
+    print("batched vs single", flush=True)
+    pts = inputs.uniform_points(n, 2, 67)
+    Q = inputs.normal_rhs(n, m, 68)
+    T = lib.build(pts, kind=0, leaf_size=64, eps=1e-8)
+    Y = apply_block(T, lib, Q, n)
+    dev = _dev()
+    for c in range(m):
+        y1 = T.apply(torch.from_numpy(Q[:, c].copy()).to(dev))
+        torch.cuda.synchronize()
+        assert rel(Y[:, c], y1.cpu().numpy()) <= 1e-13, c
+
+
+@pytest.mark.parametrize("d,kind,eps", [(2, 0, 1e-8), (3, 1, 1e-6)])
+def test_batched_fp32_within_1e5(lib, orc, inputs, d, kind, eps):
+    n, m = (8192, 5) if d == 2 else (6000, 5)
+    print(f"batched fp32 d={d}", flush=True)
+    pts = inputs.uniform_points(n, d, 69 + d)
+    Q = inputs.normal_rhs(n, m, 71 + d)
+    O = orc.Tree(pts, kind, 64, eps)
+    T = lib.build(pts, kind=kind, leaf_size=64, eps=eps, prec=lib.FP32)
+    Y = apply_block(T, lib, Q, n)
+    for c in range(m):
+        assert rel(Y[:, c], O.apply(Q[:, c])) <= 1e-5, c
+
+
+def test_multi_rhs_fallbacks_match_oracle(lib, orc, inputs):
+    """(H2+H)* and FP32_M2L take the column loop; their multi-RHS results still match."""
+    n, m = 4000, 4
+    print("multi-rhs fallbacks", flush=True)
+    pts = inputs.uniform_points(n, 2, 73)
+    Q = inputs.normal_rhs(n, m, 74)
+    O = orc.Tree(pts, 0, 48, 1e-10, variant=1)
+    T = lib.build(pts, kind=0, leaf_size=48, eps=1e-10, variant=1)
+    Y = apply_block(T, lib, Q, n)
+    for c in range(m):
+        assert rel(Y[:, c], O.apply(Q[:, c])) <= 1e-12
+    O2 = orc.Tree(pts, 0, 48, 1e-8)
+    T2 = lib.build(pts, kind=0, leaf_size=48, eps=1e-8, prec=lib.FP32_M2L)
+    Y2 = apply_block(T2, lib, Q, n)
+    for c in range(m):
+        assert rel(Y2[:, c], O2.apply(Q[:, c])) <= 1e-4

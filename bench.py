@@ -36,6 +36,7 @@ def parse():
                    help="also run one plain 256 MiB device copy (reference for the HBM byte counters)")
     p.add_argument("--no-solve", action="store_true", help="skip the RBF interpolation solve beside the MVP")
     p.add_argument("--no-multi-rhs", action="store_true", help="skip the 3D 32-RHS batched product beside the MVP")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving run (build + solve requests)")
     p.add_argument("--profile-only", action="store_true",
                    help="skip the timed steps: warm-up and the per-class profiled steps only (for rocprofv3 runs)")
     return p.parse_args()
@@ -145,6 +146,20 @@ def time_multi_rhs(h2s, torch, w, reps=3):
             "m2l_evals_per_rhs": st["m2l_evals"], "p2p_evals_per_rhs": st["p2p_evals"]}
 
 
+def time_serving(count=24, rate=4.0, workers=4, budget=16 << 30):
+    """count build + solve requests with Poisson arrivals (rate per second): d in {2, 3},
+    N log-uniform in [2^14, 2^17] (2D) / [2^14, 2^15] (3D), 1-4 right-hand sides, log r (2D) or
+    1/r (3D) in second-kind form, GMRES to 1e-8; admitted by a 16 GiB HBM budget, 4 workers."""
+    from paper_2309_14085_amd import serve
+    reqs = serve.make_requests(count, rate=rate, seed=5, n_range=(16384, 131072), n_range_3d=(16384, 32768),
+                               nrhs_max=4)
+    _, summary = serve.Server(hbm_budget_bytes=budget, workers=workers).run(reqs)
+    summary.update({"arrival_rate_per_s": rate, "workers": workers, "hbm_budget_bytes": budget,
+                    "requests_spec": "d in {2,3}; N log-uniform 2^14..2^17 (2D), 2^14..2^15 (3D); 1-4 RHS; "
+                                     "(w K + I) x = b, w = 2^d / N; GMRES(50) FP32 Krylov to 1e-8"})
+    return summary
+
+
 def algorithmic_work(stats, kernel, prec):
     """Algorithmic HBM bytes and kernel evaluations of one launch of a kernel class.
 
@@ -233,6 +248,12 @@ def main():
         multi = time_multi_rhs(h2s, torch, inputs.workload("3d_invr_n262144_m32"))
         print(f"# multi-rhs: {multi}", file=sys.stderr, flush=True)
 
+    served = None
+    if not a.no_serve:
+        print("# serving build + solve requests", file=sys.stderr, flush=True)
+        served = time_serving()
+        print(f"# serving: {served}", file=sys.stderr, flush=True)
+
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(pts, q, w)
@@ -256,6 +277,7 @@ def main():
         "cpu_baseline": cpu,
         "solve": solve,
         "multi_rhs": multi,
+        "serving": served,
         "variants": {k: {kk: vv for kk, vv in v.items() if kk != "stats"} for k, v in res.items()},
         "ranks": {"far_max_by_level": m["stats"]["rank_max_level"][0],
                   "ver_max_by_level": m["stats"]["rank_max_level"][1],

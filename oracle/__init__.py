@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE: only tests/, __graft_entry__.smoke() and bench.py's
 cpu_baseline leg may import this package.  It shares no code with the
 library in paper_2309_14085_amd/.
 
-Kernel kinds: 0 = log r, 1 = 1/r, 2 = exp(-r^2/h^2), 3 = exp(-r).
+Kernel kinds: 0 = log r, 1 = 1/r, 2 = exp(-r^2/h^2), 3 = exp(-r),
+4 = a/r (r >= a) | r/a (r < a), 5 = log r/log a (r >= a) | (r log r - 1)/(a log a - 1) (r < a).
 Variants: 0 = H2*(b+t), 1 = (H2+H)*.
 Families: 0 = far field (B2T NCA), 1 = vertex sharing (T2B NCA).
 Lists: 0 = near field N* (leaf level), 1 = IL_far, 2 = IL_ver.
@@ -17,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-LOG_R, INV_R, GAUSS, EXP_R = 0, 1, 2, 3
+LOG_R, INV_R, GAUSS, EXP_R, RBF_AR, RBF_LOG = 0, 1, 2, 3, 4, 5
 H2STAR, H2_PLUS_H = 0, 1
 FAR, VER = 0, 1
 NEAR_LIST, FAR_LIST, VER_LIST = 0, 1, 2
@@ -79,8 +80,9 @@ def _p(a, t):
 
 
 def default_diag(kind):
-    """K(x, x): 0 for log r and 1/r (the paper's convention), 1 for the others."""
-    return 0.0 if kind in (LOG_R, INV_R) else 1.0
+    """K(x, x): 0 for log r, 1/r and the two piecewise RBFs, whose systems leave out
+    j = i (the paper's convention), 1 for the Gaussian and exp(-r)."""
+    return 0.0 if kind in (LOG_R, INV_R, RBF_AR, RBF_LOG) else 1.0
 
 
 def direct(points, q, kind, param=0.0, diag=None, shift=0.0, rows=None):

@@ -39,14 +39,14 @@
 #endif
 
 /* ------------------------------------------------------------------------ */
-/* Kernel functions (Sec. 6.1.1, 6.2.1, Appendix D; Gaussian RBF for solves) */
+/* Kernel functions (Sec. 6.1.1, 6.2.1, Appendix D; RBFs of the solves)      */
 /* ------------------------------------------------------------------------ */
 
-enum { ORC_LOG_R = 0, ORC_INV_R = 1, ORC_GAUSS = 2, ORC_EXP_R = 3 };
+enum { ORC_LOG_R = 0, ORC_INV_R = 1, ORC_GAUSS = 2, ORC_EXP_R = 3, ORC_RBF_AR = 4, ORC_RBF_LOG = 5 };
 
 typedef struct {
     int kind;
-    double param; /* Gaussian length scale */
+    double param; /* Gaussian length scale; radius a of the two piecewise RBFs */
     double diag;  /* K(x_i, x_i) */
     double shift; /* adds shift * I to the matrix */
 } orc_kernel;
@@ -67,6 +67,14 @@ static double kernel_value(const orc_kernel *k, int d, const double *x, const do
     case ORC_INV_R: return 1.0 / sqrt(r2);
     case ORC_GAUSS: return exp(-r2 / (k->param * k->param));
     case ORC_EXP_R: return exp(-sqrt(r2));
+    case ORC_RBF_AR: { /* 2D RBF interpolation: a/r for r >= a, r/a below (Sec. 6, "RBF interpolation in 2D") */
+        double r = sqrt(r2), a = k->param;
+        return r >= a ? a / r : r / a;
+    }
+    case ORC_RBF_LOG: { /* 3D RBF: log r / log a for r >= a, (r log r - 1)/(a log a - 1) below (Sec. 6, 3D) */
+        double r = sqrt(r2), a = k->param;
+        return r >= a ? log(r) / log(a) : (r * log(r) - 1.0) / (a * log(a) - 1.0);
+    }
     default: return NAN;
     }
 }

@@ -6,6 +6,7 @@ the oracle's loop.
 import math
 
 import numpy as np
+import pytest
 
 
 def test_log_r_on_unit_circle(orc):
@@ -66,3 +67,27 @@ def test_symmetric_matrix(orc):
     a = x @ orc.direct(pts, y, orc.INV_R)
     b = y @ orc.direct(pts, x, orc.INV_R)
     assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_piecewise_rbfs_values_and_continuity(orc):
+    """The two RBFs of the paper's 2D / 3D interpolation solves (Sec. 6), at points worked by hand.
+
+    a/r | r/a with a = 0.5: G(1) = 0.5, G(0.25) = 0.5, G(0.5) = 1.
+    log r / log a | (r log r - 1)/(a log a - 1) with a = 1/e (log a = -1):
+    G(e) = -1, G(1/e^2) = (1 + 2/e^2) / (1 + 1/e), and G -> 1 from both sides of r = a."""
+    def pair(r, kind, a, d):
+        pts = np.zeros((2, d))
+        pts[1, 0] = r
+        return orc.direct(pts, np.array([0.0, 1.0]), kind, param=a)[0]
+
+    assert pair(1.0, orc.RBF_AR, 0.5, 2) == pytest.approx(0.5, rel=1e-15)
+    assert pair(0.25, orc.RBF_AR, 0.5, 2) == pytest.approx(0.5, rel=1e-15)
+    assert pair(0.5, orc.RBF_AR, 0.5, 2) == pytest.approx(1.0, rel=1e-15)
+    a = math.exp(-1.0)
+    assert pair(math.e, orc.RBF_LOG, a, 3) == pytest.approx(-1.0, rel=1e-14)
+    assert pair(math.exp(-2.0), orc.RBF_LOG, a, 3) == pytest.approx((1 + 2 / math.e**2) / (1 + 1 / math.e), rel=1e-14)
+    for kind, d in ((orc.RBF_AR, 2), (orc.RBF_LOG, 3)):
+        lo, hi = pair(a * (1 - 1e-9), kind, a, d), pair(a * (1 + 1e-9), kind, a, d)
+        assert abs(lo - 1.0) < 1e-7 and abs(hi - 1.0) < 1e-7
+    # their systems leave out j = i: K_ii = 0
+    assert orc.default_diag(orc.RBF_AR) == 0.0 and orc.default_diag(orc.RBF_LOG) == 0.0

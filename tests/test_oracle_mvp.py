@@ -15,7 +15,8 @@ import numpy as np
 import pytest
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-KINDS = {"log_r": (2, 0, 0.0), "inv_r": (3, 1, 0.0), "gauss": (2, 2, 0.3), "exp_r": (3, 3, 0.0)}
+KINDS = {"log_r": (2, 0, 0.0), "inv_r": (3, 1, 0.0), "gauss": (2, 2, 0.3), "exp_r": (3, 3, 0.0),
+         "rbf_ar": (2, 4, 0.05), "rbf_log": (3, 5, 0.05)}
 
 
 def rel(a, b):

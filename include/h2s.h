@@ -47,16 +47,26 @@ typedef enum {
     H2S_ERR_INTERNAL = 6
 } h2s_status;
 
-/* Kernel functions.  LOG_R: log|x-y| (2D single-layer Laplacian, Sec. 6.1.1);
- * INV_R: 1/|x-y| (3D single-layer Laplacian, Sec. 6.2.1); GAUSSIAN:
- * exp(-|x-y|^2 / param^2) (RBF interpolation); EXP_R: exp(-|x-y|) (Matern
- * nu = 1/2, Appendix D).  The closed set is compiled into the device code. */
-typedef enum { H2S_K_LOG_R = 0, H2S_K_INV_R = 1, H2S_K_GAUSSIAN = 2, H2S_K_EXP_R = 3 } h2s_kernel_kind;
+/* Kernel functions of r = |x-y|.  LOG_R: log r (2D single-layer Laplacian,
+ * Sec. 6.1.1); INV_R: 1/r (3D single-layer Laplacian, Sec. 6.2.1); GAUSSIAN:
+ * exp(-r^2 / param^2) (RBF interpolation); EXP_R: exp(-r) (Matern nu = 1/2,
+ * Appendix D); RBF_AR: a/r for r >= a, r/a for r < a (2D RBF interpolation,
+ * Sec. 6); RBF_LOG: log r / log a for r >= a, (r log r - 1)/(a log a - 1) for
+ * r < a (3D RBF interpolation, Sec. 6); a = param.  The closed set is
+ * compiled into the device code. */
+typedef enum {
+    H2S_K_LOG_R = 0,
+    H2S_K_INV_R = 1,
+    H2S_K_GAUSSIAN = 2,
+    H2S_K_EXP_R = 3,
+    H2S_K_RBF_AR = 4,
+    H2S_K_RBF_LOG = 5
+} h2s_kernel_kind;
 
 typedef struct {
     h2s_kernel_kind kind;
-    double param; /* GAUSSIAN length scale h > 0; unused otherwise */
-    double diag;  /* K(x, x), used whenever two points coincide: 0 for LOG_R / INV_R (Sec. 6.1.1, 6.2.1) */
+    double param; /* GAUSSIAN length scale h > 0; radius a > 0 of RBF_AR / RBF_LOG (a != 1 for RBF_LOG) */
+    double diag;  /* K(x, x), used whenever two points coincide: 0 for LOG_R / INV_R (Sec. 6.1.1, 6.2.1) and the RBFs */
     double shift; /* the matrix is K + shift * I */
 } h2s_kernel;
 

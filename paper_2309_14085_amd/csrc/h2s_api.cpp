@@ -265,6 +265,19 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
     D.diag = r.ker.diag;
     D.shift = r.ker.shift;
     D.kparam = r.ker.kind == H2S_K_GAUSSIAN ? -1.0 / (r.ker.param * r.ker.param) : 0.0;
+    {
+        const double a = r.ker.param;
+        if (r.ker.kind == H2S_K_RBF_AR) {
+            D.kc[0] = a * a;
+            D.kc[1] = a;
+            D.kc[2] = 1.0 / a;
+        } else if (r.ker.kind == H2S_K_RBF_LOG) {
+            const long double la = std::log((long double)a);
+            D.kc[0] = a * a;
+            D.kc[1] = (double)(1.0L / la);
+            D.kc[2] = (double)(1.0L / ((long double)a * la - 1.0L));
+        }
+    }
     D.variant = r.variant;
     D.max_leaf = 1;
     for (int32_t g = leaf0; g < nbox; ++g) D.max_leaf = std::max(D.max_leaf, r.box_end[g] - r.box_begin[g]);
@@ -404,7 +417,7 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
     {
         // tables of the kernel functions (extended precision, rounded once)
         std::vector<double> tab;
-        if (r.ker.kind == H2S_K_LOG_R) {
+        if (r.ker.kind == H2S_K_LOG_R || r.ker.kind == H2S_K_RBF_LOG) {
             // 0.5 ln x by table reduction: subinterval i of m in [1/2, 1) has centre
             // z_i = 1/2 + (i + 1/2)/512; store c_i = 1/z_i and -0.5 ln c_i
             for (int i = 0; i < 256; ++i) {
@@ -599,7 +612,10 @@ h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kerne
     if (n < 1 || n > INT32_MAX) return fail(H2S_ERR_INVALID_ARG, "n must be in [1, 2^31 - 1]");
     if (d != 2 && d != 3) return fail(H2S_ERR_INVALID_ARG, "d must be 2 or 3");
     if (!k || !o) return fail(H2S_ERR_INVALID_ARG, "kernel or options is NULL");
-    if (k->kind < H2S_K_LOG_R || k->kind > H2S_K_EXP_R) return fail(H2S_ERR_INVALID_ARG, "unknown kernel kind");
+    if (k->kind < H2S_K_LOG_R || k->kind > H2S_K_RBF_LOG) return fail(H2S_ERR_INVALID_ARG, "unknown kernel kind");
+    if ((k->kind == H2S_K_RBF_AR || k->kind == H2S_K_RBF_LOG) && !(is_finite(k->param) && k->param > 0))
+        return fail(H2S_ERR_INVALID_ARG, "the RBF radius (param) must be finite and > 0");
+    if (k->kind == H2S_K_RBF_LOG && k->param == 1.0) return fail(H2S_ERR_INVALID_ARG, "RBF_LOG needs param != 1");
     if (k->kind == H2S_K_GAUSSIAN && !(is_finite(k->param) && k->param > 0))
         return fail(H2S_ERR_INVALID_ARG, "Gaussian length scale must be finite and > 0");
     if (!is_finite(k->diag) || !is_finite(k->shift)) return fail(H2S_ERR_INVALID_ARG, "diag and shift must be finite");

@@ -94,6 +94,8 @@ template <class P> struct DevTree {
     int32_t n, d, kappa, nleaf, leaf0, nbox, kind, variant;
     int32_t max_leaf, max_rows, max_rank; // LDS sizing: largest leaf, stacked transfer rows, rank
     double diag, shift, kparam; // K(x,x); shift * I; -1/h^2 for the Gaussian (exponent r^2 kparam)
+    double kc[3];               // piecewise RBFs of radius a: a^2, then a, 1/a (a/r | r/a) or
+                                // 1/log a, 1/(a log a - 1) (log r | r log r - 1)
     const int32_t *perm;        // tree position -> user index
     const pt_t *px, *py, *pz;
     const int32_t *box_begin, *box_end, *box_cbeg, *box_cend;
@@ -106,7 +108,8 @@ template <class P> struct DevTree {
     double *qt;           // charges in tree order
     double *yn;           // near-field potentials in tree order
     double *qb, *ynb;     // multi-RHS blocks of both: kBatch entries per point (allocated on first use)
-    const double *ktab;   // kernel-function table: log r (c_i, -0.5 ln c_i) x 256; exponentials 2^(j/64) x 64
+    const double *ktab;   // kernel-function table: log r and RBF_LOG (c_i, -0.5 ln c_i) x 256;
+                          // exponentials 2^(j/64) x 64
 };
 
 // Host-side launch shapes, fixed at upload.

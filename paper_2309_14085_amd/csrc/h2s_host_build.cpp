@@ -37,6 +37,14 @@ double kernel_entry(const KernelSpec &k, int d, const double *x, const double *y
     case H2S_K_LOG_R: return std::log(std::sqrt(r2));
     case H2S_K_INV_R: return 1.0 / std::sqrt(r2);
     case H2S_K_GAUSSIAN: return std::exp(-r2 / (k.param * k.param));
+    case H2S_K_RBF_AR: {
+        const double r = std::sqrt(r2), a = k.param;
+        return r >= a ? a / r : r / a;
+    }
+    case H2S_K_RBF_LOG: {
+        const double r = std::sqrt(r2), a = k.param;
+        return r >= a ? std::log(r) / std::log(a) : (r * std::log(r) - 1.0) / (a * std::log(a) - 1.0);
+    }
     default: return std::exp(-std::sqrt(r2));
     }
 }

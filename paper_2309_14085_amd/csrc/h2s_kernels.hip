@@ -166,7 +166,9 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
     const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
-    const CT diag = (CT)t.diag, kp = (CT)t.kparam;
+    const CT diag = (CT)t.diag;
+    const KPar<CT> kp = kpar<CT>(t);
+    const KPar<double> kpd = kpar<double>(t);
     const double *cX = t.box_ctr + 3 * g;
     double uacc[M2L_OWN];
 #pragma unroll
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
                     for (int u = 0; u < 4; ++u) {
                         const double r2 = dist2<ORD, D>((double)xa - (double)sx[j + u], (double)ya - (double)sy[j + u],
                                                         D == 3 ? (double)za - (double)sz[j + u] : 0.0);
-                        kv[u] = kval_pos<KIND>(r2, (double)kp, ktab);
+                        kv[u] = kval_pos<KIND>(r2, kpd, ktab);
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) s = madd<ORD>(s, kv[u], sv[j + u]);
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
                 for (; j < je; ++j) {
                     const double r2 = dist2<ORD, D>((double)xa - (double)sx[j], (double)ya - (double)sy[j],
                                                     D == 3 ? (double)za - (double)sz[j] : 0.0);
-                    s = madd<ORD>(s, kval_pos<KIND>(r2, (double)kp, ktab), sv[j]);
+                    s = madd<ORD>(s, kval_pos<KIND>(r2, kpd, ktab), sv[j]);
                 }
             }
             part[yl * r + a] = s;
@@ -299,7 +301,7 @@ __global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t)
     const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
-    const double kp = t.kparam;
+    const KPar<double> kp = kpar<double>(t);
     for (int a0 = 0; a0 < r; a0 += 2 * NT_M2LS) {
         const int MT = min(r - a0, 2 * NT_M2LS), NP = (MT + 1) / 2, NS = NT_M2LS / NP;
         const int s = tid / NP, pa = tid % NP;
@@ -427,7 +429,8 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
     __shared__ double red[2 * NT_P2P];
     __shared__ __align__(16) double ktab[TAB ? kTabLen<KIND> : 2];
     const int tid = threadIdx.x;
-    const PT diag = (PT)t.diag, kp = (PT)t.kparam;
+    const PT diag = (PT)t.diag;
+    const KPar<PT> kp = kpar<PT>(t);
     if constexpr (TAB) stage_table<KIND>(t.ktab, ktab); // first used after a barrier
     // each block takes a contiguous chunk of leaves (one leaf when the grid covers them all)
     const int chunk = (leaf_count + gridDim.x - 1) / gridDim.x, blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -695,7 +698,11 @@ int launch_mvp(const DevTree<P> &t, const LaunchPlan &plan, const double *x, dou
     case 4: return (int)enqueue<P, H2S_K_GAUSSIAN, 2>(t, plan, x, y, mask, s, prof);
     case 5: return (int)enqueue<P, H2S_K_GAUSSIAN, 3>(t, plan, x, y, mask, s, prof);
     case 6: return (int)enqueue<P, H2S_K_EXP_R, 2>(t, plan, x, y, mask, s, prof);
-    default: return (int)enqueue<P, H2S_K_EXP_R, 3>(t, plan, x, y, mask, s, prof);
+    case 7: return (int)enqueue<P, H2S_K_EXP_R, 3>(t, plan, x, y, mask, s, prof);
+    case 8: return (int)enqueue<P, H2S_K_RBF_AR, 2>(t, plan, x, y, mask, s, prof);
+    case 9: return (int)enqueue<P, H2S_K_RBF_AR, 3>(t, plan, x, y, mask, s, prof);
+    case 10: return (int)enqueue<P, H2S_K_RBF_LOG, 2>(t, plan, x, y, mask, s, prof);
+    default: return (int)enqueue<P, H2S_K_RBF_LOG, 3>(t, plan, x, y, mask, s, prof);
     }
 }
 

@@ -146,7 +146,7 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
     const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
-    const double kp = t.kparam;
+    const KPar<double> kp = kpar<double>(t);
     for (int a0 = 0; a0 < r; a0 += 2 * NT_BM) {
         const int MT = min(r - a0, 2 * NT_BM), NP = (MT + 1) / 2, NS = NT_BM / NP;
         const int s = tid / NP, pa = tid % NP;
@@ -235,7 +235,8 @@ __global__ __launch_bounds__(NT_BP) void kb_p2p(DevTree<P> t, int32_t leaf_begin
     const int tid = threadIdx.x;
     const int leaf = leaf_begin + xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
-    const PT diag = (PT)t.diag, kp = (PT)t.kparam;
+    const PT diag = (PT)t.diag;
+    const KPar<PT> kp = kpar<PT>(t);
     const double *cX = t.box_ctr + 3 * g;
     if constexpr (TAB) stage_table<KIND>(t.ktab, ktab); // first used after a barrier
     for (int i0 = 0; i0 < n; i0 += NT_BP) {
@@ -419,7 +420,11 @@ int launch_mvp_batch(const DevTree<P> &t, const LaunchPlan &plan, const double *
     case 4: return (int)enqueue_b<P, H2S_K_GAUSSIAN, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
     case 5: return (int)enqueue_b<P, H2S_K_GAUSSIAN, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
     case 6: return (int)enqueue_b<P, H2S_K_EXP_R, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
-    default: return (int)enqueue_b<P, H2S_K_EXP_R, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 7: return (int)enqueue_b<P, H2S_K_EXP_R, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 8: return (int)enqueue_b<P, H2S_K_RBF_AR, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 9: return (int)enqueue_b<P, H2S_K_RBF_AR, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 10: return (int)enqueue_b<P, H2S_K_RBF_LOG, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
+    default: return (int)enqueue_b<P, H2S_K_RBF_LOG, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
     }
 }
 

@@ -100,16 +100,32 @@ __device__ __forceinline__ double inv_sqrt(double x)
     return y;
 }
 
-// Lookup tables of the kernel functions, in doubles: log r 256 (c_i, -0.5 ln c_i)
-// pairs, the exponential kernels 2^(j/64).  Staged in LDS per block.
+// Lookup tables of the kernel functions, in doubles: log r and the log RBF
+// 256 (c_i, -0.5 ln c_i) pairs, the exponential kernels 2^(j/64).  Staged in
+// LDS per block.
 template <int KIND>
-constexpr int kTabLen = KIND == H2S_K_LOG_R ? 512 : (KIND == H2S_K_GAUSSIAN || KIND == H2S_K_EXP_R ? 64 : 2);
+constexpr int kTabLen = KIND == H2S_K_LOG_R || KIND == H2S_K_RBF_LOG
+                            ? 512
+                            : (KIND == H2S_K_GAUSSIAN || KIND == H2S_K_EXP_R ? 64 : 2);
 
 // Stage the table in LDS (whole block; the caller synchronises).
 template <int KIND> __device__ __forceinline__ void stage_table(const double *g, double *tab)
 {
-    if constexpr (KIND != H2S_K_INV_R)
+    if constexpr (KIND != H2S_K_INV_R && KIND != H2S_K_RBF_AR)
         for (int i = threadIdx.x; i < kTabLen<KIND>; i += blockDim.x) tab[i] = g[i];
+}
+
+// Scalar parameters of the kernel function (uniform over the grid, so they
+// live in scalar registers): kp = -1/h^2 for the Gaussian; for the piecewise
+// RBFs of radius a, c0 = a^2 and the branch factors c1, c2 (a, 1/a for
+// a/r | r/a; 1/log a, 1/(a log a - 1) for log r | r log r - 1).
+template <typename T> struct KPar {
+    T kp, c0, c1, c2;
+};
+
+template <typename T, class Tree> __device__ __forceinline__ KPar<T> kpar(const Tree &t)
+{
+    return KPar<T>{(T)t.kparam, (T)t.kc[0], (T)t.kc[1], (T)t.kc[2]};
 }
 
 // Squared distance (ORD is accepted for symmetry with madd).
@@ -120,29 +136,45 @@ template <bool ORD, int D, typename T> __device__ __forceinline__ T dist2(T dx, 
     return r2;
 }
 
-// Kernel value from a squared distance r2 > 0.  kp: -1/h^2 for the Gaussian.
-template <int KIND> __device__ __forceinline__ double kval_pos(double r2, double kp, const double *tab)
+// Kernel value from a squared distance r2 > 0.  The branch of the piecewise
+// RBFs is taken on r2 >= a^2 (the functions are continuous at r = a).
+template <int KIND> __device__ __forceinline__ double kval_pos(double r2, const KPar<double> &kp, const double *tab)
 {
     if constexpr (KIND == H2S_K_LOG_R) return half_log(r2, (const double2 *)tab);
     else if constexpr (KIND == H2S_K_INV_R) return inv_sqrt(r2);
-    else if constexpr (KIND == H2S_K_GAUSSIAN) return exp_tab(r2 * kp, tab);
-    else return exp_tab(-sqrt(r2), tab);
+    else if constexpr (KIND == H2S_K_GAUSSIAN) return exp_tab(r2 * kp.kp, tab);
+    else if constexpr (KIND == H2S_K_EXP_R) return exp_tab(-sqrt(r2), tab);
+    else if constexpr (KIND == H2S_K_RBF_AR) {
+        const double rs = inv_sqrt(r2); // 1/r
+        return r2 >= kp.c0 ? kp.c1 * rs : (r2 * rs) * kp.c2;
+    } else { // H2S_K_RBF_LOG
+        const double lr = half_log(r2, (const double2 *)tab); // log r
+        return r2 >= kp.c0 ? lr * kp.c1 : fma(sqrt(r2), lr, -1.0) * kp.c2;
+    }
 }
 
 // Kernel value from the squared distance; r2 == 0 means coincident points.
-template <int KIND> __device__ __forceinline__ double kval(double r2, double diag, double kp, const double *tab)
+template <int KIND>
+__device__ __forceinline__ double kval(double r2, double diag, const KPar<double> &kp, const double *tab)
 {
     const double v = kval_pos<KIND>(r2, kp, tab);
     return r2 == 0.0 ? diag : v;
 }
 
-template <int KIND> __device__ __forceinline__ float kval(float r2, float diag, float kp)
+template <int KIND> __device__ __forceinline__ float kval(float r2, float diag, const KPar<float> &kp)
 {
     float v;
     if constexpr (KIND == H2S_K_LOG_R) v = __log2f(r2) * 0.34657359027997264f; // ln 2 / 2
     else if constexpr (KIND == H2S_K_INV_R) v = __frsqrt_rn(r2);
-    else if constexpr (KIND == H2S_K_GAUSSIAN) v = __expf(r2 * kp);
-    else v = __expf(-__fsqrt_rn(r2));
+    else if constexpr (KIND == H2S_K_GAUSSIAN) v = __expf(r2 * kp.kp);
+    else if constexpr (KIND == H2S_K_EXP_R) v = __expf(-__fsqrt_rn(r2));
+    else if constexpr (KIND == H2S_K_RBF_AR) {
+        const float rs = __frsqrt_rn(r2);
+        v = r2 >= kp.c0 ? kp.c1 * rs : (r2 * rs) * kp.c2;
+    } else {
+        const float lr = __log2f(r2) * 0.34657359027997264f;
+        v = r2 >= kp.c0 ? lr * kp.c1 : fmaf(__fsqrt_rn(r2), lr, -1.0f) * kp.c2;
+    }
     return r2 == 0.0f ? diag : v;
 }
 

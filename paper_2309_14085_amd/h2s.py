@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libh2s.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "h2s.h")
 
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED, ERR_UNSUPPORTED, ERR_INTERNAL = range(7)
-LOG_R, INV_R, GAUSSIAN, EXP_R = 0, 1, 2, 3
+LOG_R, INV_R, GAUSSIAN, EXP_R, RBF_AR, RBF_LOG = 0, 1, 2, 3, 4, 5
 H2STAR, H2_PLUS_H = 0, 1
 FP64, FP32, FP32_M2L = 0, 1, 2
 PHASE_NEAR, PHASE_FAR, PHASE_VER, PHASE_ALL = 1, 2, 4, 7
@@ -252,7 +252,7 @@ def build(points, kind=LOG_R, leaf_size=64, eps=1e-8, eps_ver=None, variant=H2ST
     pts = np.ascontiguousarray(points, dtype=np.float64)
     n, d = pts.shape
     if diag is None:
-        diag = 0.0 if kind in (LOG_R, INV_R) else 1.0
+        diag = 0.0 if kind in (LOG_R, INV_R, RBF_AR, RBF_LOG) else 1.0
     k = Kernel(kind, param, diag, shift)
     o = BuildOpts(leaf_size, eps, eps if eps_ver is None else eps_ver, variant, prec, host_threads, int(host_only))
     h = ctypes.c_void_p()

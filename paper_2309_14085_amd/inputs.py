@@ -1,22 +1,32 @@
 """Seeded synthetic inputs shared by the library's tests, the oracle's tests and the benchmark.
 
-This module holds random-number generation only: no part of the method's
-arithmetic.  Every point set is uniform in [-1, 1]^d and every right-hand side
-is N(0, 1), the distributions of the paper's MVP experiments (Sec. 6.1.1,
-Sec. 6.2.1: uniformly distributed particles in [-1,1]^d, random vectors q).
-Generators are NumPy PCG64 (`numpy.random.default_rng(seed)`), so any seed
-reproduces the same arrays on every machine.
+This module holds input generation only: no part of the method's
+arithmetic.  Random point sets are uniform in [-1, 1]^d and every right-hand
+side is N(0, 1), the distributions of the paper's MVP experiments (Sec. 6.1.1,
+Sec. 6.2.1: uniformly distributed particles in [-1,1]^d, random vectors q);
+the RBF interpolation experiments of Sec. 6 place the particles on a tensor
+Chebyshev grid instead (`chebyshev_grid`).  Generators are NumPy PCG64
+(`numpy.random.default_rng(seed)`), so any seed reproduces the same arrays on
+every machine.
 """
 from dataclasses import dataclass, field
 
 import numpy as np
 
-LOG_R, INV_R, GAUSS, EXP_R = 0, 1, 2, 3
+LOG_R, INV_R, GAUSS, EXP_R, RBF_AR, RBF_LOG = 0, 1, 2, 3, 4, 5
 
 
 def uniform_points(n: int, d: int, seed: int) -> np.ndarray:
     """n points i.i.d. uniform in [-1, 1]^d, row-major (n, d) float64."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n, d))
+
+
+def chebyshev_grid(m: int, d: int) -> np.ndarray:
+    """The m^d tensor grid of first-kind Chebyshev nodes cos((2k + 1) pi / (2m)),
+    k = 0 .. m-1, in [-1, 1]^d: row-major (m^d, d) float64, last coordinate fastest."""
+    nodes = np.cos((2.0 * np.arange(m) + 1.0) * np.pi / (2.0 * m))
+    axes = np.meshgrid(*([nodes] * d), indexing="ij")
+    return np.ascontiguousarray(np.stack([a.ravel() for a in axes], axis=1))
 
 
 def normal_rhs(n: int, m: int, seed: int) -> np.ndarray:
@@ -49,7 +59,7 @@ class Workload:
 
 def _w(c, name, d, n, kind, eps, nrhs, param=0.0, diag=None, shift=0.0, nmax=64, **extra):
     if diag is None:
-        diag = 0.0 if kind in (LOG_R, INV_R) else 1.0
+        diag = 0.0 if kind in (LOG_R, INV_R, RBF_AR, RBF_LOG) else 1.0
     return Workload(name, d, n, kind, param, diag, shift, nmax, eps, nrhs, 1000 + c, 2000 + c, extra)
 
 

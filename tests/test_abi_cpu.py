@@ -45,6 +45,10 @@ def test_validation_before_allocation(lib):
         (pts, 100, 2, None, o),
         (pts, 100, 2, lib.Kernel(9, 0, 0, 0), o),
         (pts, 100, 2, lib.Kernel(lib.GAUSSIAN, 0.0, 1.0, 0.0), o),
+        (pts, 100, 2, lib.Kernel(lib.RBF_AR, 0.0, 0.0, 0.0), o),
+        (pts, 100, 2, lib.Kernel(lib.RBF_AR, float("nan"), 0.0, 0.0), o),
+        (pts, 100, 2, lib.Kernel(lib.RBF_LOG, -0.1, 0.0, 0.0), o),
+        (pts, 100, 2, lib.Kernel(lib.RBF_LOG, 1.0, 0.0, 0.0), o),
         (pts, 100, 2, k, lib.BuildOpts(0, 1e-8, 1e-8, 0, 0, 0, 1)),
         (pts, 100, 2, k, lib.BuildOpts(64, -1.0, 1e-8, 0, 0, 0, 1)),
         (pts, 100, 2, k, lib.BuildOpts(64, float("nan"), 1e-8, 0, 0, 0, 1)),
@@ -97,6 +101,8 @@ CASES = [
     (3, 5000, 1, 64, 1e-6, 0, 0.0, 7),
     (2, 3000, 2, 32, 1e-10, 0, 0.3, 8),
     (3, 3000, 3, 20, 1e-12, 1, 0.0, 9),
+    (2, 4000, 4, 64, 1e-10, 0, 0.05, 10),
+    (3, 3000, 5, 32, 1e-8, 1, 0.1, 11),
 ]
 
 

@@ -44,6 +44,9 @@ CASES = [
     ("3d_invr_ragged_5000", 3, 5000, 1, 64, 1e-6, 0.0, 0.0, 4),
     ("2d_gauss_shift_3000", 2, 3000, 2, 32, 1e-10, 0.3, 1e-2, 5),
     ("3d_expr_3000", 3, 3000, 3, 20, 1e-12, 0.0, 0.0, 6),
+    # piecewise RBFs with radii that put both branches in the near field and the vertex blocks
+    ("2d_rbf_ar_4000", 2, 4000, 4, 64, 1e-10, 0.05, 0.0, 7),
+    ("3d_rbf_log_3000", 3, 3000, 5, 32, 1e-8, 0.1, 54.77, 8),
 ]
 
 
@@ -100,11 +103,11 @@ def test_multi_rhs_with_leading_dimension(lib, orc, inputs):
         assert np.all(y[c * ld + n:(c + 1) * ld] == 7.0)  # padding untouched
 
 
-@pytest.mark.parametrize("d,kind,eps", [(2, 0, 1e-8), (3, 1, 1e-6), (2, 2, 1e-8)])
+@pytest.mark.parametrize("d,kind,eps", [(2, 0, 1e-8), (3, 1, 1e-6), (2, 2, 1e-8), (2, 4, 1e-8), (3, 5, 1e-6)])
 @pytest.mark.parametrize("variant", [0, 1])
 def test_fp32_within_1e5_of_fp64_oracle(lib, orc, inputs, d, kind, eps, variant):
     n = 8192 if d == 2 else 6000
-    param = 0.1 if kind == 2 else 0.0
+    param = {2: 0.1, 4: 0.05, 5: 0.1}.get(kind, 0.0)
     shift = 1e-2 if kind == 2 else 0.0
     pts = inputs.uniform_points(n, d, 500 + d)
     q = inputs.normal_rhs(n, 1, 600 + d)[:, 0]

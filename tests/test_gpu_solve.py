@@ -139,3 +139,35 @@ def test_solve_rbf_full_size(lib, orc, inputs):
     print(f"  oracle residual {res:.3e}", flush=True)
     assert info[0]["converged"]
     assert res <= 1.01e-8
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_solve_piecewise_rbf_interpolation(lib, orc, inputs, d):
+    """The RBF interpolation systems of Sec. 6 on a Chebyshev grid: alpha lambda_i +
+    sum_{j != i} G(|x_i - x_j|) lambda_j = b_i, a = 1e-4, alpha = N^(1/4) with G = a/r | r/a
+    in 2D, alpha = sqrt(N) with G = log r / log a | (r log r - 1)/(a log a - 1) in 3D;
+    b = K q for a random q (exact product, oracle direct sum), and the solution is
+    compared with q (relative error in solution) and with the oracle's GMRES solution."""
+    from oracle.gmres import gmres
+    m, kind, eps, rtol, nmax = (96, lib.RBF_AR, 1e-10, 1e-12, 100) if d == 2 else (20, lib.RBF_LOG, 1e-6, 1e-10, 125)
+    pts = inputs.chebyshev_grid(m, d)
+    n = len(pts)
+    a, alpha = 1e-4, (n ** 0.25 if d == 2 else n ** 0.5)
+    print(f"solve piecewise rbf d={d} n={n}", flush=True)
+    q = inputs.normal_rhs(n, 1, 70 + d)[:, 0]
+    b = orc.direct(pts, q, kind, param=a, shift=alpha)
+    T = lib.build(pts, kind=kind, leaf_size=nmax, eps=eps, param=a, shift=alpha)
+    x, info = T.solve(torch.from_numpy(b).to(_dev()), rtol=rtol)
+    torch.cuda.synchronize()
+    lam = x.cpu().numpy()
+    print(f"  {info[0]}", flush=True)
+    assert info[0]["converged"] and info[0]["residual"] <= rtol
+    O = orc.Tree(pts, kind, nmax, eps, param=a, shift=alpha)
+    assert oracle_residual(O, lam, b) <= 2 * rtol
+    re_sol = np.linalg.norm(lam - q) / np.linalg.norm(q)
+    want, oi = gmres(O.apply, b, restart=50, rtol=rtol)
+    assert oi["converged"]
+    diff = np.linalg.norm(lam - want) / np.linalg.norm(want)
+    print(f"  RE_sol {re_sol:.2e}, vs oracle solution {diff:.2e}", flush=True)
+    assert re_sol <= (1e-10 if d == 2 else 3e-6)
+    assert diff <= (1e-10 if d == 2 else 1e-8)

@@ -37,8 +37,10 @@ def parse():
     p.add_argument("--no-solve", action="store_true", help="skip the RBF interpolation solve beside the MVP")
     p.add_argument("--no-multi-rhs", action="store_true", help="skip the 3D 32-RHS batched product beside the MVP")
     p.add_argument("--no-serve", action="store_true", help="skip the serving run (build + solve requests)")
+    p.add_argument("--no-tune", action="store_true", help="skip the autotuned-schedule leg of the FP64 product")
     p.add_argument("--profile-only", action="store_true",
-                   help="skip the timed steps: warm-up and the per-class profiled steps only (for rocprofv3 runs)")
+                   help="skip the timed steps and the solve, multi-RHS and serving legs: warm-up and the per-class "
+                        "profiled steps only (for rocprofv3 runs)")
     return p.parse_args()
 
 
@@ -79,6 +81,41 @@ def time_variant(h2s, torch, pts, q, w, variant, prec, steps, warmup, prof_steps
     return dict(ms=ms, wall_ms=1e3 * wall / steps if steps else float("nan"), t_init=t_init, stats=stats,
                 kernels={k: {"avg_ms": v[0] / max(v[1], 1), "launches_per_step": v[1] / max(prof_steps, 1)}
                          for k, v in prof.items() if v[1]}), out
+
+
+def time_tuned(h2s, torch, pts, q, w, steps, warmup):
+    """The FP64 H2* product under the default schedule and under the one h2s_tune installs
+    (same tree, same vectors; the two products must be equal bit for bit)."""
+    dev = torch.device("cuda:0")
+    T = h2s.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps, param=w.param, shift=w.shift)
+    x = torch.from_numpy(q).to(dev)
+    y = torch.empty_like(x)
+
+    def timed():
+        for _ in range(warmup):
+            T.apply(x, y)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            T.apply(x, y)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps
+
+    ms_default = timed()
+    ref = y.clone()
+    t0 = time.perf_counter()
+    info = T.tune(x, y, reps=5)
+    tune_s = time.perf_counter() - t0
+    ms_tuned = timed()
+    equal = bool(torch.equal(y, ref))
+    sc, k = T.schedule(), T.stats()["kappa"]
+    T.free()
+    return {"ms_default": ms_default, "ms_tuned": ms_tuned, "speedup": ms_default / ms_tuned,
+            "points_per_s_tuned": w.n / (ms_tuned * 1e-3), "tune_s": tune_s, "candidates": info["candidates"],
+            "bitwise_equal": equal,
+            "schedule": {"near_first": sc["near_first"], "up_threads_by_level": sc["up_threads"][1:k + 1],
+                         "dn_threads_by_level": sc["dn_threads"][1:k]}}
 
 
 def time_solve(h2s, torch, w):
@@ -193,6 +230,8 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.profile_only:  # rocprofv3 runs trace the product alone
+        a.no_solve = a.no_multi_rhs = a.no_serve = a.no_tune = True
     import numpy as np
     import torch
 
@@ -236,6 +275,12 @@ def main():
         dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
         roofline = roofline_entry(dom, kernels[dom], m["stats"], 0 if main_name.endswith("fp64") else 1)
 
+    tuned = None
+    if not a.no_tune and main_name == "h2star_fp64":
+        print("# autotuning the launch schedule of the FP64 product", file=sys.stderr, flush=True)
+        tuned = time_tuned(h2s, torch, pts, q, w, a.steps, a.warmup)
+        print(f"# tuned: {tuned}", file=sys.stderr, flush=True)
+
     solve = None
     if not a.no_solve:
         print("# building and timing the RBF interpolation solve", file=sys.stderr, flush=True)
@@ -275,6 +320,7 @@ def main():
                    "nca_tol": w.eps, "nrhs": 1, "variant": "H2*(b+t)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "tuned_schedule": tuned,
         "solve": solve,
         "multi_rhs": multi,
         "serving": served,
@@ -328,16 +374,26 @@ FP64_FLOPS_PER_EVAL = 21
 COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_2d_log_n1048576.json")
 
 
+KERNEL_SOURCES = ("h2s_kernels.hip", "h2s_kfun.hpp", "h2s_device.hpp")
+
+
+def kernel_sources_sha256():
+    """SHA-256 over the sources the single-column product kernels are compiled from, in order."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2309_14085_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
     or None if that summary was taken on other kernel sources."""
-    import hashlib
     try:
         c = json.load(open(COUNTERS))
     except (OSError, ValueError):
         return None
-    src = os.path.join(ROOT, "paper_2309_14085_amd", "csrc", "h2s_kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != c.get("kernels_sha256"):
+    if kernel_sources_sha256() != c.get("kernels_sha256"):
         return None
     k = c.get("per_launch_bytes", {}).get(kernel)
     return None if k is None else k["fetch"] + k["write"]

@@ -223,6 +223,47 @@ h2s_status h2s_export(h2s_tree t, const char *path);
 h2s_status h2s_set_profiling(h2s_tree t, int32_t enable);
 h2s_status h2s_get_profile(h2s_tree t, double *ms_total, int64_t *launches);
 
+/* Launch schedule of the single-column product.  No field changes a result:
+ * every P2M / M2M / L2L output is summed by one thread in index order
+ * whatever the block width, and a leaf's near field is the same whichever
+ * launch and stream take it, so products are equal bit for bit under any
+ * valid schedule.  Entries of up_threads / dn_threads beyond level kappa
+ * (h2s_stats.kappa) are ignored. */
+typedef struct {
+    double near_first;       /* share of the leaves (0..1) whose near field runs on the second stream
+                                beside P2M and M2M; the rest runs beside L2L.  Default 0.6 */
+    int32_t up_threads[33];  /* block width of P2M (level kappa) and M2M (levels 1..kappa-1):
+                                a multiple of 64 in [64, 512]; default: outputs of the widest box */
+    int32_t dn_threads[33];  /* block width of L2L (levels 1..kappa-1), same rule */
+} h2s_schedule;
+
+/* Read or replace the handle's schedule (valid on host_only handles too).
+ * h2s_set_schedule rejects, with H2S_ERR_INVALID_ARG and no change, a
+ * near_first outside [0, 1] or a width that is not a multiple of 64 in
+ * [64, 512] at any level 1..kappa.  It must not be called while another
+ * call uses the handle. */
+h2s_status h2s_get_schedule(h2s_tree t, h2s_schedule *s);
+h2s_status h2s_set_schedule(h2s_tree t, const h2s_schedule *s);
+
+/* Autotuner of the schedule.  Times the product y = K~ x (device vectors of
+ * length n in user order, not overlapping) on stream under candidate
+ * schedules: the near-field share, then the block width of every level of
+ * P2M, M2M and L2L, each chosen in turn with the others fixed; each
+ * candidate is timed twice over reps products (reps < 1 means 5) with HIP
+ * events, and the faster time counts.  A candidate replaces the current
+ * choice only when it is faster by more than 0.5%.  The fastest schedule is
+ * installed in the handle; info (may be NULL) receives the time of the
+ * schedule at entry and of the installed one (milliseconds per product) and
+ * the number of candidates timed.  Synchronous: it returns after the last
+ * product, and y then holds K~ x.  H2S_ERR_UNSUPPORTED for a host_only
+ * handle; H2S_ERR_DEVICE if a launch or an event fails. */
+typedef struct {
+    double ms_entry;     /* product time with the schedule at entry */
+    double ms_tuned;     /* product time with the installed schedule */
+    int32_t candidates;  /* schedules timed */
+} h2s_tune_info;
+h2s_status h2s_tune(h2s_tree t, const double *x, double *y, int32_t reps, h2s_tune_info *info, void *stream);
+
 /* Device memory hooks: alloc(ctx, bytes, &ptr) returns 0 on success.  NULL
  * functions restore hipMalloc / hipFree.  Affects later builds only. */
 typedef int (*h2s_alloc_fn)(void *ctx, size_t bytes, void **ptr);

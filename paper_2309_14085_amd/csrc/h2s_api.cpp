@@ -432,19 +432,6 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
         }
         D.ktab = up.copy(tab);
     }
-    // block sizes: one thread per output of a box (both families), whole wavefronts
-    auto threads = [](int32_t outputs) { return std::min(512, std::max(64, (outputs + 63) / 64 * 64)); };
-    t->plan = h2s::LaunchPlan{};
-    t->plan.lev_off = t->lev_off.data();
-    for (int l = 0; l <= kappa; ++l) {
-        int32_t cols = 0, rows = 0;
-        for (int32_t g = r.lev_off[l]; g < r.lev_off[l + 1]; ++g) {
-            cols = std::max(cols, r.fam[0].rank[g] + r.fam[1].rank[g]);
-            if (l < kappa) rows = std::max(rows, r.fam[0].op_rows[g] + r.fam[1].op_rows[g]);
-        }
-        t->plan.up_threads[l] = threads(cols);
-        t->plan.dn_threads[l] = threads(rows);
-    }
     if (up.st != H2S_OK) return up.st;
     if (hipStreamSynchronize(s) != hipSuccess) return fail(H2S_ERR_DEVICE, "stream synchronisation failed after upload");
     return H2S_OK;
@@ -487,14 +474,125 @@ h2s_status ensure_streams(h2s_tree t)
     return H2S_OK;
 }
 
-// One product in precision p (uploaded, streams created); hipError_t as int.
+// The default schedule: blocks as wide as the outputs of the widest box of
+// a level (both families), in whole wavefronts, and the near field split
+// kNearFirstDefault / rest around M2L.
+void default_plan(h2s_tree t)
+{
+    const h2s::HostRep &r = t->rep;
+    const int kappa = std::min(r.kappa, h2s::kMaxLevels);
+    auto threads = [](int32_t outputs) { return std::min(512, std::max(64, (outputs + 63) / 64 * 64)); };
+    t->plan = h2s::LaunchPlan{};
+    t->plan.lev_off = t->lev_off.data();
+    t->plan.near_first = h2s::kNearFirstDefault;
+    for (int l = 0; l <= h2s::kMaxLevels; ++l) t->plan.up_threads[l] = t->plan.dn_threads[l] = 64;
+    for (int l = 0; l <= kappa; ++l) {
+        int32_t cols = 0, rows = 0;
+        for (int32_t g = r.lev_off[l]; g < r.lev_off[l + 1]; ++g) {
+            cols = std::max(cols, r.fam[0].rank[g] + r.fam[1].rank[g]);
+            if (l < kappa) rows = std::max(rows, r.fam[0].op_rows[g] + r.fam[1].op_rows[g]);
+        }
+        t->plan.up_threads[l] = threads(cols);
+        t->plan.dn_threads[l] = threads(rows);
+    }
+}
+
+// One product in precision p (uploaded, streams created) under plan; hipError_t as int.
+int mvp_plan(h2s_tree t, const h2s::LaunchPlan &plan, h2s_precision p, uint32_t mask, const double *x, double *y,
+             void *stream, const h2s::ProfileHook *prof)
+{
+    const h2s::Streams st{stream, t->aux, t->ev_fork, t->ev_fork2, t->ev_join};
+    if (p == H2S_FP64) return h2s::launch_mvp<h2s::P64>(t->t64, plan, x, y, mask, st, prof);
+    if (p == H2S_FP32) return h2s::launch_mvp<h2s::P32>(t->t32, plan, x, y, mask, st, prof);
+    return h2s::launch_mvp<h2s::P32M>(t->t32m, plan, x, y, mask, st, prof);
+}
+
 int mvp(h2s_tree t, h2s_precision p, uint32_t mask, const double *x, double *y, void *stream,
         const h2s::ProfileHook *prof)
 {
-    const h2s::Streams st{stream, t->aux, t->ev_fork, t->ev_fork2, t->ev_join};
-    if (p == H2S_FP64) return h2s::launch_mvp<h2s::P64>(t->t64, t->plan, x, y, mask, st, prof);
-    if (p == H2S_FP32) return h2s::launch_mvp<h2s::P32>(t->t32, t->plan, x, y, mask, st, prof);
-    return h2s::launch_mvp<h2s::P32M>(t->t32m, t->plan, x, y, mask, st, prof);
+    return mvp_plan(t, t->plan, p, mask, x, y, stream, prof);
+}
+
+// Milliseconds per product under plan: the faster of two runs of reps products.
+h2s_status time_plan(h2s_tree t, const h2s::LaunchPlan &plan, const double *x, double *y, int reps,
+                     hipStream_t s, hipEvent_t e0, hipEvent_t e1, double &ms)
+{
+    ms = INFINITY;
+    for (int trial = 0; trial < 2; ++trial) {
+        if (hipEventRecord(e0, s) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipEventRecord failed");
+        for (int k = 0; k < reps; ++k) {
+            const int rc = mvp_plan(t, plan, t->opts.prec, H2S_PHASE_ALL, x, y, s, nullptr);
+            if (rc != 0)
+                return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
+        }
+        float f = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&f, e0, e1) != hipSuccess)
+            return fail(H2S_ERR_DEVICE, "timing the product failed");
+        ms = std::min(ms, (double)f / reps);
+    }
+    return H2S_OK;
+}
+
+// Coordinate search over the schedule (see h2s_tune).
+h2s_status tune_plan(h2s_tree t, const double *x, double *y, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                     h2s_tune_info &info)
+{
+    const int kappa = std::min(t->rep.kappa, h2s::kMaxLevels);
+    h2s::LaunchPlan best = t->plan;
+    double best_ms = 0.0, ms = 0.0;
+    h2s_status st;
+    // one untimed product, then the schedule at entry
+    if (mvp_plan(t, best, t->opts.prec, H2S_PHASE_ALL, x, y, s, nullptr) != 0)
+        return fail(H2S_ERR_DEVICE, "kernel launch failed");
+    if ((st = time_plan(t, best, x, y, reps, s, e0, e1, best_ms)) != H2S_OK) return st;
+    info.ms_entry = best_ms;
+    info.candidates = 1;
+    auto consider = [&](const h2s::LaunchPlan &cand) -> h2s_status {
+        h2s_status r2 = time_plan(t, cand, x, y, reps, s, e0, e1, ms);
+        if (r2 != H2S_OK) return r2;
+        ++info.candidates;
+        if (ms < best_ms * (1.0 - 0.005)) {
+            best = cand;
+            best_ms = ms;
+        }
+        return H2S_OK;
+    };
+    const double shares[] = {0.0, 0.2, 0.4, 0.5, 0.6, 0.7, 0.8, 1.0};
+    auto tune_share = [&]() -> h2s_status {
+        const double cur = best.near_first;
+        for (double f : shares) {
+            if (f == cur) continue;
+            h2s::LaunchPlan c = best;
+            c.near_first = f;
+            h2s_status r2 = consider(c);
+            if (r2 != H2S_OK) return r2;
+        }
+        return H2S_OK;
+    };
+    if (kappa >= 1) {
+        if ((st = tune_share()) != H2S_OK) return st;
+        // P2M (level kappa) and M2M (levels kappa-1 .. 1), then L2L (levels 1 .. kappa-1)
+        for (int pass = 0; pass < 2; ++pass) {
+            const int l0 = pass == 0 ? kappa : 1, l1 = pass == 0 ? 1 : kappa - 1, dl = pass == 0 ? -1 : 1;
+            for (int l = l0; pass == 0 ? l >= l1 : l <= l1; l += dl) {
+                const int cur = pass == 0 ? best.up_threads[l] : best.dn_threads[l];
+                for (int w = 64; w <= 512; w += 64) {
+                    if (w == cur) continue;
+                    h2s::LaunchPlan c = best;
+                    (pass == 0 ? c.up_threads[l] : c.dn_threads[l]) = w;
+                    if ((st = consider(c)) != H2S_OK) return st;
+                }
+            }
+        }
+        if ((st = tune_share()) != H2S_OK) return st;
+    }
+    t->plan = best;
+    info.ms_tuned = best_ms;
+    // leave y = K~ x under the installed schedule
+    if (mvp(t, t->opts.prec, H2S_PHASE_ALL, x, y, s, nullptr) != 0 || hipStreamSynchronize(s) != hipSuccess)
+        return fail(H2S_ERR_DEVICE, "the final product failed");
+    return H2S_OK;
 }
 
 // The batched product serves H2* with a double far field.
@@ -656,6 +754,7 @@ h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kerne
         return fail(st, err);
     }
     t->lev_off = t->rep.lev_off;
+    default_plan(t);
     if (!t->host_only) {
         st = ensure_uploaded(t, o->prec, (hipStream_t)stream);
         if (st != H2S_OK) {
@@ -769,6 +868,61 @@ h2s_status h2s_solve(h2s_tree t, const double *b, double *x, int32_t nrhs, int64
     }
     if (!all) return fail(H2S_ERR_NOT_CONVERGED, "a right-hand side did not reach rtol");
     return H2S_OK;
+}
+
+h2s_status h2s_get_schedule(h2s_tree t, h2s_schedule *sc)
+{
+    if (!t || !sc) return fail(H2S_ERR_INVALID_ARG, "tree or schedule is NULL");
+    *sc = h2s_schedule{};
+    sc->near_first = t->plan.near_first;
+    for (int l = 0; l <= h2s::kMaxLevels; ++l) {
+        sc->up_threads[l] = t->plan.up_threads[l];
+        sc->dn_threads[l] = t->plan.dn_threads[l];
+    }
+    return H2S_OK;
+}
+
+h2s_status h2s_set_schedule(h2s_tree t, const h2s_schedule *sc)
+{
+    if (!t || !sc) return fail(H2S_ERR_INVALID_ARG, "tree or schedule is NULL");
+    if (!(sc->near_first >= 0.0 && sc->near_first <= 1.0))
+        return fail(H2S_ERR_INVALID_ARG, "near_first must be in [0, 1]");
+    const int kappa = std::min(t->rep.kappa, h2s::kMaxLevels);
+    auto ok = [](int32_t w) { return w >= 64 && w <= 512 && w % 64 == 0; };
+    for (int l = 1; l <= kappa; ++l)
+        if (!ok(sc->up_threads[l]) || (l < kappa && !ok(sc->dn_threads[l])))
+            return fail(H2S_ERR_INVALID_ARG, "level " + std::to_string(l) +
+                                                 ": block widths must be multiples of 64 in [64, 512]");
+    t->plan.near_first = sc->near_first;
+    for (int l = 1; l <= kappa; ++l) {
+        t->plan.up_threads[l] = sc->up_threads[l];
+        if (l < kappa) t->plan.dn_threads[l] = sc->dn_threads[l];
+    }
+    return H2S_OK;
+}
+
+h2s_status h2s_tune(h2s_tree t, const double *x, double *y, int32_t reps, h2s_tune_info *info, void *stream)
+{
+    if (!t) return fail(H2S_ERR_INVALID_ARG, "tree is NULL");
+    if (t->host_only) return fail(H2S_ERR_UNSUPPORTED, "handle was built with host_only");
+    if (!x || !y) return fail(H2S_ERR_INVALID_ARG, "x or y is NULL");
+    const int64_t n = t->rep.n;
+    if ((const char *)x < (const char *)(y + n) && (const char *)y < (const char *)(x + n))
+        return fail(H2S_ERR_INVALID_ARG, "x and y overlap");
+    if (reps < 1) reps = 5;
+    if (hipSetDevice(t->device) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipSetDevice failed");
+    if (ensure_streams(t) != H2S_OK) return H2S_ERR_DEVICE;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(H2S_ERR_DEVICE, "creating the timing events failed");
+    }
+    h2s_tune_info res{};
+    const h2s_status st = tune_plan(t, x, y, reps, (hipStream_t)stream, e0, e1, res);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == H2S_OK && info) *info = res;
+    return st;
 }
 
 h2s_status h2s_free(h2s_tree t)

@@ -118,7 +118,10 @@ struct LaunchPlan {
     const int32_t *lev_off;              // global box range of every level (kappa + 2 entries)
     int32_t up_threads[kMaxLevels + 1];  // block size of P2M (level kappa) and M2M (levels < kappa)
     int32_t dn_threads[kMaxLevels + 1];  // block size of L2L per level
+    double near_first;                   // share of the leaves whose near field runs beside P2M and M2M
 };
+
+constexpr double kNearFirstDefault = 0.6;
 
 // Optional timing hook: mark(ctx, kernel class, 0 = before / 1 = after, stream).
 struct ProfileHook {

@@ -412,21 +412,28 @@ template <class P> __global__ __launch_bounds__(64) void k_pair_sum(DevTree<P> t
 
 // ---------------------------------------------------------------------------
 // Near field: one target leaf per block, its near list N*(X) staged in LDS;
-// yn[i] = sum_{j in N*(X)} K(x_i, x_j) q_j.  Each thread takes two targets
-// (a and a + P) against one slice of the staged sources, so every source it
-// loads serves two evaluations.
+// yn[i] = sum_{j in N*(X)} K(x_i, x_j) q_j.  Each thread takes P2P_TPT
+// targets (a, a + NP, a + 2 NP, ...) against one slice of the staged
+// sources, so every source it reads from LDS serves P2P_TPT evaluations:
+// the staged sources and the kernel-table gathers share the LDS bandwidth.
 // ---------------------------------------------------------------------------
 constexpr int NT_P2P = 256;
 constexpr int P2P_SRC = 1024;     // staged source points per group
-constexpr double kNearFirst = 0.6; // share of the leaves whose near field overlaps P2M and M2M
+constexpr int P2P_TPT = 4;        // targets per thread
 
 template <class P, int KIND, int D>
 __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin, int32_t leaf_count)
 {
     using PT = typename P::pt_t;
     constexpr bool TAB = sizeof(PT) == 8;
-    __shared__ PT sx[P2P_SRC], sy[P2P_SRC], sz[D == 3 ? P2P_SRC : 1], sq[P2P_SRC];
-    __shared__ double red[2 * NT_P2P];
+    constexpr int TPT = P2P_TPT;
+    // staged sources (x, y, q[, z]); after the last group the same memory holds the slice partials
+    constexpr size_t SRC_BYTES = (size_t)(D == 3 ? 4 : 3) * P2P_SRC * sizeof(PT);
+    constexpr size_t RED_BYTES = (size_t)TPT * NT_P2P * sizeof(double);
+    __shared__ __align__(16) unsigned char sbuf[SRC_BYTES > RED_BYTES ? SRC_BYTES : RED_BYTES];
+    PT *const sx = reinterpret_cast<PT *>(sbuf), *const sy = sx + P2P_SRC, *const sq = sy + P2P_SRC;
+    PT *const sz = sq + P2P_SRC; // used in 3D only
+    double *const red = reinterpret_cast<double *>(sbuf);
     __shared__ __align__(16) double ktab[TAB ? kTabLen<KIND> : 2];
     const int tid = threadIdx.x;
     const PT diag = (PT)t.diag;
@@ -439,19 +446,26 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
         const int leaf = leaf_begin + lf, g = t.leaf0 + leaf;
         const int b = t.box_begin[g], n = t.box_end[g] - b;
         const double *cX = t.box_ctr + 3 * g;
-        for (int i0 = 0; i0 < n; i0 += 2 * NT_P2P) {
-            // MT targets this pass as NP pairs (a, a + NP); NS source slices
-            const int MT = min(n - i0, 2 * NT_P2P), NP = (MT + 1) / 2, NS = NT_P2P / NP;
+        for (int i0 = 0; i0 < n; i0 += TPT * NT_P2P) {
+            // MT targets this pass in NP groups (a, a + NP, ...); NS source slices
+            const int MT = min(n - i0, TPT * NT_P2P), NP = (MT + TPT - 1) / TPT, NS = NT_P2P / NP;
             const int s = tid / NP, pa = tid % NP;
-            const int ia = i0 + pa, ib = pa + NP < MT ? ia + NP : ia; // a lone last target is paired with itself
-            const PT xa = t.px[b + ia], ya = t.py[b + ia], za = D == 3 ? t.pz[b + ia] : PT(0);
-            const PT xb = t.px[b + ib], yb = t.py[b + ib], zb = D == 3 ? t.pz[b + ib] : PT(0);
-            double acc_a = 0.0, acc_b = 0.0;
+            int it[TPT];
+            PT tx[TPT], ty[TPT], tz[TPT];
+            double acc[TPT];
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                it[k] = pa + k * NP < MT ? i0 + pa + k * NP : i0 + pa; // a missing target repeats the first
+                tx[k] = t.px[b + it[k]];
+                ty[k] = t.py[b + it[k]];
+                tz[k] = D == 3 ? t.pz[b + it[k]] : PT(0);
+                acc[k] = 0.0;
+            }
             int pos = 0, self0 = 0, self1 = 0; // staged positions of the target leaf's own points
             // slice s takes the staged sources jb + s, jb + s + NS, ... below je
             auto slice_sum = [&](int jb, int je, auto check) {
                 constexpr bool CHECK = decltype(check)::value;
-                auto k = [&](PT r2) -> PT {
+                auto kv = [&](PT r2) -> PT {
                     if constexpr (sizeof(PT) == 8) {
                         if constexpr (CHECK) return kval<KIND>(r2, diag, kp, ktab);
                         else return kval_pos<KIND>(r2, kp, ktab);
@@ -459,24 +473,26 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
                         return kval<KIND>(r2, diag, kp);
                     }
                 };
-                PT a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-                int j = jb + s;
-                for (; j + NS < je; j += 2 * NS) {
-                    const int j1 = j + NS;
-                    const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
-                    const PT x1 = sx[j1], y1 = sy[j1], z1 = D == 3 ? sz[j1] : PT(0), q1 = sq[j1];
-                    a0 += k(dist2<false, D>(xa - x0, ya - y0, za - z0)) * q0;
-                    b0 += k(dist2<false, D>(xb - x0, yb - y0, zb - z0)) * q0;
-                    a1 += k(dist2<false, D>(xa - x1, ya - y1, za - z1)) * q1;
-                    b1 += k(dist2<false, D>(xb - x1, yb - y1, zb - z1)) * q1;
+                if constexpr (sizeof(PT) == 8) {
+                    for (int j = jb + s; j < je; j += NS) {
+                        const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
+#pragma unroll
+                        for (int k = 0; k < TPT; ++k)
+                            acc[k] = fma(kv(dist2<false, D>(tx[k] - x0, ty[k] - y0, tz[k] - z0)), q0, acc[k]);
+                    }
+                } else {
+                    // float partial sums per slice, accumulated in double
+                    PT a[TPT];
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) a[k] = PT(0);
+                    for (int j = jb + s; j < je; j += NS) {
+                        const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
+#pragma unroll
+                        for (int k = 0; k < TPT; ++k) a[k] += kv(dist2<false, D>(tx[k] - x0, ty[k] - y0, tz[k] - z0)) * q0;
+                    }
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) acc[k] += (double)a[k];
                 }
-                if (j < je) {
-                    const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
-                    a0 += k(dist2<false, D>(xa - x0, ya - y0, za - z0)) * q0;
-                    b0 += k(dist2<false, D>(xb - x0, yb - y0, zb - z0)) * q0;
-                }
-                acc_a += (double)(a0 + a1);
-                acc_b += (double)(b0 + b1);
             };
             auto flush = [&]() {
                 __syncthreads();
@@ -522,18 +538,17 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
                     if (pos == P2P_SRC) flush();
                 }
             }
-            if (pos > 0) flush();
-            red[tid] = s < NS ? acc_a : 0.0;
-            red[NT_P2P + tid] = s < NS ? acc_b : 0.0;
+            if (pos > 0) flush(); // ends with a barrier: the staging memory is free for the partials
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) red[k * NT_P2P + tid] = s < NS ? acc[k] : 0.0;
             __syncthreads();
             if (tid < NP) {
-                double phi_a = 0.0, phi_b = 0.0;
-                for (int q = 0; q < NS; ++q) {
-                    phi_a += red[q * NP + tid];
-                    phi_b += red[NT_P2P + q * NP + tid];
+#pragma unroll
+                for (int k = 0; k < TPT; ++k) {
+                    double phi = 0.0;
+                    for (int q = 0; q < NS; ++q) phi += red[k * NT_P2P + q * NP + tid];
+                    if (k == 0 || it[k] != it[0]) t.yn[b + it[k]] = phi;
                 }
-                t.yn[b + ia] = phi_a;
-                if (ib != ia) t.yn[b + ib] = phi_b;
             }
             __syncthreads();
         }
@@ -615,13 +630,13 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     // The near field needs only the permuted charges.  It runs on the second
-    // stream in two pieces: the first kNearFirst of the leaves beside P2P and
+    // stream in two pieces: the first near_first of the leaves beside P2M and
     // M2M (HBM- and latency-bound), the rest beside L2L, so that it shares
     // the GPU with the memory-bound sweeps rather than with the ALU-bound
     // M2L.  Under the profiling hook it runs on the main stream instead, so
     // that every kernel class is timed alone.
     const bool overlap = (mask & kNear) && !prof;
-    const int near1 = overlap && fam_on ? (int)(kNearFirst * t.nleaf) : t.nleaf;
+    const int near1 = overlap && fam_on ? (int)(plan.near_first * t.nleaf) : t.nleaf;
     auto fork_near = [&](hipEvent_t ev, int lb, int le) -> hipError_t {
         hipError_t e2;
         if ((e2 = hipEventRecord(ev, s)) != hipSuccess) return e2;

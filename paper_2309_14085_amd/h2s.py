@@ -72,6 +72,15 @@ class SolveOpts(ctypes.Structure):
                 ("use_x0", ctypes.c_int32)]
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [("near_first", ctypes.c_double), ("up_threads", ctypes.c_int32 * 33),
+                ("dn_threads", ctypes.c_int32 * 33)]
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("ms_entry", ctypes.c_double), ("ms_tuned", ctypes.c_double), ("candidates", ctypes.c_int32)]
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("refinements", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("residual", ctypes.c_double)]
@@ -102,9 +111,12 @@ def load():
     lib.h2s_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     lib.h2s_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
     lib.h2s_solve.argtypes = [vp, vp, vp, i32, i64, i64, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
+    lib.h2s_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+    lib.h2s_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+    lib.h2s_tune.argtypes = [vp, vp, vp, i32, ctypes.POINTER(TuneInfo), vp]
     for name in ("h2s_build", "h2s_apply", "h2s_apply_phases", "h2s_free", "h2s_get_stats", "h2s_export",
                  "h2s_set_allocator", "h2s_last_error", "h2s_set_profiling", "h2s_get_profile",
-                 "h2s_solve_opts_default", "h2s_solve"):
+                 "h2s_solve_opts_default", "h2s_solve", "h2s_get_schedule", "h2s_set_schedule", "h2s_tune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -227,6 +239,33 @@ class Tree:
 
     def set_profiling(self, on=True):
         check(load().h2s_set_profiling(self._h, int(bool(on))))
+
+    def schedule(self):
+        """The launch schedule: {"near_first", "up_threads", "dn_threads"} (widths per level 0..32)."""
+        sc = Schedule()
+        check(load().h2s_get_schedule(self._h, ctypes.byref(sc)))
+        return {"near_first": sc.near_first, "up_threads": list(sc.up_threads), "dn_threads": list(sc.dn_threads)}
+
+    def set_schedule(self, near_first=None, up_threads=None, dn_threads=None):
+        """Replace fields of the launch schedule (others kept); see h2s_set_schedule."""
+        cur = self.schedule()
+        sc = Schedule()
+        sc.near_first = cur["near_first"] if near_first is None else float(near_first)
+        for name, new in (("up_threads", up_threads), ("dn_threads", dn_threads)):
+            vals = list(cur[name])
+            if new is not None:
+                for l, w in (new.items() if isinstance(new, dict) else enumerate(new)):
+                    vals[l] = int(w)
+            getattr(sc, name)[:] = vals
+        check(load().h2s_set_schedule(self._h, ctypes.byref(sc)))
+
+    def tune(self, x, y, reps=5, stream=None):
+        """Autotune the launch schedule on device vectors x, y (CUDA float64, length n); y = K~ x on return.
+        Returns {"ms_entry", "ms_tuned", "candidates"}."""
+        info = TuneInfo()
+        check(load().h2s_tune(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), int(reps),
+                              ctypes.byref(info), _stream_ptr(stream)))
+        return {"ms_entry": info.ms_entry, "ms_tuned": info.ms_tuned, "candidates": info.candidates}
 
     def profile(self):
         """{kernel class: (total ms, launches)} since the last call; waits for the recorded events."""

@@ -127,9 +127,13 @@ template <class P> __global__ __launch_bounds__(NT_BG) void kb_l2l(DevTree<P> t,
     }
 }
 
-// M2L in double, slice form (as k_m2l_slices), kBatch columns per evaluation.
+// M2L in double, slice form, kBatch columns per evaluation.  Each thread takes
+// BM_TPT target pivots (a, a + NP, ...) against one slice of the staged
+// sources, so the coordinates and the kBatch multipoles of a source, read
+// once from LDS, serve BM_TPT evaluations and BM_TPT x kBatch multiply-adds.
 constexpr int NT_BM = 256;
 constexpr int BM_SRC = 512;
+constexpr int BM_TPT = 4;
 
 template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM) void kb_m2l(DevTree<P> t)
 {
@@ -137,47 +141,48 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
         if constexpr (FAR) return t.far;
         else return t.ver;
     }();
+    constexpr int TPT = BM_TPT;
     __shared__ double sx[BM_SRC], sy[BM_SRC], sz[D == 3 ? BM_SRC : 1];
-    __shared__ double sv[BM_SRC * NB];
-    __shared__ double red[2 * NT_BM];
+    __shared__ double sv[BM_SRC * NB]; // after the last group: the slice partials of one column
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
+    static_assert(BM_SRC * NB >= TPT * NT_BM, "slice partials fit in the multipole buffer");
     const int tid = threadIdx.x;
     stage_table<KIND>(t.ktab, ktab); // first used after a barrier
     const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
     const KPar<double> kp = kpar<double>(t);
-    for (int a0 = 0; a0 < r; a0 += 2 * NT_BM) {
-        const int MT = min(r - a0, 2 * NT_BM), NP = (MT + 1) / 2, NS = NT_BM / NP;
+    for (int a0 = 0; a0 < r; a0 += TPT * NT_BM) {
+        const int MT = min(r - a0, TPT * NT_BM), NP = (MT + TPT - 1) / TPT, NS = NT_BM / NP;
         const int s = tid / NP, pa = tid % NP;
-        const int ia = a0 + pa, ib = pa + NP < MT ? ia + NP : ia;
-        const double xa = F.pvx[c0 + ia], ya = F.pvy[c0 + ia], za = D == 3 ? (double)F.pvz[c0 + ia] : 0.0;
-        const double xb = F.pvx[c0 + ib], yb = F.pvy[c0 + ib], zb = D == 3 ? (double)F.pvz[c0 + ib] : 0.0;
-        double acc_a[NB], acc_b[NB];
+        int it[TPT];
+        double tx[TPT], ty[TPT], tz[TPT];
+        double acc[TPT][NB];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) acc_a[c] = acc_b[c] = 0.0;
+        for (int k = 0; k < TPT; ++k) {
+            it[k] = pa + k * NP < MT ? a0 + pa + k * NP : a0 + pa; // a missing target repeats the first
+            tx[k] = F.pvx[c0 + it[k]];
+            ty[k] = F.pvy[c0 + it[k]];
+            tz[k] = D == 3 ? (double)F.pvz[c0 + it[k]] : 0.0;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) acc[k][c] = 0.0;
+        }
         int pos = 0;
         auto flush = [&]() {
             __syncthreads();
             if (s < NS) {
-                double pa0[NB], pb0[NB];
-#pragma unroll
-                for (int c = 0; c < NB; ++c) pa0[c] = pb0[c] = 0.0;
                 for (int j = s; j < pos; j += NS) {
                     const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0;
-                    const double ka = kval_pos<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), kp, ktab);
-                    const double kb = kval_pos<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), kp, ktab);
+                    double kv[TPT];
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k)
+                        kv[k] = kval_pos<KIND>(dist2<false, D>(tx[k] - x0, ty[k] - y0, tz[k] - z0), kp, ktab);
 #pragma unroll
                     for (int c = 0; c < NB; ++c) {
                         const double v = sv[j * NB + c];
-                        pa0[c] = fma(ka, v, pa0[c]);
-                        pb0[c] = fma(kb, v, pb0[c]);
-                    }
-                }
 #pragma unroll
-                for (int c = 0; c < NB; ++c) {
-                    acc_a[c] += pa0[c];
-                    acc_b[c] += pb0[c];
+                        for (int k = 0; k < TPT; ++k) acc[k][c] = fma(kv[k], v, acc[k][c]);
+                    }
                 }
             }
             __syncthreads();
@@ -199,20 +204,21 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
                 if (pos == BM_SRC) flush();
             }
         }
-        if (pos > 0) flush();
-        // slice partials, one column at a time
+        if (pos > 0) flush(); // ends with a barrier (or nothing was staged): sv is free
+        // slice partials, one column at a time, summed in slice order
+        double *const red = sv;
+#pragma unroll
         for (int c = 0; c < NB; ++c) {
-            red[tid] = s < NS ? acc_a[c] : 0.0;
-            red[NT_BM + tid] = s < NS ? acc_b[c] : 0.0;
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) red[k * NT_BM + tid] = s < NS ? acc[k][c] : 0.0;
             __syncthreads();
             if (tid < NP) {
-                double ua = 0.0, ub = 0.0;
-                for (int q = 0; q < NS; ++q) {
-                    ua += red[q * NP + tid];
-                    ub += red[NT_BM + q * NP + tid];
+#pragma unroll
+                for (int k = 0; k < TPT; ++k) {
+                    double u = 0.0;
+                    for (int q = 0; q < NS; ++q) u += red[k * NT_BM + q * NP + tid];
+                    if (k == 0 || it[k] != it[0]) F.ub[(size_t)(c0 + it[k]) * NB + c] = u;
                 }
-                F.ub[(size_t)(c0 + ia) * NB + c] = ua;
-                if (ib != ia) F.ub[(size_t)(c0 + ib) * NB + c] = ub;
             }
             __syncthreads();
         }

@@ -5,7 +5,8 @@ cpu_baseline leg may import this package.  It shares no code with the
 library in paper_2309_14085_amd/.
 
 Kernel kinds: 0 = log r, 1 = 1/r, 2 = exp(-r^2/h^2), 3 = exp(-r),
-4 = a/r (r >= a) | r/a (r < a), 5 = log r/log a (r >= a) | (r log r - 1)/(a log a - 1) (r < a).
+4 = a/r (r >= a) | r/a (r < a), 5 = log r/log a (r >= a) | (r log r - 1)/(a log a - 1) (r < a),
+6 = (|x-y|^2 + (c(x) - c(y))^2 + 1)^(3/2) with c(x) = exp(-(x_1 + x_3)) (3D only).
 Variants: 0 = H2*(b+t), 1 = (H2+H)*.
 Families: 0 = far field (B2T NCA), 1 = vertex sharing (T2B NCA).
 Lists: 0 = near field N* (leaf level), 1 = IL_far, 2 = IL_ver.
@@ -18,7 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-LOG_R, INV_R, GAUSS, EXP_R, RBF_AR, RBF_LOG = 0, 1, 2, 3, 4, 5
+LOG_R, INV_R, GAUSS, EXP_R, RBF_AR, RBF_LOG, NTI_MQ = 0, 1, 2, 3, 4, 5, 6
 H2STAR, H2_PLUS_H = 0, 1
 FAR, VER = 0, 1
 NEAR_LIST, FAR_LIST, VER_LIST = 0, 1, 2
@@ -81,8 +82,14 @@ def _p(a, t):
 
 def default_diag(kind):
     """K(x, x): 0 for log r, 1/r and the two piecewise RBFs, whose systems leave out
-    j = i (the paper's convention), 1 for the Gaussian and exp(-r)."""
+    j = i (the paper's convention), 1 for the Gaussian, exp(-r) and the NTI multiquadric
+    (its value at x = y)."""
     return 0.0 if kind in (LOG_R, INV_R, RBF_AR, RBF_LOG) else 1.0
+
+
+def _check_dim(kind, d):
+    if kind == NTI_MQ and d != 3:
+        raise ValueError("the NTI multiquadric is defined in 3D only")
 
 
 def direct(points, q, kind, param=0.0, diag=None, shift=0.0, rows=None):
@@ -90,6 +97,7 @@ def direct(points, q, kind, param=0.0, diag=None, shift=0.0, rows=None):
     lib = _load()
     pts = np.ascontiguousarray(points, dtype=np.float64)
     n, d = pts.shape
+    _check_dim(kind, d)
     q = np.ascontiguousarray(q, dtype=np.float64)
     if diag is None:
         diag = default_diag(kind)
@@ -135,6 +143,7 @@ class Tree:
         lib = _load()
         pts = np.ascontiguousarray(points, dtype=np.float64)
         n, d = pts.shape
+        _check_dim(kind, d)
         if eps_ver is None:
             eps_ver = eps_far
         if diag is None:

@@ -42,7 +42,7 @@
 /* Kernel functions (Sec. 6.1.1, 6.2.1, Appendix D; RBFs of the solves)      */
 /* ------------------------------------------------------------------------ */
 
-enum { ORC_LOG_R = 0, ORC_INV_R = 1, ORC_GAUSS = 2, ORC_EXP_R = 3, ORC_RBF_AR = 4, ORC_RBF_LOG = 5 };
+enum { ORC_LOG_R = 0, ORC_INV_R = 1, ORC_GAUSS = 2, ORC_EXP_R = 3, ORC_RBF_AR = 4, ORC_RBF_LOG = 5, ORC_NTI_MQ = 6 };
 
 typedef struct {
     int kind;
@@ -74,6 +74,13 @@ static double kernel_value(const orc_kernel *k, int d, const double *x, const do
     case ORC_RBF_LOG: { /* 3D RBF: log r / log a for r >= a, (r log r - 1)/(a log a - 1) below (Sec. 6, 3D) */
         double r = sqrt(r2), a = k->param;
         return r >= a ? log(r) / log(a) : (r * log(r) - 1.0) / (a * log(a) - 1.0);
+    }
+    case ORC_NTI_MQ: { /* non-translation-invariant scaled multiquadric (Sec. 6, 3D):
+                          (|x - y|^2 + (c(x) - c(y))^2 + 1)^(3/2), c(x) = exp(-(x_1 + x_3)) */
+        if (d != 3) return NAN;
+        double dc = exp(-(x[0] + x[2])) - exp(-(y[0] + y[2]));
+        double t = r2 + dc * dc + 1.0;
+        return t * sqrt(t);
     }
     default: return NAN;
     }

@@ -91,3 +91,31 @@ def test_piecewise_rbfs_values_and_continuity(orc):
         assert abs(lo - 1.0) < 1e-7 and abs(hi - 1.0) < 1e-7
     # their systems leave out j = i: K_ii = 0
     assert orc.default_diag(orc.RBF_AR) == 0.0 and orc.default_diag(orc.RBF_LOG) == 0.0
+
+
+def test_nti_multiquadric_values_and_invariances(orc):
+    """The NTI scaled multiquadric of Sec. 6, F(x, y) = (|x - y|^2 + (c(x) - c(y))^2 + 1)^(3/2),
+    c(x) = exp(-(x_1 + x_3)), at points worked by hand, and the invariances its definition gives.
+
+    x = 0 and y = (0, sqrt 3, 0): c(x) = c(y) = 1, |x - y|^2 = 3, so F = 4^(3/2) = 8.
+    x = 0 and y = (-ln 2, sqrt(2 - ln^2 2), 0): c(y) = 2, |x - y|^2 = 2, (c(x) - c(y))^2 = 1, so F = 8.
+    x = y: F = 1, the default diagonal.  F is symmetric; moving both points along (1, 0, -1)
+    or along (0, 1, 0) keeps |x - y| and every c, so F is unchanged; along (1, 0, 0) it is not."""
+    def F(x, y):
+        pts = np.array([x, y], dtype=np.float64)
+        return orc.direct(pts, np.array([0.0, 1.0]), orc.NTI_MQ)[0]
+
+    o = [0.0, 0.0, 0.0]
+    assert F(o, [0.0, math.sqrt(3.0), 0.0]) == pytest.approx(8.0, rel=1e-15)
+    l2 = math.log(2.0)
+    assert F(o, [-l2, math.sqrt(2.0 - l2 * l2), 0.0]) == pytest.approx(8.0, rel=1e-14)
+    assert orc.default_diag(orc.NTI_MQ) == 1.0
+    x, y = [0.3, -0.2, 0.1], [-0.4, 0.5, 0.7]
+    f0 = F(x, y)
+    assert F(y, x) == f0
+    for sh in ([0.25, 0.0, -0.25], [0.0, 0.6, 0.0]):
+        assert F(np.add(x, sh), np.add(y, sh)) == pytest.approx(f0, rel=1e-14)
+    moved = F(np.add(x, [0.5, 0, 0]), np.add(y, [0.5, 0, 0]))
+    assert abs(moved - f0) > 1e-3 * f0  # not translation invariant
+    with pytest.raises(ValueError):
+        orc.direct(np.zeros((2, 2)), np.ones(2), orc.NTI_MQ)

@@ -16,7 +16,7 @@ import pytest
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 KINDS = {"log_r": (2, 0, 0.0), "inv_r": (3, 1, 0.0), "gauss": (2, 2, 0.3), "exp_r": (3, 3, 0.0),
-         "rbf_ar": (2, 4, 0.05), "rbf_log": (3, 5, 0.05)}
+         "rbf_ar": (2, 4, 0.05), "rbf_log": (3, 5, 0.05), "nti_mq": (3, 6, 0.0)}
 
 
 def rel(a, b):
@@ -150,3 +150,17 @@ def test_paper_re_band_3d(orc, inputs, case):
         res.append(rel(T.apply(q)[rows], orc.direct(pts, q, orc.INV_R, rows=rows)))
     re = float(np.mean(res))
     assert case["re"] / 10 <= re <= case["re"] * 10, (re, case["re"])
+
+
+def test_nti_multiquadric_error_follows_tolerance(orc, inputs):
+    """The NTI multiquadric (a kernel of x and y, not of |x - y| alone) through the same
+    NCA bases on the 16^3 Chebyshev grid of the paper's NTI experiment (Sec. 6): the error
+    against the direct sum falls with the tolerance and stays within 10 eps."""
+    pts = inputs.chebyshev_grid(16, 3)
+    q = inputs.normal_rhs(len(pts), 1, 5)[:, 0]
+    want = orc.direct(pts, q, orc.NTI_MQ)
+    errs = []
+    for eps in (1e-4, 1e-6, 1e-8, 1e-10):
+        errs.append(rel(orc.Tree(pts, orc.NTI_MQ, 64, eps).apply(q), want))
+        assert errs[-1] <= 10 * eps, (eps, errs[-1])
+    assert all(b < a for a, b in zip(errs, errs[1:]))

@@ -52,15 +52,18 @@ typedef enum {
  * exp(-r^2 / param^2) (RBF interpolation); EXP_R: exp(-r) (Matern nu = 1/2,
  * Appendix D); RBF_AR: a/r for r >= a, r/a for r < a (2D RBF interpolation,
  * Sec. 6); RBF_LOG: log r / log a for r >= a, (r log r - 1)/(a log a - 1) for
- * r < a (3D RBF interpolation, Sec. 6); a = param.  The closed set is
- * compiled into the device code. */
+ * r < a (3D RBF interpolation, Sec. 6); a = param.  NTI_MQ: the non-
+ * translation-invariant scaled multiquadric (r^2 + (c(x) - c(y))^2 + 1)^(3/2)
+ * with c(x) = exp(-(x_1 + x_3)) (3D RBF interpolation, Sec. 6); d = 3 only,
+ * not with H2S_FP32_M2L.  The closed set is compiled into the device code. */
 typedef enum {
     H2S_K_LOG_R = 0,
     H2S_K_INV_R = 1,
     H2S_K_GAUSSIAN = 2,
     H2S_K_EXP_R = 3,
     H2S_K_RBF_AR = 4,
-    H2S_K_RBF_LOG = 5
+    H2S_K_RBF_LOG = 5,
+    H2S_K_NTI_MQ = 6
 } h2s_kernel_kind;
 
 typedef struct {

@@ -182,7 +182,8 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     for (int32_t g = 0; g <= nbox; ++g) co[g] = (int32_t)F.coef_off[g];
     G.coef_off = up.copy(co);
     const size_t nc = (size_t)F.coef_off[nbox];
-    std::vector<CT> pvx(nc ? nc : 1), pvy(nc ? nc : 1), pvz(nc ? nc : 1);
+    const bool xw = r.ker.kind == H2S_K_NTI_MQ; // pivots carry c(x) = exp(-(x_1 + x_3))
+    std::vector<CT> pvx(nc ? nc : 1), pvy(nc ? nc : 1), pvz(nc ? nc : 1), pvw(xw && nc ? nc : 1);
     for (int32_t g = 0; g < nbox; ++g)
         for (int64_t c = F.coef_off[g]; c < F.coef_off[g + 1]; ++c) {
             const double *p = &r.pts[(size_t)F.piv_row[c] * d];
@@ -190,10 +191,12 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
             pvx[c] = (CT)(local ? p[0] - cc[0] : p[0]);
             pvy[c] = (CT)(local ? p[1] - cc[1] : p[1]);
             pvz[c] = d == 3 ? (CT)(local ? p[2] - cc[2] : p[2]) : CT(0);
+            if (xw) pvw[c] = (CT)std::exp(-(p[0] + p[2]));
         }
     G.pvx = up.copy(pvx);
     G.pvy = up.copy(pvy);
     G.pvz = up.copy(pvz);
+    G.pvw = up.copy(pvw);
     // leaf bases: the host keeps U_X column-major (n_X x r); add the row-major copy
     std::vector<int64_t> uoff(r.nleaf() + 1, 0);
     for (int32_t lf = 0; lf < r.nleaf(); ++lf) uoff[lf + 1] = uoff[lf] + F.op_off[leaf0 + lf + 1] - F.op_off[leaf0 + lf];
@@ -306,7 +309,8 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
 
     D.perm = up.copy(r.perm);
     {
-        std::vector<PT> px(n), py(n), pz(d == 3 ? n : 1);
+        const bool xw = r.ker.kind == H2S_K_NTI_MQ; // points carry c(x) = exp(-(x_1 + x_3)), not centred
+        std::vector<PT> px(n), py(n), pz(d == 3 ? n : 1), pw(xw ? n : 1);
         for (int32_t g = leaf0; g < nbox; ++g)
             for (int32_t i = r.box_begin[g]; i < r.box_end[g]; ++i) {
                 const double *p = &r.pts[(size_t)i * d];
@@ -314,10 +318,12 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
                 px[i] = (PT)(P::local ? p[0] - c[0] : p[0]);
                 py[i] = (PT)(P::local ? p[1] - c[1] : p[1]);
                 if (d == 3) pz[i] = (PT)(P::local ? p[2] - c[2] : p[2]);
+                if (xw) pw[i] = (PT)std::exp(-(p[0] + p[2]));
             }
         D.px = up.copy(px);
         D.py = up.copy(py);
         D.pz = up.copy(pz);
+        D.pw = up.copy(pw);
     }
     D.box_begin = up.copy(r.box_begin);
     D.box_end = up.copy(r.box_end);
@@ -710,7 +716,10 @@ h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kerne
     if (n < 1 || n > INT32_MAX) return fail(H2S_ERR_INVALID_ARG, "n must be in [1, 2^31 - 1]");
     if (d != 2 && d != 3) return fail(H2S_ERR_INVALID_ARG, "d must be 2 or 3");
     if (!k || !o) return fail(H2S_ERR_INVALID_ARG, "kernel or options is NULL");
-    if (k->kind < H2S_K_LOG_R || k->kind > H2S_K_RBF_LOG) return fail(H2S_ERR_INVALID_ARG, "unknown kernel kind");
+    if (k->kind < H2S_K_LOG_R || k->kind > H2S_K_NTI_MQ) return fail(H2S_ERR_INVALID_ARG, "unknown kernel kind");
+    if (k->kind == H2S_K_NTI_MQ && d != 3) return fail(H2S_ERR_INVALID_ARG, "the NTI multiquadric needs d = 3");
+    if (k->kind == H2S_K_NTI_MQ && o && o->prec == H2S_FP32_M2L)
+        return fail(H2S_ERR_UNSUPPORTED, "H2S_FP32_M2L is not available for the NTI multiquadric");
     if ((k->kind == H2S_K_RBF_AR || k->kind == H2S_K_RBF_LOG) && !(is_finite(k->param) && k->param > 0))
         return fail(H2S_ERR_INVALID_ARG, "the RBF radius (param) must be finite and > 0");
     if (k->kind == H2S_K_RBF_LOG && k->param == 1.0) return fail(H2S_ERR_INVALID_ARG, "RBF_LOG needs param != 1");
@@ -824,6 +833,8 @@ h2s_status h2s_solve(h2s_tree t, const double *b, double *x, int32_t nrhs, int64
     if (o.max_iter < 0 || o.max_refine < 0) return fail(H2S_ERR_INVALID_ARG, "max_iter and max_refine must be >= 0");
     if (!(o.rtol >= 0.0) || !is_finite(o.rtol) || !(o.inner_rtol >= 0.0) || !is_finite(o.inner_rtol))
         return fail(H2S_ERR_INVALID_ARG, "rtol and inner_rtol must be finite and >= 0");
+    if (o.inner_prec == H2S_FP32_M2L && t->ker.kind == H2S_K_NTI_MQ)
+        return fail(H2S_ERR_UNSUPPORTED, "H2S_FP32_M2L is not available for the NTI multiquadric");
     if (o.inner_prec != H2S_FP64 && o.inner_prec != H2S_FP32 && o.inner_prec != H2S_FP32_M2L)
         return fail(H2S_ERR_INVALID_ARG, "bad inner precision");
     const char *bb = (const char *)b, *be = (const char *)(b + ldb * (nrhs - 1) + n);

@@ -59,6 +59,7 @@ template <typename CT, typename BT> struct DevFamily {
     int32_t lmin;
     const int32_t *coef_off;     // nbox + 1
     const CT *pvx, *pvy, *pvz;   // pivot coordinates per coefficient
+    const CT *pvw;               // NTI multiquadric: c(x) of each pivot (absolute)
     const BT *U_rm, *U_cm;       // leaf bases
     const int64_t *uoff;         // per leaf (local index)
     const double *Tr_rm, *Tr_cm; // stacked transfers
@@ -98,6 +99,7 @@ template <class P> struct DevTree {
                                 // 1/log a, 1/(a log a - 1) (log r | r log r - 1)
     const int32_t *perm;        // tree position -> user index
     const pt_t *px, *py, *pz;
+    const pt_t *pw;             // NTI multiquadric: c(x) = exp(-(x_1 + x_3)) per point (absolute)
     const int32_t *box_begin, *box_end, *box_cbeg, *box_cend;
     const double *box_ctr;      // 3 per box
     const int32_t *leaf_anc;    // (kappa + 1) per leaf: ancestor at each level

@@ -45,6 +45,11 @@ double kernel_entry(const KernelSpec &k, int d, const double *x, const double *y
         const double r = std::sqrt(r2), a = k.param;
         return r >= a ? std::log(r) / std::log(a) : (r * std::log(r) - 1.0) / (a * std::log(a) - 1.0);
     }
+    case H2S_K_NTI_MQ: { // d == 3 (checked at build)
+        const double dc = std::exp(-(x[0] + x[2])) - std::exp(-(y[0] + y[2]));
+        const double t = r2 + dc * dc + 1.0;
+        return t * std::sqrt(t);
+    }
     default: return std::exp(-std::sqrt(r2));
     }
 }

@@ -293,7 +293,8 @@ __global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t)
         if constexpr (FAR) return t.far;
         else return t.ver;
     }();
-    __shared__ double sx[M2LS_SRC], sy[M2LS_SRC], sz[D == 3 ? M2LS_SRC : 1], sv[M2LS_SRC];
+    constexpr bool XW = kExtraCoord<KIND>;
+    __shared__ double sx[M2LS_SRC], sy[M2LS_SRC], sz[D == 3 ? M2LS_SRC : 1], sv[M2LS_SRC], sw[XW ? M2LS_SRC : 1];
     __shared__ double red[2 * NT_M2LS];
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
     const int tid = threadIdx.x;
@@ -308,6 +309,7 @@ __global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t)
         const int ia = a0 + pa, ib = pa + NP < MT ? ia + NP : ia; // a lone last target is paired with itself
         const double xa = F.pvx[c0 + ia], ya = F.pvy[c0 + ia], za = D == 3 ? (double)F.pvz[c0 + ia] : 0.0;
         const double xb = F.pvx[c0 + ib], yb = F.pvy[c0 + ib], zb = D == 3 ? (double)F.pvz[c0 + ib] : 0.0;
+        const double wa = XW ? (double)F.pvw[c0 + ia] : 0.0, wb = XW ? (double)F.pvw[c0 + ib] : 0.0;
         double acc_a = 0.0, acc_b = 0.0;
         int pos = 0;
         auto flush = [&]() {
@@ -319,15 +321,23 @@ __global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t)
                     const int j1 = j + NS;
                     const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, v0 = sv[j];
                     const double x1 = sx[j1], y1 = sy[j1], z1 = D == 3 ? sz[j1] : 0.0, v1 = sv[j1];
-                    a0s = fma(kval_pos<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), kp, ktab), v0, a0s);
-                    b0s = fma(kval_pos<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), kp, ktab), v0, b0s);
-                    a1s = fma(kval_pos<KIND>(dist2<false, D>(xa - x1, ya - y1, za - z1), kp, ktab), v1, a1s);
-                    b1s = fma(kval_pos<KIND>(dist2<false, D>(xb - x1, yb - y1, zb - z1), kp, ktab), v1, b1s);
+                    const double w0 = XW ? sw[j] : 0.0, w1 = XW ? sw[j1] : 0.0;
+                    a0s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), wa, w0), kp, ktab),
+                              v0, a0s);
+                    b0s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), wb, w0), kp, ktab),
+                              v0, b0s);
+                    a1s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - x1, ya - y1, za - z1), wa, w1), kp, ktab),
+                              v1, a1s);
+                    b1s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xb - x1, yb - y1, zb - z1), wb, w1), kp, ktab),
+                              v1, b1s);
                 }
                 if (j < pos) {
                     const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, v0 = sv[j];
-                    a0s = fma(kval_pos<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), kp, ktab), v0, a0s);
-                    b0s = fma(kval_pos<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), kp, ktab), v0, b0s);
+                    const double w0 = XW ? sw[j] : 0.0;
+                    a0s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), wa, w0), kp, ktab),
+                              v0, a0s);
+                    b0s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), wb, w0), kp, ktab),
+                              v0, b0s);
                 }
                 acc_a += a0s + a1s;
                 acc_b += b0s + b1s;
@@ -344,6 +354,7 @@ __global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t)
                     sx[pos + j] = F.pvx[cy + j0 + j];
                     sy[pos + j] = F.pvy[cy + j0 + j];
                     if constexpr (D == 3) sz[pos + j] = F.pvz[cy + j0 + j];
+                    if constexpr (XW) sw[pos + j] = F.pvw[cy + j0 + j];
                     sv[pos + j] = F.v[cy + j0 + j];
                 }
                 pos += take;
@@ -427,12 +438,14 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
     using PT = typename P::pt_t;
     constexpr bool TAB = sizeof(PT) == 8;
     constexpr int TPT = P2P_TPT;
-    // staged sources (x, y, q[, z]); after the last group the same memory holds the slice partials
-    constexpr size_t SRC_BYTES = (size_t)(D == 3 ? 4 : 3) * P2P_SRC * sizeof(PT);
+    constexpr bool XW = kExtraCoord<KIND>;
+    // staged sources (x, y, q[, z][, w]); after the last group the same memory holds the slice partials
+    constexpr size_t SRC_BYTES = (size_t)(3 + (D == 3) + XW) * P2P_SRC * sizeof(PT);
     constexpr size_t RED_BYTES = (size_t)TPT * NT_P2P * sizeof(double);
     __shared__ __align__(16) unsigned char sbuf[SRC_BYTES > RED_BYTES ? SRC_BYTES : RED_BYTES];
     PT *const sx = reinterpret_cast<PT *>(sbuf), *const sy = sx + P2P_SRC, *const sq = sy + P2P_SRC;
-    PT *const sz = sq + P2P_SRC; // used in 3D only
+    PT *const sz = sq + P2P_SRC;                      // used in 3D only
+    PT *const sw = sz + (D == 3 ? P2P_SRC : 0);       // used by kernels of an extra coordinate only
     double *const red = reinterpret_cast<double *>(sbuf);
     __shared__ __align__(16) double ktab[TAB ? kTabLen<KIND> : 2];
     const int tid = threadIdx.x;
@@ -451,7 +464,7 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
             const int MT = min(n - i0, TPT * NT_P2P), NP = (MT + TPT - 1) / TPT, NS = NT_P2P / NP;
             const int s = tid / NP, pa = tid % NP;
             int it[TPT];
-            PT tx[TPT], ty[TPT], tz[TPT];
+            PT tx[TPT], ty[TPT], tz[TPT], tw[TPT];
             double acc[TPT];
 #pragma unroll
             for (int k = 0; k < TPT; ++k) {
@@ -459,6 +472,7 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
                 tx[k] = t.px[b + it[k]];
                 ty[k] = t.py[b + it[k]];
                 tz[k] = D == 3 ? t.pz[b + it[k]] : PT(0);
+                tw[k] = XW ? t.pw[b + it[k]] : PT(0);
                 acc[k] = 0.0;
             }
             int pos = 0, self0 = 0, self1 = 0; // staged positions of the target leaf's own points
@@ -476,9 +490,11 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
                 if constexpr (sizeof(PT) == 8) {
                     for (int j = jb + s; j < je; j += NS) {
                         const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
+                        const PT w0 = XW ? sw[j] : PT(0);
 #pragma unroll
                         for (int k = 0; k < TPT; ++k)
-                            acc[k] = fma(kv(dist2<false, D>(tx[k] - x0, ty[k] - y0, tz[k] - z0)), q0, acc[k]);
+                            acc[k] = fma(kv(add_extra<KIND>(dist2<false, D>(tx[k] - x0, ty[k] - y0, tz[k] - z0), tw[k], w0)),
+                                         q0, acc[k]);
                     }
                 } else {
                     // float partial sums per slice, accumulated in double
@@ -487,8 +503,10 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
                     for (int k = 0; k < TPT; ++k) a[k] = PT(0);
                     for (int j = jb + s; j < je; j += NS) {
                         const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
+                        const PT w0 = XW ? sw[j] : PT(0);
 #pragma unroll
-                        for (int k = 0; k < TPT; ++k) a[k] += kv(dist2<false, D>(tx[k] - x0, ty[k] - y0, tz[k] - z0)) * q0;
+                        for (int k = 0; k < TPT; ++k)
+                            a[k] += kv(add_extra<KIND>(dist2<false, D>(tx[k] - x0, ty[k] - y0, tz[k] - z0), tw[k], w0)) * q0;
                     }
 #pragma unroll
                     for (int k = 0; k < TPT; ++k) acc[k] += (double)a[k];
@@ -528,6 +546,7 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
                             if constexpr (D == 3) sz[pos + j] = t.pz[src];
                         }
                         sq[pos + j] = (PT)t.qt[src];
+                        if constexpr (XW) sw[pos + j] = t.pw[src];
                     }
                     if (gs == g) {
                         self0 = pos;
@@ -717,7 +736,11 @@ int launch_mvp(const DevTree<P> &t, const LaunchPlan &plan, const double *x, dou
     case 8: return (int)enqueue<P, H2S_K_RBF_AR, 2>(t, plan, x, y, mask, s, prof);
     case 9: return (int)enqueue<P, H2S_K_RBF_AR, 3>(t, plan, x, y, mask, s, prof);
     case 10: return (int)enqueue<P, H2S_K_RBF_LOG, 2>(t, plan, x, y, mask, s, prof);
-    default: return (int)enqueue<P, H2S_K_RBF_LOG, 3>(t, plan, x, y, mask, s, prof);
+    case 11: return (int)enqueue<P, H2S_K_RBF_LOG, 3>(t, plan, x, y, mask, s, prof);
+    case 13: // the NTI multiquadric: 3D, not with the float far field of FP32_M2L
+        if constexpr (std::is_same_v<P, P32M>) return (int)hipErrorInvalidValue;
+        else return (int)enqueue<P, H2S_K_NTI_MQ, 3>(t, plan, x, y, mask, s, prof);
+    default: return (int)hipErrorInvalidValue;
     }
 }
 

@@ -142,7 +142,8 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
         else return t.ver;
     }();
     constexpr int TPT = BM_TPT;
-    __shared__ double sx[BM_SRC], sy[BM_SRC], sz[D == 3 ? BM_SRC : 1];
+    constexpr bool XW = kExtraCoord<KIND>;
+    __shared__ double sx[BM_SRC], sy[BM_SRC], sz[D == 3 ? BM_SRC : 1], sw[XW ? BM_SRC : 1];
     __shared__ double sv[BM_SRC * NB]; // after the last group: the slice partials of one column
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
     static_assert(BM_SRC * NB >= TPT * NT_BM, "slice partials fit in the multipole buffer");
@@ -156,7 +157,7 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
         const int MT = min(r - a0, TPT * NT_BM), NP = (MT + TPT - 1) / TPT, NS = NT_BM / NP;
         const int s = tid / NP, pa = tid % NP;
         int it[TPT];
-        double tx[TPT], ty[TPT], tz[TPT];
+        double tx[TPT], ty[TPT], tz[TPT], tw[TPT];
         double acc[TPT][NB];
 #pragma unroll
         for (int k = 0; k < TPT; ++k) {
@@ -164,6 +165,7 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
             tx[k] = F.pvx[c0 + it[k]];
             ty[k] = F.pvy[c0 + it[k]];
             tz[k] = D == 3 ? (double)F.pvz[c0 + it[k]] : 0.0;
+            tw[k] = XW ? (double)F.pvw[c0 + it[k]] : 0.0;
 #pragma unroll
             for (int c = 0; c < NB; ++c) acc[k][c] = 0.0;
         }
@@ -172,11 +174,12 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
             __syncthreads();
             if (s < NS) {
                 for (int j = s; j < pos; j += NS) {
-                    const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0;
+                    const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, w0 = XW ? sw[j] : 0.0;
                     double kv[TPT];
 #pragma unroll
                     for (int k = 0; k < TPT; ++k)
-                        kv[k] = kval_pos<KIND>(dist2<false, D>(tx[k] - x0, ty[k] - y0, tz[k] - z0), kp, ktab);
+                        kv[k] = kval_pos<KIND>(
+                            add_extra<KIND>(dist2<false, D>(tx[k] - x0, ty[k] - y0, tz[k] - z0), tw[k], w0), kp, ktab);
 #pragma unroll
                     for (int c = 0; c < NB; ++c) {
                         const double v = sv[j * NB + c];
@@ -197,6 +200,7 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
                     sx[pos + j] = F.pvx[cy + j0 + j];
                     sy[pos + j] = F.pvy[cy + j0 + j];
                     if constexpr (D == 3) sz[pos + j] = F.pvz[cy + j0 + j];
+                    if constexpr (XW) sw[pos + j] = F.pvw[cy + j0 + j];
                 }
                 for (int e2 = tid; e2 < take * NB; e2 += NT_BM) sv[pos * NB + e2] = F.vb[(size_t)(cy + j0) * NB + e2];
                 pos += take;
@@ -234,7 +238,8 @@ __global__ __launch_bounds__(NT_BP) void kb_p2p(DevTree<P> t, int32_t leaf_begin
 {
     using PT = typename P::pt_t;
     constexpr bool TAB = sizeof(PT) == 8;
-    __shared__ PT sx[BP_SRC], sy[BP_SRC], sz[D == 3 ? BP_SRC : 1];
+    constexpr bool XW = kExtraCoord<KIND>;
+    __shared__ PT sx[BP_SRC], sy[BP_SRC], sz[D == 3 ? BP_SRC : 1], sw[XW ? BP_SRC : 1];
     __shared__ PT sq[BP_SRC * NB];
     __shared__ double red[NT_BP];
     __shared__ __align__(16) double ktab[TAB ? kTabLen<KIND> : 2];
@@ -248,6 +253,7 @@ __global__ __launch_bounds__(NT_BP) void kb_p2p(DevTree<P> t, int32_t leaf_begin
     for (int i0 = 0; i0 < n; i0 += NT_BP) {
         const int m = min(n - i0, NT_BP), S = NT_BP / m, s = tid / m, i = i0 + tid % m;
         const PT xi = t.px[b + i], yi = t.py[b + i], zi = D == 3 ? t.pz[b + i] : PT(0);
+        const PT wi = XW ? t.pw[b + i] : PT(0);
         double acc[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) acc[c] = 0.0;
@@ -258,7 +264,8 @@ __global__ __launch_bounds__(NT_BP) void kb_p2p(DevTree<P> t, int32_t leaf_begin
 #pragma unroll
             for (int c = 0; c < NB; ++c) part[c] = 0;
             for (int j = jb + s; j < je; j += S) {
-                const PT r2 = dist2<false, D>(xi - sx[j], yi - sy[j], zi - sz[D == 3 ? j : 0]);
+                const PT r2 = add_extra<KIND>(dist2<false, D>(xi - sx[j], yi - sy[j], zi - sz[D == 3 ? j : 0]), wi,
+                                              XW ? sw[j] : PT(0));
                 PT k;
                 if constexpr (sizeof(PT) == 8) k = CHECK ? kval<KIND>(r2, diag, kp, ktab) : kval_pos<KIND>(r2, kp, ktab);
                 else k = kval<KIND>(r2, diag, kp);
@@ -300,6 +307,7 @@ __global__ __launch_bounds__(NT_BP) void kb_p2p(DevTree<P> t, int32_t leaf_begin
                         sy[pos + j] = t.py[src];
                         if constexpr (D == 3) sz[pos + j] = t.pz[src];
                     }
+                    if constexpr (XW) sw[pos + j] = t.pw[src];
                 }
                 for (int e2 = tid; e2 < take * NB; e2 += NT_BP)
                     sq[pos * NB + e2] = (PT)t.qb[(size_t)(sb + j0) * NB + e2];
@@ -430,7 +438,9 @@ int launch_mvp_batch(const DevTree<P> &t, const LaunchPlan &plan, const double *
     case 8: return (int)enqueue_b<P, H2S_K_RBF_AR, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
     case 9: return (int)enqueue_b<P, H2S_K_RBF_AR, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
     case 10: return (int)enqueue_b<P, H2S_K_RBF_LOG, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
-    default: return (int)enqueue_b<P, H2S_K_RBF_LOG, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 11: return (int)enqueue_b<P, H2S_K_RBF_LOG, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
+    case 13: return (int)enqueue_b<P, H2S_K_NTI_MQ, 3>(t, plan, x, ldx, y, ldy, na, mask, s); // 3D only
+    default: return (int)hipErrorInvalidValue;
     }
 }
 

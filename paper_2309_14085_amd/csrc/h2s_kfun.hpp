@@ -115,6 +115,21 @@ template <int KIND> __device__ __forceinline__ void stage_table(const double *g,
         for (int i = threadIdx.x; i < kTabLen<KIND>; i += blockDim.x) tab[i] = g[i];
 }
 
+// Kernels of an extra per-point coordinate w besides the position: the NTI
+// multiquadric stages w = c(x) = exp(-(x_1 + x_3)) with the coordinates and
+// adds (w_x - w_y)^2 to r^2.
+template <int KIND> constexpr bool kExtraCoord = KIND == H2S_K_NTI_MQ;
+
+template <int KIND, typename T> __device__ __forceinline__ T add_extra(T r2, T wa, T wb)
+{
+    if constexpr (kExtraCoord<KIND>) {
+        const T dw = wa - wb;
+        return r2 + dw * dw;
+    } else {
+        return r2;
+    }
+}
+
 // Scalar parameters of the kernel function (uniform over the grid, so they
 // live in scalar registers): kp = -1/h^2 for the Gaussian; for the piecewise
 // RBFs of radius a, c0 = a^2 and the branch factors c1, c2 (a, 1/a for
@@ -147,9 +162,12 @@ template <int KIND> __device__ __forceinline__ double kval_pos(double r2, const 
     else if constexpr (KIND == H2S_K_RBF_AR) {
         const double rs = inv_sqrt(r2); // 1/r
         return r2 >= kp.c0 ? kp.c1 * rs : (r2 * rs) * kp.c2;
-    } else { // H2S_K_RBF_LOG
+    } else if constexpr (KIND == H2S_K_RBF_LOG) {
         const double lr = half_log(r2, (const double2 *)tab); // log r
         return r2 >= kp.c0 ? lr * kp.c1 : fma(sqrt(r2), lr, -1.0) * kp.c2;
+    } else { // H2S_K_NTI_MQ: r2 already holds |x - y|^2 + (c(x) - c(y))^2
+        const double t = r2 + 1.0;
+        return t * sqrt(t);
     }
 }
 
@@ -171,9 +189,12 @@ template <int KIND> __device__ __forceinline__ float kval(float r2, float diag, 
     else if constexpr (KIND == H2S_K_RBF_AR) {
         const float rs = __frsqrt_rn(r2);
         v = r2 >= kp.c0 ? kp.c1 * rs : (r2 * rs) * kp.c2;
-    } else {
+    } else if constexpr (KIND == H2S_K_RBF_LOG) {
         const float lr = __log2f(r2) * 0.34657359027997264f;
         v = r2 >= kp.c0 ? lr * kp.c1 : fmaf(__fsqrt_rn(r2), lr, -1.0f) * kp.c2;
+    } else {
+        const float t = r2 + 1.0f;
+        v = t * __fsqrt_rn(t);
     }
     return r2 == 0.0f ? diag : v;
 }

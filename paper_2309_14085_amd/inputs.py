@@ -13,7 +13,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-LOG_R, INV_R, GAUSS, EXP_R, RBF_AR, RBF_LOG = 0, 1, 2, 3, 4, 5
+LOG_R, INV_R, GAUSS, EXP_R, RBF_AR, RBF_LOG, NTI_MQ = 0, 1, 2, 3, 4, 5, 6
 
 
 def uniform_points(n: int, d: int, seed: int) -> np.ndarray:

@@ -49,6 +49,8 @@ def test_validation_before_allocation(lib):
         (pts, 100, 2, lib.Kernel(lib.RBF_AR, float("nan"), 0.0, 0.0), o),
         (pts, 100, 2, lib.Kernel(lib.RBF_LOG, -0.1, 0.0, 0.0), o),
         (pts, 100, 2, lib.Kernel(lib.RBF_LOG, 1.0, 0.0, 0.0), o),
+        (pts, 100, 2, lib.Kernel(lib.NTI_MQ, 0.0, 1.0, 0.0), o),  # 3D only
+        (pts, 100, 2, lib.Kernel(7, 0.0, 1.0, 0.0), o),
         (pts, 100, 2, k, lib.BuildOpts(0, 1e-8, 1e-8, 0, 0, 0, 1)),
         (pts, 100, 2, k, lib.BuildOpts(64, -1.0, 1e-8, 0, 0, 0, 1)),
         (pts, 100, 2, k, lib.BuildOpts(64, float("nan"), 1e-8, 0, 0, 0, 1)),
@@ -103,6 +105,8 @@ CASES = [
     (3, 3000, 3, 20, 1e-12, 1, 0.0, 9),
     (2, 4000, 4, 64, 1e-10, 0, 0.05, 10),
     (3, 3000, 5, 32, 1e-8, 1, 0.1, 11),
+    (3, 3000, 6, 32, 1e-8, 0, 0.0, 12),
+    (3, 3000, 6, 64, 1e-6, 1, 0.0, 13),
 ]
 
 
@@ -183,3 +187,11 @@ def test_schedule_defaults_and_validation(lib, inputs):
     # tuning needs a device handle
     st = lib.load().h2s_tune(T.handle, ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), 1, None, None)
     assert st == lib.ERR_UNSUPPORTED
+
+
+def test_nti_multiquadric_rejects_fp32_m2l(lib, inputs):
+    """The float far field of H2S_FP32_M2L is not built for the NTI multiquadric."""
+    pts = inputs.uniform_points(500, 3, 2)
+    k = lib.Kernel(lib.NTI_MQ, 0.0, 1.0, 0.0)
+    assert _raw_build(lib, pts, 500, 3, k, lib.BuildOpts(64, 1e-6, 1e-6, 0, lib.FP32_M2L, 0, 1))[0] == lib.ERR_UNSUPPORTED
+    assert _raw_build(lib, pts, 500, 3, k, lib.BuildOpts(64, 1e-6, 1e-6, 0, lib.FP32, 0, 1))[0] == lib.OK

@@ -55,6 +55,7 @@ CASES = [
     ("2d_gauss_4000", 2, 4000, 2, 32, 1e-10, 0.2, 1e-2, 63),
     ("3d_expr_3000", 3, 3000, 3, 32, 1e-10, 0.0, 0.0, 64),
     ("3d_rbf_log_3000", 3, 3000, 5, 32, 1e-8, 0.1, 54.77, 65),
+    ("3d_nti_mq_3000", 3, 3000, 6, 32, 1e-8, 0.0, 54.77, 66),
 ]
 
 

@@ -47,6 +47,8 @@ CASES = [
     # piecewise RBFs with radii that put both branches in the near field and the vertex blocks
     ("2d_rbf_ar_4000", 2, 4000, 4, 64, 1e-10, 0.05, 0.0, 7),
     ("3d_rbf_log_3000", 3, 3000, 5, 32, 1e-8, 0.1, 54.77, 8),
+    # the NTI multiquadric: c(x) = exp(-(x_1 + x_3)) staged with the coordinates
+    ("3d_nti_mq_3000", 3, 3000, 6, 32, 1e-10, 0.0, 54.77, 9),
 ]
 
 
@@ -103,7 +105,8 @@ def test_multi_rhs_with_leading_dimension(lib, orc, inputs):
         assert np.all(y[c * ld + n:(c + 1) * ld] == 7.0)  # padding untouched
 
 
-@pytest.mark.parametrize("d,kind,eps", [(2, 0, 1e-8), (3, 1, 1e-6), (2, 2, 1e-8), (2, 4, 1e-8), (3, 5, 1e-6)])
+@pytest.mark.parametrize("d,kind,eps", [(2, 0, 1e-8), (3, 1, 1e-6), (2, 2, 1e-8), (2, 4, 1e-8), (3, 5, 1e-6),
+                                         (3, 6, 1e-6)])
 @pytest.mark.parametrize("variant", [0, 1])
 def test_fp32_within_1e5_of_fp64_oracle(lib, orc, inputs, d, kind, eps, variant):
     n = 8192 if d == 2 else 6000

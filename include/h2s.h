@@ -238,12 +238,14 @@ typedef struct {
     int32_t up_threads[33];  /* block width of P2M (level kappa) and M2M (levels 1..kappa-1):
                                 a multiple of 64 in [64, 512]; default: outputs of the widest box */
     int32_t dn_threads[33];  /* block width of L2L (levels 1..kappa-1), same rule */
+    int32_t m2l_stream;      /* 1: the leaf-level M2L runs on a third stream from the end of P2M, beside
+                                the coarse M2M levels; 0: all M2L after M2M.  Default 1 */
 } h2s_schedule;
 
 /* Read or replace the handle's schedule (valid on host_only handles too).
  * h2s_set_schedule rejects, with H2S_ERR_INVALID_ARG and no change, a
- * near_first outside [0, 1] or a width that is not a multiple of 64 in
- * [64, 512] at any level 1..kappa.  It must not be called while another
+ * near_first outside [0, 1], an m2l_stream other than 0 or 1, or a width
+ * that is not a multiple of 64 in [64, 512] at any level 1..kappa.  It must not be called while another
  * call uses the handle. */
 h2s_status h2s_get_schedule(h2s_tree t, h2s_schedule *s);
 h2s_status h2s_set_schedule(h2s_tree t, const h2s_schedule *s);
@@ -251,7 +253,8 @@ h2s_status h2s_set_schedule(h2s_tree t, const h2s_schedule *s);
 /* Autotuner of the schedule.  Times the product y = K~ x (device vectors of
  * length n in user order, not overlapping) on stream under candidate
  * schedules: the near-field share, then the block width of every level of
- * P2M, M2M and L2L, each chosen in turn with the others fixed; each
+ * P2M, M2M and L2L, and whether the leaf-level M2L gets its own stream, each chosen in turn with the
+ * others fixed; each
  * candidate is timed twice over reps products (reps < 1 means 5) with HIP
  * events, and the faster time counts.  A candidate replaces the current
  * choice only when it is faster by more than 0.5%.  The fastest schedule is

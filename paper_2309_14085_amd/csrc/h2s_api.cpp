@@ -69,6 +69,9 @@ struct h2s_tree_s {
     // second stream for the near field and the events that fork / join it
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_fork2 = nullptr, ev_join = nullptr;
+    // third stream for the leaf-level M2L and its fork / join events
+    hipStream_t aux2 = nullptr;
+    hipEvent_t ev_fork3 = nullptr, ev_join2 = nullptr;
     // which precisions are on the device
     bool up[3] = {false, false, false};
     // multi-RHS block buffers allocated for these precisions
@@ -96,6 +99,12 @@ struct h2s_tree_s {
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_fork2) (void)hipEventDestroy(ev_fork2);
         if (ev_join) (void)hipEventDestroy(ev_join);
+        if (aux2) {
+            (void)hipStreamSynchronize(aux2);
+            (void)hipStreamDestroy(aux2);
+        }
+        if (ev_fork3) (void)hipEventDestroy(ev_fork3);
+        if (ev_join2) (void)hipEventDestroy(ev_join2);
         if (work.small_host) (void)hipHostFree(work.small_host);
         for (void *p : allocs) ffn(actx, p);
     }
@@ -241,6 +250,7 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     for (int32_t g = 0; g < nbox; ++g)
         if (F.rank[g] > 0) targets.push_back(g);
     G.ntargets = (int32_t)targets.size();
+    G.targets_leaf = (int32_t)(std::lower_bound(targets.begin(), targets.end(), leaf0) - targets.begin());
     G.targets = up.copy(targets);
     G.v = up.template zeros<double>(nc ? nc : 1);
     G.u = up.template zeros<double>(nc ? nc : 1);
@@ -457,27 +467,36 @@ h2s_status ensure_uploaded(h2s_tree t, h2s_precision p, hipStream_t s)
     return st;
 }
 
-// The near-field stream and its fork / join events, created on first use on
-// the handle's device at the default priority.
+// The near-field and leaf-level M2L streams and their fork / join events,
+// created on first use on the handle's device at the default priority.
 h2s_status ensure_streams(h2s_tree t)
 {
     if (t->aux) return H2S_OK;
-    hipStream_t a = nullptr;
-    hipEvent_t f = nullptr, f2 = nullptr, j = nullptr;
-    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&f2, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+    hipStream_t a = nullptr, a2 = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool ok = hipStreamCreateWithFlags(&a, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&a2, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; ok && i < 5; ++i) ok = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
         if (a) (void)hipStreamDestroy(a);
-        if (f) (void)hipEventDestroy(f);
-        if (f2) (void)hipEventDestroy(f2);
-        return fail(H2S_ERR_DEVICE, "creating the near-field stream or its events failed");
+        if (a2) (void)hipStreamDestroy(a2);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        return fail(H2S_ERR_DEVICE, "creating the near-field / M2L streams or their events failed");
     }
     t->aux = a;
-    t->ev_fork = f;
-    t->ev_fork2 = f2;
-    t->ev_join = j;
+    t->aux2 = a2;
+    t->ev_fork = ev[0];
+    t->ev_fork2 = ev[1];
+    t->ev_join = ev[2];
+    t->ev_fork3 = ev[3];
+    t->ev_join2 = ev[4];
     return H2S_OK;
+}
+
+h2s::Streams streams_of(h2s_tree t, void *stream)
+{
+    return h2s::Streams{stream, t->aux, t->ev_fork, t->ev_fork2, t->ev_join, t->aux2, t->ev_fork3, t->ev_join2};
 }
 
 // The default schedule: blocks as wide as the outputs of the widest box of
@@ -491,6 +510,7 @@ void default_plan(h2s_tree t)
     t->plan = h2s::LaunchPlan{};
     t->plan.lev_off = t->lev_off.data();
     t->plan.near_first = h2s::kNearFirstDefault;
+    t->plan.m2l_stream = 1;
     for (int l = 0; l <= h2s::kMaxLevels; ++l) t->plan.up_threads[l] = t->plan.dn_threads[l] = 64;
     for (int l = 0; l <= kappa; ++l) {
         int32_t cols = 0, rows = 0;
@@ -507,7 +527,7 @@ void default_plan(h2s_tree t)
 int mvp_plan(h2s_tree t, const h2s::LaunchPlan &plan, h2s_precision p, uint32_t mask, const double *x, double *y,
              void *stream, const h2s::ProfileHook *prof)
 {
-    const h2s::Streams st{stream, t->aux, t->ev_fork, t->ev_fork2, t->ev_join};
+    const h2s::Streams st = streams_of(t, stream);
     if (p == H2S_FP64) return h2s::launch_mvp<h2s::P64>(t->t64, plan, x, y, mask, st, prof);
     if (p == H2S_FP32) return h2s::launch_mvp<h2s::P32>(t->t32, plan, x, y, mask, st, prof);
     return h2s::launch_mvp<h2s::P32M>(t->t32m, plan, x, y, mask, st, prof);
@@ -577,6 +597,11 @@ h2s_status tune_plan(h2s_tree t, const double *x, double *y, int reps, hipStream
         return H2S_OK;
     };
     if (kappa >= 1) {
+        {
+            h2s::LaunchPlan c = best;
+            c.m2l_stream = 1 - best.m2l_stream;
+            if ((st = consider(c)) != H2S_OK) return st;
+        }
         if ((st = tune_share()) != H2S_OK) return st;
         // P2M (level kappa) and M2M (levels kappa-1 .. 1), then L2L (levels 1 .. kappa-1)
         for (int pass = 0; pass < 2; ++pass) {
@@ -631,7 +656,7 @@ template <class P>
 h2s_status apply_columns(h2s_tree t, h2s::DevTree<P> &D, int p, uint32_t mask, const double *x, double *y,
                          int32_t nrhs, int64_t ldx, int64_t ldy, void *stream, const h2s::ProfileHook *prof)
 {
-    const h2s::Streams st{stream, t->aux, t->ev_fork, t->ev_fork2, t->ev_join};
+    const h2s::Streams st = streams_of(t, stream);
     int32_t c = 0;
     if constexpr (sizeof(typename P::far_t) == 8) { // the batched kernels exist for a double far field only
         if (nrhs > 1 && !prof && batch_supported(t, D)) {
@@ -886,6 +911,7 @@ h2s_status h2s_get_schedule(h2s_tree t, h2s_schedule *sc)
     if (!t || !sc) return fail(H2S_ERR_INVALID_ARG, "tree or schedule is NULL");
     *sc = h2s_schedule{};
     sc->near_first = t->plan.near_first;
+    sc->m2l_stream = t->plan.m2l_stream;
     for (int l = 0; l <= h2s::kMaxLevels; ++l) {
         sc->up_threads[l] = t->plan.up_threads[l];
         sc->dn_threads[l] = t->plan.dn_threads[l];
@@ -898,6 +924,7 @@ h2s_status h2s_set_schedule(h2s_tree t, const h2s_schedule *sc)
     if (!t || !sc) return fail(H2S_ERR_INVALID_ARG, "tree or schedule is NULL");
     if (!(sc->near_first >= 0.0 && sc->near_first <= 1.0))
         return fail(H2S_ERR_INVALID_ARG, "near_first must be in [0, 1]");
+    if (sc->m2l_stream != 0 && sc->m2l_stream != 1) return fail(H2S_ERR_INVALID_ARG, "m2l_stream must be 0 or 1");
     const int kappa = std::min(t->rep.kappa, h2s::kMaxLevels);
     auto ok = [](int32_t w) { return w >= 64 && w <= 512 && w % 64 == 0; };
     for (int l = 1; l <= kappa; ++l)
@@ -905,6 +932,7 @@ h2s_status h2s_set_schedule(h2s_tree t, const h2s_schedule *sc)
             return fail(H2S_ERR_INVALID_ARG, "level " + std::to_string(l) +
                                                  ": block widths must be multiples of 64 in [64, 512]");
     t->plan.near_first = sc->near_first;
+    t->plan.m2l_stream = sc->m2l_stream;
     for (int l = 1; l <= kappa; ++l) {
         t->plan.up_threads[l] = sc->up_threads[l];
         if (l < kappa) t->plan.dn_threads[l] = sc->dn_threads[l];

@@ -66,8 +66,9 @@ template <typename CT, typename BT> struct DevFamily {
     const int64_t *troff;        // per global box
     const int32_t *il_off;       // nbox + 1
     const int32_t *il_idx;
-    const int32_t *targets;      // boxes with rank > 0 at levels >= lmin
+    const int32_t *targets;      // boxes with rank > 0 at levels >= lmin, in box (so level) order
     int32_t ntargets;
+    int32_t targets_leaf;        // index in targets of the first leaf-level box
     double *v, *u;
     double *vb, *ub;             // multi-RHS blocks: kBatch entries per coefficient (allocated on first use)
 };
@@ -121,6 +122,7 @@ struct LaunchPlan {
     int32_t up_threads[kMaxLevels + 1];  // block size of P2M (level kappa) and M2M (levels < kappa)
     int32_t dn_threads[kMaxLevels + 1];  // block size of L2L per level
     double near_first;                   // share of the leaves whose near field runs beside P2M and M2M
+    int32_t m2l_stream;                  // 1: leaf-level M2L on a third stream right after P2M
 };
 
 constexpr double kNearFirstDefault = 0.6;
@@ -134,8 +136,10 @@ struct ProfileHook {
 // The caller's stream, the handle's second stream (near field) and the
 // events that fork the second stream from the first (twice per product) and
 // join it back.
+// The caller's stream, the near-field stream (forked at fork / fork2, joined
+// at join) and the leaf-level M2L stream (forked at fork3, joined at join2).
 struct Streams {
-    void *main, *aux, *fork, *fork2, *join;
+    void *main, *aux, *fork, *fork2, *join, *aux2, *fork3, *join2;
 };
 
 // Right-hand sides per block of the batched product.

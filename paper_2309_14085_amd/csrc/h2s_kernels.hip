@@ -144,7 +144,7 @@ constexpr int M2L_OWN = 4;     // targets per thread: rank <= NT_M2L * M2L_OWN
 // difference of the two box centres: the first term is taken in double once
 // per source box, the second in float.
 template <class P, bool FAR, int KIND, int D>
-__global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
+__global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t, int32_t t0)
 {
     constexpr bool LOWP = FAR && sizeof(typename P::far_t) == 4;
     using CT = std::conditional_t<LOWP, float, double>;
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t)
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
     const int tid = threadIdx.x;
     if constexpr (!LOWP) stage_table<KIND>(t.ktab, ktab);
-    const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
+    const int g = F.targets[t0 + xcd_remap(blockIdx.x, gridDim.x)]; // targets t0 .. t0 + gridDim.x - 1
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
     const CT diag = (CT)t.diag;
@@ -287,7 +287,7 @@ constexpr int NT_M2LS = 256;
 constexpr int M2LS_SRC = 512; // staged source pivots per group
 
 template <class P, bool FAR, int KIND, int D>
-__global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t)
+__global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t, int32_t t0)
 {
     const auto &F = [&]() -> const auto & {
         if constexpr (FAR) return t.far;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t)
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
     const int tid = threadIdx.x;
     stage_table<KIND>(t.ktab, ktab); // first used after a barrier
-    const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
+    const int g = F.targets[t0 + xcd_remap(blockIdx.x, gridDim.x)]; // targets t0 .. t0 + gridDim.x - 1
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
     const KPar<double> kp = kpar<double>(t);
@@ -652,9 +652,13 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
     // stream in two pieces: the first near_first of the leaves beside P2M and
     // M2M (HBM- and latency-bound), the rest beside L2L, so that it shares
     // the GPU with the memory-bound sweeps rather than with the ALU-bound
-    // M2L.  Under the profiling hook it runs on the main stream instead, so
-    // that every kernel class is timed alone.
+    // M2L.  The leaf-level M2L needs only the leaf multipoles: with
+    // plan.m2l_stream it runs on a third stream from the end of P2M, beside
+    // the coarse M2M levels (latency-bound, few boxes), and only the L2L into
+    // the leaves waits for it.  Under the profiling hook everything runs on
+    // the main stream instead, so that every kernel class is timed alone.
     const bool overlap = (mask & kNear) && !prof;
+    const bool split = fam_on && !prof && plan.m2l_stream != 0;
     const int near1 = overlap && fam_on ? (int)(plan.near_first * t.nleaf) : t.nleaf;
     auto fork_near = [&](hipEvent_t ev, int lb, int le) -> hipError_t {
         hipError_t e2;
@@ -663,6 +667,21 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
         if (le > lb) hipLaunchKernelGGL((k_p2p<P, KIND, D>), dim3(le - lb), dim3(NT_P2P), 0, aux, t, lb, le - lb);
         return hipEventRecord((hipEvent_t)st.join, aux);
     };
+    // M2L of one family over its targets [tb, te) on stream `on`
+    auto m2l = [&](bool far, int32_t tb, int32_t te, hipStream_t on) {
+        if (te <= tb) return;
+        if (far) {
+            if constexpr (sizeof(typename P::far_t) == 4)
+                hipLaunchKernelGGL((k_m2l<P, true, KIND, D>), dim3(te - tb), dim3(NT_M2L), 0, on, t, tb);
+            else
+                hipLaunchKernelGGL((k_m2l_slices<P, true, KIND, D>), dim3(te - tb), dim3(NT_M2LS), 0, on, t, tb);
+        } else {
+            hipLaunchKernelGGL((k_m2l_slices<P, false, KIND, D>), dim3(te - tb), dim3(NT_M2LS), 0, on, t, tb);
+        }
+    };
+    const bool far_on = (mask & kFar) != 0, ver_on = (mask & kVer) != 0;
+    const int32_t far_split = split ? t.far.targets_leaf : t.far.ntargets;
+    const int32_t ver_split = split ? t.ver.targets_leaf : t.ver.ntargets;
     if (overlap && (err = fork_near((hipEvent_t)st.fork, 0, near1)) != hipSuccess) return err;
     if (fam_on) hipLaunchKernelGGL(k_up_leaf<P>, dim3(t.nleaf), dim3(plan.up_threads[t.kappa]), lds_leaf, s, t, mask);
     mark(H2S_PROF_LEAF_UP, 1, s);
@@ -670,6 +689,14 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
         mark(H2S_PROF_NEAR, 0, s);
         hipLaunchKernelGGL((k_p2p<P, KIND, D>), dim3(t.nleaf), dim3(NT_P2P), 0, s, t, 0, t.nleaf);
         mark(H2S_PROF_NEAR, 1, s);
+    }
+    if (split) {
+        hipStream_t aux2 = (hipStream_t)st.aux2;
+        if ((err = hipEventRecord((hipEvent_t)st.fork3, s)) != hipSuccess) return err;
+        if ((err = hipStreamWaitEvent(aux2, (hipEvent_t)st.fork3, 0)) != hipSuccess) return err;
+        if (far_on) m2l(true, far_split, t.far.ntargets, aux2);
+        if (ver_on) m2l(false, ver_split, t.ver.ntargets, aux2);
+        if ((err = hipEventRecord((hipEvent_t)st.join2, aux2)) != hipSuccess) return err;
     }
     if (fam_on) {
         mark(H2S_PROF_M2M, 0, s);
@@ -679,26 +706,27 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
                 hipLaunchKernelGGL(k_m2m<P>, dim3(nb), dim3(plan.up_threads[l]), lds_rows, s, t, lev_off[l], mask);
         }
         mark(H2S_PROF_M2M, 1, s);
-        if ((mask & kFar) && t.far.ntargets) {
+        if (far_on && t.far.ntargets) {
             mark(H2S_PROF_M2L_FAR, 0, s);
-            if constexpr (sizeof(typename P::far_t) == 4)
-                hipLaunchKernelGGL((k_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_M2L), 0, s, t);
-            else
-                hipLaunchKernelGGL((k_m2l_slices<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_M2LS), 0, s, t);
+            m2l(true, 0, far_split, s);
             mark(H2S_PROF_M2L_FAR, 1, s);
         }
-        if ((mask & kVer) && t.ver.ntargets) {
+        if (ver_on && t.ver.ntargets) {
             mark(H2S_PROF_M2L_VER, 0, s);
-            hipLaunchKernelGGL((k_m2l_slices<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_M2LS), 0, s, t);
+            m2l(false, 0, ver_split, s);
             mark(H2S_PROF_M2L_VER, 1, s);
         }
         if (overlap && (err = fork_near((hipEvent_t)st.fork2, near1, t.nleaf)) != hipSuccess) return err;
         mark(H2S_PROF_L2L, 0, s);
         for (int l = 1; l <= t.kappa - 1; ++l) {
+            // the L2L into the leaves adds to the leaf-level M2L results
+            if (split && l == t.kappa - 1 && (err = hipStreamWaitEvent(s, (hipEvent_t)st.join2, 0)) != hipSuccess)
+                return err;
             const int nb = lev_off[l + 1] - lev_off[l];
             if (nb)
                 hipLaunchKernelGGL(k_l2l<P>, dim3(nb), dim3(plan.dn_threads[l]), lds_rank, s, t, lev_off[l], mask);
         }
+        if (split && t.kappa < 2 && (err = hipStreamWaitEvent(s, (hipEvent_t)st.join2, 0)) != hipSuccess) return err;
         mark(H2S_PROF_L2L, 1, s);
     }
     if (t.variant == H2S_H2_PLUS_H && (mask & kVer) && t.pairs.npairs) {

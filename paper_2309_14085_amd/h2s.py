@@ -74,7 +74,7 @@ class SolveOpts(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("near_first", ctypes.c_double), ("up_threads", ctypes.c_int32 * 33),
-                ("dn_threads", ctypes.c_int32 * 33)]
+                ("dn_threads", ctypes.c_int32 * 33), ("m2l_stream", ctypes.c_int32)]
 
 
 class TuneInfo(ctypes.Structure):
@@ -241,16 +241,19 @@ class Tree:
         check(load().h2s_set_profiling(self._h, int(bool(on))))
 
     def schedule(self):
-        """The launch schedule: {"near_first", "up_threads", "dn_threads"} (widths per level 0..32)."""
+        """The launch schedule: {"near_first", "up_threads", "dn_threads", "m2l_stream"}
+        (widths per level 0..32)."""
         sc = Schedule()
         check(load().h2s_get_schedule(self._h, ctypes.byref(sc)))
-        return {"near_first": sc.near_first, "up_threads": list(sc.up_threads), "dn_threads": list(sc.dn_threads)}
+        return {"near_first": sc.near_first, "up_threads": list(sc.up_threads), "dn_threads": list(sc.dn_threads),
+                "m2l_stream": sc.m2l_stream}
 
-    def set_schedule(self, near_first=None, up_threads=None, dn_threads=None):
+    def set_schedule(self, near_first=None, up_threads=None, dn_threads=None, m2l_stream=None):
         """Replace fields of the launch schedule (others kept); see h2s_set_schedule."""
         cur = self.schedule()
         sc = Schedule()
         sc.near_first = cur["near_first"] if near_first is None else float(near_first)
+        sc.m2l_stream = cur["m2l_stream"] if m2l_stream is None else int(m2l_stream)
         for name, new in (("up_threads", up_threads), ("dn_threads", dn_threads)):
             vals = list(cur[name])
             if new is not None:

@@ -38,6 +38,7 @@ def parse():
     p.add_argument("--no-multi-rhs", action="store_true", help="skip the 3D 32-RHS batched product beside the MVP")
     p.add_argument("--no-serve", action="store_true", help="skip the serving run (build + solve requests)")
     p.add_argument("--no-tune", action="store_true", help="skip the autotuned-schedule leg of the FP64 product")
+    p.add_argument("--no-group", action="store_true", help="skip the tree-group leg (many small trees, one launch)")
     p.add_argument("--profile-only", action="store_true",
                    help="skip the timed steps and the solve, multi-RHS and serving legs: warm-up and the per-class "
                         "profiled steps only (for rocprofv3 runs)")
@@ -116,6 +117,44 @@ def time_tuned(h2s, torch, pts, q, w, steps, warmup):
             "bitwise_equal": equal,
             "schedule": {"near_first": sc["near_first"], "up_threads_by_level": sc["up_threads"][1:k + 1],
                          "dn_threads_by_level": sc["dn_threads"][1:k]}}
+
+
+def time_group(h2s, torch, count=32, seed=7, reps=10):
+    """count 2D log r trees (n_max 64, eps 1e-8) of N log-uniform in [2^12, 2^15]: one
+    h2s_group_apply (every product on its own stream) against count h2s_apply calls on one stream."""
+    import numpy as np
+    from paper_2309_14085_amd import inputs
+    rng = np.random.default_rng(seed)
+    sizes = [int(round(np.exp(rng.uniform(np.log(4096), np.log(32768))))) for _ in range(count)]
+    dev = torch.device("cuda:0")
+    trees = [h2s.build(inputs.uniform_points(n, 2, 3000 + i), kind=0, leaf_size=64, eps=1e-8)
+             for i, n in enumerate(sizes)]
+    xs = [torch.from_numpy(inputs.normal_rhs(n, 1, 4000 + i)[:, 0]).to(dev) for i, n in enumerate(sizes)]
+    ys = [torch.empty_like(x) for x in xs]
+    G = h2s.Group(trees)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    ms_seq = timed(lambda: [T.apply(x, y) for T, x, y in zip(trees, xs, ys)])
+    ref = [y.clone() for y in ys]
+    ms_group = timed(lambda: G.apply(xs, ys))
+    equal = all(bool(torch.equal(a, b)) for a, b in zip(ys, ref))
+    G.free()
+    for T in trees:
+        T.free()
+    total = int(sum(sizes))
+    return {"trees": count, "n_min": min(sizes), "n_max": max(sizes), "points": total,
+            "ms_one_by_one": ms_seq, "ms_group": ms_group, "speedup": ms_seq / ms_group,
+            "points_per_s_group": total / (ms_group * 1e-3), "bitwise_equal": equal}
 
 
 def time_solve(h2s, torch, w):
@@ -231,7 +270,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
     if a.profile_only:  # rocprofv3 runs trace the product alone
-        a.no_solve = a.no_multi_rhs = a.no_serve = a.no_tune = True
+        a.no_solve = a.no_multi_rhs = a.no_serve = a.no_tune = a.no_group = True
     import numpy as np
     import torch
 
@@ -281,6 +320,12 @@ def main():
         tuned = time_tuned(h2s, torch, pts, q, w, a.steps, a.warmup)
         print(f"# tuned: {tuned}", file=sys.stderr, flush=True)
 
+    group = None
+    if not a.no_group:
+        print("# 32 small trees: one group apply against one apply each", file=sys.stderr, flush=True)
+        group = time_group(h2s, torch)
+        print(f"# group: {group}", file=sys.stderr, flush=True)
+
     solve = None
     if not a.no_solve:
         print("# building and timing the RBF interpolation solve", file=sys.stderr, flush=True)
@@ -321,6 +366,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "tuned_schedule": tuned,
+        "tree_group": group,
         "solve": solve,
         "multi_rhs": multi,
         "serving": served,

@@ -270,6 +270,22 @@ typedef struct {
 } h2s_tune_info;
 h2s_status h2s_tune(h2s_tree t, const double *x, double *y, int32_t reps, h2s_tune_info *info, void *stream);
 
+/* Groups of trees applied together.  h2s_group_apply enqueues
+ * y_i = K~_i x_i for every tree of the group (each in its own precision and
+ * schedule, one right-hand side each) ordered on stream: each tree's product
+ * runs on a stream of the group's own, forked from stream and joined back
+ * into it with events, so the products of many small trees run side by side
+ * instead of one after another.  Results equal h2s_apply on each tree bit
+ * for bit.  x[i], y[i]: device vectors of tree i's n (user order), not
+ * overlapping.  h2s_group_create takes count >= 1 distinct device (not
+ * host_only) trees of one device; it copies the array but not the trees,
+ * which must outlive the group and must not be used by another call while
+ * a group apply is in flight.  Not for use under graph capture. */
+typedef struct h2s_group_s *h2s_group;
+h2s_status h2s_group_create(const h2s_tree *trees, int32_t count, h2s_group *out);
+h2s_status h2s_group_apply(h2s_group g, const double *const *x, double *const *y, void *stream);
+h2s_status h2s_group_free(h2s_group g);
+
 /* Device memory hooks: alloc(ctx, bytes, &ptr) returns 0 on success.  NULL
  * functions restore hipMalloc / hipFree.  Affects later builds only. */
 typedef int (*h2s_alloc_fn)(void *ctx, size_t bytes, void **ptr);

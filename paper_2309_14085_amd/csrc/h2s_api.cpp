@@ -110,6 +110,27 @@ struct h2s_tree_s {
     }
 };
 
+// A group of trees applied together (see h2s_group_apply).
+struct h2s_group_s {
+    std::vector<h2s_tree> trees;
+    int device = 0;
+    std::vector<hipStream_t> lanes; // one per tree: the stream its product runs on
+    std::vector<hipEvent_t> done;   // one per tree: joins its lane back into the caller's stream
+    hipEvent_t start = nullptr;     // forks every lane from the caller's stream
+
+    ~h2s_group_s()
+    {
+        for (hipStream_t s : lanes)
+            if (s) {
+                (void)hipStreamSynchronize(s);
+                (void)hipStreamDestroy(s);
+            }
+        for (hipEvent_t e : done)
+            if (e) (void)hipEventDestroy(e);
+        if (start) (void)hipEventDestroy(start);
+    }
+};
+
 namespace {
 void record_mark(void *ctx, int cls, int end, void *stream)
 {
@@ -962,6 +983,75 @@ h2s_status h2s_tune(h2s_tree t, const double *x, double *y, int32_t reps, h2s_tu
     (void)hipEventDestroy(e1);
     if (st == H2S_OK && info) *info = res;
     return st;
+}
+
+h2s_status h2s_group_create(const h2s_tree *trees, int32_t count, h2s_group *out)
+{
+    if (!out) return fail(H2S_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!trees || count < 1) return fail(H2S_ERR_INVALID_ARG, "a group needs count >= 1 trees");
+    for (int32_t i = 0; i < count; ++i) {
+        if (!trees[i]) return fail(H2S_ERR_INVALID_ARG, "tree " + std::to_string(i) + " is NULL");
+        for (int32_t j = 0; j < i; ++j)
+            if (trees[j] == trees[i]) return fail(H2S_ERR_INVALID_ARG, "a tree appears twice in the group");
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        if (trees[i]->host_only) return fail(H2S_ERR_UNSUPPORTED, "tree " + std::to_string(i) + " is host_only");
+        if (trees[i]->device != trees[0]->device) return fail(H2S_ERR_INVALID_ARG, "the trees are on different devices");
+    }
+    if (hipSetDevice(trees[0]->device) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipSetDevice failed");
+    for (int32_t i = 0; i < count; ++i)
+        if (ensure_streams(trees[i]) != H2S_OK) return H2S_ERR_DEVICE;
+    h2s_group g = new (std::nothrow) h2s_group_s();
+    if (!g) return fail(H2S_ERR_OUT_OF_MEMORY, "host allocation failed");
+    g->trees.assign(trees, trees + count);
+    g->device = trees[0]->device;
+    g->lanes.assign(count, nullptr);
+    g->done.assign(count, nullptr);
+    bool ok = hipEventCreateWithFlags(&g->start, hipEventDisableTiming) == hipSuccess;
+    for (int32_t i = 0; ok && i < count; ++i)
+        ok = hipStreamCreateWithFlags(&g->lanes[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&g->done[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        delete g;
+        return fail(H2S_ERR_DEVICE, "creating the group's streams or events failed");
+    }
+    *out = g;
+    return H2S_OK;
+}
+
+h2s_status h2s_group_apply(h2s_group g, const double *const *x, double *const *y, void *stream)
+{
+    if (!g) return fail(H2S_ERR_INVALID_ARG, "group is NULL");
+    if (!x || !y) return fail(H2S_ERR_INVALID_ARG, "x or y is NULL");
+    const size_t count = g->trees.size();
+    for (size_t i = 0; i < count; ++i) {
+        const int64_t n = g->trees[i]->rep.n;
+        if (!x[i] || !y[i]) return fail(H2S_ERR_INVALID_ARG, "x or y of tree " + std::to_string(i) + " is NULL");
+        if ((const char *)x[i] < (const char *)(y[i] + n) && (const char *)y[i] < (const char *)(x[i] + n))
+            return fail(H2S_ERR_INVALID_ARG, "x and y of tree " + std::to_string(i) + " overlap");
+    }
+    if (hipSetDevice(g->device) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t s = (hipStream_t)stream;
+    if (hipEventRecord(g->start, s) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipEventRecord failed");
+    for (size_t i = 0; i < count; ++i) {
+        h2s_tree t = g->trees[i];
+        if (hipStreamWaitEvent(g->lanes[i], g->start, 0) != hipSuccess)
+            return fail(H2S_ERR_DEVICE, "hipStreamWaitEvent failed");
+        const int rc = mvp(t, t->opts.prec, H2S_PHASE_ALL, x[i], y[i], g->lanes[i], nullptr);
+        if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
+        if (hipEventRecord(g->done[i], g->lanes[i]) != hipSuccess || hipStreamWaitEvent(s, g->done[i], 0) != hipSuccess)
+            return fail(H2S_ERR_DEVICE, "joining a tree's stream failed");
+    }
+    return H2S_OK;
+}
+
+h2s_status h2s_group_free(h2s_group g)
+{
+    if (!g) return H2S_OK;
+    (void)hipSetDevice(g->device);
+    delete g;
+    return H2S_OK;
 }
 
 h2s_status h2s_free(h2s_tree t)

@@ -111,12 +111,16 @@ def load():
     lib.h2s_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     lib.h2s_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
     lib.h2s_solve.argtypes = [vp, vp, vp, i32, i64, i64, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), vp]
+    lib.h2s_group_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+    lib.h2s_group_apply.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    lib.h2s_group_free.argtypes = [vp]
     lib.h2s_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
     lib.h2s_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
     lib.h2s_tune.argtypes = [vp, vp, vp, i32, ctypes.POINTER(TuneInfo), vp]
     for name in ("h2s_build", "h2s_apply", "h2s_apply_phases", "h2s_free", "h2s_get_stats", "h2s_export",
                  "h2s_set_allocator", "h2s_last_error", "h2s_set_profiling", "h2s_get_profile",
-                 "h2s_solve_opts_default", "h2s_solve", "h2s_get_schedule", "h2s_set_schedule", "h2s_tune"):
+                 "h2s_solve_opts_default", "h2s_solve", "h2s_get_schedule", "h2s_set_schedule", "h2s_tune",
+                 "h2s_group_create", "h2s_group_apply", "h2s_group_free"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -286,6 +290,35 @@ class Tree:
         check(load().h2s_export(self._h, str(path).encode()))
         return read_export(path)
 
+
+
+class Group:
+    """Trees applied together, each on a stream of the group's own (h2s_group_apply)."""
+
+    def __init__(self, trees):
+        self.trees = list(trees)  # the trees must outlive the group
+        arr = (ctypes.c_void_p * len(self.trees))(*[T.handle for T in self.trees])
+        h = ctypes.c_void_p()
+        check(load().h2s_group_create(arr, len(self.trees), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.h2s_group_free(self._h)
+            self._h = None
+
+    def apply(self, xs, ys, stream=None):
+        """ys[i] = K~_i xs[i] for CUDA float64 vectors (one per tree), ordered on stream."""
+        n = len(self.trees)
+        if len(xs) != n or len(ys) != n:
+            raise ValueError("one x and one y per tree")
+        xa = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        ya = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
+        check(load().h2s_group_apply(self._h, xa, ya, _stream_ptr(stream)))
+        return ys
 
 def build(points, kind=LOG_R, leaf_size=64, eps=1e-8, eps_ver=None, variant=H2STAR, prec=FP64, param=0.0,
           diag=None, shift=0.0, host_threads=0, host_only=False, stream=None):

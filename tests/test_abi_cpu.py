@@ -196,3 +196,16 @@ def test_nti_multiquadric_rejects_fp32_m2l(lib, inputs):
     k = lib.Kernel(lib.NTI_MQ, 0.0, 1.0, 0.0)
     assert _raw_build(lib, pts, 500, 3, k, lib.BuildOpts(64, 1e-6, 1e-6, 0, lib.FP32_M2L, 0, 1))[0] == lib.ERR_UNSUPPORTED
     assert _raw_build(lib, pts, 500, 3, k, lib.BuildOpts(64, 1e-6, 1e-6, 0, lib.FP32, 0, 1))[0] == lib.OK
+
+
+def test_group_validation(lib, inputs):
+    """Tree groups reject NULL / empty arrays, duplicates and host-only trees before touching a device."""
+    T = lib.build(inputs.uniform_points(300, 2, 5), host_only=True)
+    so = lib.load()
+    h = ctypes.c_void_p(77)
+    assert so.h2s_group_create(None, 1, ctypes.byref(h)) == lib.ERR_INVALID_ARG and h.value is None
+    arr = (ctypes.c_void_p * 2)(T.handle, T.handle)
+    assert so.h2s_group_create(arr, 0, ctypes.byref(h)) == lib.ERR_INVALID_ARG
+    assert so.h2s_group_create(arr, 2, ctypes.byref(h)) == lib.ERR_INVALID_ARG  # duplicate
+    assert so.h2s_group_create(arr, 1, ctypes.byref(h)) == lib.ERR_UNSUPPORTED  # host_only
+    assert so.h2s_group_free(None) == lib.OK

@@ -1,0 +1,70 @@
+"""Tree groups (h2s_group_apply): the products of many trees of uneven size, each on a stream of
+the group's own forked from and joined back into the caller's stream, must equal each tree's own
+h2s_apply bit for bit, on repeated calls (with other work between them), after the inputs are
+refilled, and with other vectors."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_14085_amd import h2s
+    h2s.load()
+    return h2s
+
+
+# d, n, kind, param, shift, variant, prec, leaf size, eps
+SPECS = [(2, 2000, 0, 0.0, 0.0, 0, 0, 64, 1e-8), (2, 9000, 0, 0.0, 0.0, 1, 0, 64, 1e-8),
+         (3, 5000, 1, 0.0, 0.0, 0, 0, 64, 1e-6), (2, 30000, 0, 0.0, 0.0, 0, 1, 64, 1e-8),
+         (3, 12000, 1, 0.0, 0.0, 0, 1, 64, 1e-6), (2, 4096, 2, 0.2, 1e-2, 0, 0, 32, 1e-10),
+         (3, 3000, 6, 0.0, 50.0, 0, 0, 32, 1e-8), (2, 700, 4, 0.05, 0.0, 0, 0, 64, 1e-10),
+         (2, 20000, 0, 0.0, 0.0, 0, 2, 64, 1e-8), (3, 2500, 5, 0.1, 0.0, 1, 0, 32, 1e-8), (2, 50, 0, 0.0, 0.0, 0, 0, 64, 1e-8)]
+
+
+def test_group_equals_each_tree(lib, inputs):
+    dev = torch.device("cuda:0")
+    trees, xs = [], []
+    for i, (d, n, kind, param, shift, variant, prec, nmax, eps) in enumerate(SPECS):
+        trees.append(lib.build(inputs.uniform_points(n, d, 300 + i), kind=kind, leaf_size=nmax, eps=eps,
+                               variant=variant, prec=prec, param=param, shift=shift))
+        xs.append(torch.from_numpy(inputs.normal_rhs(n, 1, 400 + i)[:, 0]).to(dev))
+    refs = [T.apply(x).clone() for T, x in zip(trees, xs)]
+    torch.cuda.synchronize()
+    G = lib.Group(trees)
+    ys = [torch.zeros_like(x) for x in xs]
+    for rep in range(3):
+        print(f"group call {rep}", flush=True)
+        G.apply(xs, ys)
+        torch.cuda.synchronize()
+        for i in range(len(trees)):
+            assert torch.equal(ys[i], refs[i]), (rep, i)
+        trees[3].apply(xs[3])  # other work of the program between calls
+        torch.cuda.synchronize()
+    # new contents, same pointers
+    for i, x in enumerate(xs):
+        x.copy_(torch.from_numpy(inputs.normal_rhs(len(x), 1, 500 + i)[:, 0]).to(dev))
+    refs2 = [T.apply(x).clone() for T, x in zip(trees, xs)]
+    G.apply(xs, ys)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(ys, refs2))
+    # other vectors
+    xs2 = [x.clone() for x in xs]
+    ys2 = [torch.full_like(x, 7.0) for x in xs]
+    G.apply(xs2, ys2)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(ys2, refs2))
+    G.free()
+
+
+@pytest.mark.skip(reason="capturing the products of many trees as parallel branches of one HIP graph (a capture "
+                         "origin stream forking one stream per tree, each forking its tree's near-field and M2L "
+                         "streams) ended the host process with a segmentation fault inside the group apply, whose "
+                         "cause is not identified; groups run eagerly and graph capture of a group is not offered")
+def test_group_captured_as_one_graph():
+    pass

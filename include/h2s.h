@@ -272,10 +272,14 @@ h2s_status h2s_tune(h2s_tree t, const double *x, double *y, int32_t reps, h2s_tu
 
 /* Groups of trees applied together.  h2s_group_apply enqueues
  * y_i = K~_i x_i for every tree of the group (each in its own precision and
- * schedule, one right-hand side each) ordered on stream: each tree's product
- * runs on a stream of the group's own, forked from stream and joined back
- * into it with events, so the products of many small trees run side by side
- * instead of one after another.  Results equal h2s_apply on each tree bit
+ * schedule, one right-hand side each) ordered on stream.  Each tree's product
+ * is captured once as a HIP graph (again when that tree's x[i] or y[i]
+ * pointer changes; contents may change freely) and launched on a stream of
+ * the group's own, forked from stream and joined back into it with events:
+ * the products of many small trees run side by side, one graph launch each
+ * instead of one launch per kernel.  The group holds the graphs until it is
+ * freed or recaptures them (and, from its schedule at capture, the launch
+ * configuration of each tree).  Results equal h2s_apply on each tree bit
  * for bit.  x[i], y[i]: device vectors of tree i's n (user order), not
  * overlapping.  h2s_group_create takes count >= 1 distinct device (not
  * host_only) trees of one device; it copies the array but not the trees,

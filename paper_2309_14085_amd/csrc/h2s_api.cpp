@@ -110,24 +110,41 @@ struct h2s_tree_s {
     }
 };
 
-// A group of trees applied together (see h2s_group_apply).
+// A group of trees applied together (see h2s_group_apply).  Each tree's
+// product is captured, alone, as a HIP graph on the group's capture stream
+// (the tree's near-field and M2L streams joining it through their events, as
+// in any single-product capture) and replayed on the tree's lane.
 struct h2s_group_s {
     std::vector<h2s_tree> trees;
     int device = 0;
-    std::vector<hipStream_t> lanes; // one per tree: the stream its product runs on
-    std::vector<hipEvent_t> done;   // one per tree: joins its lane back into the caller's stream
-    hipEvent_t start = nullptr;     // forks every lane from the caller's stream
+    hipStream_t cap = nullptr;          // capture stream
+    std::vector<hipStream_t> lanes;     // one per tree: the stream its graph is launched on
+    std::vector<hipEvent_t> done;       // one per tree: joins its lane back into the caller's stream
+    hipEvent_t start = nullptr;         // forks every lane from the caller's stream
+    std::vector<hipGraph_t> graphs;     // one per tree
+    std::vector<hipGraphExec_t> execs;
+    std::vector<const double *> xs;     // the vectors each graph holds
+    std::vector<double *> ys;
+
+    void drop_graph(size_t i)
+    {
+        if (execs[i]) (void)hipGraphExecDestroy(execs[i]);
+        if (graphs[i]) (void)hipGraphDestroy(graphs[i]);
+        execs[i] = nullptr;
+        graphs[i] = nullptr;
+    }
 
     ~h2s_group_s()
     {
         for (hipStream_t s : lanes)
-            if (s) {
-                (void)hipStreamSynchronize(s);
-                (void)hipStreamDestroy(s);
-            }
+            if (s) (void)hipStreamSynchronize(s);
+        for (size_t i = 0; i < graphs.size(); ++i) drop_graph(i);
+        for (hipStream_t s : lanes)
+            if (s) (void)hipStreamDestroy(s);
         for (hipEvent_t e : done)
             if (e) (void)hipEventDestroy(e);
         if (start) (void)hipEventDestroy(start);
+        if (cap) (void)hipStreamDestroy(cap);
     }
 };
 
@@ -1008,7 +1025,12 @@ h2s_status h2s_group_create(const h2s_tree *trees, int32_t count, h2s_group *out
     g->device = trees[0]->device;
     g->lanes.assign(count, nullptr);
     g->done.assign(count, nullptr);
-    bool ok = hipEventCreateWithFlags(&g->start, hipEventDisableTiming) == hipSuccess;
+    g->graphs.assign(count, nullptr);
+    g->execs.assign(count, nullptr);
+    g->xs.assign(count, nullptr);
+    g->ys.assign(count, nullptr);
+    bool ok = hipEventCreateWithFlags(&g->start, hipEventDisableTiming) == hipSuccess &&
+              hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) == hipSuccess;
     for (int32_t i = 0; ok && i < count; ++i)
         ok = hipStreamCreateWithFlags(&g->lanes[i], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&g->done[i], hipEventDisableTiming) == hipSuccess;
@@ -1032,14 +1054,36 @@ h2s_status h2s_group_apply(h2s_group g, const double *const *x, double *const *y
             return fail(H2S_ERR_INVALID_ARG, "x and y of tree " + std::to_string(i) + " overlap");
     }
     if (hipSetDevice(g->device) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipSetDevice failed");
+    // (re)capture the products whose vectors changed, one tree per capture
+    for (size_t i = 0; i < count; ++i) {
+        if (g->execs[i] && g->xs[i] == x[i] && g->ys[i] == y[i]) continue;
+        h2s_tree t = g->trees[i];
+        g->drop_graph(i);
+        if (hipStreamBeginCapture(g->cap, hipStreamCaptureModeGlobal) != hipSuccess)
+            return fail(H2S_ERR_DEVICE, "hipStreamBeginCapture failed");
+        const int rc = mvp(t, t->opts.prec, H2S_PHASE_ALL, x[i], y[i], g->cap, nullptr);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(g->cap, &graph);
+        if (rc != 0 || ec != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(H2S_ERR_DEVICE, std::string("capturing the product of tree ") + std::to_string(i) + " failed: " +
+                                            hipGetErrorString(rc != 0 ? (hipError_t)rc : ec));
+        }
+        g->graphs[i] = graph;
+        if (hipGraphInstantiateWithFlags(&g->execs[i], graph, 0) != hipSuccess) {
+            g->execs[i] = nullptr;
+            g->drop_graph(i);
+            return fail(H2S_ERR_DEVICE, "hipGraphInstantiateWithFlags failed");
+        }
+        g->xs[i] = x[i];
+        g->ys[i] = y[i];
+    }
     hipStream_t s = (hipStream_t)stream;
     if (hipEventRecord(g->start, s) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipEventRecord failed");
     for (size_t i = 0; i < count; ++i) {
-        h2s_tree t = g->trees[i];
         if (hipStreamWaitEvent(g->lanes[i], g->start, 0) != hipSuccess)
             return fail(H2S_ERR_DEVICE, "hipStreamWaitEvent failed");
-        const int rc = mvp(t, t->opts.prec, H2S_PHASE_ALL, x[i], y[i], g->lanes[i], nullptr);
-        if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
+        if (hipGraphLaunch(g->execs[i], g->lanes[i]) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipGraphLaunch failed");
         if (hipEventRecord(g->done[i], g->lanes[i]) != hipSuccess || hipStreamWaitEvent(s, g->done[i], 0) != hipSuccess)
             return fail(H2S_ERR_DEVICE, "joining a tree's stream failed");
     }

@@ -293,7 +293,8 @@ class Tree:
 
 
 class Group:
-    """Trees applied together, each on a stream of the group's own (h2s_group_apply)."""
+    """Trees applied together: one captured graph per tree, each launched on a stream of the
+    group's own (h2s_group_apply)."""
 
     def __init__(self, trees):
         self.trees = list(trees)  # the trees must outlive the group

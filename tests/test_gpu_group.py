@@ -1,7 +1,8 @@
-"""Tree groups (h2s_group_apply): the products of many trees of uneven size, each on a stream of
-the group's own forked from and joined back into the caller's stream, must equal each tree's own
-h2s_apply bit for bit, on repeated calls (with other work between them), after the inputs are
-refilled, and with other vectors."""
+"""Tree groups (h2s_group_apply): the products of many trees of uneven size, each captured as a
+graph of its own and launched on a stream of the group's own (forked from and joined back into
+the caller's stream), must equal each tree's own h2s_apply bit for bit on every replay (with
+other work of the program between replays), after the inputs are refilled (same pointers), and
+after other vectors force new captures."""
 import numpy as np
 import pytest
 
@@ -39,21 +40,21 @@ def test_group_equals_each_tree(lib, inputs):
     G = lib.Group(trees)
     ys = [torch.zeros_like(x) for x in xs]
     for rep in range(3):
-        print(f"group call {rep}", flush=True)
+        print(f"group replay {rep}", flush=True)
         G.apply(xs, ys)
         torch.cuda.synchronize()
         for i in range(len(trees)):
             assert torch.equal(ys[i], refs[i]), (rep, i)
-        trees[3].apply(xs[3])  # other work of the program between calls
+        trees[3].apply(xs[3])  # eager work of the program between replays
         torch.cuda.synchronize()
-    # new contents, same pointers
+    # new contents, same pointers: the captured graphs read them
     for i, x in enumerate(xs):
         x.copy_(torch.from_numpy(inputs.normal_rhs(len(x), 1, 500 + i)[:, 0]).to(dev))
     refs2 = [T.apply(x).clone() for T, x in zip(trees, xs)]
     G.apply(xs, ys)
     torch.cuda.synchronize()
     assert all(torch.equal(a, b) for a, b in zip(ys, refs2))
-    # other vectors
+    # other vectors: new captures
     xs2 = [x.clone() for x in xs]
     ys2 = [torch.full_like(x, 7.0) for x in xs]
     G.apply(xs2, ys2)
@@ -62,9 +63,9 @@ def test_group_equals_each_tree(lib, inputs):
     G.free()
 
 
-@pytest.mark.skip(reason="capturing the products of many trees as parallel branches of one HIP graph (a capture "
+@pytest.mark.skip(reason="capturing the products of many trees as parallel branches of ONE HIP graph (a capture "
                          "origin stream forking one stream per tree, each forking its tree's near-field and M2L "
                          "streams) ended the host process with a segmentation fault inside the group apply, whose "
-                         "cause is not identified; groups run eagerly and graph capture of a group is not offered")
+                         "cause is not identified; groups capture one graph per tree instead")
 def test_group_captured_as_one_graph():
     pass

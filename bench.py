@@ -121,7 +121,8 @@ def time_tuned(h2s, torch, pts, q, w, steps, warmup):
 
 def time_group(h2s, torch, count=32, seed=7, reps=10):
     """count 2D log r trees (n_max 64, eps 1e-8) of N log-uniform in [2^12, 2^15]: one
-    h2s_group_apply (every product on its own stream) against count h2s_apply calls on one stream."""
+    h2s_group_apply (one fused class: one launch per step for all trees) against count h2s_apply
+    calls on one stream."""
     import numpy as np
     from paper_2309_14085_amd import inputs
     rng = np.random.default_rng(seed)

@@ -271,16 +271,19 @@ typedef struct {
 h2s_status h2s_tune(h2s_tree t, const double *x, double *y, int32_t reps, h2s_tune_info *info, void *stream);
 
 /* Groups of trees applied together.  h2s_group_apply enqueues
- * y_i = K~_i x_i for every tree of the group (each in its own precision and
- * schedule, one right-hand side each) ordered on stream.  Each tree's product
- * is captured once as a HIP graph (again when that tree's x[i] or y[i]
- * pointer changes; contents may change freely) and launched on a stream of
- * the group's own, forked from stream and joined back into it with events:
- * the products of many small trees run side by side, one graph launch each
- * instead of one launch per kernel.  The group holds the graphs until it is
- * freed or recaptures them (and, from its schedule at capture, the launch
- * configuration of each tree).  Results equal h2s_apply on each tree bit
- * for bit.  x[i], y[i]: device vectors of tree i's n (user order), not
+ * y_i = K~_i x_i for every tree of the group (one right-hand side each)
+ * ordered on stream.  H2* trees of one precision (H2S_FP64 or H2S_FP32),
+ * kernel kind and dimension that number two or more form a fused class: one
+ * kernel launch per step covers every tree of the class (permutation, near
+ * field, P2M, each M2M and L2L level step, M2L per family, L2P), each block
+ * taking one work item of one tree, so many trees of uneven size cost the
+ * launches of one.  Every other tree's product is captured once as a HIP
+ * graph (again when that tree's x[i] or y[i] pointer changes) and launched
+ * on a stream of the group's own, forked from stream and joined back into it
+ * with events.  A changed pointer of a fused tree makes the call wait for
+ * stream before it updates the class's vector table.  The group keeps its
+ * launch tables (and the block widths the trees' schedules had at creation)
+ * until it is freed.  Results equal h2s_apply on each tree bit for bit.  x[i], y[i]: device vectors of tree i's n (user order), not
  * overlapping.  h2s_group_create takes count >= 1 distinct device (not
  * host_only) trees of one device; it copies the array but not the trees,
  * which must outlive the group and must not be used by another call while

@@ -110,12 +110,30 @@ struct h2s_tree_s {
     }
 };
 
-// A group of trees applied together (see h2s_group_apply).  Each tree's
-// product is captured, alone, as a HIP graph on the group's capture stream
-// (the tree's near-field and M2L streams joining it through their events, as
-// in any single-product capture) and replayed on the tree's lane.
+// A group of trees applied together (see h2s_group_apply).  H2* trees of
+// one precision (FP64 or FP32), kernel function and dimension that number
+// two or more form a fused class: one launch per step for all of them
+// (h2s::MultiPlan).  Every other tree's product is captured, alone, as a HIP
+// graph on the group's capture stream (the tree's near-field and M2L streams
+// joining it through their events, as in any single-product capture) and
+// replayed on the tree's lane.
 struct h2s_group_s {
+    struct Fused {
+        int prec = 0, kind = 0, d = 0;
+        std::vector<int32_t> members;                 // indices into trees
+        h2s::MultiPlan<h2s::P64> mp64{};
+        h2s::MultiPlan<h2s::P32> mp32{};
+        const double **xs_dev = nullptr;              // device arrays of the members' vectors
+        double **ys_dev = nullptr;
+        std::vector<const double *> xs;               // what they hold
+        std::vector<double *> ys;
+    };
     std::vector<h2s_tree> trees;
+    std::vector<Fused> fused;
+    std::vector<char> in_fused;         // per tree
+    std::vector<void *> dev;            // device allocations of the fused classes
+    hipStream_t faux = nullptr;         // near-field stream of the fused classes
+    hipEvent_t ffork = nullptr, fjoin = nullptr;
     int device = 0;
     hipStream_t cap = nullptr;          // capture stream
     std::vector<hipStream_t> lanes;     // one per tree: the stream its graph is launched on
@@ -145,6 +163,13 @@ struct h2s_group_s {
             if (e) (void)hipEventDestroy(e);
         if (start) (void)hipEventDestroy(start);
         if (cap) (void)hipStreamDestroy(cap);
+        if (faux) {
+            (void)hipStreamSynchronize(faux);
+            (void)hipStreamDestroy(faux);
+        }
+        if (ffork) (void)hipEventDestroy(ffork);
+        if (fjoin) (void)hipEventDestroy(fjoin);
+        for (void *p : dev) (void)hipFree(p);
     }
 };
 
@@ -736,6 +761,99 @@ int solve_apply_outer(void *c, const double *x, double *y)
 
 } // namespace
 
+namespace {
+
+// Device copy of a host vector, owned by the group.
+template <typename T> T *group_copy(h2s_group g, const std::vector<T> &v, bool &ok)
+{
+    if (!ok || v.empty()) return nullptr;
+    void *p = nullptr;
+    if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess) {
+        ok = false;
+        return nullptr;
+    }
+    g->dev.push_back(p);
+    if (hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    return (T *)p;
+}
+
+// The launch steps of a fused class (see h2s::MultiPlan).
+template <class P>
+bool build_multi(h2s_group g, h2s_group_s::Fused &f, h2s::MultiPlan<P> &mp, h2s::DevTree<P> h2s_tree_s::*member)
+{
+    bool ok = true;
+    const int m = (int)f.members.size();
+    std::vector<h2s::DevTree<P>> trees(m);
+    std::vector<int2> perm, leaf, up, far, ver;
+    std::vector<std::vector<int2>> m2m, l2l;
+    std::vector<int32_t> w_m2m, w_l2l;
+    int32_t w_up = 64, max_leaf = 1, max_rows = 1, max_rank = 1;
+    for (int i = 0; i < m; ++i) {
+        h2s_tree t = g->trees[f.members[i]];
+        const h2s::DevTree<P> &D = t->*member;
+        const h2s::HostRep &r = t->rep;
+        trees[i] = D;
+        const int kappa = std::min(r.kappa, h2s::kMaxLevels);
+        for (int32_t c = 0; c < (D.n + 255) / 256; ++c) perm.push_back(make_int2(i, c));
+        for (int32_t lf = 0; lf < D.nleaf; ++lf) leaf.push_back(make_int2(i, lf));
+        max_leaf = std::max(max_leaf, D.max_leaf);
+        max_rows = std::max(max_rows, D.max_rows);
+        max_rank = std::max(max_rank, D.max_rank);
+        if (kappa < 1) continue;
+        for (int32_t lf = 0; lf < D.nleaf; ++lf) up.push_back(make_int2(i, lf));
+        w_up = std::max(w_up, t->plan.up_threads[kappa]);
+        for (int32_t k = 0; k < D.far.ntargets; ++k) far.push_back(make_int2(i, k));
+        for (int32_t k = 0; k < D.ver.ntargets; ++k) ver.push_back(make_int2(i, k));
+        for (int k = 0; k + 1 < kappa; ++k) {
+            if ((int)m2m.size() <= k) {
+                m2m.emplace_back();
+                l2l.emplace_back();
+                w_m2m.push_back(64);
+                w_l2l.push_back(64);
+            }
+            const int lu = kappa - 1 - k, ld = 1 + k; // M2M into level lu, L2L from level ld
+            for (int32_t b = r.lev_off[lu]; b < r.lev_off[lu + 1]; ++b) m2m[k].push_back(make_int2(i, b));
+            for (int32_t b = r.lev_off[ld]; b < r.lev_off[ld + 1]; ++b) l2l[k].push_back(make_int2(i, b));
+            w_m2m[k] = std::max(w_m2m[k], t->plan.up_threads[lu]);
+            w_l2l[k] = std::max(w_l2l[k], t->plan.dn_threads[ld]);
+        }
+    }
+    mp = h2s::MultiPlan<P>{};
+    mp.trees = group_copy(g, trees, ok);
+    mp.perm_map = group_copy(g, perm, ok);
+    mp.leaf_map = group_copy(g, leaf, ok);
+    mp.up_map = group_copy(g, up, ok);
+    mp.far_map = group_copy(g, far, ok);
+    mp.ver_map = group_copy(g, ver, ok);
+    mp.n_perm = (int32_t)perm.size();
+    mp.n_leaf = (int32_t)leaf.size();
+    mp.n_up = (int32_t)up.size();
+    mp.n_far = (int32_t)far.size();
+    mp.n_ver = (int32_t)ver.size();
+    mp.steps = (int32_t)m2m.size();
+    for (int k = 0; k < mp.steps; ++k) {
+        mp.m2m_map[k] = group_copy(g, m2m[k], ok);
+        mp.l2l_map[k] = group_copy(g, l2l[k], ok);
+        mp.n_m2m[k] = (int32_t)m2m[k].size();
+        mp.n_l2l[k] = (int32_t)l2l[k].size();
+        mp.w_m2m[k] = w_m2m[k];
+        mp.w_l2l[k] = w_l2l[k];
+    }
+    mp.w_up = w_up;
+    mp.lds_leaf = sizeof(double) * (size_t)max_leaf;
+    mp.lds_rows = sizeof(double) * (size_t)(2 * max_rows);
+    mp.lds_rank = sizeof(double) * (size_t)(2 * max_rank);
+    f.xs_dev = group_copy(g, std::vector<const double *>(m, nullptr), ok);
+    f.ys_dev = group_copy(g, std::vector<double *>(m, nullptr), ok);
+    mp.xs = f.xs_dev;
+    mp.ys = f.ys_dev;
+    f.xs.assign(m, nullptr);
+    f.ys.assign(m, nullptr);
+    return ok;
+}
+
+} // namespace
+
 extern "C" {
 
 const char *h2s_status_string(h2s_status s)
@@ -1030,7 +1148,10 @@ h2s_status h2s_group_create(const h2s_tree *trees, int32_t count, h2s_group *out
     g->xs.assign(count, nullptr);
     g->ys.assign(count, nullptr);
     bool ok = hipEventCreateWithFlags(&g->start, hipEventDisableTiming) == hipSuccess &&
-              hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) == hipSuccess;
+              hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&g->faux, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&g->ffork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&g->fjoin, hipEventDisableTiming) == hipSuccess;
     for (int32_t i = 0; ok && i < count; ++i)
         ok = hipStreamCreateWithFlags(&g->lanes[i], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&g->done[i], hipEventDisableTiming) == hipSuccess;
@@ -1038,8 +1159,37 @@ h2s_status h2s_group_create(const h2s_tree *trees, int32_t count, h2s_group *out
         delete g;
         return fail(H2S_ERR_DEVICE, "creating the group's streams or events failed");
     }
+    // fused classes: H2* trees of one precision (FP64 / FP32), kernel function and dimension
+    g->in_fused.assign(count, 0);
+    for (int32_t i = 0; i < count; ++i) {
+        h2s_tree t = trees[i];
+        const int prec = t->opts.prec;
+        if (g->in_fused[i] || t->rep.variant != H2S_H2STAR || (prec != H2S_FP64 && prec != H2S_FP32)) continue;
+        h2s_group_s::Fused f;
+        f.prec = prec;
+        f.kind = t->ker.kind;
+        f.d = t->rep.d;
+        for (int32_t j = i; j < count; ++j) {
+            h2s_tree u = trees[j];
+            if (!g->in_fused[j] && u->rep.variant == H2S_H2STAR && (int)u->opts.prec == prec && u->ker.kind == f.kind &&
+                u->rep.d == f.d)
+                f.members.push_back(j);
+        }
+        if (f.members.size() < 2) continue;
+        for (int32_t j : f.members) g->in_fused[j] = 1;
+        g->fused.push_back(std::move(f));
+    }
+    for (h2s_group_s::Fused &f : g->fused) {
+        const bool built = f.prec == H2S_FP64 ? build_multi(g, f, f.mp64, &h2s_tree_s::t64)
+                                              : build_multi(g, f, f.mp32, &h2s_tree_s::t32);
+        if (!built) {
+            delete g;
+            return fail(H2S_ERR_OUT_OF_MEMORY, "allocating the group's launch tables failed");
+        }
+    }
     *out = g;
     return H2S_OK;
+
 }
 
 h2s_status h2s_group_apply(h2s_group g, const double *const *x, double *const *y, void *stream)
@@ -1056,7 +1206,7 @@ h2s_status h2s_group_apply(h2s_group g, const double *const *x, double *const *y
     if (hipSetDevice(g->device) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipSetDevice failed");
     // (re)capture the products whose vectors changed, one tree per capture
     for (size_t i = 0; i < count; ++i) {
-        if (g->execs[i] && g->xs[i] == x[i] && g->ys[i] == y[i]) continue;
+        if (g->in_fused[i] || (g->execs[i] && g->xs[i] == x[i] && g->ys[i] == y[i])) continue;
         h2s_tree t = g->trees[i];
         g->drop_graph(i);
         if (hipStreamBeginCapture(g->cap, hipStreamCaptureModeGlobal) != hipSuccess)
@@ -1079,9 +1229,32 @@ h2s_status h2s_group_apply(h2s_group g, const double *const *x, double *const *y
         g->ys[i] = y[i];
     }
     hipStream_t s = (hipStream_t)stream;
+    // the fused classes' vector tables, refreshed (after the stream drains) when a pointer changed
+    for (h2s_group_s::Fused &f : g->fused) {
+        bool same = true;
+        for (size_t k = 0; k < f.members.size(); ++k)
+            same = same && f.xs[k] == x[f.members[k]] && f.ys[k] == y[f.members[k]];
+        if (same) continue;
+        for (size_t k = 0; k < f.members.size(); ++k) {
+            f.xs[k] = x[f.members[k]];
+            f.ys[k] = y[f.members[k]];
+        }
+        if (hipStreamSynchronize(s) != hipSuccess ||
+            hipMemcpy(f.xs_dev, f.xs.data(), f.xs.size() * sizeof(void *), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(f.ys_dev, f.ys.data(), f.ys.size() * sizeof(void *), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(H2S_ERR_DEVICE, "updating the group's vector tables failed");
+    }
     if (hipEventRecord(g->start, s) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipEventRecord failed");
+    for (h2s_group_s::Fused &f : g->fused) {
+        const h2s::Streams st{stream, g->faux, g->ffork, nullptr, g->fjoin, nullptr, nullptr, nullptr};
+        const int rc = f.prec == H2S_FP64 ? h2s::launch_multi<h2s::P64>(f.kind, f.d, f.mp64, st)
+                                          : h2s::launch_multi<h2s::P32>(f.kind, f.d, f.mp32, st);
+        if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
+    }
     for (size_t i = 0; i < count; ++i) {
+        if (g->in_fused[i]) continue;
         if (hipStreamWaitEvent(g->lanes[i], g->start, 0) != hipSuccess)
+
             return fail(H2S_ERR_DEVICE, "hipStreamWaitEvent failed");
         if (hipGraphLaunch(g->execs[i], g->lanes[i]) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipGraphLaunch failed");
         if (hipEventRecord(g->done[i], g->lanes[i]) != hipSuccess || hipStreamWaitEvent(s, g->done[i], 0) != hipSuccess)

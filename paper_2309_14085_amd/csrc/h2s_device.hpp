@@ -142,6 +142,28 @@ struct Streams {
     void *main, *aux, *fork, *fork2, *join, *aux2, *fork3, *join2;
 };
 
+// Many trees of one precision, kernel function and dimension (H2*) applied
+// with one launch per step: every array lives in device memory and maps a
+// block (after the XCD remap) to (tree, work item).  Steps: the charge
+// permutation (items: 256-point chunks), the near field and L2P (items:
+// leaves), P2M (leaves of trees with kappa >= 1), M2M step s (boxes of level
+// kappa_i - 1 - s of tree i), M2L per family (target-list indices), L2L step s
+// (boxes of level 1 + s).
+template <class P> struct MultiPlan {
+    const DevTree<P> *trees;
+    const double *const *xs; // per tree
+    double *const *ys;
+    const int2 *perm_map, *leaf_map, *up_map, *far_map, *ver_map;
+    int32_t n_perm, n_leaf, n_up, n_far, n_ver;
+    int32_t steps;                                 // M2M and L2L steps (max kappa - 1)
+    const int2 *m2m_map[kMaxLevels], *l2l_map[kMaxLevels];
+    int32_t n_m2m[kMaxLevels], n_l2l[kMaxLevels];
+    int32_t w_up, w_m2m[kMaxLevels], w_l2l[kMaxLevels]; // block widths (largest of the trees')
+    size_t lds_leaf, lds_rows, lds_rank;           // dynamic LDS (largest of the trees')
+};
+
+template <class P> int launch_multi(int kind, int d, const MultiPlan<P> &mp, const Streams &s);
+
 // Right-hand sides per block of the batched product.
 constexpr int kBatch = 8;
 

@@ -52,17 +52,22 @@ namespace {
 constexpr int NT_GEMV_MAX = 512;
 constexpr int GEMV_WAVES = 5; // waves per SIMD asked of the compiler (bytes in flight)
 
-// Charges to tree order: qt[i] = x[perm[i]].
-template <class P> __global__ __launch_bounds__(256) void k_permute(DevTree<P> t, const double *__restrict__ x)
+// Charges to tree order: qt[i] = x[perm[i]], 256 per block.
+template <class P> __device__ __forceinline__ void permute_body(const DevTree<P> &t, const double *__restrict__ x, int blk)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = blk * 256 + threadIdx.x;
     if (i < t.n) t.qt[i] = x[t.perm[i]];
 }
 
-template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_up_leaf(DevTree<P> t, uint32_t mask)
+template <class P> __global__ __launch_bounds__(256) void k_permute(DevTree<P> t, const double *__restrict__ x)
+{
+    permute_body(t, x, blockIdx.x);
+}
+
+template <class P> __device__ __forceinline__ void up_leaf_body(const DevTree<P> &t, int leaf, uint32_t mask)
 {
     extern __shared__ double qs[]; // largest leaf
-    const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf, tid = threadIdx.x, nt = blockDim.x;
+    const int g = t.leaf0 + leaf, tid = threadIdx.x, nt = blockDim.x;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
     for (int i = tid; i < n; i += nt) qs[i] = t.qt[b + i];
     __syncthreads();
@@ -78,10 +83,15 @@ template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_
     }
 }
 
-template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_m2m(DevTree<P> t, int32_t g0, uint32_t mask)
+template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_up_leaf(DevTree<P> t, uint32_t mask)
+{
+    up_leaf_body(t, xcd_remap(blockIdx.x, gridDim.x), mask);
+}
+
+template <class P> __device__ __forceinline__ void m2m_body(const DevTree<P> &t, int g, uint32_t mask)
 {
     extern __shared__ double xs[]; // both families' child coefficients
-    const int g = g0 + blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
     const auto &Fa = t.far;
     const auto &Ve = t.ver;
     const int cf = Fa.coef_off[g], rf = (mask & kFar) ? Fa.coef_off[g + 1] - cf : 0;
@@ -101,11 +111,16 @@ template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_
     }
 }
 
-template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_l2l(DevTree<P> t, int32_t g0, uint32_t mask)
+template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_m2m(DevTree<P> t, int32_t g0, uint32_t mask)
+{
+    m2m_body(t, g0 + (int)blockIdx.x, mask);
+}
+
+template <class P> __device__ __forceinline__ void l2l_body(const DevTree<P> &t, int g, uint32_t mask)
 {
     extern __shared__ double xs[]; // both families' parent locals
     constexpr bool ORD = P::ordered;
-    const int g = g0 + blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
     const auto &Fa = t.far;
     const auto &Ve = t.ver;
     const int cf = Fa.coef_off[g], rf = (mask & kFar) ? Fa.coef_off[g + 1] - cf : 0;
@@ -124,6 +139,11 @@ template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_
         const double s = ordered_dot<ORD>(A, (size_t)(f ? Rf : Rv), f ? rf : rv, f ? xs : xs + rf);
         *out = *out + s;
     }
+}
+
+template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_l2l(DevTree<P> t, int32_t g0, uint32_t mask)
+{
+    l2l_body(t, g0 + (int)blockIdx.x, mask);
 }
 
 // ---------------------------------------------------------------------------
@@ -286,8 +306,7 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t, int32_t t0)
 constexpr int NT_M2LS = 256;
 constexpr int M2LS_SRC = 512; // staged source pivots per group
 
-template <class P, bool FAR, int KIND, int D>
-__global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t, int32_t t0)
+template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2l_slices_body(const DevTree<P> &t, int ti)
 {
     const auto &F = [&]() -> const auto & {
         if constexpr (FAR) return t.far;
@@ -299,7 +318,7 @@ __global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t, int32_t t0
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
     const int tid = threadIdx.x;
     stage_table<KIND>(t.ktab, ktab); // first used after a barrier
-    const int g = F.targets[t0 + xcd_remap(blockIdx.x, gridDim.x)]; // targets t0 .. t0 + gridDim.x - 1
+    const int g = F.targets[ti];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
     const KPar<double> kp = kpar<double>(t);
@@ -379,6 +398,13 @@ __global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t, int32_t t0
     }
 }
 
+// targets t0 .. t0 + gridDim.x - 1 of the family
+template <class P, bool FAR, int KIND, int D>
+__global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t, int32_t t0)
+{
+    m2l_slices_body<P, FAR, KIND, D>(t, t0 + xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // (H2+H)*: partial sums over one row chunk of G^T q, G = Vb over the rows of
 // Y (side 0: w = Vb^T q_Y) or Ub over the rows of X (side 1: w' = Ub^T q_X).
@@ -432,8 +458,7 @@ constexpr int NT_P2P = 256;
 constexpr int P2P_SRC = 1024;     // staged source points per group
 constexpr int P2P_TPT = 4;        // targets per thread
 
-template <class P, int KIND, int D>
-__global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin, int32_t leaf_count)
+template <class P, int KIND, int D> __device__ __forceinline__ void p2p_body(const DevTree<P> &t, int leaf)
 {
     using PT = typename P::pt_t;
     constexpr bool TAB = sizeof(PT) == 8;
@@ -452,11 +477,8 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
     const PT diag = (PT)t.diag;
     const KPar<PT> kp = kpar<PT>(t);
     if constexpr (TAB) stage_table<KIND>(t.ktab, ktab); // first used after a barrier
-    // each block takes a contiguous chunk of leaves (one leaf when the grid covers them all)
-    const int chunk = (leaf_count + gridDim.x - 1) / gridDim.x, blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int l_end = min(leaf_count, (blk + 1) * chunk);
-    for (int lf = blk * chunk; lf < l_end; ++lf) {
-        const int leaf = leaf_begin + lf, g = t.leaf0 + leaf;
+    {
+        const int g = t.leaf0 + leaf;
         const int b = t.box_begin[g], n = t.box_end[g] - b;
         const double *cX = t.box_ctr + 3 * g;
         for (int i0 = 0; i0 < n; i0 += TPT * NT_P2P) {
@@ -574,6 +596,14 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
     }
 }
 
+// leaves leaf_begin .. leaf_begin + gridDim.x - 1, one per block
+template <class P, int KIND, int D>
+__global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin, int32_t leaf_count)
+{
+    (void)leaf_count; // == gridDim.x
+    p2p_body<P, KIND, D>(t, leaf_begin + xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // Leaf pass down: near field + shift q, L2P (in index order), the (H2+H)*
 // vertex blocks, sum and scatter to user order.  One thread per point.
@@ -581,13 +611,13 @@ __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin
 constexpr int NT_LEAF = 128;
 
 template <class P>
-__global__ __launch_bounds__(NT_LEAF, GEMV_WAVES) void k_down_leaf(DevTree<P> t, double *__restrict__ y, uint32_t mask)
+__device__ __forceinline__ void down_leaf_body(const DevTree<P> &t, int leaf, double *__restrict__ y, uint32_t mask)
 {
     constexpr bool ORD = P::ordered;
     constexpr int HALF = NT_LEAF / 2;
     using BT = typename P::basis_t;
     __shared__ double ver_part[HALF];
-    const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf;
+    const int g = t.leaf0 + leaf;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
     // threads [0, HALF) take the far family of point i, [HALF, NT_LEAF) the vertex family
     const int f = threadIdx.x < HALF ? 0 : 1, il = threadIdx.x - f * HALF;
@@ -629,6 +659,108 @@ __global__ __launch_bounds__(NT_LEAF, GEMV_WAVES) void k_down_leaf(DevTree<P> t,
         }
         __syncthreads();
     }
+}
+
+template <class P>
+__global__ __launch_bounds__(NT_LEAF, GEMV_WAVES) void k_down_leaf(DevTree<P> t, double *__restrict__ y, uint32_t mask)
+{
+    down_leaf_body(t, xcd_remap(blockIdx.x, gridDim.x), y, mask);
+}
+
+// ---------------------------------------------------------------------------
+// Many trees in one launch per step (MultiPlan): block b takes work item
+// map[b].y of tree map[b].x; the tree's description is copied from device
+// memory (uniform over the block, so it lands in scalar registers) and the
+// single-tree body runs on it, so every output is the one h2s_apply gives.
+// ---------------------------------------------------------------------------
+template <class P>
+__global__ __launch_bounds__(256) void km_permute(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map,
+                                                  const double *const *__restrict__ xs)
+{
+    const int2 w = map[blockIdx.x];
+    const DevTree<P> t = trees[w.x];
+    permute_body(t, xs[w.x], w.y);
+}
+
+template <class P>
+__global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void km_up_leaf(const DevTree<P> *__restrict__ trees,
+                                                                       const int2 *__restrict__ map)
+{
+    const int2 w = map[xcd_remap(blockIdx.x, gridDim.x)];
+    const DevTree<P> t = trees[w.x];
+    up_leaf_body(t, w.y, kFar | kVer);
+}
+
+template <class P>
+__global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void km_m2m(const DevTree<P> *__restrict__ trees,
+                                                                   const int2 *__restrict__ map)
+{
+    const int2 w = map[blockIdx.x];
+    const DevTree<P> t = trees[w.x];
+    m2m_body(t, w.y, kFar | kVer);
+}
+
+template <class P>
+__global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void km_l2l(const DevTree<P> *__restrict__ trees,
+                                                                   const int2 *__restrict__ map)
+{
+    const int2 w = map[blockIdx.x];
+    const DevTree<P> t = trees[w.x];
+    l2l_body(t, w.y, kFar | kVer);
+}
+
+template <class P, bool FAR, int KIND, int D>
+__global__ __launch_bounds__(NT_M2LS) void km_m2l(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map)
+{
+    const int2 w = map[xcd_remap(blockIdx.x, gridDim.x)];
+    const DevTree<P> t = trees[w.x];
+    m2l_slices_body<P, FAR, KIND, D>(t, w.y);
+}
+
+template <class P, int KIND, int D>
+__global__ __launch_bounds__(NT_P2P) void km_p2p(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map)
+{
+    const int2 w = map[xcd_remap(blockIdx.x, gridDim.x)];
+    const DevTree<P> t = trees[w.x];
+    p2p_body<P, KIND, D>(t, w.y);
+}
+
+// (no waves-per-SIMD bound: under the single-tree bound this one spills)
+template <class P>
+__global__ __launch_bounds__(NT_LEAF) void km_down_leaf(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map,
+                                                        double *const *__restrict__ ys)
+{
+    const int2 w = map[xcd_remap(blockIdx.x, gridDim.x)];
+    const DevTree<P> t = trees[w.x];
+    down_leaf_body(t, w.y, ys[w.x], kNear | kFar | kVer);
+}
+
+// The steps of MultiPlan on st.main, the near field on st.aux (forked after
+// the permutation, joined before L2P).
+template <class P, int KIND, int D> hipError_t enqueue_multi(const MultiPlan<P> &mp, const Streams &st)
+{
+    hipStream_t s = (hipStream_t)st.main, aux = (hipStream_t)st.aux;
+    hipError_t err;
+    if (mp.n_perm) hipLaunchKernelGGL(km_permute<P>, dim3(mp.n_perm), dim3(256), 0, s, mp.trees, mp.perm_map, mp.xs);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = hipEventRecord((hipEvent_t)st.fork, s)) != hipSuccess) return err;
+    if ((err = hipStreamWaitEvent(aux, (hipEvent_t)st.fork, 0)) != hipSuccess) return err;
+    if (mp.n_leaf) hipLaunchKernelGGL((km_p2p<P, KIND, D>), dim3(mp.n_leaf), dim3(NT_P2P), 0, aux, mp.trees, mp.leaf_map);
+    if ((err = hipEventRecord((hipEvent_t)st.join, aux)) != hipSuccess) return err;
+    if (mp.n_up) hipLaunchKernelGGL(km_up_leaf<P>, dim3(mp.n_up), dim3(mp.w_up), mp.lds_leaf, s, mp.trees, mp.up_map);
+    for (int k = 0; k < mp.steps; ++k)
+        if (mp.n_m2m[k])
+            hipLaunchKernelGGL(km_m2m<P>, dim3(mp.n_m2m[k]), dim3(mp.w_m2m[k]), mp.lds_rows, s, mp.trees, mp.m2m_map[k]);
+    if (mp.n_far)
+        hipLaunchKernelGGL((km_m2l<P, true, KIND, D>), dim3(mp.n_far), dim3(NT_M2LS), 0, s, mp.trees, mp.far_map);
+    if (mp.n_ver)
+        hipLaunchKernelGGL((km_m2l<P, false, KIND, D>), dim3(mp.n_ver), dim3(NT_M2LS), 0, s, mp.trees, mp.ver_map);
+    for (int k = 0; k < mp.steps; ++k)
+        if (mp.n_l2l[k])
+            hipLaunchKernelGGL(km_l2l<P>, dim3(mp.n_l2l[k]), dim3(mp.w_l2l[k]), mp.lds_rank, s, mp.trees, mp.l2l_map[k]);
+    if ((err = hipStreamWaitEvent(s, (hipEvent_t)st.join, 0)) != hipSuccess) return err;
+    if (mp.n_leaf) hipLaunchKernelGGL(km_down_leaf<P>, dim3(mp.n_leaf), dim3(NT_LEAF), 0, s, mp.trees, mp.leaf_map, mp.ys);
+    return hipGetLastError();
 }
 
 template <class P, int KIND, int D>
@@ -771,6 +903,29 @@ int launch_mvp(const DevTree<P> &t, const LaunchPlan &plan, const double *x, dou
     default: return (int)hipErrorInvalidValue;
     }
 }
+
+template <class P> int launch_multi(int kind, int d, const MultiPlan<P> &mp, const Streams &s)
+{
+    switch (kind * 2 + (d == 3)) {
+    case 0: return (int)enqueue_multi<P, H2S_K_LOG_R, 2>(mp, s);
+    case 1: return (int)enqueue_multi<P, H2S_K_LOG_R, 3>(mp, s);
+    case 2: return (int)enqueue_multi<P, H2S_K_INV_R, 2>(mp, s);
+    case 3: return (int)enqueue_multi<P, H2S_K_INV_R, 3>(mp, s);
+    case 4: return (int)enqueue_multi<P, H2S_K_GAUSSIAN, 2>(mp, s);
+    case 5: return (int)enqueue_multi<P, H2S_K_GAUSSIAN, 3>(mp, s);
+    case 6: return (int)enqueue_multi<P, H2S_K_EXP_R, 2>(mp, s);
+    case 7: return (int)enqueue_multi<P, H2S_K_EXP_R, 3>(mp, s);
+    case 8: return (int)enqueue_multi<P, H2S_K_RBF_AR, 2>(mp, s);
+    case 9: return (int)enqueue_multi<P, H2S_K_RBF_AR, 3>(mp, s);
+    case 10: return (int)enqueue_multi<P, H2S_K_RBF_LOG, 2>(mp, s);
+    case 11: return (int)enqueue_multi<P, H2S_K_RBF_LOG, 3>(mp, s);
+    case 13: return (int)enqueue_multi<P, H2S_K_NTI_MQ, 3>(mp, s);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+template int launch_multi<P64>(int, int, const MultiPlan<P64> &, const Streams &);
+template int launch_multi<P32>(int, int, const MultiPlan<P32> &, const Streams &);
 
 template int launch_mvp<P64>(const DevTree<P64> &, const LaunchPlan &, const double *, double *, uint32_t, const Streams &,
                              const ProfileHook *);

@@ -63,6 +63,43 @@ def test_group_equals_each_tree(lib, inputs):
     G.free()
 
 
+
+def test_fused_classes_equal_each_tree(lib, inputs):
+    """Trees of one precision, kernel function and dimension run fused (one launch per step for
+    the whole class): classes of uneven sizes and depths, including kernel parameters that differ
+    between members, beside a lone tree that keeps its own graph."""
+    dev = torch.device("cuda:0")
+    specs = []
+    for i, n in enumerate((500, 1200, 4096, 9000, 20000, 41000, 3000, 64, 15000, 700, 30000, 2500)):
+        specs.append((2, n, 0, 0.0, 0.0, 0, 64, 1e-8))              # FP64 log r, 2D
+    for i, n in enumerate((3000, 12000, 800, 26000, 5000, 9000)):
+        specs.append((3, n, 1, 0.0, 0.0, 1, 64, 1e-6))              # FP32 1/r, 3D
+    for i, (n, h) in enumerate(((2000, 0.2), (6000, 0.1), (4000, 0.3), (9000, 0.15))):
+        specs.append((2, n, 2, h, 1e-2, 0, 32, 1e-10))              # FP64 Gaussian, different h
+    for i, n in enumerate((3000, 8000, 1500)):
+        specs.append((3, n, 6, 0.0, 60.0, 0, 32, 1e-8))             # FP64 NTI multiquadric
+    specs.append((3, 7000, 3, 0.0, 0.0, 0, 48, 1e-10))              # a lone exp(-r) tree
+    trees, xs = [], []
+    for i, (d, n, kind, param, shift, prec, nmax, eps) in enumerate(specs):
+        trees.append(lib.build(inputs.uniform_points(n, d, 700 + i), kind=kind, leaf_size=nmax, eps=eps, prec=prec,
+                               param=param, shift=shift))
+        xs.append(torch.from_numpy(inputs.normal_rhs(n, 1, 800 + i)[:, 0]).to(dev))
+    refs = [T.apply(x).clone() for T, x in zip(trees, xs)]
+    torch.cuda.synchronize()
+    print(f"fused group of {len(trees)} trees", flush=True)
+    G = lib.Group(trees)
+    ys = [torch.zeros_like(x) for x in xs]
+    for rep in range(2):
+        G.apply(xs, ys)
+        torch.cuda.synchronize()
+        for i in range(len(trees)):
+            assert torch.equal(ys[i], refs[i]), (rep, i, specs[i])
+    ys2 = [torch.full_like(x, -1.0) for x in xs]  # other output vectors: the tables are refreshed
+    G.apply(xs, ys2)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(ys2, refs))
+    G.free()
+
 @pytest.mark.skip(reason="capturing the products of many trees as parallel branches of ONE HIP graph (a capture "
                          "origin stream forking one stream per tree, each forking its tree's near-field and M2L "
                          "streams) ended the host process with a segmentation fault inside the group apply, whose "

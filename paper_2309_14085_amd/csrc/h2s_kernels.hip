@@ -617,15 +617,20 @@ __device__ __forceinline__ void down_leaf_body(const DevTree<P> &t, int leaf, do
     constexpr int HALF = NT_LEAF / 2;
     using BT = typename P::basis_t;
     __shared__ double ver_part[HALF];
+    extern __shared__ double ucs[]; // the leaf's locals: far family, then vertex family
     const int g = t.leaf0 + leaf;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
+    const int cf = t.far.coef_off[g], cv = t.ver.coef_off[g];
+    const int rf = (mask & kFar) && t.kappa >= t.far.lmin ? t.far.coef_off[g + 1] - cf : 0;
+    const int rv = (mask & kVer) && t.kappa >= t.ver.lmin ? t.ver.coef_off[g + 1] - cv : 0;
+    for (int k = threadIdx.x; k < rf; k += NT_LEAF) ucs[k] = t.far.u[cf + k];
+    for (int k = threadIdx.x; k < rv; k += NT_LEAF) ucs[rf + k] = t.ver.u[cv + k];
+    __syncthreads();
     // threads [0, HALF) take the far family of point i, [HALF, NT_LEAF) the vertex family
     const int f = threadIdx.x < HALF ? 0 : 1, il = threadIdx.x - f * HALF;
-    const bool on = f == 0 ? (mask & kFar) && t.kappa >= t.far.lmin : (mask & kVer) && t.kappa >= t.ver.lmin;
-    const int c0 = f == 0 ? t.far.coef_off[g] : t.ver.coef_off[g];
-    const int r = on ? (f == 0 ? t.far.coef_off[g + 1] : t.ver.coef_off[g + 1]) - c0 : 0;
+    const int r = f == 0 ? rf : rv;
     const BT *U = f == 0 ? t.far.U_cm + t.far.uoff[leaf] : t.ver.U_cm + t.ver.uoff[leaf];
-    const double *uc = (f == 0 ? t.far.u : t.ver.u) + c0;
+    const double *uc = f == 0 ? ucs : ucs + rf;
     for (int i0 = 0; i0 < n; i0 += HALF) {
         const int i = i0 + il;
         double fam = 0.0;
@@ -759,7 +764,8 @@ template <class P, int KIND, int D> hipError_t enqueue_multi(const MultiPlan<P> 
         if (mp.n_l2l[k])
             hipLaunchKernelGGL(km_l2l<P>, dim3(mp.n_l2l[k]), dim3(mp.w_l2l[k]), mp.lds_rank, s, mp.trees, mp.l2l_map[k]);
     if ((err = hipStreamWaitEvent(s, (hipEvent_t)st.join, 0)) != hipSuccess) return err;
-    if (mp.n_leaf) hipLaunchKernelGGL(km_down_leaf<P>, dim3(mp.n_leaf), dim3(NT_LEAF), 0, s, mp.trees, mp.leaf_map, mp.ys);
+    if (mp.n_leaf)
+        hipLaunchKernelGGL(km_down_leaf<P>, dim3(mp.n_leaf), dim3(NT_LEAF), mp.lds_rank, s, mp.trees, mp.leaf_map, mp.ys);
     return hipGetLastError();
 }
 
@@ -872,7 +878,7 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
     if (overlap)
         if ((err = hipStreamWaitEvent(s, (hipEvent_t)st.join, 0)) != hipSuccess) return err;
     mark(H2S_PROF_LEAF_DOWN, 0, s);
-    hipLaunchKernelGGL(k_down_leaf<P>, dim3(t.nleaf), dim3(NT_LEAF), 0, s, t, y, mask);
+    hipLaunchKernelGGL(k_down_leaf<P>, dim3(t.nleaf), dim3(NT_LEAF), lds_rank, s, t, y, mask);
     mark(H2S_PROF_LEAF_DOWN, 1, s);
     return hipGetLastError();
 }

@@ -315,6 +315,7 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     G.ntargets = (int32_t)targets.size();
     G.targets_leaf = (int32_t)(std::lower_bound(targets.begin(), targets.end(), leaf0) - targets.begin());
     G.targets = up.copy(targets);
+    G.ncoef = (int32_t)nc;
     G.v = up.template zeros<double>(nc ? nc : 1);
     G.u = up.template zeros<double>(nc ? nc : 1);
     (void)kappa;
@@ -700,7 +701,7 @@ template <class P> h2s_status ensure_batch(h2s_tree t, h2s::DevTree<P> &D, int p
 {
     if (t->batch[p]) return H2S_OK;
     Uploader up{t, s};
-    const size_t nb = h2s::kBatch;
+    const size_t nb = (size_t)h2s::kBatch * h2s::kGroupBlocks; // kGroupBlocks blocks of kBatch columns
     D.qb = up.template zeros<double>((size_t)D.n * nb);
     D.ynb = up.template zeros<double>((size_t)D.n * nb);
     const size_t nf = (size_t)t->rep.fam[0].coef_off.back(), nv = (size_t)t->rep.fam[1].coef_off.back();
@@ -725,8 +726,8 @@ h2s_status apply_columns(h2s_tree t, h2s::DevTree<P> &D, int p, uint32_t mask, c
         if (nrhs > 1 && !prof && batch_supported(t, D)) {
             const h2s_status bs = ensure_batch(t, D, p, (hipStream_t)stream);
             if (bs != H2S_OK) return bs;
-            for (; c + 1 < nrhs; c += h2s::kBatch) {
-                const int na = std::min<int32_t>(h2s::kBatch, nrhs - c);
+            for (; c + 1 < nrhs; c += h2s::kGroupCols) {
+                const int na = std::min<int32_t>(h2s::kGroupCols, nrhs - c);
                 const int rc = h2s::launch_mvp_batch<P>(D, t->plan, x + c * ldx, ldx, y + c * ldy, ldy, na, mask, st);
                 if (rc != 0)
                     return fail(H2S_ERR_DEVICE,

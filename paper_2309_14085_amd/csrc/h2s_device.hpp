@@ -69,8 +69,9 @@ template <typename CT, typename BT> struct DevFamily {
     const int32_t *targets;      // boxes with rank > 0 at levels >= lmin, in box (so level) order
     int32_t ntargets;
     int32_t targets_leaf;        // index in targets of the first leaf-level box
+    int32_t ncoef;               // coefficients of the family (all boxes)
     double *v, *u;
-    double *vb, *ub;             // multi-RHS blocks: kBatch entries per coefficient (allocated on first use)
+    double *vb, *ub;             // multi-RHS: kGroupBlocks blocks of ncoef x kBatch (allocated on first use)
 };
 
 // (H2+H)* vertex-sharing low-rank blocks.
@@ -164,15 +165,19 @@ template <class P> struct MultiPlan {
 
 template <class P> int launch_multi(int kind, int d, const MultiPlan<P> &mp, const Streams &s);
 
-// Right-hand sides per block of the batched product.
+// Right-hand sides per block of the batched product, and blocks taken
+// through one launch sequence (their M2L shares each kernel evaluation).
 constexpr int kBatch = 8;
+constexpr int kGroupBlocks = 4;
+constexpr int kGroupCols = kBatch * kGroupBlocks;
 
-// Enqueue the product for na <= kBatch right-hand sides at once (x, y
-// column-major with leading dimensions ldx, ldy), ordered on st.main.  H2*
-// with a double far field only; the block buffers must be allocated.
+// Enqueue the product for ncols <= kGroupCols right-hand sides at once (x, y
+// column-major with leading dimensions ldx, ldy), ordered on st.main, as
+// ceil(ncols / kBatch) blocks of kBatch columns.  H2* with a double far field
+// only; the block buffers must be allocated.
 template <class P>
 int launch_mvp_batch(const DevTree<P> &t, const LaunchPlan &plan, const double *x, int64_t ldx, double *y,
-                     int64_t ldy, int na, uint32_t mask, const Streams &st);
+                     int64_t ldy, int ncols, uint32_t mask, const Streams &st);
 
 // Enqueue one product y = K~ x (single right-hand side), ordered on st.main.
 // Returns a hipError_t as int.

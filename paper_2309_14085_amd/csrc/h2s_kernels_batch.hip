@@ -229,6 +229,143 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
     }
 }
 
+// M2L in double on the matrix cores for up to kGroupBlocks blocks of kBatch
+// columns at once: u_X (r_X x cols) += sum over Y in IL(X) of T_XY V_Y, tiled
+// for v_mfma_f64_16x16x4f64 (D 16 x 16 += A 16 x 4 . B 4 x 16 per wave).  A
+// holds the kernel values of 16 target pivots against 4 staged sources, one
+// evaluation per lane (target lane % 16, source lane / 16); B the multipoles
+// of those sources for 16 columns (column lane % 16); D is 16 targets x 16
+// columns, lane l holding rows l / 16 + 4 q (q = 0..3) of column l % 16.  Two
+// column tiles share every evaluation, so one kernel value serves up to 32
+// columns: the vector units evaluate, the matrix cores multiply-add.  Tiles
+// of 16 targets go to the 4 waves; with fewer than 4 tiles the waves of a
+// tile split the 4-source steps and add their partial tiles in wave order.
+// Two accumulators per column tile take alternate steps (independent MFMAs).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int NT_BMM = 256;  // 4 waves
+constexpr int BMM_SRC = 128; // staged source pivots per group
+
+template <class P, bool FAR, int KIND, int D>
+__global__ __launch_bounds__(NT_BMM) void kb_m2l_mfma(DevTree<P> t, int nblk)
+{
+    constexpr int GC = kGroupCols;
+    static_assert(GC == 32, "two column tiles of 16");
+    const auto &F = [&]() -> const auto & {
+        if constexpr (FAR) return t.far;
+        else return t.ver;
+    }();
+    constexpr bool XW = kExtraCoord<KIND>;
+    __shared__ double sx[BMM_SRC], sy[BMM_SRC], sz[D == 3 ? BMM_SRC : 1], sw[XW ? BMM_SRC : 1];
+    __shared__ double sv[BMM_SRC * GC]; // after the last group: the waves' partial tiles
+    __shared__ __align__(16) double ktab[kTabLen<KIND>];
+    static_assert(BMM_SRC * GC >= 4 * 64 * 8, "partial tiles fit in the multipole buffer");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    stage_table<KIND>(t.ktab, ktab); // first used after a barrier
+    const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
+    const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
+    const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
+    const KPar<double> kp = kpar<double>(t);
+    const size_t bstride = (size_t)F.ncoef * NB; // one block's coefficients
+    const bool two = nblk * NB > 16;             // the second column tile holds active columns
+    const int ntiles = (r + 15) / 16;
+    if (ntiles == 0) return; // uniform over the block, before any barrier
+    const int ks = ntiles >= 3 ? 1 : 4 / ntiles; // waves per tile
+    const int per_round = 4 / ks;
+    for (int tb = 0; tb < ntiles; tb += per_round) {
+        const int tile = tb + wave / ks, part = wave % ks;
+        const bool act = tile < ntiles;
+        const int ia = tile * 16 + li;
+        const int ial = act && ia < r ? ia : 0; // rows past r use pivot 0 and are not written
+        const double xa = F.pvx[c0 + ial], ya = F.pvy[c0 + ial], za = D == 3 ? (double)F.pvz[c0 + ial] : 0.0;
+        const double wa = XW ? (double)F.pvw[c0 + ial] : 0.0;
+        dbl4 a00 = {0.0, 0.0, 0.0, 0.0}, a01 = a00, a10 = a00, a11 = a00; // [step parity][column tile]
+        int pos = 0;
+        auto flush = [&]() {
+            __syncthreads();
+            if (act) {
+                // this wave's 4-source steps: part, part + ks, ... (two per iteration)
+                for (int j0 = 4 * part; j0 < pos; j0 += 8 * ks) {
+                    const int ja = j0 + lk, jb = j0 + 4 * ks + lk;
+                    double ka = 0.0, kb = 0.0, va0 = 0.0, va1 = 0.0, vb0 = 0.0, vb1 = 0.0;
+                    if (ja < pos) {
+                        ka = kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - sx[ja], ya - sy[ja],
+                                                                              za - (D == 3 ? sz[ja] : 0.0)),
+                                                             wa, XW ? sw[ja] : 0.0),
+                                            kp, ktab);
+                        va0 = sv[ja * GC + li];
+                        va1 = sv[ja * GC + 16 + li];
+                    }
+                    if (jb < pos) {
+                        kb = kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - sx[jb], ya - sy[jb],
+                                                                              za - (D == 3 ? sz[jb] : 0.0)),
+                                                             wa, XW ? sw[jb] : 0.0),
+                                            kp, ktab);
+                        vb0 = sv[jb * GC + li];
+                        vb1 = sv[jb * GC + 16 + li];
+                    }
+                    a00 = __builtin_amdgcn_mfma_f64_16x16x4f64(ka, va0, a00, 0, 0, 0);
+                    a10 = __builtin_amdgcn_mfma_f64_16x16x4f64(kb, vb0, a10, 0, 0, 0);
+                    if (two) {
+                        a01 = __builtin_amdgcn_mfma_f64_16x16x4f64(ka, va1, a01, 0, 0, 0);
+                        a11 = __builtin_amdgcn_mfma_f64_16x16x4f64(kb, vb1, a11, 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+            pos = 0;
+        };
+        for (int e = e0; e < e1; ++e) {
+            const int y = F.il_idx[e];
+            const int cy = F.coef_off[y], ry = F.coef_off[y + 1] - cy;
+            for (int j0 = 0; j0 < ry;) {
+                const int take = min(ry - j0, BMM_SRC - pos);
+                for (int j = tid; j < take; j += NT_BMM) {
+                    sx[pos + j] = F.pvx[cy + j0 + j];
+                    sy[pos + j] = F.pvy[cy + j0 + j];
+                    if constexpr (D == 3) sz[pos + j] = F.pvz[cy + j0 + j];
+                    if constexpr (XW) sw[pos + j] = F.pvw[cy + j0 + j];
+                }
+                // multipoles of the staged sources, column gc = block * kBatch + c; absent blocks read as 0
+                for (int e2 = tid; e2 < take * GC; e2 += NT_BMM) {
+                    const int jj = e2 / GC, gc = e2 % GC, bk = gc / NB, c = gc % NB;
+                    sv[(pos + jj) * GC + gc] = bk < nblk ? F.vb[bk * bstride + (size_t)(cy + j0 + jj) * NB + c] : 0.0;
+                }
+                pos += take;
+                j0 += take;
+                if (pos == BMM_SRC) flush();
+            }
+        }
+        if (pos > 0) flush(); // ends with a barrier (or nothing was staged): sv is free
+        const dbl4 t0 = a00 + a10, t1 = a01 + a11;
+        if (ks > 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                sv[(wave * 64 + lane) * 8 + q] = t0[q];
+                sv[(wave * 64 + lane) * 8 + 4 + q] = t1[q];
+            }
+            __syncthreads();
+        }
+        if (act && part == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double u0 = t0[q], u1 = t1[q];
+                for (int w2 = 1; w2 < ks; ++w2) {
+                    u0 += sv[((wave + w2) * 64 + lane) * 8 + q];
+                    u1 += sv[((wave + w2) * 64 + lane) * 8 + 4 + q];
+                }
+                const int i = tile * 16 + lk + 4 * q;
+                if (i < r) {
+                    const int b0 = li / NB, b1 = (16 + li) / NB, c = li % NB;
+                    if (b0 < nblk) F.ub[b0 * bstride + (size_t)(c0 + i) * NB + c] = u0;
+                    if (two && b1 < nblk) F.ub[b1 * bstride + (size_t)(c0 + i) * NB + c] = u1;
+                }
+            }
+        }
+        if (ks > 1) __syncthreads();
+    }
+}
+
 // Near field (as k_p2p), kBatch columns per evaluation; one target per thread.
 constexpr int NT_BP = 256;
 constexpr int BP_SRC = 512;
@@ -383,39 +520,69 @@ __global__ __launch_bounds__(NT_BL) void kb_down_leaf(DevTree<P> t, double *__re
 
 template <class P, int KIND, int D>
 hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *x, int64_t ldx, double *y,
-                     int64_t ldy, int na, uint32_t mask, const Streams &st)
+                     int64_t ldy, int ncols, uint32_t mask, const Streams &st)
 {
     hipStream_t s = (hipStream_t)st.main, aux = (hipStream_t)st.aux;
     const int32_t *lev_off = plan.lev_off;
     const bool fam_on = (mask & (kFar | kVer)) && t.kappa >= 1;
-    hipLaunchKernelGGL(kb_permute<P>, dim3((t.n + 255) / 256), dim3(256), 0, s, t, x, ldx, na);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    // the near field on the second stream, beside the whole sweep
     const bool near = (mask & kNear) != 0;
-    if (near) {
-        if ((err = hipEventRecord((hipEvent_t)st.fork, s)) != hipSuccess) return err;
-        if ((err = hipStreamWaitEvent(aux, (hipEvent_t)st.fork, 0)) != hipSuccess) return err;
-        hipLaunchKernelGGL((kb_p2p<P, KIND, D>), dim3(t.nleaf), dim3(NT_BP), 0, aux, t, 0);
-        if ((err = hipEventRecord((hipEvent_t)st.join, aux)) != hipSuccess) return err;
+    const int nblk = (ncols + NB - 1) / NB;
+    // one description per block of kBatch columns: the same tree, that block's buffers
+    DevTree<P> tb[kGroupBlocks];
+    for (int k = 0; k < nblk; ++k) {
+        tb[k] = t;
+        tb[k].qb = t.qb + (size_t)k * t.n * NB;
+        tb[k].ynb = t.ynb + (size_t)k * t.n * NB;
+        tb[k].far.vb = t.far.vb + (size_t)k * t.far.ncoef * NB;
+        tb[k].far.ub = t.far.ub + (size_t)k * t.far.ncoef * NB;
+        tb[k].ver.vb = t.ver.vb + (size_t)k * t.ver.ncoef * NB;
+        tb[k].ver.ub = t.ver.ub + (size_t)k * t.ver.ncoef * NB;
     }
+    auto active = [&](int k) { return min(NB, ncols - k * NB); };
+    hipError_t err;
+    // up: permutation, near field (second stream), P2M and M2M block by block
+    for (int k = 0; k < nblk; ++k) {
+        hipLaunchKernelGGL(kb_permute<P>, dim3((t.n + 255) / 256), dim3(256), 0, s, tb[k], x + (size_t)k * NB * ldx, ldx,
+                           active(k));
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if (near) {
+            if ((err = hipEventRecord((hipEvent_t)st.fork, s)) != hipSuccess) return err;
+            if ((err = hipStreamWaitEvent(aux, (hipEvent_t)st.fork, 0)) != hipSuccess) return err;
+            hipLaunchKernelGGL((kb_p2p<P, KIND, D>), dim3(t.nleaf), dim3(NT_BP), 0, aux, tb[k], 0);
+        }
+        if (fam_on) {
+            hipLaunchKernelGGL(kb_up_leaf<P>, dim3(t.nleaf), dim3(NT_BG), 0, s, tb[k], mask);
+            for (int l = t.kappa - 1; l >= 1; --l) {
+                const int nb = lev_off[l + 1] - lev_off[l];
+                if (nb) hipLaunchKernelGGL(kb_m2m<P>, dim3(nb), dim3(NT_BG), 0, s, tb[k], lev_off[l], mask);
+            }
+        }
+    }
+    if (near && (err = hipEventRecord((hipEvent_t)st.join, aux)) != hipSuccess) return err;
     if (fam_on) {
-        hipLaunchKernelGGL(kb_up_leaf<P>, dim3(t.nleaf), dim3(NT_BG), 0, s, t, mask);
-        for (int l = t.kappa - 1; l >= 1; --l) {
-            const int nb = lev_off[l + 1] - lev_off[l];
-            if (nb) hipLaunchKernelGGL(kb_m2m<P>, dim3(nb), dim3(NT_BG), 0, s, t, lev_off[l], mask);
+        // M2L: one launch per family for every block (matrix cores when two or more blocks share it)
+        if ((mask & kFar) && t.far.ntargets) {
+            if (nblk > 1)
+                hipLaunchKernelGGL((kb_m2l_mfma<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_BMM), 0, s, t, nblk);
+            else
+                hipLaunchKernelGGL((kb_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_BM), 0, s, tb[0]);
         }
-        if ((mask & kFar) && t.far.ntargets)
-            hipLaunchKernelGGL((kb_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_BM), 0, s, t);
-        if ((mask & kVer) && t.ver.ntargets)
-            hipLaunchKernelGGL((kb_m2l<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_BM), 0, s, t);
-        for (int l = 1; l <= t.kappa - 1; ++l) {
-            const int nb = lev_off[l + 1] - lev_off[l];
-            if (nb) hipLaunchKernelGGL(kb_l2l<P>, dim3(nb), dim3(NT_BG), 0, s, t, lev_off[l], mask);
+        if ((mask & kVer) && t.ver.ntargets) {
+            if (nblk > 1)
+                hipLaunchKernelGGL((kb_m2l_mfma<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_BMM), 0, s, t, nblk);
+            else
+                hipLaunchKernelGGL((kb_m2l<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_BM), 0, s, tb[0]);
         }
+        for (int k = 0; k < nblk; ++k)
+            for (int l = 1; l <= t.kappa - 1; ++l) {
+                const int nb = lev_off[l + 1] - lev_off[l];
+                if (nb) hipLaunchKernelGGL(kb_l2l<P>, dim3(nb), dim3(NT_BG), 0, s, tb[k], lev_off[l], mask);
+            }
     }
     if (near && (err = hipStreamWaitEvent(s, (hipEvent_t)st.join, 0)) != hipSuccess) return err;
-    hipLaunchKernelGGL(kb_down_leaf<P>, dim3(t.nleaf), dim3(NT_BL), 0, s, t, y, ldy, na, mask);
+    for (int k = 0; k < nblk; ++k)
+        hipLaunchKernelGGL(kb_down_leaf<P>, dim3(t.nleaf), dim3(NT_BL), 0, s, tb[k], y + (size_t)k * NB * ldy, ldy,
+                           active(k), mask);
     return hipGetLastError();
 }
 
@@ -423,7 +590,7 @@ hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *
 
 template <class P>
 int launch_mvp_batch(const DevTree<P> &t, const LaunchPlan &plan, const double *x, int64_t ldx, double *y,
-                     int64_t ldy, int na, uint32_t mask, const Streams &s)
+                     int64_t ldy, int na, uint32_t mask, const Streams &s) // na: columns, at most kGroupCols
 {
     const int key = t.kind * 2 + (t.d == 3);
     switch (key) {

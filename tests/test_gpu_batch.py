@@ -60,7 +60,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("m", [3, 8, 11])
+@pytest.mark.parametrize("m", [3, 8, 11, 20, 32, 40])
 def test_batched_fp64_matches_oracle_per_column(lib, orc, inputs, case, m):
     name, d, n, kind, nmax, eps, param, shift, seed = case
     print(f"batched {name} m={m}", flush=True)
@@ -87,9 +87,12 @@ def test_batched_phases_match_oracle_parts(lib, orc, inputs):
             assert rel(Y[:, c], parts[c][idx]) <= 1e-12, (mask, c)
 
 
-def test_batched_agrees_with_single_column_path(lib, inputs):
-    n, m = 20000, 8
-    print("batched vs single", flush=True)
+@pytest.mark.parametrize("m", [8, 32])
+def test_batched_agrees_with_single_column_path(lib, inputs, m):
+    """8 columns: one block (M2L on the vector units); 32: four blocks sharing every M2L kernel
+    value on the matrix cores."""
+    n = 20000
+    print(f"batched vs single m={m}", flush=True)
     pts = inputs.uniform_points(n, 2, 67)
     Q = inputs.normal_rhs(n, m, 68)
     T = lib.build(pts, kind=0, leaf_size=64, eps=1e-8)

@@ -308,6 +308,8 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     std::vector<int32_t> ilo(nbox + 1);
     for (int32_t g = 0; g <= nbox; ++g) ilo[g] = (int32_t)r.list_off[w][g];
     G.il_off = up.copy(ilo);
+    G.max_il = 0;
+    for (int32_t g = 0; g < nbox; ++g) G.max_il = std::max(G.max_il, ilo[g + 1] - ilo[g]);
     G.il_idx = up.copy(r.list_idx[w]);
     std::vector<int32_t> targets;
     for (int32_t g = 0; g < nbox; ++g)

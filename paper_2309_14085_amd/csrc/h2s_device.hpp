@@ -66,6 +66,7 @@ template <typename CT, typename BT> struct DevFamily {
     const int64_t *troff;        // per global box
     const int32_t *il_off;       // nbox + 1
     const int32_t *il_idx;
+    int32_t max_il;              // longest interaction list
     const int32_t *targets;      // boxes with rank > 0 at levels >= lmin, in box (so level) order
     int32_t ntargets;
     int32_t targets_leaf;        // index in targets of the first leaf-level box

@@ -127,6 +127,141 @@ template <class P> __global__ __launch_bounds__(NT_BG) void kb_l2l(DevTree<P> t,
     }
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// M2M and L2L of every column block at once, on the FP64 matrix cores: one wave per (box, row
+// tile of 16 outputs), 16x16x4 products over the contraction index in index order, one 16-column
+// tile per product (two for more than 16 columns).  A transfer is read once for all columns; the
+// column blocks share it.  Operand layouts: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
+// the result holds rows l / 16 + 4 q of column l % 16.
+constexpr int NT_BT = 64;
+
+// out (rows x cols) = A (rows x K) * B (K x cols), A[i][k] = a[k * lda_k + i * lda_i], B[k] of
+// column n at b_n[k * NB]; rows past `rows` and columns of absent blocks are neither read nor written
+struct TileIO {
+    const double *a;
+    size_t lda_k, lda_i;
+    const double *b;  // the first column block's B[0][0]
+    double *out;      // the first column block's out[0][0]
+    size_t bstride;   // one column block to the next, in B and out
+    int rows, K, nblk;
+    bool add;         // out += A B instead of out = A B
+};
+
+// Every load is issued unconditionally (absent rows and column blocks read row 0 and block 0)
+// and masked after, so that the unrolled steps keep their loads in flight together.
+template <bool TWO> __device__ __forceinline__ void tile_product_t(const TileIO &io, int tile)
+{
+    constexpr int U = 4; // 4-term steps per iteration
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int i = tile * 16 + li;
+    const bool iok = i < io.rows;
+    const int n0 = li, n1 = 16 + li; // columns of the two tiles
+    const bool ok0 = n0 / NB < io.nblk, ok1 = TWO && n1 / NB < io.nblk;
+    const double *B0 = io.b + (ok0 ? (size_t)(n0 / NB) * io.bstride : 0) + n0 % NB;
+    const double *B1 = io.b + (ok1 ? (size_t)(n1 / NB) * io.bstride : 0) + n1 % NB;
+    const double *A = io.a + (size_t)(iok ? i : 0) * io.lda_i;
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    const int Kf = io.K & ~(4 * U - 1);
+    for (int k0 = 0; k0 < Kf; k0 += 4 * U) {
+        double a[U], b0[U], b1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t k = (size_t)(k0 + 4 * u + lk);
+            a[u] = A[k * io.lda_k];
+            b0[u] = B0[k * NB];
+            if constexpr (TWO) b1[u] = B1[k * NB];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double au = iok ? a[u] : 0.0;
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(au, ok0 ? b0[u] : 0.0, acc0, 0, 0, 0);
+            if constexpr (TWO) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(au, ok1 ? b1[u] : 0.0, acc1, 0, 0, 0);
+        }
+    }
+    for (int k0 = Kf; k0 < io.K; k0 += 4) { // the remaining terms, 4 at a time
+        const int k = k0 + lk;
+        const bool kok = k < io.K;
+        const size_t kc = (size_t)(kok ? k : 0);
+        const double a = A[kc * io.lda_k], b0 = B0[kc * NB];
+        const double au = iok && kok ? a : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(au, ok0 ? b0 : 0.0, acc0, 0, 0, 0);
+        if constexpr (TWO) {
+            const double b1 = B1[kc * NB];
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(au, ok1 ? b1 : 0.0, acc1, 0, 0, 0);
+        }
+    }
+    double *O0 = io.out + (size_t)(n0 / NB) * io.bstride + n0 % NB;
+    double *O1 = io.out + (size_t)(n1 / NB) * io.bstride + n1 % NB;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int row = tile * 16 + lk + 4 * q;
+        if (row < io.rows) {
+            if (ok0) O0[(size_t)row * NB] = io.add ? O0[(size_t)row * NB] + acc0[q] : acc0[q];
+            if (ok1) O1[(size_t)row * NB] = io.add ? O1[(size_t)row * NB] + acc1[q] : acc1[q];
+        }
+    }
+}
+
+__device__ __forceinline__ void tile_product(const TileIO &io, int tile)
+{
+    if (io.nblk * NB > 16) tile_product_t<true>(io, tile);
+    else tile_product_t<false>(io, tile);
+}
+
+// M2M: the parent's multipoles (rank rows) = transfer^T (rank x children's coefficients) times
+// the children's multipoles.  Grid: (boxes of the level, row tiles of the largest rank).
+template <class P, bool FAR> __global__ __launch_bounds__(NT_BT) void kb_m2m_mfma(DevTree<P> t, int32_t g0, int nblk)
+{
+    const auto &F = [&]() -> const auto & {
+        if constexpr (FAR) return t.far;
+        else return t.ver;
+    }();
+    const int g = g0 + blockIdx.x, tile = blockIdx.y;
+    const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
+    if (tile * 16 >= r) return; // whole wave
+    const int b0 = F.coef_off[t.box_cbeg[g]], R = F.coef_off[t.box_cend[g]] - b0;
+    TileIO io;
+    io.a = F.Tr_rm + F.troff[g]; // R x r row-major: transfer^T[i][k] at k * r + i
+    io.lda_k = (size_t)r;
+    io.lda_i = 1;
+    io.b = F.vb + (size_t)b0 * NB;
+    io.out = F.vb + (size_t)c0 * NB;
+    io.bstride = (size_t)F.ncoef * NB;
+    io.rows = r;
+    io.K = R;
+    io.nblk = nblk;
+    io.add = false;
+    tile_product(io, tile);
+}
+
+// L2L: the children's locals (children's coefficients rows) += transfer (rows x rank) times the
+// parent's locals.  Grid: (boxes of the level, row tiles of the largest stacked transfer).
+template <class P, bool FAR> __global__ __launch_bounds__(NT_BT) void kb_l2l_mfma(DevTree<P> t, int32_t g0, int nblk)
+{
+    const auto &F = [&]() -> const auto & {
+        if constexpr (FAR) return t.far;
+        else return t.ver;
+    }();
+    const int g = g0 + blockIdx.x, tile = blockIdx.y;
+    const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
+    if (r == 0) return;
+    const int b0 = F.coef_off[t.box_cbeg[g]], R = F.coef_off[t.box_cend[g]] - b0;
+    if (tile * 16 >= R) return; // whole wave
+    TileIO io;
+    io.a = F.Tr_cm + F.troff[g]; // column-major R x r: transfer[i][k] at k * R + i
+    io.lda_k = (size_t)R;
+    io.lda_i = 1;
+    io.b = F.ub + (size_t)c0 * NB;
+    io.out = F.ub + (size_t)b0 * NB;
+    io.bstride = (size_t)F.ncoef * NB;
+    io.rows = R;
+    io.K = r;
+    io.nblk = nblk;
+    io.add = true;
+    tile_product(io, tile);
+}
+
 // M2L in double, slice form, kBatch columns per evaluation.  Each thread takes
 // BM_TPT target pivots (a, a + NP, ...) against one slice of the staged
 // sources, so the coordinates and the kBatch multipoles of a source, read
@@ -241,15 +376,18 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
 // of 16 targets go to the 4 waves; with fewer than 4 tiles the waves of a
 // tile split the 4-source steps and add their partial tiles in wave order.
 // Two accumulators per column tile take alternate steps (independent MFMAs).
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int NT_BMM = 256;  // 4 waves
-constexpr int BMM_SRC = 128; // staged source pivots per group
+constexpr int BMM_SRC = 64;  // staged source pivots per group
+constexpr int BMM_STEPS = 4; // 4-source product steps per iteration
+constexpr int BMM_IL = 256;  // interaction-list boxes the slot table holds (a list has at most 6^d boxes)
 
 template <class P, bool FAR, int KIND, int D>
-__global__ __launch_bounds__(NT_BMM) void kb_m2l_mfma(DevTree<P> t, int nblk)
+__global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(4))) void kb_m2l_mfma(DevTree<P> t, int nblk)
 {
     constexpr int GC = kGroupCols;
-    static_assert(GC == 32, "two column tiles of 16");
+    constexpr int TPS = NT_BMM / BMM_SRC, CPT = GC / TPS; // staging: threads per source, columns per thread
+    static_assert(GC == 32 && TPS * BMM_SRC == NT_BMM && CPT * TPS == GC, "staging covers a group exactly");
+    static_assert(BMM_SRC % (16 * BMM_STEPS) == 0 && BMM_STEPS % 2 == 0, "an iteration's steps stay inside a group");
     const auto &F = [&]() -> const auto & {
         if constexpr (FAR) return t.far;
         else return t.ver;
@@ -257,6 +395,8 @@ __global__ __launch_bounds__(NT_BMM) void kb_m2l_mfma(DevTree<P> t, int nblk)
     constexpr bool XW = kExtraCoord<KIND>;
     __shared__ double sx[BMM_SRC], sy[BMM_SRC], sz[D == 3 ? BMM_SRC : 1], sw[XW ? BMM_SRC : 1];
     __shared__ double sv[BMM_SRC * GC]; // after the last group: the waves' partial tiles
+    __shared__ int32_t boxoff[BMM_IL + 1], boxcoef[BMM_IL];
+    __shared__ double tx[64], ty[64], tz[D == 3 ? 64 : 1], tw[XW ? 64 : 1]; // the round's target pivots
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
     static_assert(BMM_SRC * GC >= 4 * 64 * 8, "partial tiles fit in the multipole buffer");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -264,79 +404,126 @@ __global__ __launch_bounds__(NT_BMM) void kb_m2l_mfma(DevTree<P> t, int nblk)
     stage_table<KIND>(t.ktab, ktab); // first used after a barrier
     const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
-    const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
+    const int e0 = F.il_off[g], nil = F.il_off[g + 1] - e0; // nil <= BMM_IL: longer lists take kb_m2l
     const KPar<double> kp = kpar<double>(t);
     const size_t bstride = (size_t)F.ncoef * NB; // one block's coefficients
     const bool two = nblk * NB > 16;             // the second column tile holds active columns
     const int ntiles = (r + 15) / 16;
     if (ntiles == 0) return; // uniform over the block, before any barrier
+    // the sources of IL(X) in list order as slots 0 .. S-1: slot s lies in list box e with
+    // boxoff[e] <= s < boxoff[e + 1], coefficient boxcoef[e] + s - boxoff[e]
+    for (int k = tid; k < nil; k += NT_BMM) {
+        const int y = F.il_idx[e0 + k];
+        boxcoef[k] = F.coef_off[y];
+        boxoff[k + 1] = F.coef_off[y + 1] - F.coef_off[y];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        boxoff[0] = 0;
+        for (int k = 1; k <= nil; ++k) boxoff[k] += boxoff[k - 1];
+    }
+    __syncthreads();
+    const int S = boxoff[nil], ngroups = (S + BMM_SRC - 1) / BMM_SRC;
+    auto coef_of = [&](int s) -> int {
+        int lo = 0, hi = nil - 1; // largest e with boxoff[e] <= s
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (boxoff[mid] <= s) lo = mid;
+            else hi = mid - 1;
+        }
+        return boxcoef[lo] + (s - boxoff[lo]);
+    };
+    // staging of a group of BMM_SRC slots: thread tid < BMM_SRC loads slot tid's coordinates,
+    // thread tid loads CPT of slot tid / TPS's 32 columns (prefetching the next group into
+    // registers during the products measured no faster and spilled)
+    double rx = 0.0, ry = 0.0, rz = 0.0, rw = 0.0, rv[CPT];
+    auto load = [&](int gi) {
+        // slots past the end of the list (last group only) repeat the group's first source
+        // with zero multipoles: every product step reads a full group and adds exact zeros
+        const int base = gi * BMM_SRC, take = min(BMM_SRC, S - base);
+        if (tid < BMM_SRC) {
+            const int c = coef_of(base + (tid < take ? tid : 0));
+            rx = F.pvx[c];
+            ry = F.pvy[c];
+            if constexpr (D == 3) rz = F.pvz[c];
+            if constexpr (XW) rw = F.pvw[c];
+        }
+        const int sl = tid / TPS, part = tid % TPS;
+        const int c = coef_of(base + (sl < take ? sl : 0));
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int gc = part * CPT + k, bk = gc / NB;
+            rv[k] = sl < take && bk < nblk ? F.vb[bk * bstride + (size_t)c * NB + gc % NB] : 0.0;
+        }
+    };
+    auto store = [&]() {
+        if (tid < BMM_SRC) {
+            sx[tid] = rx;
+            sy[tid] = ry;
+            if constexpr (D == 3) sz[tid] = rz;
+            if constexpr (XW) sw[tid] = rw;
+        }
+        const int sl = tid / TPS, part = tid % TPS;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) sv[sl * GC + part * CPT + k] = rv[k];
+    };
     const int ks = ntiles >= 3 ? 1 : 4 / ntiles; // waves per tile
     const int per_round = 4 / ks;
     for (int tb = 0; tb < ntiles; tb += per_round) {
         const int tile = tb + wave / ks, part = wave % ks;
         const bool act = tile < ntiles;
-        const int ia = tile * 16 + li;
-        const int ial = act && ia < r ? ia : 0; // rows past r use pivot 0 and are not written
-        const double xa = F.pvx[c0 + ial], ya = F.pvy[c0 + ial], za = D == 3 ? (double)F.pvz[c0 + ial] : 0.0;
-        const double wa = XW ? (double)F.pvw[c0 + ial] : 0.0;
+        // the round's rows tb * 16 .. through LDS (read once the first group is staged)
+        if (tid < 64) {
+            const int ia = tb * 16 + tid, ial = ia < r ? ia : 0; // rows past r use pivot 0, not written
+            tx[tid] = F.pvx[c0 + ial];
+            ty[tid] = F.pvy[c0 + ial];
+            if constexpr (D == 3) tz[tid] = F.pvz[c0 + ial];
+            if constexpr (XW) tw[tid] = F.pvw[c0 + ial];
+        }
+        double xa = 0.0, ya = 0.0, za = 0.0, wa = 0.0;
         dbl4 a00 = {0.0, 0.0, 0.0, 0.0}, a01 = a00, a10 = a00, a11 = a00; // [step parity][column tile]
-        int pos = 0;
-        auto flush = [&]() {
+        for (int gi = 0; gi < ngroups; ++gi) {
+            const int pos = min(BMM_SRC, S - gi * BMM_SRC);
+            __syncthreads(); // every wave is done with the previous group
+            load(gi);
+            store();
             __syncthreads();
-            if (act) {
-                // this wave's 4-source steps: part, part + ks, ... (two per iteration)
-                for (int j0 = 4 * part; j0 < pos; j0 += 8 * ks) {
-                    const int ja = j0 + lk, jb = j0 + 4 * ks + lk;
-                    double ka = 0.0, kb = 0.0, va0 = 0.0, va1 = 0.0, vb0 = 0.0, vb1 = 0.0;
-                    if (ja < pos) {
-                        ka = kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - sx[ja], ya - sy[ja],
-                                                                              za - (D == 3 ? sz[ja] : 0.0)),
-                                                             wa, XW ? sw[ja] : 0.0),
-                                            kp, ktab);
-                        va0 = sv[ja * GC + li];
-                        va1 = sv[ja * GC + 16 + li];
-                    }
-                    if (jb < pos) {
-                        kb = kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - sx[jb], ya - sy[jb],
-                                                                              za - (D == 3 ? sz[jb] : 0.0)),
-                                                             wa, XW ? sw[jb] : 0.0),
-                                            kp, ktab);
-                        vb0 = sv[jb * GC + li];
-                        vb1 = sv[jb * GC + 16 + li];
-                    }
-                    a00 = __builtin_amdgcn_mfma_f64_16x16x4f64(ka, va0, a00, 0, 0, 0);
-                    a10 = __builtin_amdgcn_mfma_f64_16x16x4f64(kb, vb0, a10, 0, 0, 0);
-                    if (two) {
-                        a01 = __builtin_amdgcn_mfma_f64_16x16x4f64(ka, va1, a01, 0, 0, 0);
-                        a11 = __builtin_amdgcn_mfma_f64_16x16x4f64(kb, vb1, a11, 0, 0, 0);
-                    }
-                }
+            if (gi == 0) {
+                const int row = (wave / ks) * 16 + li; // < 64
+                xa = tx[row];
+                ya = ty[row];
+                if constexpr (D == 3) za = tz[row];
+                if constexpr (XW) wa = tw[row];
             }
-            __syncthreads();
-            pos = 0;
-        };
-        for (int e = e0; e < e1; ++e) {
-            const int y = F.il_idx[e];
-            const int cy = F.coef_off[y], ry = F.coef_off[y + 1] - cy;
-            for (int j0 = 0; j0 < ry;) {
-                const int take = min(ry - j0, BMM_SRC - pos);
-                for (int j = tid; j < take; j += NT_BMM) {
-                    sx[pos + j] = F.pvx[cy + j0 + j];
-                    sy[pos + j] = F.pvy[cy + j0 + j];
-                    if constexpr (D == 3) sz[pos + j] = F.pvz[cy + j0 + j];
-                    if constexpr (XW) sw[pos + j] = F.pvw[cy + j0 + j];
+            if (act) {
+                // this wave's 4-source steps: part, part + ks, ... (BMM_STEPS per iteration, all inside
+                // the staged group since BMM_SRC is a multiple of 4 * BMM_STEPS * ks); step parity picks
+                // the accumulator
+                for (int j0 = 4 * part; j0 < pos; j0 += 4 * BMM_STEPS * ks) {
+                    double kv[BMM_STEPS], v0[BMM_STEPS], v1[BMM_STEPS];
+#pragma unroll
+                    for (int u = 0; u < BMM_STEPS; ++u) {
+                        const int j = j0 + 4 * ks * u + lk;
+                        v0[u] = sv[j * GC + li];
+                        v1[u] = sv[j * GC + 16 + li];
+                        kv[u] = kval_pos<KIND>(
+                            add_extra<KIND>(dist2<false, D>(xa - sx[j], ya - sy[j], za - (D == 3 ? sz[j] : 0.0)), wa,
+                                            XW ? sw[j] : 0.0),
+                            kp, ktab);
+                    }
+#pragma unroll
+                    for (int u = 0; u < BMM_STEPS; u += 2) {
+                        a00 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u], v0[u], a00, 0, 0, 0);
+                        a10 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u + 1], v0[u + 1], a10, 0, 0, 0);
+                        if (two) {
+                            a01 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u], v1[u], a01, 0, 0, 0);
+                            a11 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u + 1], v1[u + 1], a11, 0, 0, 0);
+                        }
+                    }
                 }
-                // multipoles of the staged sources, column gc = block * kBatch + c; absent blocks read as 0
-                for (int e2 = tid; e2 < take * GC; e2 += NT_BMM) {
-                    const int jj = e2 / GC, gc = e2 % GC, bk = gc / NB, c = gc % NB;
-                    sv[(pos + jj) * GC + gc] = bk < nblk ? F.vb[bk * bstride + (size_t)(cy + j0 + jj) * NB + c] : 0.0;
-                }
-                pos += take;
-                j0 += take;
-                if (pos == BMM_SRC) flush();
             }
         }
-        if (pos > 0) flush(); // ends with a barrier (or nothing was staged): sv is free
+        __syncthreads(); // every wave is done with sv
         const dbl4 t0 = a00 + a10, t1 = a01 + a11;
         if (ks > 1) {
 #pragma unroll
@@ -362,7 +549,7 @@ __global__ __launch_bounds__(NT_BMM) void kb_m2l_mfma(DevTree<P> t, int nblk)
                 }
             }
         }
-        if (ks > 1) __syncthreads();
+        __syncthreads(); // the partial tiles are read before the next round stages
     }
 }
 
@@ -527,6 +714,7 @@ hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *
     const bool fam_on = (mask & (kFar | kVer)) && t.kappa >= 1;
     const bool near = (mask & kNear) != 0;
     const int nblk = (ncols + NB - 1) / NB;
+    const bool mfma = nblk > 1; // transfers and M2L of all blocks per launch, on the matrix cores
     // one description per block of kBatch columns: the same tree, that block's buffers
     DevTree<P> tb[kGroupBlocks];
     for (int k = 0; k < nblk; ++k) {
@@ -552,32 +740,47 @@ hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *
         }
         if (fam_on) {
             hipLaunchKernelGGL(kb_up_leaf<P>, dim3(t.nleaf), dim3(NT_BG), 0, s, tb[k], mask);
-            for (int l = t.kappa - 1; l >= 1; --l) {
+            for (int l = t.kappa - 1; l >= 1 && !mfma; --l) {
                 const int nb = lev_off[l + 1] - lev_off[l];
                 if (nb) hipLaunchKernelGGL(kb_m2m<P>, dim3(nb), dim3(NT_BG), 0, s, tb[k], lev_off[l], mask);
             }
         }
     }
+    // several blocks: M2M of every block per launch, on the matrix cores
+    for (int l = t.kappa - 1; l >= 1 && fam_on && mfma; --l) {
+        const int nb = lev_off[l + 1] - lev_off[l];
+        const dim3 grid(nb, (t.max_rank + 15) / 16);
+        if (nb && (mask & kFar)) hipLaunchKernelGGL((kb_m2m_mfma<P, true>), grid, dim3(NT_BT), 0, s, t, lev_off[l], nblk);
+        if (nb && (mask & kVer)) hipLaunchKernelGGL((kb_m2m_mfma<P, false>), grid, dim3(NT_BT), 0, s, t, lev_off[l], nblk);
+    }
     if (near && (err = hipEventRecord((hipEvent_t)st.join, aux)) != hipSuccess) return err;
     if (fam_on) {
         // M2L: one launch per family for every block (matrix cores when two or more blocks share it)
         if ((mask & kFar) && t.far.ntargets) {
-            if (nblk > 1)
+            if (nblk > 1 && t.far.max_il <= BMM_IL)
                 hipLaunchKernelGGL((kb_m2l_mfma<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_BMM), 0, s, t, nblk);
             else
-                hipLaunchKernelGGL((kb_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_BM), 0, s, tb[0]);
+                for (int k = 0; k < nblk; ++k)
+                    hipLaunchKernelGGL((kb_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_BM), 0, s, tb[k]);
         }
         if ((mask & kVer) && t.ver.ntargets) {
-            if (nblk > 1)
+            if (nblk > 1 && t.ver.max_il <= BMM_IL)
                 hipLaunchKernelGGL((kb_m2l_mfma<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_BMM), 0, s, t, nblk);
             else
-                hipLaunchKernelGGL((kb_m2l<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_BM), 0, s, tb[0]);
+                for (int k = 0; k < nblk; ++k)
+                    hipLaunchKernelGGL((kb_m2l<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_BM), 0, s, tb[k]);
         }
-        for (int k = 0; k < nblk; ++k)
+        for (int k = 0; k < nblk && !mfma; ++k)
             for (int l = 1; l <= t.kappa - 1; ++l) {
                 const int nb = lev_off[l + 1] - lev_off[l];
                 if (nb) hipLaunchKernelGGL(kb_l2l<P>, dim3(nb), dim3(NT_BG), 0, s, tb[k], lev_off[l], mask);
             }
+        for (int l = 1; l <= t.kappa - 1 && mfma; ++l) {
+            const int nb = lev_off[l + 1] - lev_off[l];
+            const dim3 grid(nb, (t.max_rows + 15) / 16);
+            if (nb && (mask & kFar)) hipLaunchKernelGGL((kb_l2l_mfma<P, true>), grid, dim3(NT_BT), 0, s, t, lev_off[l], nblk);
+            if (nb && (mask & kVer)) hipLaunchKernelGGL((kb_l2l_mfma<P, false>), grid, dim3(NT_BT), 0, s, t, lev_off[l], nblk);
+        }
     }
     if (near && (err = hipStreamWaitEvent(s, (hipEvent_t)st.join, 0)) != hipSuccess) return err;
     for (int k = 0; k < nblk; ++k)

@@ -61,8 +61,7 @@ __device__ __forceinline__ void ordered_dot_b(const AT *__restrict__ A, size_t s
     }
 }
 
-// The vectors a block multiplies (a leaf's charges, the children's multipoles,
-// the parent's locals) are read by every thread at the same index, so they
+// P2M: the leaf's charges are read by every thread at the same index, so they
 // are read in place through the caches rather than staged.
 template <class P> __global__ __launch_bounds__(NT_BG) void kb_up_leaf(DevTree<P> t, uint32_t mask)
 {
@@ -80,50 +79,6 @@ template <class P> __global__ __launch_bounds__(NT_BG) void kb_up_leaf(DevTree<P
         ordered_dot_b<P::ordered>(A, (size_t)(f ? rf : rv), n, qs, acc);
 #pragma unroll
         for (int c = 0; c < NB; ++c) out[c] = acc[c];
-    }
-}
-
-template <class P> __global__ __launch_bounds__(NT_BG) void kb_m2m(DevTree<P> t, int32_t g0, uint32_t mask)
-{
-    const int g = g0 + blockIdx.x, tid = threadIdx.x;
-    const auto &Fa = t.far;
-    const auto &Ve = t.ver;
-    const int cf = Fa.coef_off[g], rf = (mask & kFar) ? Fa.coef_off[g + 1] - cf : 0;
-    const int cv = Ve.coef_off[g], rv = (mask & kVer) ? Ve.coef_off[g + 1] - cv : 0;
-    const int bf = Fa.coef_off[t.box_cbeg[g]], Rf = rf ? Fa.coef_off[t.box_cend[g]] - bf : 0;
-    const int bv = Ve.coef_off[t.box_cbeg[g]], Rv = rv ? Ve.coef_off[t.box_cend[g]] - bv : 0;
-    for (int k = tid; k < rf + rv; k += NT_BG) {
-        const bool f = k < rf;
-        const int kk = f ? k : k - rf;
-        const double *A = f ? Fa.Tr_rm + Fa.troff[g] + kk : Ve.Tr_rm + Ve.troff[g] + kk;
-        double *out = f ? Fa.vb + (size_t)(cf + kk) * NB : Ve.vb + (size_t)(cv + kk) * NB;
-        const double *xs = f ? Fa.vb + (size_t)bf * NB : Ve.vb + (size_t)bv * NB; // the children's multipoles
-        double acc[NB];
-        ordered_dot_b<P::ordered>(A, (size_t)(f ? rf : rv), f ? Rf : Rv, xs, acc);
-#pragma unroll
-        for (int c = 0; c < NB; ++c) out[c] = acc[c];
-    }
-}
-
-template <class P> __global__ __launch_bounds__(NT_BG) void kb_l2l(DevTree<P> t, int32_t g0, uint32_t mask)
-{
-    const int g = g0 + blockIdx.x, tid = threadIdx.x;
-    const auto &Fa = t.far;
-    const auto &Ve = t.ver;
-    const int cf = Fa.coef_off[g], rf = (mask & kFar) ? Fa.coef_off[g + 1] - cf : 0;
-    const int cv = Ve.coef_off[g], rv = (mask & kVer) ? Ve.coef_off[g + 1] - cv : 0;
-    const int bf = Fa.coef_off[t.box_cbeg[g]], Rf = rf ? Fa.coef_off[t.box_cend[g]] - bf : 0;
-    const int bv = Ve.coef_off[t.box_cbeg[g]], Rv = rv ? Ve.coef_off[t.box_cend[g]] - bv : 0;
-    for (int j = tid; j < Rf + Rv; j += NT_BG) {
-        const bool f = j < Rf;
-        const int jj = f ? j : j - Rf;
-        const double *A = f ? Fa.Tr_cm + Fa.troff[g] + jj : Ve.Tr_cm + Ve.troff[g] + jj;
-        double *out = f ? Fa.ub + (size_t)(bf + jj) * NB : Ve.ub + (size_t)(bv + jj) * NB;
-        const double *xs = f ? Fa.ub + (size_t)cf * NB : Ve.ub + (size_t)cv * NB; // the parent's locals
-        double acc[NB];
-        ordered_dot_b<P::ordered>(A, (size_t)(f ? Rf : Rv), f ? rf : rv, xs, acc);
-#pragma unroll
-        for (int c = 0; c < NB; ++c) out[c] = out[c] + acc[c];
     }
 }
 
@@ -714,7 +669,6 @@ hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *
     const bool fam_on = (mask & (kFar | kVer)) && t.kappa >= 1;
     const bool near = (mask & kNear) != 0;
     const int nblk = (ncols + NB - 1) / NB;
-    const bool mfma = nblk > 1; // transfers and M2L of all blocks per launch, on the matrix cores
     // one description per block of kBatch columns: the same tree, that block's buffers
     DevTree<P> tb[kGroupBlocks];
     for (int k = 0; k < nblk; ++k) {
@@ -728,7 +682,7 @@ hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *
     }
     auto active = [&](int k) { return min(NB, ncols - k * NB); };
     hipError_t err;
-    // up: permutation, near field (second stream), P2M and M2M block by block
+    // up: permutation, near field (second stream) and P2M block by block
     for (int k = 0; k < nblk; ++k) {
         hipLaunchKernelGGL(kb_permute<P>, dim3((t.n + 255) / 256), dim3(256), 0, s, tb[k], x + (size_t)k * NB * ldx, ldx,
                            active(k));
@@ -738,16 +692,10 @@ hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *
             if ((err = hipStreamWaitEvent(aux, (hipEvent_t)st.fork, 0)) != hipSuccess) return err;
             hipLaunchKernelGGL((kb_p2p<P, KIND, D>), dim3(t.nleaf), dim3(NT_BP), 0, aux, tb[k], 0);
         }
-        if (fam_on) {
-            hipLaunchKernelGGL(kb_up_leaf<P>, dim3(t.nleaf), dim3(NT_BG), 0, s, tb[k], mask);
-            for (int l = t.kappa - 1; l >= 1 && !mfma; --l) {
-                const int nb = lev_off[l + 1] - lev_off[l];
-                if (nb) hipLaunchKernelGGL(kb_m2m<P>, dim3(nb), dim3(NT_BG), 0, s, tb[k], lev_off[l], mask);
-            }
-        }
+        if (fam_on) hipLaunchKernelGGL(kb_up_leaf<P>, dim3(t.nleaf), dim3(NT_BG), 0, s, tb[k], mask);
     }
-    // several blocks: M2M of every block per launch, on the matrix cores
-    for (int l = t.kappa - 1; l >= 1 && fam_on && mfma; --l) {
+    // M2M of every block per launch, on the matrix cores
+    for (int l = t.kappa - 1; l >= 1 && fam_on; --l) {
         const int nb = lev_off[l + 1] - lev_off[l];
         const dim3 grid(nb, (t.max_rank + 15) / 16);
         if (nb && (mask & kFar)) hipLaunchKernelGGL((kb_m2m_mfma<P, true>), grid, dim3(NT_BT), 0, s, t, lev_off[l], nblk);
@@ -770,12 +718,8 @@ hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *
                 for (int k = 0; k < nblk; ++k)
                     hipLaunchKernelGGL((kb_m2l<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_BM), 0, s, tb[k]);
         }
-        for (int k = 0; k < nblk && !mfma; ++k)
-            for (int l = 1; l <= t.kappa - 1; ++l) {
-                const int nb = lev_off[l + 1] - lev_off[l];
-                if (nb) hipLaunchKernelGGL(kb_l2l<P>, dim3(nb), dim3(NT_BG), 0, s, tb[k], lev_off[l], mask);
-            }
-        for (int l = 1; l <= t.kappa - 1 && mfma; ++l) {
+        // L2L of every block per launch, on the matrix cores
+        for (int l = 1; l <= t.kappa - 1; ++l) {
             const int nb = lev_off[l + 1] - lev_off[l];
             const dim3 grid(nb, (t.max_rows + 15) / 16);
             if (nb && (mask & kFar)) hipLaunchKernelGGL((kb_l2l_mfma<P, true>), grid, dim3(NT_BT), 0, s, t, lev_off[l], nblk);

@@ -269,23 +269,67 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     G.pvy = up.copy(pvy);
     G.pvz = up.copy(pvz);
     G.pvw = up.copy(pvw);
-    // leaf bases: the host keeps U_X column-major (n_X x r); add the row-major copy
-    std::vector<int64_t> uoff(r.nleaf() + 1, 0);
-    for (int32_t lf = 0; lf < r.nleaf(); ++lf) uoff[lf + 1] = uoff[lf] + F.op_off[leaf0 + lf + 1] - F.op_off[leaf0 + lf];
-    std::vector<BT> ucm(uoff.back() ? uoff.back() : 1), urm(uoff.back() ? uoff.back() : 1);
-    for (int32_t lf = 0; lf < r.nleaf(); ++lf) {
-        const int32_t g = leaf0 + lf;
+    // leaf bases: the host keeps U_X column-major (n_X x r).  The row of U_X at the point of row
+    // pivot a is e_a (K(t, s) K(t, s)^-1, Sec. 3.4.3); rows that are exactly e_a are not stored:
+    // P2M adds the pivot's charge in the row's place and L2P copies the local.  The kept rows, in
+    // order, are stored column-major and row-major; ukeep[b + j] = local row of kept row j,
+    // urow[b + i] = kept index of local row i or ~a for the unit row of coefficient a, uprow[c] =
+    // local row of coefficient c's unit row or -1, upos[c] = kept rows before that row.
+    const int32_t nleaf = r.nleaf();
+    const size_t npt = (size_t)r.n;
+    std::vector<uint16_t> ukeep(npt ? npt : 1, 0);
+    std::vector<int16_t> urow(npt ? npt : 1, 0), uprow(nc ? nc : 1, -1), upos(nc ? nc : 1, 0);
+    std::vector<int32_t> unk(nleaf ? nleaf : 1, 0);
+    std::vector<int64_t> uoff(nleaf + 1, 0);
+    for (int32_t lf = 0; lf < nleaf; ++lf) {
+        const int32_t g = leaf0 + lf, b = r.box_begin[g];
         const int64_t rk = F.rank[g], nx = F.op_rows[g];
         const double *src = F.op.data() + F.op_off[g];
+        std::vector<int> unit(nx, -1);
+        for (int64_t a = 0; a < rk; ++a) {
+            const int64_t i = F.piv_row[F.coef_off[g] + a] - b;
+            if (i < 0 || i >= nx || unit[i] >= 0) continue;
+            bool e = true;
+            for (int64_t k = 0; k < rk && e; ++k) e = src[k * nx + i] == (k == a ? 1.0 : 0.0);
+            if (e) {
+                unit[i] = (int)a;
+                uprow[F.coef_off[g] + a] = (int16_t)i;
+            }
+        }
+        int32_t j = 0;
+        for (int64_t i = 0; i < nx; ++i) {
+            if (unit[i] >= 0) {
+                urow[b + i] = (int16_t)~unit[i];
+                upos[F.coef_off[g] + unit[i]] = (int16_t)j;
+            } else {
+                urow[b + i] = (int16_t)j;
+                ukeep[b + j] = (uint16_t)i;
+                ++j;
+            }
+        }
+        unk[lf] = j;
+        uoff[lf + 1] = uoff[lf] + (int64_t)j * rk;
+    }
+    std::vector<BT> ucm(uoff.back() ? uoff.back() : 1), urm(uoff.back() ? uoff.back() : 1);
+    for (int32_t lf = 0; lf < nleaf; ++lf) {
+        const int32_t g = leaf0 + lf, b = r.box_begin[g];
+        const int64_t rk = F.rank[g], nx = F.op_rows[g], nk = unk[lf];
+        const double *src = F.op.data() + F.op_off[g];
         for (int64_t k = 0; k < rk; ++k)
-            for (int64_t i = 0; i < nx; ++i) {
-                ucm[uoff[lf] + k * nx + i] = (BT)src[k * nx + i];
-                urm[uoff[lf] + i * rk + k] = (BT)src[k * nx + i];
+            for (int64_t j = 0; j < nk; ++j) {
+                const int64_t i = ukeep[b + j];
+                ucm[uoff[lf] + k * nk + j] = (BT)src[k * nx + i];
+                urm[uoff[lf] + j * rk + k] = (BT)src[k * nx + i];
             }
     }
     G.U_cm = up.copy(ucm);
     G.U_rm = up.copy(urm);
     G.uoff = up.copy(uoff);
+    G.ukeep = up.copy(ukeep);
+    G.urow = up.copy(urow);
+    G.uprow = up.copy(uprow);
+    G.upos = up.copy(upos);
+    G.unk = up.copy(unk);
     op_bytes += (int64_t)(2 * sizeof(BT) * uoff.back());
     // transfers: the host keeps them row-major ((sum r_c) x r); add the column-major copy
     std::vector<int64_t> toff(nbox + 1, 0);
@@ -843,7 +887,7 @@ bool build_multi(h2s_group g, h2s_group_s::Fused &f, h2s::MultiPlan<P> &mp, h2s:
         mp.w_l2l[k] = w_l2l[k];
     }
     mp.w_up = w_up;
-    mp.lds_leaf = sizeof(double) * (size_t)max_leaf;
+    mp.lds_leaf = sizeof(double) * (size_t)(3 * max_leaf);
     mp.lds_rows = sizeof(double) * (size_t)(2 * max_rows);
     mp.lds_rank = sizeof(double) * (size_t)(2 * max_rank);
     f.xs_dev = group_copy(g, std::vector<const double *>(m, nullptr), ok);

@@ -60,8 +60,13 @@ template <typename CT, typename BT> struct DevFamily {
     const int32_t *coef_off;     // nbox + 1
     const CT *pvx, *pvy, *pvz;   // pivot coordinates per coefficient
     const CT *pvw;               // NTI multiquadric: c(x) of each pivot (absolute)
-    const BT *U_rm, *U_cm;       // leaf bases
+    const BT *U_rm, *U_cm;       // leaf bases: the rows that are not unit rows, in order
     const int64_t *uoff;         // per leaf (local index)
+    const uint16_t *ukeep;       // per point slot b + j: local row of the leaf's kept row j
+    const int16_t *urow;         // per point: kept index of its row, or ~a for the unit row e_a
+    const int16_t *uprow;        // per coefficient: local row of its unit row, or -1
+    const int16_t *upos;         // per coefficient with a unit row: kept rows before that row
+    const int32_t *unk;          // per leaf: kept rows
     const double *Tr_rm, *Tr_cm; // stacked transfers
     const int64_t *troff;        // per global box
     const int32_t *il_off;       // nbox + 1

@@ -66,20 +66,28 @@ template <class P> __global__ __launch_bounds__(256) void k_permute(DevTree<P> t
 
 template <class P> __device__ __forceinline__ void up_leaf_body(const DevTree<P> &t, int leaf, uint32_t mask)
 {
-    extern __shared__ double qs[]; // largest leaf
+    extern __shared__ double qs[]; // the leaf's charges, then the kept rows' charges of each family
     const int g = t.leaf0 + leaf, tid = threadIdx.x, nt = blockDim.x;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
-    for (int i = tid; i < n; i += nt) qs[i] = t.qt[b + i];
-    __syncthreads();
     const int cf = t.far.coef_off[g], rf = (mask & kFar) && t.kappa >= t.far.lmin ? t.far.coef_off[g + 1] - cf : 0;
     const int cv = t.ver.coef_off[g], rv = (mask & kVer) && t.kappa >= t.ver.lmin ? t.ver.coef_off[g + 1] - cv : 0;
-    // one column of the two families per thread (U row-major n x r: column k strided by r)
+    const int nkf = rf ? t.far.unk[leaf] : 0, nkv = rv ? t.ver.unk[leaf] : 0;
+    double *qf = qs + n, *qv = qf + nkf;
+    for (int i = tid; i < n; i += nt) qs[i] = t.qt[b + i];
+    for (int j = tid; j < nkf; j += nt) qf[j] = t.qt[b + t.far.ukeep[b + j]];
+    for (int j = tid; j < nkv; j += nt) qv[j] = t.qt[b + t.ver.ukeep[b + j]];
+    __syncthreads();
+    // one column of the two families per thread (kept rows of U row-major: column k strided by r);
+    // the column's unit row adds the pivot's charge where its row lies among the kept rows, so the
+    // sum is the one over all rows in index order
     for (int k = tid; k < rf + rv; k += nt) {
         const bool f = k < rf;
         const int kk = f ? k : k - rf;
         const auto *A = f ? t.far.U_rm + t.far.uoff[leaf] + kk : t.ver.U_rm + t.ver.uoff[leaf] + kk;
+        const int pr = f ? t.far.uprow[cf + kk] : t.ver.uprow[cv + kk];
+        const int pos = pr < 0 ? -1 : f ? t.far.upos[cf + kk] : t.ver.upos[cv + kk];
         double *out = f ? t.far.v + cf + kk : t.ver.v + cv + kk;
-        *out = ordered_dot<P::ordered>(A, (size_t)(f ? rf : rv), n, qs);
+        *out = ordered_dot<P::ordered>(A, (size_t)(f ? rf : rv), f ? nkf : nkv, f ? qf : qv, pos, pr < 0 ? 0.0 : qs[pr]);
     }
 }
 
@@ -629,12 +637,18 @@ __device__ __forceinline__ void down_leaf_body(const DevTree<P> &t, int leaf, do
     // threads [0, HALF) take the far family of point i, [HALF, NT_LEAF) the vertex family
     const int f = threadIdx.x < HALF ? 0 : 1, il = threadIdx.x - f * HALF;
     const int r = f == 0 ? rf : rv;
+    // kept rows of U column-major (nk x r); a unit row e_a gives the local a itself
     const BT *U = f == 0 ? t.far.U_cm + t.far.uoff[leaf] : t.ver.U_cm + t.ver.uoff[leaf];
+    const int16_t *urow = (f == 0 ? t.far.urow : t.ver.urow) + b;
+    const int nk = r ? (f == 0 ? t.far.unk[leaf] : t.ver.unk[leaf]) : 0;
     const double *uc = f == 0 ? ucs : ucs + rf;
     for (int i0 = 0; i0 < n; i0 += HALF) {
         const int i = i0 + il;
         double fam = 0.0;
-        if (i < n && r) fam = ordered_dot<ORD>(U + i, (size_t)n, r, uc);
+        if (i < n && r) {
+            const int ki = urow[i];
+            fam = ki >= 0 ? ordered_dot<ORD>(U + ki, (size_t)nk, r, uc) : uc[~ki];
+        }
         if (f == 1 && i < n) {
             double v = fam;
             if (t.variant == H2S_H2_PLUS_H && (mask & kVer)) {
@@ -778,7 +792,7 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
         if (prof) prof->mark(prof->ctx, cls, end, on);
     };
     const int32_t *lev_off = plan.lev_off;
-    const size_t lds_leaf = sizeof(double) * (size_t)t.max_leaf;
+    const size_t lds_leaf = sizeof(double) * (size_t)(3 * t.max_leaf);
     const size_t lds_rows = sizeof(double) * (size_t)(2 * t.max_rows);
     const size_t lds_rank = sizeof(double) * (size_t)(2 * t.max_rank);
     const bool fam_on = (mask & (kFar | kVer)) && t.kappa >= 1;

@@ -62,11 +62,14 @@ __device__ __forceinline__ void ordered_dot_b(const AT *__restrict__ A, size_t s
 }
 
 // P2M: the leaf's charges are read by every thread at the same index, so they
-// are read in place through the caches rather than staged.
+// are read in place through the caches rather than staged.  Kept row j of U
+// holds local row keep[j]; the column's unit row adds the pivot's charges where
+// its row lies among the kept rows (before kept row pos).
 template <class P> __global__ __launch_bounds__(NT_BG) void kb_up_leaf(DevTree<P> t, uint32_t mask)
 {
+    constexpr bool ORD = P::ordered;
     const int leaf = xcd_remap(blockIdx.x, gridDim.x), g = t.leaf0 + leaf, tid = threadIdx.x;
-    const int b = t.box_begin[g], n = t.box_end[g] - b;
+    const int b = t.box_begin[g];
     const double *qs = t.qb + (size_t)b * NB;
     const int cf = t.far.coef_off[g], rf = (mask & kFar) && t.kappa >= t.far.lmin ? t.far.coef_off[g + 1] - cf : 0;
     const int cv = t.ver.coef_off[g], rv = (mask & kVer) && t.kappa >= t.ver.lmin ? t.ver.coef_off[g + 1] - cv : 0;
@@ -74,11 +77,38 @@ template <class P> __global__ __launch_bounds__(NT_BG) void kb_up_leaf(DevTree<P
         const bool f = k < rf;
         const int kk = f ? k : k - rf;
         const auto *A = f ? t.far.U_rm + t.far.uoff[leaf] + kk : t.ver.U_rm + t.ver.uoff[leaf] + kk;
+        const size_t stride = (size_t)(f ? rf : rv);
+        const int nk = f ? t.far.unk[leaf] : t.ver.unk[leaf];
+        const uint16_t *keep = (f ? t.far.ukeep : t.ver.ukeep) + b;
+        const int pr = f ? t.far.uprow[cf + kk] : t.ver.uprow[cv + kk];
+        const int pos = pr < 0 ? -1 : f ? t.far.upos[cf + kk] : t.ver.upos[cv + kk];
+        const double *qp = qs + (size_t)(pr < 0 ? 0 : pr) * NB;
         double *out = (f ? t.far.vb + (size_t)(cf + kk) * NB : t.ver.vb + (size_t)(cv + kk) * NB);
         double acc[NB];
-        ordered_dot_b<P::ordered>(A, (size_t)(f ? rf : rv), n, qs, acc);
 #pragma unroll
-        for (int c = 0; c < NB; ++c) out[c] = acc[c];
+        for (int c = 0; c < NB; ++c) acc[c] = 0.0;
+        int j = 0;
+        for (; j + 4 <= nk; j += 4) {
+            double a[4];
+            const double *x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = (double)A[(size_t)(j + u) * stride];
+                x[u] = qs + (size_t)keep[j + u] * NB;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) acc[c] = madd<ORD>(j + u == pos ? acc[c] + qp[c] : acc[c], a[u], x[u][c]);
+        }
+        for (; j < nk; ++j) {
+            const double a = (double)A[(size_t)j * stride];
+            const double *x = qs + (size_t)keep[j] * NB;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) acc[c] = madd<ORD>(j == pos ? acc[c] + qp[c] : acc[c], a, x[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) out[c] = pos == nk ? acc[c] + qp[c] : acc[c];
     }
 }
 
@@ -631,14 +661,23 @@ __global__ __launch_bounds__(NT_BL) void kb_down_leaf(DevTree<P> t, double *__re
     const bool on = f == 0 ? (mask & kFar) && t.kappa >= t.far.lmin : (mask & kVer) && t.kappa >= t.ver.lmin;
     const int c0 = f == 0 ? t.far.coef_off[g] : t.ver.coef_off[g];
     const int r = on ? (f == 0 ? t.far.coef_off[g + 1] : t.ver.coef_off[g + 1]) - c0 : 0;
+    // kept rows of U column-major (nk x r); a unit row e_a gives the locals of a themselves
     const BT *U = f == 0 ? t.far.U_cm + t.far.uoff[leaf] : t.ver.U_cm + t.ver.uoff[leaf];
+    const int16_t *urow = (f == 0 ? t.far.urow : t.ver.urow) + b;
+    const int nk = r ? (f == 0 ? t.far.unk[leaf] : t.ver.unk[leaf]) : 0;
     const double *uc = (f == 0 ? t.far.ub : t.ver.ub) + (size_t)c0 * NB;
     for (int i0 = 0; i0 < n; i0 += HALF) {
         const int i = i0 + il;
         double fam[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) fam[c] = 0.0;
-        if (i < n && r) ordered_dot_b<ORD>(U + i, (size_t)n, r, uc, fam);
+        if (i < n && r) {
+            const int ki = urow[i];
+            if (ki >= 0) ordered_dot_b<ORD>(U + ki, (size_t)nk, r, uc, fam);
+            else
+#pragma unroll
+                for (int c = 0; c < NB; ++c) fam[c] = uc[(size_t)(~ki) * NB + c];
+        }
         if (f == 1 && i < n)
 #pragma unroll
             for (int c = 0; c < NB; ++c) ver_part[il * NB + c] = fam[c];

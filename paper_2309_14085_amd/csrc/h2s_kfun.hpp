@@ -206,15 +206,19 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
-// Ordered dot product sum_j a(j) x[j], a(j) = A[j stride].  The sum itself is
-// sequential; the operator loads are software-pipelined two batches of UNR
-// deep so that a batch is in flight while the previous one is accumulated.
+// Ordered dot product sum_j a(j) x[j], a(j) = A[j stride], with qp added to the
+// running sum just before term pos (pos == R: after the last; pos < 0: never).
+// The sum itself is sequential; the operator loads are software-pipelined two
+// batches of UNR deep so that a batch is in flight while the previous one is
+// accumulated.
 constexpr int UNR = 8;
 
 template <bool ORD, typename AT>
-__device__ __forceinline__ double ordered_dot(const AT *__restrict__ A, size_t stride, int R, const double *xs)
+__device__ __forceinline__ double ordered_dot(const AT *__restrict__ A, size_t stride, int R, const double *xs,
+                                              int pos = -1, double qp = 0.0)
 {
     double s = 0.0;
+    auto step = [&](int j, double a) { s = madd<ORD>(j == pos ? s + qp : s, a, xs[j]); };
     int j = 0;
     if (R >= 2 * UNR) {
         double a[UNR], b[UNR];
@@ -224,15 +228,15 @@ __device__ __forceinline__ double ordered_dot(const AT *__restrict__ A, size_t s
 #pragma unroll
             for (int u = 0; u < UNR; ++u) b[u] = (double)A[(size_t)(j + UNR + u) * stride];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) s = madd<ORD>(s, a[u], xs[j + u]);
+            for (int u = 0; u < UNR; ++u) step(j + u, a[u]);
 #pragma unroll
             for (int u = 0; u < UNR; ++u) a[u] = (double)A[(size_t)(j + 2 * UNR + u) * stride];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) s = madd<ORD>(s, b[u], xs[j + UNR + u]);
+            for (int u = 0; u < UNR; ++u) step(j + UNR + u, b[u]);
         }
         // a holds rows j .. j + UNR - 1 (fewer than 3 UNR rows were left)
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) s = madd<ORD>(s, a[u], xs[j + u]);
+        for (int u = 0; u < UNR; ++u) step(j + u, a[u]);
         j += UNR;
     }
     // the remaining rows, one predicated batch of loads at a time
@@ -242,9 +246,9 @@ __device__ __forceinline__ double ordered_dot(const AT *__restrict__ A, size_t s
         for (int u = 0; u < UNR; ++u) c[u] = j + u < R ? (double)A[(size_t)(j + u) * stride] : 0.0;
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
-            if (j + u < R) s = madd<ORD>(s, c[u], xs[j + u]);
+            if (j + u < R) step(j + u, c[u]);
     }
-    return s;
+    return pos == R ? s + qp : s;
 }
 
 } // namespace

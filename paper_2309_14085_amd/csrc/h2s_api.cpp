@@ -331,22 +331,72 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     G.upos = up.copy(upos);
     G.unk = up.copy(unk);
     op_bytes += (int64_t)(2 * sizeof(BT) * uoff.back());
-    // transfers: the host keeps them row-major ((sum r_c) x r); add the column-major copy
+    // transfers: the host keeps them row-major ((sum r_c) x r).  Row k of box g's transfer
+    // belongs to child coefficient bf + k (bf = the first child's first coefficient).  With
+    // nested pivots, the row of a child pivot that is also the box's row pivot a is e_a; rows
+    // that are exactly e_a are not stored, as for the leaf bases: M2M adds that child's
+    // coefficient in the row's place, L2L copies the box's local.  tkeep[bf + j] = stacked row
+    // of kept row j, trow[bf + k] = kept index of row k or ~a, tprow[c] = stacked row of
+    // coefficient c's unit row or -1, tpos[c] = kept rows before it, tnk[g] = kept rows.
+    std::vector<int32_t> tnk(nbox ? nbox : 1, 0);
+    std::vector<uint16_t> tkeep(nc ? nc : 1, 0);
+    std::vector<int16_t> trow(nc ? nc : 1, 0), tprow(nc ? nc : 1, -1), tpos(nc ? nc : 1, 0);
     std::vector<int64_t> toff(nbox + 1, 0);
-    for (int32_t g = 0; g < nbox; ++g) toff[g + 1] = toff[g] + (g < leaf0 ? F.op_off[g + 1] - F.op_off[g] : 0);
+    for (int32_t g = 0; g < nbox; ++g) {
+        toff[g + 1] = toff[g];
+        if (g >= leaf0 || F.rank[g] == 0) continue;
+        const int64_t rk = F.rank[g], rows = F.op_rows[g];
+        const int64_t c0 = F.coef_off[g], bf = F.coef_off[r.box_cbeg[g]];
+        const double *src = F.op.data() + F.op_off[g];
+        std::vector<std::pair<int32_t, int32_t>> pv; // (pivot point, a), sorted
+        for (int64_t a = 0; a < rk; ++a) pv.push_back({F.piv_row[c0 + a], (int32_t)a});
+        std::sort(pv.begin(), pv.end());
+        std::vector<char> used(rk, 0);
+        int32_t j = 0;
+        for (int64_t k = 0; k < rows; ++k) {
+            const int32_t pt = F.piv_row[bf + k];
+            auto it = std::lower_bound(pv.begin(), pv.end(), std::make_pair(pt, (int32_t)-1));
+            int a = -1;
+            if (it != pv.end() && it->first == pt && !used[it->second]) {
+                a = it->second;
+                for (int64_t c = 0; c < rk && a >= 0; ++c)
+                    if (src[k * rk + c] != (c == a ? 1.0 : 0.0)) a = -1;
+            }
+            if (a >= 0) {
+                used[a] = 1;
+                trow[bf + k] = (int16_t)~a;
+                tprow[c0 + a] = (int16_t)k;
+                tpos[c0 + a] = (int16_t)j;
+            } else {
+                trow[bf + k] = (int16_t)j;
+                tkeep[bf + j] = (uint16_t)k;
+                ++j;
+            }
+        }
+        tnk[g] = j;
+        toff[g + 1] = toff[g] + (int64_t)j * rk;
+    }
     std::vector<double> trm(toff.back() ? toff.back() : 1), tcm(toff.back() ? toff.back() : 1);
     for (int32_t g = 0; g < leaf0; ++g) {
-        const int64_t rk = F.rank[g], rows = F.op_rows[g];
+        const int64_t rk = F.rank[g], nk = tnk[g];
+        if (rk == 0) continue;
+        const int64_t bf = F.coef_off[r.box_cbeg[g]];
         const double *src = F.op.data() + F.op_off[g];
-        for (int64_t j = 0; j < rows; ++j)
+        for (int64_t j = 0; j < nk; ++j)
             for (int64_t k = 0; k < rk; ++k) {
-                trm[toff[g] + j * rk + k] = src[j * rk + k];
-                tcm[toff[g] + k * rows + j] = src[j * rk + k];
+                const double v = src[(int64_t)tkeep[bf + j] * rk + k];
+                trm[toff[g] + j * rk + k] = v;
+                tcm[toff[g] + k * nk + j] = v;
             }
     }
     G.Tr_rm = up.copy(trm);
     G.Tr_cm = up.copy(tcm);
     G.troff = up.copy(toff);
+    G.tnk = up.copy(tnk);
+    G.tkeep = up.copy(tkeep);
+    G.trow = up.copy(trow);
+    G.tprow = up.copy(tprow);
+    G.tpos = up.copy(tpos);
     op_bytes += (int64_t)(2 * sizeof(double) * toff.back());
     const int w = f == 0 ? 1 : 2;
     std::vector<int32_t> ilo(nbox + 1);

@@ -67,8 +67,13 @@ template <typename CT, typename BT> struct DevFamily {
     const int16_t *uprow;        // per coefficient: local row of its unit row, or -1
     const int16_t *upos;         // per coefficient with a unit row: kept rows before that row
     const int32_t *unk;          // per leaf: kept rows
-    const double *Tr_rm, *Tr_cm; // stacked transfers
+    const double *Tr_rm, *Tr_cm; // stacked transfers: the rows that are not unit rows, in order
     const int64_t *troff;        // per global box
+    const int32_t *tnk;          // per box: kept rows of its transfer
+    const uint16_t *tkeep;       // per child coefficient slot bf + j: stacked row of kept row j
+    const int16_t *trow;         // per child coefficient: kept index of its row, or ~a for e_a
+    const int16_t *tprow;        // per coefficient: stacked row of its unit row, or -1
+    const int16_t *tpos;         // per coefficient with a unit row: kept rows before that row
     const int32_t *il_off;       // nbox + 1
     const int32_t *il_idx;
     int32_t max_il;              // longest interaction list

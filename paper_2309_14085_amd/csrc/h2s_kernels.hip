@@ -98,24 +98,28 @@ template <class P> __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void k_
 
 template <class P> __device__ __forceinline__ void m2m_body(const DevTree<P> &t, int g, uint32_t mask)
 {
-    extern __shared__ double xs[]; // both families' child coefficients
+    extern __shared__ double xs[]; // both families' child coefficients of the kept transfer rows
     const int tid = threadIdx.x, nt = blockDim.x;
     const auto &Fa = t.far;
     const auto &Ve = t.ver;
     const int cf = Fa.coef_off[g], rf = (mask & kFar) ? Fa.coef_off[g + 1] - cf : 0;
     const int cv = Ve.coef_off[g], rv = (mask & kVer) ? Ve.coef_off[g + 1] - cv : 0;
-    const int bf = Fa.coef_off[t.box_cbeg[g]], Rf = rf ? Fa.coef_off[t.box_cend[g]] - bf : 0;
-    const int bv = Ve.coef_off[t.box_cbeg[g]], Rv = rv ? Ve.coef_off[t.box_cend[g]] - bv : 0;
-    for (int j = tid; j < Rf; j += nt) xs[j] = Fa.v[bf + j];
-    for (int j = tid; j < Rv; j += nt) xs[Rf + j] = Ve.v[bv + j];
+    const int bf = Fa.coef_off[t.box_cbeg[g]], nkf = rf ? Fa.tnk[g] : 0;
+    const int bv = Ve.coef_off[t.box_cbeg[g]], nkv = rv ? Ve.tnk[g] : 0;
+    for (int j = tid; j < nkf; j += nt) xs[j] = Fa.v[bf + Fa.tkeep[bf + j]];
+    for (int j = tid; j < nkv; j += nt) xs[nkf + j] = Ve.v[bv + Ve.tkeep[bv + j]];
     __syncthreads();
-    // stacked transfers row-major (sum r_c) x r: column k strided by r
+    // kept rows of the stacked transfer row-major: column k strided by r; the column's unit row
+    // adds its child coefficient where the row lies among the kept rows (the full row order)
     for (int k = tid; k < rf + rv; k += nt) {
         const bool f = k < rf;
         const int kk = f ? k : k - rf;
         const double *A = f ? Fa.Tr_rm + Fa.troff[g] + kk : Ve.Tr_rm + Ve.troff[g] + kk;
+        const int pr = f ? Fa.tprow[cf + kk] : Ve.tprow[cv + kk];
+        const int pos = pr < 0 ? -1 : f ? Fa.tpos[cf + kk] : Ve.tpos[cv + kk];
+        const double qp = pr < 0 ? 0.0 : f ? Fa.v[bf + pr] : Ve.v[bv + pr];
         double *out = f ? Fa.v + cf + kk : Ve.v + cv + kk;
-        *out = ordered_dot<P::ordered>(A, (size_t)(f ? rf : rv), f ? Rf : Rv, f ? xs : xs + Rf);
+        *out = ordered_dot<P::ordered>(A, (size_t)(f ? rf : rv), f ? nkf : nkv, f ? xs : xs + nkf, pos, qp);
     }
 }
 
@@ -138,13 +142,17 @@ template <class P> __device__ __forceinline__ void l2l_body(const DevTree<P> &t,
     for (int k = tid; k < rf; k += nt) xs[k] = Fa.u[cf + k];
     for (int k = tid; k < rv; k += nt) xs[rf + k] = Ve.u[cv + k];
     __syncthreads();
-    // stacked transfers column-major (sum r_c) x r: row j strided by the row count
+    // kept rows of the stacked transfer column-major (row j strided by the kept-row count); a
+    // unit row e_a gives the local a itself
+    const int nkf = rf ? Fa.tnk[g] : 0, nkv = rv ? Ve.tnk[g] : 0;
     for (int j = tid; j < Rf + Rv; j += nt) {
         const bool f = j < Rf;
         const int jj = f ? j : j - Rf;
-        const double *A = f ? Fa.Tr_cm + Fa.troff[g] + jj : Ve.Tr_cm + Ve.troff[g] + jj;
+        const int kj = f ? Fa.trow[bf + jj] : Ve.trow[bv + jj];
+        const double *A = (f ? Fa.Tr_cm + Fa.troff[g] : Ve.Tr_cm + Ve.troff[g]) + (kj >= 0 ? kj : 0);
+        const double *x = f ? xs : xs + rf;
         double *out = f ? Fa.u + bf + jj : Ve.u + bv + jj;
-        const double s = ordered_dot<ORD>(A, (size_t)(f ? Rf : Rv), f ? rf : rv, f ? xs : xs + rf);
+        const double s = kj >= 0 ? ordered_dot<ORD>(A, (size_t)(f ? nkf : nkv), f ? rf : rv, x) : x[~kj];
         *out = *out + s;
     }
 }

@@ -122,15 +122,21 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int NT_BT = 64;
 
 // out (rows x cols) = A (rows x K) * B (K x cols), A[i][k] = a[k * lda_k + i * lda_i], B[k] of
-// column n at b_n[k * NB]; rows past `rows` and columns of absent blocks are neither read nor written
+// column n at b_n[brow(k) * NB] (brow = bidx, or k itself); output row i goes to row orow(i) of
+// out (oidx, or i); an output row i with unit[i] >= 0 also adds B row unit[i] (a unit row of the
+// operator that is not stored).  Rows past `rows` and columns of absent blocks are neither read
+// nor written.
 struct TileIO {
     const double *a;
     size_t lda_k, lda_i;
-    const double *b;  // the first column block's B[0][0]
-    double *out;      // the first column block's out[0][0]
-    size_t bstride;   // one column block to the next, in B and out
+    const double *b;         // the first column block's B[0][0]
+    double *out;             // the first column block's out[0][0]
+    size_t bstride;          // one column block to the next, in B and out
     int rows, K, nblk;
-    bool add;         // out += A B instead of out = A B
+    bool add;                // out += A B instead of out = A B
+    const uint16_t *bidx;    // or null
+    const uint16_t *oidx;    // or null
+    const int16_t *unit;     // or null
 };
 
 // Every load is issued unconditionally (absent rows and column blocks read row 0 and block 0)
@@ -146,16 +152,18 @@ template <bool TWO> __device__ __forceinline__ void tile_product_t(const TileIO 
     const double *B0 = io.b + (ok0 ? (size_t)(n0 / NB) * io.bstride : 0) + n0 % NB;
     const double *B1 = io.b + (ok1 ? (size_t)(n1 / NB) * io.bstride : 0) + n1 % NB;
     const double *A = io.a + (size_t)(iok ? i : 0) * io.lda_i;
+    auto brow = [&](int k) -> size_t { return (size_t)(io.bidx ? io.bidx[k] : k); };
     dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
     const int Kf = io.K & ~(4 * U - 1);
     for (int k0 = 0; k0 < Kf; k0 += 4 * U) {
         double a[U], b0[U], b1[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const size_t k = (size_t)(k0 + 4 * u + lk);
-            a[u] = A[k * io.lda_k];
-            b0[u] = B0[k * NB];
-            if constexpr (TWO) b1[u] = B1[k * NB];
+            const int k = k0 + 4 * u + lk;
+            const size_t kb = brow(k);
+            a[u] = A[(size_t)k * io.lda_k];
+            b0[u] = B0[kb * NB];
+            if constexpr (TWO) b1[u] = B1[kb * NB];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -167,12 +175,13 @@ template <bool TWO> __device__ __forceinline__ void tile_product_t(const TileIO 
     for (int k0 = Kf; k0 < io.K; k0 += 4) { // the remaining terms, 4 at a time
         const int k = k0 + lk;
         const bool kok = k < io.K;
-        const size_t kc = (size_t)(kok ? k : 0);
-        const double a = A[kc * io.lda_k], b0 = B0[kc * NB];
+        const int kc = kok ? k : 0;
+        const size_t kb = brow(kc);
+        const double a = A[(size_t)kc * io.lda_k], b0 = B0[kb * NB];
         const double au = iok && kok ? a : 0.0;
         acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(au, ok0 ? b0 : 0.0, acc0, 0, 0, 0);
         if constexpr (TWO) {
-            const double b1 = B1[kc * NB];
+            const double b1 = B1[kb * NB];
             acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(au, ok1 ? b1 : 0.0, acc1, 0, 0, 0);
         }
     }
@@ -182,8 +191,15 @@ template <bool TWO> __device__ __forceinline__ void tile_product_t(const TileIO 
     for (int q = 0; q < 4; ++q) {
         const int row = tile * 16 + lk + 4 * q;
         if (row < io.rows) {
-            if (ok0) O0[(size_t)row * NB] = io.add ? O0[(size_t)row * NB] + acc0[q] : acc0[q];
-            if (ok1) O1[(size_t)row * NB] = io.add ? O1[(size_t)row * NB] + acc1[q] : acc1[q];
+            const size_t o = (size_t)(io.oidx ? io.oidx[row] : row) * NB;
+            const int ur = io.unit ? io.unit[row] : -1;
+            double v0 = acc0[q], v1 = acc1[q];
+            if (ur >= 0) {
+                v0 = v0 + B0[(size_t)ur * NB];
+                if (ok1) v1 = v1 + B1[(size_t)ur * NB];
+            }
+            if (ok0) O0[o] = io.add ? O0[o] + v0 : v0;
+            if (ok1) O1[o] = io.add ? O1[o] + v1 : v1;
         }
     }
 }
@@ -194,8 +210,9 @@ __device__ __forceinline__ void tile_product(const TileIO &io, int tile)
     else tile_product_t<false>(io, tile);
 }
 
-// M2M: the parent's multipoles (rank rows) = transfer^T (rank x children's coefficients) times
-// the children's multipoles.  Grid: (boxes of the level, row tiles of the largest rank).
+// M2M: the parent's multipoles (rank rows) = transfer^T (rank x kept rows) times the children's
+// multipoles of the kept rows, plus the child coefficient of each unit row.  Grid: (boxes of
+// the level, row tiles of the largest rank).
 template <class P, bool FAR> __global__ __launch_bounds__(NT_BT) void kb_m2m_mfma(DevTree<P> t, int32_t g0, int nblk)
 {
     const auto &F = [&]() -> const auto & {
@@ -205,23 +222,27 @@ template <class P, bool FAR> __global__ __launch_bounds__(NT_BT) void kb_m2m_mfm
     const int g = g0 + blockIdx.x, tile = blockIdx.y;
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     if (tile * 16 >= r) return; // whole wave
-    const int b0 = F.coef_off[t.box_cbeg[g]], R = F.coef_off[t.box_cend[g]] - b0;
+    const int b0 = F.coef_off[t.box_cbeg[g]];
     TileIO io;
-    io.a = F.Tr_rm + F.troff[g]; // R x r row-major: transfer^T[i][k] at k * r + i
+    io.a = F.Tr_rm + F.troff[g]; // kept rows x r row-major: transfer^T[i][k] at k * r + i
     io.lda_k = (size_t)r;
     io.lda_i = 1;
     io.b = F.vb + (size_t)b0 * NB;
     io.out = F.vb + (size_t)c0 * NB;
     io.bstride = (size_t)F.ncoef * NB;
     io.rows = r;
-    io.K = R;
+    io.K = F.tnk[g];
     io.nblk = nblk;
     io.add = false;
+    io.bidx = F.tkeep + b0;
+    io.oidx = nullptr;
+    io.unit = F.tprow + c0;
     tile_product(io, tile);
 }
 
-// L2L: the children's locals (children's coefficients rows) += transfer (rows x rank) times the
-// parent's locals.  Grid: (boxes of the level, row tiles of the largest stacked transfer).
+// L2L: the children's locals of the kept rows += transfer (kept rows x rank) times the parent's
+// locals; the wave of tile 0 also adds the parent's local a to the child coefficient of each
+// unit row e_a.  Grid: (boxes of the level, row tiles of the largest stacked transfer).
 template <class P, bool FAR> __global__ __launch_bounds__(NT_BT) void kb_l2l_mfma(DevTree<P> t, int32_t g0, int nblk)
 {
     const auto &F = [&]() -> const auto & {
@@ -231,19 +252,30 @@ template <class P, bool FAR> __global__ __launch_bounds__(NT_BT) void kb_l2l_mfm
     const int g = g0 + blockIdx.x, tile = blockIdx.y;
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     if (r == 0) return;
-    const int b0 = F.coef_off[t.box_cbeg[g]], R = F.coef_off[t.box_cend[g]] - b0;
-    if (tile * 16 >= R) return; // whole wave
+    const int b0 = F.coef_off[t.box_cbeg[g]], nk = F.tnk[g];
+    const size_t bstride = (size_t)F.ncoef * NB;
+    if (tile == 0) // unit rows: rows disjoint from the kept rows the tiles write
+        for (int e = threadIdx.x; e < r * nblk * NB; e += NT_BT) {
+            const int a = e / (nblk * NB), col = e % (nblk * NB), pr = F.tprow[c0 + a];
+            if (pr < 0) continue;
+            double *o = F.ub + (size_t)(col / NB) * bstride + (size_t)(b0 + pr) * NB + col % NB;
+            *o = *o + F.ub[(size_t)(col / NB) * bstride + (size_t)(c0 + a) * NB + col % NB];
+        }
+    if (tile * 16 >= nk) return; // whole wave
     TileIO io;
-    io.a = F.Tr_cm + F.troff[g]; // column-major R x r: transfer[i][k] at k * R + i
-    io.lda_k = (size_t)R;
+    io.a = F.Tr_cm + F.troff[g]; // column-major kept rows x r: transfer[i][k] at k * nk + i
+    io.lda_k = (size_t)nk;
     io.lda_i = 1;
     io.b = F.ub + (size_t)c0 * NB;
     io.out = F.ub + (size_t)b0 * NB;
-    io.bstride = (size_t)F.ncoef * NB;
-    io.rows = R;
+    io.bstride = bstride;
+    io.rows = nk;
     io.K = r;
     io.nblk = nblk;
     io.add = true;
+    io.bidx = nullptr;
+    io.oidx = F.tkeep + b0;
+    io.unit = nullptr;
     tile_product(io, tile);
 }
 

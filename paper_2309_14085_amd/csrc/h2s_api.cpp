@@ -402,8 +402,6 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     std::vector<int32_t> ilo(nbox + 1);
     for (int32_t g = 0; g <= nbox; ++g) ilo[g] = (int32_t)r.list_off[w][g];
     G.il_off = up.copy(ilo);
-    G.max_il = 0;
-    for (int32_t g = 0; g < nbox; ++g) G.max_il = std::max(G.max_il, ilo[g + 1] - ilo[g]);
     G.il_idx = up.copy(r.list_idx[w]);
     std::vector<int32_t> targets;
     for (int32_t g = 0; g < nbox; ++g)
@@ -468,6 +466,10 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
     if (D.max_leaf > lds_cap || 2 * D.max_rows > lds_cap)
         return fail(H2S_ERR_UNSUPPORTED, "a leaf or stacked transfer exceeds " + std::to_string(lds_cap) +
                                              " entries; use a smaller leaf_size");
+    for (int w = 1; w <= 2; ++w)
+        for (int32_t g = 0; g < nbox; ++g)
+            if (r.list_off[w][g + 1] - r.list_off[w][g] > h2s::kMaxList)
+                return fail(H2S_ERR_UNSUPPORTED, "an interaction list exceeds " + std::to_string(h2s::kMaxList) + " boxes");
     if (kappa > h2s::kMaxLevels)
         return fail(H2S_ERR_UNSUPPORTED, "tree depth exceeds " + std::to_string(h2s::kMaxLevels) + " levels");
     if (D.max_rank > rank_cap)

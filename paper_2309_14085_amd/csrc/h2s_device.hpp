@@ -76,7 +76,6 @@ template <typename CT, typename BT> struct DevFamily {
     const int16_t *tpos;         // per coefficient with a unit row: kept rows before that row
     const int32_t *il_off;       // nbox + 1
     const int32_t *il_idx;
-    int32_t max_il;              // longest interaction list
     const int32_t *targets;      // boxes with rank > 0 at levels >= lmin, in box (so level) order
     int32_t ntargets;
     int32_t targets_leaf;        // index in targets of the first leaf-level box
@@ -129,6 +128,7 @@ template <class P> struct DevTree {
 
 // Host-side launch shapes, fixed at upload.
 constexpr int kMaxLevels = 32;
+constexpr int kMaxList = 256; // boxes of an interaction list (6^d at most in a 2^d tree); checked at build
 struct LaunchPlan {
     const int32_t *lev_off;              // global box range of every level (kappa + 2 entries)
     int32_t up_threads[kMaxLevels + 1];  // block size of P2M (level kappa) and M2M (levels < kappa)

@@ -331,13 +331,38 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
     constexpr bool XW = kExtraCoord<KIND>;
     __shared__ double sx[M2LS_SRC], sy[M2LS_SRC], sz[D == 3 ? M2LS_SRC : 1], sv[M2LS_SRC], sw[XW ? M2LS_SRC : 1];
     __shared__ double red[2 * NT_M2LS];
+    __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList];
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
     const int tid = threadIdx.x;
     stage_table<KIND>(t.ktab, ktab); // first used after a barrier
     const int g = F.targets[ti];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
-    const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
+    const int e0 = F.il_off[g], nil = F.il_off[g + 1] - e0; // nil <= kMaxList (checked at build)
     const KPar<double> kp = kpar<double>(t);
+    // the sources of IL(X) in list order as slots 0 .. S-1: slot s lies in list box e with
+    // boxoff[e] <= s < boxoff[e + 1], coefficient boxcoef[e] + s - boxoff[e].  A group of
+    // M2LS_SRC slots is staged with all its loads in flight at once.
+    for (int k = tid; k < nil; k += NT_M2LS) {
+        const int y = F.il_idx[e0 + k];
+        boxcoef[k] = F.coef_off[y];
+        boxoff[k + 1] = F.coef_off[y + 1] - F.coef_off[y];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        boxoff[0] = 0;
+        for (int k = 1; k <= nil; ++k) boxoff[k] += boxoff[k - 1];
+    }
+    __syncthreads();
+    const int S = boxoff[nil];
+    auto coef_of = [&](int sl) -> int {
+        int lo = 0, hi = nil - 1; // largest e with boxoff[e] <= sl
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (boxoff[mid] <= sl) lo = mid;
+            else hi = mid - 1;
+        }
+        return boxcoef[lo] + (sl - boxoff[lo]);
+    };
     for (int a0 = 0; a0 < r; a0 += 2 * NT_M2LS) {
         const int MT = min(r - a0, 2 * NT_M2LS), NP = (MT + 1) / 2, NS = NT_M2LS / NP;
         const int s = tid / NP, pa = tid % NP;
@@ -380,24 +405,19 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
             __syncthreads();
             pos = 0;
         };
-        for (int e = e0; e < e1; ++e) {
-            const int y = F.il_idx[e];
-            const int cy = F.coef_off[y], ry = F.coef_off[y + 1] - cy;
-            for (int j0 = 0; j0 < ry;) {
-                const int take = min(ry - j0, M2LS_SRC - pos);
-                for (int j = tid; j < take; j += NT_M2LS) {
-                    sx[pos + j] = F.pvx[cy + j0 + j];
-                    sy[pos + j] = F.pvy[cy + j0 + j];
-                    if constexpr (D == 3) sz[pos + j] = F.pvz[cy + j0 + j];
-                    if constexpr (XW) sw[pos + j] = F.pvw[cy + j0 + j];
-                    sv[pos + j] = F.v[cy + j0 + j];
-                }
-                pos += take;
-                j0 += take;
-                if (pos == M2LS_SRC) flush();
+        for (int base = 0; base < S; base += M2LS_SRC) {
+            const int take = min(S - base, M2LS_SRC);
+            for (int j = tid; j < take; j += NT_M2LS) {
+                const int c = coef_of(base + j);
+                sx[j] = F.pvx[c];
+                sy[j] = F.pvy[c];
+                if constexpr (D == 3) sz[j] = F.pvz[c];
+                if constexpr (XW) sw[j] = F.pvw[c];
+                sv[j] = F.v[c];
             }
+            pos = take;
+            flush();
         }
-        if (pos > 0) flush();
         red[tid] = s < NS ? acc_a : 0.0;
         red[NT_M2LS + tid] = s < NS ? acc_b : 0.0;
         __syncthreads();

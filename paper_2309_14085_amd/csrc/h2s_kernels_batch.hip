@@ -396,7 +396,6 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
 constexpr int NT_BMM = 256;  // 4 waves
 constexpr int BMM_SRC = 64;  // staged source pivots per group
 constexpr int BMM_STEPS = 4; // 4-source product steps per iteration
-constexpr int BMM_IL = 256;  // interaction-list boxes the slot table holds (a list has at most 6^d boxes)
 
 template <class P, bool FAR, int KIND, int D>
 __global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(4))) void kb_m2l_mfma(DevTree<P> t, int nblk)
@@ -412,7 +411,7 @@ __global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(4))) voi
     constexpr bool XW = kExtraCoord<KIND>;
     __shared__ double sx[BMM_SRC], sy[BMM_SRC], sz[D == 3 ? BMM_SRC : 1], sw[XW ? BMM_SRC : 1];
     __shared__ double sv[BMM_SRC * GC]; // after the last group: the waves' partial tiles
-    __shared__ int32_t boxoff[BMM_IL + 1], boxcoef[BMM_IL];
+    __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList];
     __shared__ double tx[64], ty[64], tz[D == 3 ? 64 : 1], tw[XW ? 64 : 1]; // the round's target pivots
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
     static_assert(BMM_SRC * GC >= 4 * 64 * 8, "partial tiles fit in the multipole buffer");
@@ -421,7 +420,7 @@ __global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(4))) voi
     stage_table<KIND>(t.ktab, ktab); // first used after a barrier
     const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
-    const int e0 = F.il_off[g], nil = F.il_off[g + 1] - e0; // nil <= BMM_IL: longer lists take kb_m2l
+    const int e0 = F.il_off[g], nil = F.il_off[g + 1] - e0; // nil <= kMaxList (checked at build)
     const KPar<double> kp = kpar<double>(t);
     const size_t bstride = (size_t)F.ncoef * NB; // one block's coefficients
     const bool two = nblk * NB > 16;             // the second column tile holds active columns
@@ -776,14 +775,14 @@ hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *
     if (fam_on) {
         // M2L: one launch per family for every block (matrix cores when two or more blocks share it)
         if ((mask & kFar) && t.far.ntargets) {
-            if (nblk > 1 && t.far.max_il <= BMM_IL)
+            if (nblk > 1)
                 hipLaunchKernelGGL((kb_m2l_mfma<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_BMM), 0, s, t, nblk);
             else
                 for (int k = 0; k < nblk; ++k)
                     hipLaunchKernelGGL((kb_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_BM), 0, s, tb[k]);
         }
         if ((mask & kVer) && t.ver.ntargets) {
-            if (nblk > 1 && t.ver.max_il <= BMM_IL)
+            if (nblk > 1)
                 hipLaunchKernelGGL((kb_m2l_mfma<P, false, KIND, D>), dim3(t.ver.ntargets), dim3(NT_BMM), 0, s, t, nblk);
             else
                 for (int k = 0; k < nblk; ++k)

@@ -466,8 +466,8 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
     if (D.max_leaf > lds_cap || 2 * D.max_rows > lds_cap)
         return fail(H2S_ERR_UNSUPPORTED, "a leaf or stacked transfer exceeds " + std::to_string(lds_cap) +
                                              " entries; use a smaller leaf_size");
-    for (int w = 1; w <= 2; ++w)
-        for (int32_t g = 0; g < nbox; ++g)
+    for (int w = 0; w <= 2; ++w) // near, far and vertex lists
+        for (int32_t g = 0; g + 1 < (int32_t)r.list_off[w].size(); ++g)
             if (r.list_off[w][g + 1] - r.list_off[w][g] > h2s::kMaxList)
                 return fail(H2S_ERR_UNSUPPORTED, "an interaction list exceeds " + std::to_string(h2s::kMaxList) + " boxes");
     if (kappa > h2s::kMaxLevels)

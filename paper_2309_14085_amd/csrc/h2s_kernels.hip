@@ -509,6 +509,9 @@ template <class P, int KIND, int D> __device__ __forceinline__ void p2p_body(con
     PT *const sw = sz + (D == 3 ? P2P_SRC : 0);       // used by kernels of an extra coordinate only
     double *const red = reinterpret_cast<double *>(sbuf);
     __shared__ __align__(16) double ktab[TAB ? kTabLen<KIND> : 2];
+    // the near list's points in list order as slots 0 .. S-1: slot s lies in list box e with
+    // nboff[e] <= s < nboff[e + 1], point nbbeg[e] + s - nboff[e]; nself = the leaf's own entry
+    __shared__ int32_t nboff[kMaxList + 1], nbbeg[kMaxList], nself;
     const int tid = threadIdx.x;
     const PT diag = (PT)t.diag;
     const KPar<PT> kp = kpar<PT>(t);
@@ -517,6 +520,32 @@ template <class P, int KIND, int D> __device__ __forceinline__ void p2p_body(con
         const int g = t.leaf0 + leaf;
         const int b = t.box_begin[g], n = t.box_end[g] - b;
         const double *cX = t.box_ctr + 3 * g;
+        const int ne0 = t.near_off[leaf], nne = t.near_off[leaf + 1] - ne0; // nne <= kMaxList (checked at build)
+        for (int k = tid; k < nne; k += NT_P2P) {
+            const int gs = t.leaf0 + t.near_idx[ne0 + k];
+            nbbeg[k] = t.box_begin[gs];
+            nboff[k + 1] = t.box_end[gs] - t.box_begin[gs];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            nboff[0] = 0;
+            nself = -1;
+            for (int k = 0; k < nne; ++k) {
+                nboff[k + 1] += nboff[k];
+                if (t.leaf0 + t.near_idx[ne0 + k] == g) nself = k;
+            }
+        }
+        __syncthreads();
+        const int S = nboff[nne];
+        auto box_of = [&](int sl) -> int {
+            int lo = 0, hi = nne - 1; // largest e with nboff[e] <= sl
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (nboff[mid] <= sl) lo = mid;
+                else hi = mid - 1;
+            }
+            return lo;
+        };
         for (int i0 = 0; i0 < n; i0 += TPT * NT_P2P) {
             // MT targets this pass in NP groups (a, a + NP, ...); NS source slices
             const int MT = min(n - i0, TPT * NT_P2P), NP = (MT + TPT - 1) / TPT, NS = NT_P2P / NP;
@@ -581,41 +610,32 @@ template <class P, int KIND, int D> __device__ __forceinline__ void p2p_body(con
                 __syncthreads();
                 pos = self0 = self1 = 0;
             };
-            for (int e = t.near_off[leaf]; e < t.near_off[leaf + 1]; ++e) {
-                const int gs = t.leaf0 + t.near_idx[e];
-                const int sb = t.box_begin[gs], sn = t.box_end[gs] - sb;
-                double dcx = 0, dcy = 0, dcz = 0;
-                if constexpr (P::local) {
-                    dcx = t.box_ctr[3 * gs] - cX[0];
-                    dcy = t.box_ctr[3 * gs + 1] - cX[1];
-                    dcz = t.box_ctr[3 * gs + 2] - cX[2];
-                }
-                for (int j0 = 0; j0 < sn;) {
-                    const int take = min(sn - j0, P2P_SRC - pos);
-                    for (int j = tid; j < take; j += NT_P2P) {
-                        const int src = sb + j0 + j;
-                        if constexpr (P::local) {
-                            sx[pos + j] = (PT)(dcx + (double)t.px[src]);
-                            sy[pos + j] = (PT)(dcy + (double)t.py[src]);
-                            if constexpr (D == 3) sz[pos + j] = (PT)(dcz + (double)t.pz[src]);
-                        } else {
-                            sx[pos + j] = t.px[src];
-                            sy[pos + j] = t.py[src];
-                            if constexpr (D == 3) sz[pos + j] = t.pz[src];
-                        }
-                        sq[pos + j] = (PT)t.qt[src];
-                        if constexpr (XW) sw[pos + j] = t.pw[src];
+            // a group of P2P_SRC slots is staged with all its loads in flight at once
+            for (int base = 0; base < S; base += P2P_SRC) {
+                const int take = min(S - base, P2P_SRC);
+                for (int j = tid; j < take; j += NT_P2P) {
+                    const int e = box_of(base + j);
+                    const int src = nbbeg[e] + (base + j - nboff[e]);
+                    if constexpr (P::local) {
+                        const int gs = t.leaf0 + t.near_idx[ne0 + e];
+                        sx[j] = (PT)((t.box_ctr[3 * gs] - cX[0]) + (double)t.px[src]);
+                        sy[j] = (PT)((t.box_ctr[3 * gs + 1] - cX[1]) + (double)t.py[src]);
+                        if constexpr (D == 3) sz[j] = (PT)((t.box_ctr[3 * gs + 2] - cX[2]) + (double)t.pz[src]);
+                    } else {
+                        sx[j] = t.px[src];
+                        sy[j] = t.py[src];
+                        if constexpr (D == 3) sz[j] = t.pz[src];
                     }
-                    if (gs == g) {
-                        self0 = pos;
-                        self1 = pos + take;
-                    }
-                    pos += take;
-                    j0 += take;
-                    if (pos == P2P_SRC) flush();
+                    sq[j] = (PT)t.qt[src];
+                    if constexpr (XW) sw[j] = t.pw[src];
                 }
+                pos = take;
+                if (nself >= 0) {
+                    self0 = min(max(nboff[nself] - base, 0), take);
+                    self1 = min(max(nboff[nself + 1] - base, 0), take);
+                }
+                flush();
             }
-            if (pos > 0) flush(); // ends with a barrier: the staging memory is free for the partials
 #pragma unroll
             for (int k = 0; k < TPT; ++k) red[k * NT_P2P + tid] = s < NS ? acc[k] : 0.0;
             __syncthreads();

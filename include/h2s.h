@@ -102,7 +102,10 @@ typedef struct h2s_tree_s *h2s_tree;
  * points: host, row-major n x d doubles (copied).  d in {2, 3}; n >= 1; all
  * coordinates finite.  The handle owns all device memory until h2s_free.
  * Errors: INVALID_ARG (bad argument), OUT_OF_MEMORY (host or device),
- * DEVICE (no HIP device / HIP error), INTERNAL. */
+ * DEVICE (no HIP device / HIP error), UNSUPPORTED (a leaf of more than 4096
+ * points, a stacked transfer of more than 2560 rows, a rank above 512 or an
+ * interaction list of more than 256 boxes: the kernels stage these whole in
+ * LDS), INTERNAL. */
 h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kernel *kernel,
                      const h2s_build_opts *opts, void *stream, h2s_tree *out);
 

@@ -459,13 +459,17 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
             D.max_rank = std::max(D.max_rank, r.fam[f].rank[g]);
             if (g < leaf0) D.max_rows = std::max(D.max_rows, r.fam[f].op_rows[g]);
         }
-    // Leaves, stacked transfer rows (both families at once) and ranks are
-    // staged whole in LDS (64 KiB per block); an M2L source box must fit the
-    // kernel's staging group, which bounds the rank.
-    const int32_t lds_cap = 5120, rank_cap = 512;
-    if (D.max_leaf > lds_cap || 2 * D.max_rows > lds_cap)
-        return fail(H2S_ERR_UNSUPPORTED, "a leaf or stacked transfer exceeds " + std::to_string(lds_cap) +
-                                             " entries; use a smaller leaf_size");
+    // Leaves (P2M: the kept rows' charges of both families), stacked transfer
+    // rows (both families at once) and ranks are staged whole in LDS (64 KiB
+    // per block); an M2L source box must fit the kernel's staging group, which
+    // bounds the rank.
+    const int32_t leaf_cap = 4096, lds_cap = 5120, rank_cap = 512;
+    if (D.max_leaf > leaf_cap)
+        return fail(H2S_ERR_UNSUPPORTED, "a leaf holds more than " + std::to_string(leaf_cap) +
+                                             " points; use a smaller leaf_size");
+    if (2 * D.max_rows > lds_cap)
+        return fail(H2S_ERR_UNSUPPORTED, "a stacked transfer exceeds " + std::to_string(lds_cap / 2) +
+                                             " rows; use a smaller leaf_size");
     for (int w = 0; w <= 2; ++w) // near, far and vertex lists
         for (int32_t g = 0; g + 1 < (int32_t)r.list_off[w].size(); ++g)
             if (r.list_off[w][g + 1] - r.list_off[w][g] > h2s::kMaxList)
@@ -939,7 +943,7 @@ bool build_multi(h2s_group g, h2s_group_s::Fused &f, h2s::MultiPlan<P> &mp, h2s:
         mp.w_l2l[k] = w_l2l[k];
     }
     mp.w_up = w_up;
-    mp.lds_leaf = sizeof(double) * (size_t)(3 * max_leaf);
+    mp.lds_leaf = sizeof(double) * (size_t)(2 * max_leaf);
     mp.lds_rows = sizeof(double) * (size_t)(2 * max_rows);
     mp.lds_rank = sizeof(double) * (size_t)(2 * max_rank);
     f.xs_dev = group_copy(g, std::vector<const double *>(m, nullptr), ok);

@@ -66,15 +66,14 @@ template <class P> __global__ __launch_bounds__(256) void k_permute(DevTree<P> t
 
 template <class P> __device__ __forceinline__ void up_leaf_body(const DevTree<P> &t, int leaf, uint32_t mask)
 {
-    extern __shared__ double qs[]; // the leaf's charges, then the kept rows' charges of each family
+    extern __shared__ double qs[]; // the kept rows' charges: far family, then vertex family
     const int g = t.leaf0 + leaf, tid = threadIdx.x, nt = blockDim.x;
     const int b = t.box_begin[g], n = t.box_end[g] - b;
     const int cf = t.far.coef_off[g], rf = (mask & kFar) && t.kappa >= t.far.lmin ? t.far.coef_off[g + 1] - cf : 0;
     const int cv = t.ver.coef_off[g], rv = (mask & kVer) && t.kappa >= t.ver.lmin ? t.ver.coef_off[g + 1] - cv : 0;
     const int nkf = rf ? t.far.unk[leaf] : 0, nkv = rv ? t.ver.unk[leaf] : 0;
-    double *qf = qs + n, *qv = qf + nkf;
-    for (int i = tid; i < n; i += nt) qs[i] = t.qt[b + i];
-    for (int j = tid; j < nkf; j += nt) qf[j] = t.qt[b + t.far.ukeep[b + j]];
+    double *const qv = qs + nkf;
+    for (int j = tid; j < nkf; j += nt) qs[j] = t.qt[b + t.far.ukeep[b + j]];
     for (int j = tid; j < nkv; j += nt) qv[j] = t.qt[b + t.ver.ukeep[b + j]];
     __syncthreads();
     // one column of the two families per thread (kept rows of U row-major: column k strided by r);
@@ -87,7 +86,7 @@ template <class P> __device__ __forceinline__ void up_leaf_body(const DevTree<P>
         const int pr = f ? t.far.uprow[cf + kk] : t.ver.uprow[cv + kk];
         const int pos = pr < 0 ? -1 : f ? t.far.upos[cf + kk] : t.ver.upos[cv + kk];
         double *out = f ? t.far.v + cf + kk : t.ver.v + cv + kk;
-        *out = ordered_dot<P::ordered>(A, (size_t)(f ? rf : rv), f ? nkf : nkv, f ? qf : qv, pos, pr < 0 ? 0.0 : qs[pr]);
+        *out = ordered_dot<P::ordered>(A, (size_t)(f ? rf : rv), f ? nkf : nkv, f ? qs : qv, pos, pr < 0 ? 0.0 : t.qt[b + pr]);
     }
 }
 
@@ -679,9 +678,6 @@ __device__ __forceinline__ void down_leaf_body(const DevTree<P> &t, int leaf, do
     const int cf = t.far.coef_off[g], cv = t.ver.coef_off[g];
     const int rf = (mask & kFar) && t.kappa >= t.far.lmin ? t.far.coef_off[g + 1] - cf : 0;
     const int rv = (mask & kVer) && t.kappa >= t.ver.lmin ? t.ver.coef_off[g + 1] - cv : 0;
-    for (int k = threadIdx.x; k < rf; k += NT_LEAF) ucs[k] = t.far.u[cf + k];
-    for (int k = threadIdx.x; k < rv; k += NT_LEAF) ucs[rf + k] = t.ver.u[cv + k];
-    __syncthreads();
     // threads [0, HALF) take the far family of point i, [HALF, NT_LEAF) the vertex family
     const int f = threadIdx.x < HALF ? 0 : 1, il = threadIdx.x - f * HALF;
     const int r = f == 0 ? rf : rv;
@@ -690,13 +686,27 @@ __device__ __forceinline__ void down_leaf_body(const DevTree<P> &t, int leaf, do
     const int16_t *urow = (f == 0 ? t.far.urow : t.ver.urow) + b;
     const int nk = r ? (f == 0 ? t.far.unk[leaf] : t.ver.unk[leaf]) : 0;
     const double *uc = f == 0 ? ucs : ucs + rf;
+    // a point's row map and near-field values; the first chunk's are read before the barrier,
+    // beside the locals
+    int ki = 0, dst = 0;
+    double yv = 0.0, qv = 0.0;
+    auto point_loads = [&](int i) {
+        if (i < n && r) ki = urow[i];
+        if (f == 0 && i < n) {
+            yv = t.yn[b + i];
+            qv = t.qt[b + i];
+            dst = t.perm[b + i];
+        }
+    };
+    point_loads(il);
+    for (int k = threadIdx.x; k < rf; k += NT_LEAF) ucs[k] = t.far.u[cf + k];
+    for (int k = threadIdx.x; k < rv; k += NT_LEAF) ucs[rf + k] = t.ver.u[cv + k];
+    __syncthreads();
     for (int i0 = 0; i0 < n; i0 += HALF) {
         const int i = i0 + il;
+        if (i0 > 0) point_loads(i);
         double fam = 0.0;
-        if (i < n && r) {
-            const int ki = urow[i];
-            fam = ki >= 0 ? ordered_dot<ORD>(U + ki, (size_t)nk, r, uc) : uc[~ki];
-        }
+        if (i < n && r) fam = ki >= 0 ? ordered_dot<ORD>(U + ki, (size_t)nk, r, uc) : uc[~ki];
         if (f == 1 && i < n) {
             double v = fam;
             if (t.variant == H2S_H2_PLUS_H && (mask & kVer)) {
@@ -719,10 +729,10 @@ __device__ __forceinline__ void down_leaf_body(const DevTree<P> &t, int leaf, do
         __syncthreads();
         if (f == 0 && i < n) {
             double phi = 0.0;
-            if (mask & kNear) phi = madd<ORD>(t.yn[b + i], t.shift, t.qt[b + i]);
+            if (mask & kNear) phi = madd<ORD>(yv, t.shift, qv);
             if (mask & kFar) phi = phi + fam;
             if (mask & kVer) phi = phi + ver_part[il];
-            y[t.perm[b + i]] = phi;
+            y[dst] = phi;
         }
         __syncthreads();
     }
@@ -840,7 +850,7 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
         if (prof) prof->mark(prof->ctx, cls, end, on);
     };
     const int32_t *lev_off = plan.lev_off;
-    const size_t lds_leaf = sizeof(double) * (size_t)(3 * t.max_leaf);
+    const size_t lds_leaf = sizeof(double) * (size_t)(2 * t.max_leaf);
     const size_t lds_rows = sizeof(double) * (size_t)(2 * t.max_rows);
     const size_t lds_rank = sizeof(double) * (size_t)(2 * t.max_rank);
     const bool fam_on = (mask & (kFar | kVer)) && t.kappa >= 1;

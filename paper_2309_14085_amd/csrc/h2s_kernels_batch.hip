@@ -398,7 +398,7 @@ constexpr int BMM_SRC = 64;  // staged source pivots per group
 constexpr int BMM_STEPS = 4; // 4-source product steps per iteration
 
 template <class P, bool FAR, int KIND, int D>
-__global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(4))) void kb_m2l_mfma(DevTree<P> t, int nblk)
+__global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(5))) void kb_m2l_mfma(DevTree<P> t, int nblk)
 {
     constexpr int GC = kGroupCols;
     constexpr int TPS = NT_BMM / BMM_SRC, CPT = GC / TPS; // staging: threads per source, columns per thread
@@ -410,11 +410,12 @@ __global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(4))) voi
     }();
     constexpr bool XW = kExtraCoord<KIND>;
     __shared__ double sx[BMM_SRC], sy[BMM_SRC], sz[D == 3 ? BMM_SRC : 1], sw[XW ? BMM_SRC : 1];
-    __shared__ double sv[BMM_SRC * GC]; // after the last group: the waves' partial tiles
+    constexpr int SVS = GC + 16; // row stride of sv: rows j and j + 1 in different bank halves
+    __shared__ double sv[BMM_SRC * SVS]; // after the last group: the waves' partial tiles
     __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList];
     __shared__ double tx[64], ty[64], tz[D == 3 ? 64 : 1], tw[XW ? 64 : 1]; // the round's target pivots
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
-    static_assert(BMM_SRC * GC >= 4 * 64 * 8, "partial tiles fit in the multipole buffer");
+    static_assert(BMM_SRC * SVS >= 4 * 64 * 8, "partial tiles fit in the multipole buffer");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     stage_table<KIND>(t.ktab, ktab); // first used after a barrier
@@ -481,7 +482,7 @@ __global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         const int sl = tid / TPS, part = tid % TPS;
 #pragma unroll
-        for (int k = 0; k < CPT; ++k) sv[sl * GC + part * CPT + k] = rv[k];
+        for (int k = 0; k < CPT; ++k) sv[sl * SVS + part * CPT + k] = rv[k];
     };
     const int ks = ntiles >= 3 ? 1 : 4 / ntiles; // waves per tile
     const int per_round = 4 / ks;
@@ -497,7 +498,7 @@ __global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(4))) voi
             if constexpr (XW) tw[tid] = F.pvw[c0 + ial];
         }
         double xa = 0.0, ya = 0.0, za = 0.0, wa = 0.0;
-        dbl4 a00 = {0.0, 0.0, 0.0, 0.0}, a01 = a00, a10 = a00, a11 = a00; // [step parity][column tile]
+        dbl4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = a0; // column tiles 0 and 1
         for (int gi = 0; gi < ngroups; ++gi) {
             const int pos = min(BMM_SRC, S - gi * BMM_SRC);
             __syncthreads(); // every wave is done with the previous group
@@ -513,15 +514,15 @@ __global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(4))) voi
             }
             if (act) {
                 // this wave's 4-source steps: part, part + ks, ... (BMM_STEPS per iteration, all inside
-                // the staged group since BMM_SRC is a multiple of 4 * BMM_STEPS * ks); step parity picks
-                // the accumulator
+                // the staged group since BMM_SRC is a multiple of 4 * BMM_STEPS * ks); one accumulator
+                // per column tile (dependent 16x16x4 products issue back to back)
                 for (int j0 = 4 * part; j0 < pos; j0 += 4 * BMM_STEPS * ks) {
                     double kv[BMM_STEPS], v0[BMM_STEPS], v1[BMM_STEPS];
 #pragma unroll
                     for (int u = 0; u < BMM_STEPS; ++u) {
                         const int j = j0 + 4 * ks * u + lk;
-                        v0[u] = sv[j * GC + li];
-                        v1[u] = sv[j * GC + 16 + li];
+                        v0[u] = sv[j * SVS + li];
+                        v1[u] = sv[j * SVS + 16 + li];
                         kv[u] = kval_pos<KIND>(
                             add_extra<KIND>(dist2<false, D>(xa - sx[j], ya - sy[j], za - (D == 3 ? sz[j] : 0.0)), wa,
                                             XW ? sw[j] : 0.0),
@@ -529,18 +530,18 @@ __global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(4))) voi
                     }
 #pragma unroll
                     for (int u = 0; u < BMM_STEPS; u += 2) {
-                        a00 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u], v0[u], a00, 0, 0, 0);
-                        a10 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u + 1], v0[u + 1], a10, 0, 0, 0);
+                        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u], v0[u], a0, 0, 0, 0);
+                        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u + 1], v0[u + 1], a0, 0, 0, 0);
                         if (two) {
-                            a01 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u], v1[u], a01, 0, 0, 0);
-                            a11 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u + 1], v1[u + 1], a11, 0, 0, 0);
+                            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u], v1[u], a1, 0, 0, 0);
+                            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(kv[u + 1], v1[u + 1], a1, 0, 0, 0);
                         }
                     }
                 }
             }
         }
         __syncthreads(); // every wave is done with sv
-        const dbl4 t0 = a00 + a10, t1 = a01 + a11;
+        const dbl4 t0 = a0, t1 = a1;
         if (ks > 1) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {

@@ -26,8 +26,8 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=25)  # the clocks settle over the first ~20 products
     p.add_argument("--profile-steps", type=int, default=3)
     p.add_argument("--workload", default="2d_log_n1048576")
     p.add_argument("--no-cpu-baseline", action="store_true")

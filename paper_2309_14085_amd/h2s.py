@@ -180,11 +180,44 @@ class Tree:
     def handle(self):
         return self._h
 
+    def _check_shape(self, v, name, ncols=None):
+        """Reject a vector the kernels would read or write out of bounds: it must be a vector or
+        an (n, m) matrix with n rows (and ncols columns when given)."""
+        import torch
+        if not isinstance(v, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if v.dim() not in (1, 2) or v.shape[0] != self.n:
+            raise ValueError(f"{name} must have {self.n} rows (got shape {tuple(v.shape)})")
+        if v.dim() == 2 and v.shape[1] == 0:
+            raise ValueError(f"{name} has no columns")
+        if ncols is not None and (1 if v.dim() == 1 else v.shape[1]) != ncols:
+            raise ValueError(f"{name} must have {ncols} columns (got shape {tuple(v.shape)})")
+
+    @staticmethod
+    def _check_type(v, name):
+        import torch
+        if v.dtype != torch.float64 or not v.is_cuda:
+            raise TypeError(f"{name} must be a CUDA float64 tensor")
+
+    def _check_vec(self, v, name, ncols=None):
+        self._check_shape(v, name, ncols)
+        self._check_type(v, name)
+
+    def _out_ld(self, y, name, m):
+        """Leading dimension of an output y (checked like an input), which must be contiguous in
+        its rows (column-major)."""
+        self._check_vec(y, name, m)
+        if y.stride(0) != 1:
+            raise ValueError(f"{name} must be column-major (stride(0) == 1)")
+        return self.n if y.dim() == 1 or y.shape[1] == 1 else y.stride(1)
+
     def apply(self, x, y=None, mask=PHASE_ALL, stream=None):
         """y = K~ x for a CUDA float64 tensor x of shape (n,) or column-major (n, m)."""
         import torch
-        if x.dtype != torch.float64 or not x.is_cuda:
-            raise TypeError("x must be a CUDA float64 tensor")
+        self._check_shape(x, "x")
+        if y is not None:
+            self._check_shape(y, "y", 1 if x.dim() == 1 else x.shape[1])
+        self._check_type(x, "x")
         if x.dim() == 1:
             xx = x.contiguous()
             m, ldx = 1, self.n
@@ -195,7 +228,7 @@ class Tree:
         if y is None:
             y = torch.empty_strided(tuple(x.shape), (1,) if x.dim() == 1 else (1, self.n), dtype=torch.float64,
                                     device=x.device)
-        ldy = self.n if y.dim() == 1 or y.shape[1] == 1 else y.stride(1)
+        ldy = self._out_ld(y, "y", m)
         check(load().h2s_apply_phases(self._h, mask, ctypes.c_void_p(xx.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                       m, ldx, ldy, _stream_ptr(stream)))
         return y
@@ -211,8 +244,10 @@ class Tree:
 
         Returns (x, [info dict per right-hand side]).  NOT_CONVERGED raises unless raise_on_fail is False."""
         import torch
-        if b.dtype != torch.float64 or not b.is_cuda:
-            raise TypeError("b must be a CUDA float64 tensor")
+        self._check_shape(b, "b")
+        if x is not None:
+            self._check_shape(x, "x", 1 if b.dim() == 1 else b.shape[1])
+        self._check_type(b, "b")
         if b.dim() == 1:
             bb, m, ldb = b.contiguous(), 1, self.n
         else:
@@ -222,7 +257,7 @@ class Tree:
         if x is None:
             x = torch.zeros_like(bb) if bb.dim() == 1 else torch.zeros(
                 (m, self.n), dtype=torch.float64, device=b.device).t()
-        ldx = self.n if x.dim() == 1 or x.shape[1] == 1 else x.stride(1)
+        ldx = self._out_ld(x, "x", m)
         o = SolveOpts()
         check(load().h2s_solve_opts_default(ctypes.byref(o)))
         o.restart, o.rtol, o.inner_prec, o.inner_rtol = restart, rtol, inner_prec, inner_rtol
@@ -269,6 +304,10 @@ class Tree:
     def tune(self, x, y, reps=5, stream=None):
         """Autotune the launch schedule on device vectors x, y (CUDA float64, length n); y = K~ x on return.
         Returns {"ms_entry", "ms_tuned", "candidates"}."""
+        self._check_vec(x, "x", 1)
+        self._out_ld(y, "y", 1)
+        if x.dim() == 1 and x.stride(0) != 1:
+            raise ValueError("x must be contiguous")
         info = TuneInfo()
         check(load().h2s_tune(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), int(reps),
                               ctypes.byref(info), _stream_ptr(stream)))
@@ -316,6 +355,11 @@ class Group:
         n = len(self.trees)
         if len(xs) != n or len(ys) != n:
             raise ValueError("one x and one y per tree")
+        for T, x, y in zip(self.trees, xs, ys):
+            T._check_vec(x, "x", 1)
+            T._out_ld(y, "y", 1)
+            if x.stride(0) != 1:
+                raise ValueError("x must be contiguous")
         xa = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
         ya = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
         check(load().h2s_group_apply(self._h, xa, ya, _stream_ptr(stream)))

@@ -209,3 +209,27 @@ def test_group_validation(lib, inputs):
     assert so.h2s_group_create(arr, 2, ctypes.byref(h)) == lib.ERR_INVALID_ARG  # duplicate
     assert so.h2s_group_create(arr, 1, ctypes.byref(h)) == lib.ERR_UNSUPPORTED  # host_only
     assert so.h2s_group_free(None) == lib.OK
+
+
+def test_binding_rejects_vectors_of_the_wrong_shape_before_any_launch(lib):
+    """The binding checks every vector's rows, type and layout before it passes a pointer on:
+    a short x or y would otherwise be read or written past its end by the kernels."""
+    import torch
+    pts = np.random.default_rng(3).uniform(-1, 1, (300, 2))
+    T = lib.build(pts, leaf_size=32, eps=1e-6, host_only=True)
+    good = torch.zeros(300, dtype=torch.float64)
+    for bad in (torch.zeros(299, dtype=torch.float64), torch.zeros(301, dtype=torch.float64),
+                torch.zeros((299, 2), dtype=torch.float64), torch.zeros((300, 2, 1), dtype=torch.float64)):
+        with pytest.raises(ValueError):
+            T.apply(bad)
+        with pytest.raises(ValueError):
+            T.apply(good, y=bad)
+        with pytest.raises(ValueError):
+            T.solve(bad)
+    with pytest.raises(ValueError):
+        T.apply(torch.zeros((300, 2), dtype=torch.float64), y=torch.zeros((300, 3), dtype=torch.float64))
+    with pytest.raises(TypeError):  # right shape, but a host tensor
+        T.apply(good)
+    with pytest.raises(TypeError):
+        T.apply(good.float())
+    T.free()

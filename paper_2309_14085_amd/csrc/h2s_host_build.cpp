@@ -73,6 +73,14 @@ struct Cross {
     std::vector<int32_t> prow, pcol; // positions in I and J
 };
 
+// The iteration ends when ||u_p|| ||v_p|| <= eps ||S||_F (the condition of
+// Sec. 3.4) has held for kAcaRun successive terms.  Partial pivoting sees only
+// the rows and columns it visits, so a single small term can end it while the
+// residual elsewhere is still large (vertex-sharing blocks keep theirs on the
+// close pairs near the shared corner); six successive terms give the relative
+// errors of the paper's 2D and 3D MVP tables (smvp2d_lap_*, smvp3d_lap_*).
+constexpr int kAcaRun = 6;
+
 // `entry(a, b)` is K(I[a], J[b]).  `par` lets the elementwise loops use the
 // OpenMP team (used when few large approximations run one after another);
 // every reduction stays sequential so the result does not depend on it.
@@ -89,6 +97,7 @@ void cross_approx(const Entry &entry, int64_t nI, int64_t nJ, double eps, bool p
     std::vector<double> R(nJ);
     double s2 = 0.0;
     int64_t istar = 0;
+    int run = 0;  // successive terms whose norm met the tolerance
     const bool parJ = par && nJ >= 16384, parI = par && nI >= 16384;
     for (;;) {
         rowused[istar] = 1;
@@ -149,7 +158,8 @@ void cross_approx(const Entry &entry, int64_t nI, int64_t nJ, double eps, bool p
         c.prow.push_back((int32_t)istar);
         c.pcol.push_back((int32_t)jstar);
         c.rank = p + 1;
-        if (std::sqrt(nu2 * nv2) <= eps * std::sqrt(s2) || c.rank == maxr) break;
+        run = std::sqrt(nu2 * nv2) <= eps * std::sqrt(s2) ? run + 1 : 0;
+        if (run == kAcaRun || c.rank == maxr) break;
         int64_t inext = -1;
         best = -1.0;
         for (int64_t i = 0; i < nI; ++i)

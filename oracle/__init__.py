@@ -70,6 +70,8 @@ def _load():
     lib.orc_hph_pair.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, _i64p, _f64p, _f64p]
     lib.orc_tree_points.argtypes = [ctypes.c_void_p, _f64p]
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_import.restype = ctypes.c_void_p
+    lib.orc_import.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.orc_depth.restype = ctypes.c_int
     lib.orc_depth.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int64]
     _lib = lib
@@ -155,6 +157,26 @@ class Tree:
         info = np.zeros(6, np.int64)
         lib.orc_info(self._h, _p(info, _i64p))
         self.d, self.n, self.kappa, self.variant, self.nmax, self.total_boxes = (int(v) for v in info)
+
+    @classmethod
+    def from_export(cls, path, kind, param=0.0, diag=None, shift=0.0):
+        """Import mode: the representation another builder wrote to `path` (the library's
+        export container: tree, permutation, lists, pivots, FP64 operators, (H2+H)* factors),
+        for the kernel it was built with.  apply() then runs the MVP of Sec. 5.1.2 / 5.2.2 on
+        exactly those operators."""
+        lib = _load()
+        if diag is None:
+            diag = default_diag(kind)
+        h = lib.orc_import(str(path).encode(), kind, param, diag, shift)
+        if not h:
+            raise ValueError(f"oracle import rejected {path}")
+        self = cls.__new__(cls)
+        self.kind, self.param, self.diag, self.shift = kind, param, diag, shift
+        self._h = h
+        info = np.zeros(6, np.int64)
+        lib.orc_info(self._h, _p(info, _i64p))
+        self.d, self.n, self.kappa, self.variant, self.nmax, self.total_boxes = (int(v) for v in info)
+        return self
 
     def __del__(self):
         h = getattr(self, "_h", None)

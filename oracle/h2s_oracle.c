@@ -32,6 +32,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -1051,4 +1052,235 @@ int orc_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Import mode: the MVP on a representation another builder wrote           */
+/* ------------------------------------------------------------------------ */
+
+/* The container the library's export writes: "H2SX", uint32 version, uint32
+ * count, then per array a NUL-padded name[32], uint32 dtype (1 int32, 2 int64,
+ * 3 float64), uint32 ndim, int64 dims[ndim] and the data.  Boxes are numbered
+ * globally (level by level, Morton order inside a level); lists are CSR over
+ * global boxes; a family stores per box its rank, its pivots (offsets
+ * coef_off) and its operator (offsets op_off, op_rows rows): a leaf's U_X
+ * column-major n_X x r, a non-leaf's stacked transfers row-major (sum r_c) x r. */
+typedef struct { char name[33]; int dtype; int64_t count; void *data; } imp_arr;
+
+static void imp_free_all(imp_arr *a, int n)
+{
+    for (int i = 0; i < n; ++i) free(a[i].data);
+    free(a);
+}
+
+static const imp_arr *imp_get(const imp_arr *a, int n, const char *name, int dtype)
+{
+    for (int i = 0; i < n; ++i)
+        if (strcmp(a[i].name, name) == 0) return a[i].dtype == dtype ? &a[i] : NULL;
+    return NULL;
+}
+
+/* element e of an integer array as int64 */
+static int64_t imp_i(const imp_arr *a, int64_t e)
+{
+    return a->dtype == 1 ? (int64_t)((const int32_t *)a->data)[e] : ((const int64_t *)a->data)[e];
+}
+
+/* Read the arrays of `path`; returns the array list (count in *n) or NULL. */
+static imp_arr *imp_read(const char *path, int *n)
+{
+    FILE *f = fopen(path, "rb");
+    if (!f) return NULL;
+    char magic[4];
+    uint32_t version, count;
+    if (fread(magic, 1, 4, f) != 4 || memcmp(magic, "H2SX", 4) != 0 || fread(&version, 4, 1, f) != 1 ||
+        version != 1 || fread(&count, 4, 1, f) != 1 || count > 4096) {
+        fclose(f);
+        return NULL;
+    }
+    imp_arr *a = calloc(count ? count : 1, sizeof(imp_arr));
+    int ok = 1;
+    for (uint32_t i = 0; i < count && ok; ++i) {
+        uint32_t dt, nd;
+        if (fread(a[i].name, 1, 32, f) != 32 || fread(&dt, 4, 1, f) != 1 || fread(&nd, 4, 1, f) != 1 ||
+            dt < 1 || dt > 3 || nd > 4) { ok = 0; break; }
+        a[i].name[32] = 0;
+        a[i].dtype = (int)dt;
+        int64_t cnt = 1;
+        for (uint32_t k = 0; k < nd; ++k) {
+            int64_t dim;
+            if (fread(&dim, 8, 1, f) != 1 || dim < 0) { ok = 0; break; }
+            cnt *= dim;
+        }
+        if (!ok) break;
+        size_t es = dt == 1 ? 4 : 8;
+        a[i].count = cnt;
+        a[i].data = malloc(es * (size_t)(cnt ? cnt : 1));
+        if ((int64_t)fread(a[i].data, es, (size_t)cnt, f) != cnt) ok = 0;
+    }
+    fclose(f);
+    if (!ok) { imp_free_all(a, (int)count); return NULL; }
+    *n = (int)count;
+    return a;
+}
+
+/* Build an oracle tree from an export file and the kernel it was built for.
+ * The MVP (orc_apply) then runs the steps of Sec. 5.1.2 / 5.2.2 on exactly
+ * the exported tree, lists, pivots and operators.  Returns NULL if the file
+ * is missing or inconsistent. */
+orc_tree *orc_import(const char *path, int kind, double param, double diag, double shift)
+{
+    int na = 0;
+    imp_arr *a = imp_read(path, &na);
+    if (!a) return NULL;
+    const imp_arr *meta = imp_get(a, na, "meta", 2), *perm = imp_get(a, na, "perm", 1),
+                  *pts = imp_get(a, na, "points", 3), *lev_off = imp_get(a, na, "lev_off", 1),
+                  *bb = imp_get(a, na, "box_begin", 1), *be = imp_get(a, na, "box_end", 1),
+                  *bp = imp_get(a, na, "box_parent", 1), *bc = imp_get(a, na, "box_coord", 1),
+                  *bm = imp_get(a, na, "box_morton", 2), *pairs = imp_get(a, na, "pairs", 2),
+                  *pdata = imp_get(a, na, "pair_data", 3);
+    const char *lname[3] = {"near", "far", "ver"}, *fname[2] = {"far", "ver"};
+    const imp_arr *loff[3], *lidx[3], *frank[2], *fcoef[2], *frow[2], *fcol[2], *fopo[2], *fopr[2], *fop[2];
+    char nm[48];
+    int ok = meta && perm && pts && lev_off && bb && be && bp && bc && bm && pairs && pdata && meta->count == 4;
+    for (int w = 0; w < 3 && ok; ++w) {
+        snprintf(nm, sizeof nm, "%s_off", lname[w]); loff[w] = imp_get(a, na, nm, 2);
+        snprintf(nm, sizeof nm, "%s_idx", lname[w]); lidx[w] = imp_get(a, na, nm, 1);
+        ok = loff[w] && lidx[w];
+    }
+    for (int fm = 0; fm < 2 && ok; ++fm) {
+        snprintf(nm, sizeof nm, "fam_%s_rank", fname[fm]); frank[fm] = imp_get(a, na, nm, 1);
+        snprintf(nm, sizeof nm, "fam_%s_coef_off", fname[fm]); fcoef[fm] = imp_get(a, na, nm, 2);
+        snprintf(nm, sizeof nm, "fam_%s_piv_row", fname[fm]); frow[fm] = imp_get(a, na, nm, 1);
+        snprintf(nm, sizeof nm, "fam_%s_piv_col", fname[fm]); fcol[fm] = imp_get(a, na, nm, 1);
+        snprintf(nm, sizeof nm, "fam_%s_op_off", fname[fm]); fopo[fm] = imp_get(a, na, nm, 2);
+        snprintf(nm, sizeof nm, "fam_%s_op_rows", fname[fm]); fopr[fm] = imp_get(a, na, nm, 1);
+        snprintf(nm, sizeof nm, "fam_%s_op", fname[fm]); fop[fm] = imp_get(a, na, nm, 3);
+        ok = frank[fm] && fcoef[fm] && frow[fm] && fcol[fm] && fopo[fm] && fopr[fm] && fop[fm];
+    }
+    if (!ok) { imp_free_all(a, na); return NULL; }
+    const int64_t *mv = meta->data;
+    int d = (int)mv[0], kappa = (int)mv[1];
+    int64_t n = mv[2];
+    if ((d != 2 && d != 3) || kappa < 0 || kappa > 30 || n < 1 || perm->count != n || pts->count != n * d ||
+        lev_off->count != kappa + 2) {
+        imp_free_all(a, na);
+        return NULL;
+    }
+    int64_t nbox = imp_i(lev_off, kappa + 1);
+    for (int w = 0; w < 3; ++w) ok = ok && loff[w]->count == nbox + 1;
+    for (int fm = 0; fm < 2; ++fm)
+        ok = ok && frank[fm]->count == nbox && fcoef[fm]->count == nbox + 1 && fopo[fm]->count == nbox + 1 &&
+             fopr[fm]->count == nbox;
+    ok = ok && bb->count == nbox && be->count == nbox && bp->count == nbox && bm->count == nbox &&
+         bc->count == 3 * nbox && pairs->count % 6 == 0;
+    if (!ok) { imp_free_all(a, na); return NULL; }
+
+    orc_tree *t = calloc(1, sizeof(orc_tree));
+    t->d = d; t->kappa = kappa; t->n = n; t->variant = (int)mv[3];
+    t->ker.kind = kind; t->ker.param = param; t->ker.diag = diag; t->ker.shift = shift;
+    t->perm = malloc(sizeof(int64_t) * n);
+    for (int64_t i = 0; i < n; ++i) t->perm[i] = imp_i(perm, i);
+    t->pts = malloc(sizeof(double) * n * d);
+    memcpy(t->pts, pts->data, sizeof(double) * n * d);
+    t->lev = calloc(kappa + 1, sizeof(olevel));
+    for (int l = 0; l <= kappa; ++l) {
+        olevel *L = &t->lev[l];
+        int64_t g0 = imp_i(lev_off, l), g1 = imp_i(lev_off, l + 1), nb = g1 - g0;
+        int64_t gp = l > 0 ? imp_i(lev_off, l - 1) : 0;
+        L->nbox = nb;
+        L->morton = malloc(sizeof(int64_t) * (nb ? nb : 1));
+        L->begin = malloc(sizeof(int64_t) * (nb ? nb : 1));
+        L->end = malloc(sizeof(int64_t) * (nb ? nb : 1));
+        L->parent = malloc(sizeof(int64_t) * (nb ? nb : 1));
+        L->cbeg = calloc(nb ? nb : 1, sizeof(int64_t));
+        L->cend = calloc(nb ? nb : 1, sizeof(int64_t));
+        L->coord = malloc(sizeof(int32_t) * (nb ? nb : 1) * d);
+        for (int64_t b = 0; b < nb; ++b) {
+            int64_t g = g0 + b;
+            L->morton[b] = imp_i(bm, g);
+            L->begin[b] = imp_i(bb, g);
+            L->end[b] = imp_i(be, g);
+            L->parent[b] = l > 0 ? imp_i(bp, g) - gp : -1;
+            for (int c = 0; c < d; ++c) L->coord[b * d + c] = (int32_t)imp_i(bc, 3 * g + c);
+        }
+        for (int w = 0; w < 3; ++w) {
+            int64_t e0 = imp_i(loff[w], g0), e1 = imp_i(loff[w], g1);
+            L->off[w] = malloc(sizeof(int64_t) * (nb + 1));
+            L->idx[w] = malloc(sizeof(int64_t) * (e1 > e0 ? e1 - e0 : 1));
+            for (int64_t b = 0; b <= nb; ++b) L->off[w][b] = imp_i(loff[w], g0 + b) - e0;
+            for (int64_t e = e0; e < e1; ++e) L->idx[w][e - e0] = imp_i(lidx[w], e) - g0;
+        }
+    }
+    for (int l = 0; l < kappa; ++l) {
+        olevel *L = &t->lev[l], *C = &t->lev[l + 1];
+        for (int64_t c = 0; c < C->nbox; ++c) {
+            int64_t p = C->parent[c];
+            if (p < 0 || p >= L->nbox) { ok = 0; break; }
+            if (L->cend[p] == 0) L->cbeg[p] = c;
+            L->cend[p] = c + 1;
+        }
+    }
+    /* bases: leaf U_X stays column-major; stacked transfers turn from row-major to column-major */
+    for (int fm = 0; fm < 2 && ok; ++fm) {
+        for (int l = 1; l <= kappa; ++l) {
+            olevel *L = &t->lev[l];
+            int64_t g0 = imp_i(lev_off, l);
+            L->fam[fm] = calloc(L->nbox ? L->nbox : 1, sizeof(obasis));
+            for (int64_t x = 0; x < L->nbox; ++x) {
+                obasis *B = &L->fam[fm][x];
+                int64_t g = g0 + x, r = imp_i(frank[fm], g), c0 = imp_i(fcoef[fm], g);
+                int64_t o0 = imp_i(fopo[fm], g), rows = imp_i(fopr[fm], g);
+                B->rank = r;
+                B->row = malloc(sizeof(int64_t) * (r ? r : 1));
+                B->col = malloc(sizeof(int64_t) * (r ? r : 1));
+                for (int64_t k = 0; k < r; ++k) { B->row[k] = imp_i(frow[fm], c0 + k); B->col[k] = imp_i(fcol[fm], c0 + k); }
+                B->nrow_op = r ? rows : 0;
+                B->ncol_op = r;
+                B->op = malloc(sizeof(double) * (r > 0 && rows > 0 ? rows * r : 1));
+                if (!r) continue;
+                if (o0 + rows * r > fop[fm]->count) { ok = 0; break; }
+                const double *src = (const double *)fop[fm]->data + o0;
+                if (l == kappa) {
+                    memcpy(B->op, src, sizeof(double) * rows * r);
+                } else {
+                    for (int64_t i = 0; i < rows; ++i)
+                        for (int64_t b = 0; b < r; ++b) B->op[b * rows + i] = src[i * r + b];
+                }
+            }
+            if (!ok) break;
+        }
+    }
+    /* (H2+H)* pairs: level, x, y (global ids), rank, offsets of Ub and Vb */
+    int64_t npr = pairs->count / 6;
+    for (int l = 0; l <= kappa; ++l) { t->lev[l].npair = 0; t->lev[l].pair = NULL; }
+    for (int64_t p = 0; p < npr && ok; ++p) {
+        int l = (int)imp_i(pairs, 6 * p);
+        if (l < 1 || l > kappa) { ok = 0; break; }
+        t->lev[l].npair++;
+    }
+    for (int l = 0; l <= kappa; ++l)
+        t->lev[l].pair = calloc(t->lev[l].npair ? t->lev[l].npair : 1, sizeof(ohph));
+    int64_t *fill = calloc(kappa + 1, sizeof(int64_t));
+    for (int64_t p = 0; p < npr && ok; ++p) {
+        int l = (int)imp_i(pairs, 6 * p);
+        olevel *L = &t->lev[l];
+        int64_t g0 = imp_i(lev_off, l);
+        ohph *H = &L->pair[fill[l]++];
+        H->x = imp_i(pairs, 6 * p + 1) - g0;
+        H->y = imp_i(pairs, 6 * p + 2) - g0;
+        H->rank = imp_i(pairs, 6 * p + 3);
+        int64_t ou = imp_i(pairs, 6 * p + 4), ov = imp_i(pairs, 6 * p + 5);
+        if (H->x < 0 || H->x >= L->nbox || H->y < 0 || H->y >= L->nbox) { ok = 0; break; }
+        int64_t nx = L->end[H->x] - L->begin[H->x], ny = L->end[H->y] - L->begin[H->y];
+        if (ou + nx * H->rank > pdata->count || ov + ny * H->rank > pdata->count) { ok = 0; break; }
+        H->ub = malloc(sizeof(double) * (nx * H->rank > 0 ? nx * H->rank : 1));
+        H->vb = malloc(sizeof(double) * (ny * H->rank > 0 ? ny * H->rank : 1));
+        memcpy(H->ub, (const double *)pdata->data + ou, sizeof(double) * nx * H->rank);
+        memcpy(H->vb, (const double *)pdata->data + ov, sizeof(double) * ny * H->rank);
+    }
+    free(fill);
+    imp_free_all(a, na);
+    if (!ok) { orc_free(t); return NULL; }
+    return t;
 }

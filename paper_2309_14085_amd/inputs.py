@@ -86,3 +86,38 @@ def scaled(w: Workload, n: int, seed_offset: int = 0) -> Workload:
     """The same workload recipe at another size (and optionally other seeds)."""
     return Workload(w.name + f"_n{n}", w.d, n, w.kind, w.param, w.diag, w.shift, w.nmax, w.eps, w.nrhs,
                     w.seed_points + seed_offset, w.seed_rhs + seed_offset, dict(w.extra))
+
+
+def clustered_points(n: int, d: int, seed: int, clusters: int = 6, frac: float = 0.7,
+                     width: float = 0.01) -> np.ndarray:
+    """Points whose leaves are very uneven: a fraction `frac` of them in `clusters` tight Gaussian
+    clusters of standard deviation `width` (clipped to [-1, 1]^d), the rest uniform.  With the
+    paper's depth rule (the average leaf holds n_max) this leaves many boxes empty and puts far
+    more than n_max points into the clusters' leaves.  Two points are pinned at opposite corners
+    so the bounding cube is [-1, 1]^d."""
+    rng = np.random.default_rng(seed)
+    nc = int(frac * n)
+    centres = rng.uniform(-0.9, 0.9, size=(clusters, d))
+    which = rng.integers(0, clusters, size=nc)
+    pc = np.clip(centres[which] + width * rng.standard_normal(size=(nc, d)), -1.0, 1.0)
+    pu = rng.uniform(-1.0, 1.0, size=(n - nc, d))
+    out = np.concatenate([pc, pu])[rng.permutation(n)]
+    out[0], out[1] = -1.0, 1.0
+    return np.ascontiguousarray(out)
+
+
+def with_coincident_points(points: np.ndarray, copies: int, seed: int) -> np.ndarray:
+    """The same set with `copies` of its points repeated exactly (coincident pairs, which the
+    kernels give the diagonal value), appended in a seeded order."""
+    rng = np.random.default_rng(seed)
+    src = rng.choice(len(points), size=copies, replace=False)
+    return np.ascontiguousarray(np.concatenate([points, points[src]]))
+
+
+def face_grid_points(m: int, d: int) -> np.ndarray:
+    """The m^d tensor grid of equally spaced points -1 + 2k/(m-1), k = 0 .. m-1: with m - 1 a
+    power of two every coordinate is a dyadic fraction, so many points lie exactly on the faces
+    of the tree's boxes (the root cube is [-1, 1]^d).  Row-major (m^d, d), last coordinate fastest."""
+    nodes = -1.0 + 2.0 * np.arange(m) / (m - 1)
+    axes = np.meshgrid(*([nodes] * d), indexing="ij")
+    return np.ascontiguousarray(np.stack([a.ravel() for a in axes], axis=1))

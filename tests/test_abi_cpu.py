@@ -233,3 +233,32 @@ def test_binding_rejects_vectors_of_the_wrong_shape_before_any_launch(lib):
     with pytest.raises(TypeError):
         T.apply(good.float())
     T.free()
+
+
+@pytest.mark.parametrize("d,kind,variant", [(2, 0, 0), (2, 0, 1), (3, 1, 0), (3, 1, 1)])
+def test_oracle_import_of_the_library_export(lib, orc, inputs, tmp_path, d, kind, variant):
+    """The oracle's import mode reads the library's export and runs its own MVP on it.  The host
+    build takes the same integer decisions as the oracle's build, so the imported product equals
+    the oracle's own product bit for bit, part by part; this pins the reader (layouts, offsets,
+    the row-major to column-major turn of the stacked transfers, the (H2+H)* factors)."""
+    n = 3000
+    pts = inputs.uniform_points(n, d, 321 + d)
+    q = inputs.normal_rhs(n, 1, 654)[:, 0]
+    T = lib.build(pts, kind=kind, leaf_size=32, eps=1e-8, variant=variant, shift=0.5, host_only=True)
+    path = tmp_path / "rep.h2sx"
+    T.export(path)
+    T.free()
+    imp = orc.Tree.from_export(path, kind, shift=0.5)
+    own = orc.Tree(pts, kind, 32, 1e-8, variant=variant, shift=0.5)
+    assert (imp.kappa, imp.variant, imp.n) == (own.kappa, variant, n)
+    for a, b in zip(imp.apply_parts(q), own.apply_parts(q)):
+        assert np.array_equal(a, b)
+
+
+def test_oracle_import_rejects_a_damaged_file(orc, tmp_path):
+    p = tmp_path / "bad.h2sx"
+    p.write_bytes(b"H2SX" + b"\x01\x00\x00\x00" + b"\x05\x00\x00\x00" + b"\x00" * 20)
+    with pytest.raises(ValueError):
+        orc.Tree.from_export(p, 0)
+    with pytest.raises(ValueError):
+        orc.Tree.from_export(tmp_path / "missing.h2sx", 0)

@@ -26,3 +26,16 @@ def test_uniform_points_and_rhs_are_seeded():
     q = inputs.normal_rhs(1000, 4, 6)
     assert q.shape == (1000, 4) and q.flags.f_contiguous
     assert not np.array_equal(q[:, 0], q[:, 1])
+
+
+def test_irregular_point_sets():
+    from paper_2309_14085_amd import inputs
+    a = inputs.clustered_points(20000, 2, 11)
+    assert a.shape == (20000, 2) and np.all(np.abs(a) <= 1.0)
+    assert np.array_equal(a, inputs.clustered_points(20000, 2, 11))
+    assert a.min() == -1.0 and a.max() == 1.0
+    b = inputs.with_coincident_points(a, 50, 12)
+    assert b.shape == (20050, 2) and len(np.unique(b, axis=0)) == len(np.unique(a, axis=0))
+    g = inputs.face_grid_points(33, 2)
+    assert g.shape == (33 * 33, 2) and g.min() == -1.0 and g.max() == 1.0
+    assert np.all((g * 16) == np.round(g * 16))  # dyadic: on the faces of boxes down to level 4

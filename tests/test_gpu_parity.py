@@ -1,8 +1,11 @@
 """GPU parity: the HIP MVP (through the C ABI) against the FP64 oracle, element by element.
 
 Bars: FP64 <= 1e-12 relative 2-norm per phase and in total; FP32 <= 1e-5
-against the FP64 oracle product.  Inputs are the seeded synthetic workloads
-(uniform points in [-1,1]^d, N(0,1) right-hand sides).
+against the FP64 oracle product.  Beside the 2-norm, the largest elementwise
+difference relative to the largest element (`relmax`) must be <= 1e-11 in FP64
+(<= 1e-4 in FP32): a single wrong leaf of a large vector moves the 2-norm too
+little to fail it.  Inputs are the seeded synthetic workloads (uniform points in
+[-1,1]^d, N(0,1) right-hand sides).
 """
 import numpy as np
 import pytest
@@ -28,6 +31,17 @@ def lib():
 def rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def relmax(a, b):
+    mb = np.abs(b).max()
+    return np.abs(a - b).max() / (mb if mb > 0 else 1.0)
+
+
+def check64(got, want, what=""):
+    e2, em = rel(got, want), relmax(got, want)
+    assert e2 <= 1e-12 and em <= 1e-11, (what, e2, em)
+    return e2, em
 
 
 def gpu_apply(T, q, mask=7):
@@ -63,11 +77,28 @@ def test_fp64_matches_oracle_per_phase(lib, orc, inputs, case, variant):
     near, far, ver = O.apply_parts(q)
     T = lib.build(pts, kind=kind, leaf_size=nmax, eps=eps, variant=variant, param=param, shift=shift)
     total = near + far + ver
-    assert rel(gpu_apply(T, q, lib.PHASE_NEAR), near) <= 1e-12
+    check64(gpu_apply(T, q, lib.PHASE_NEAR), near, "near")
     if np.any(far):
-        assert rel(gpu_apply(T, q, lib.PHASE_FAR), far) <= 1e-12
-    assert rel(gpu_apply(T, q, lib.PHASE_VER), ver) <= 1e-12
-    assert rel(gpu_apply(T, q), total) <= 1e-12
+        check64(gpu_apply(T, q, lib.PHASE_FAR), far, "far")
+    check64(gpu_apply(T, q, lib.PHASE_VER), ver, "ver")
+    check64(gpu_apply(T, q), total, "total")
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fp64_2d_32768_several_pair_chunks_per_phase(lib, orc, inputs, variant):
+    """2D log r, N = 2^15, n_max 64: each level-1 box holds about 8192 points, so the (H2+H)*
+    vertex blocks of level 1 span several 2048-row chunks of the pair kernels."""
+    n = 1 << 15
+    print(f"2^15 per phase variant {variant}", flush=True)
+    pts = inputs.uniform_points(n, 2, 31)
+    q = inputs.normal_rhs(n, 1, 32)[:, 0]
+    O = orc.Tree(pts, 0, 64, 1e-8, variant=variant)
+    near, far, ver = O.apply_parts(q)
+    T = lib.build(pts, kind=0, leaf_size=64, eps=1e-8, variant=variant)
+    for mask, want, what in ((lib.PHASE_NEAR, near, "near"), (lib.PHASE_FAR, far, "far"),
+                             (lib.PHASE_VER, ver, "ver"), (lib.PHASE_ALL, near + far + ver, "total")):
+        e2, em = check64(gpu_apply(T, q, mask), want, what)
+        print(f"  {what}: {e2:.2e} (max {em:.2e})", flush=True)
 
 
 @pytest.mark.parametrize("n,nmax", [(1, 64), (50, 64), (200, 64), (257, 64)])
@@ -83,7 +114,7 @@ def test_degenerate_sizes(lib, orc, inputs, n, nmax, variant):
     if n == 1:
         assert got[0] == want[0] == 0.0
     else:
-        assert rel(got, want) <= 1e-12
+        check64(got, want)
 
 
 def test_multi_rhs_with_leading_dimension(lib, orc, inputs):
@@ -101,7 +132,7 @@ def test_multi_rhs_with_leading_dimension(lib, orc, inputs):
     torch.cuda.synchronize()
     y = yb.cpu().numpy()
     for c in range(m):
-        assert rel(y[c * ld:c * ld + n], O.apply(Q[:, c])) <= 1e-12
+        check64(y[c * ld:c * ld + n], O.apply(Q[:, c]), c)
         assert np.all(y[c * ld + n:(c + 1) * ld] == 7.0)  # padding untouched
 
 
@@ -116,9 +147,10 @@ def test_fp32_within_1e5_of_fp64_oracle(lib, orc, inputs, d, kind, eps, variant)
     q = inputs.normal_rhs(n, 1, 600 + d)[:, 0]
     O = orc.Tree(pts, kind, 64, eps, variant=variant, param=param, shift=shift)
     T = lib.build(pts, kind=kind, leaf_size=64, eps=eps, variant=variant, prec=lib.FP32, param=param, shift=shift)
-    err = rel(gpu_apply(T, q), O.apply(q))
+    got, want = gpu_apply(T, q), O.apply(q)
+    err = rel(got, want)
     print(f"fp32 d={d} kind={kind} variant={variant}: rel err vs fp64 oracle {err:.2e}", flush=True)
-    assert err <= 1e-5
+    assert err <= 1e-5 and relmax(got, want) <= 1e-4
 
 
 @pytest.mark.parametrize("d,kind,eps", [(2, 0, 1e-8), (3, 1, 1e-6)])
@@ -141,25 +173,50 @@ def test_fp64_65536_matches_oracle(lib, orc, inputs):
     q = inputs.normal_rhs(n, 1, 2001)[:, 0]
     O = orc.Tree(pts, 0, 64, 1e-8)
     T = lib.build(pts, kind=0, leaf_size=64, eps=1e-8)
-    assert rel(gpu_apply(T, q), O.apply(q)) <= 1e-12
+    check64(gpu_apply(T, q), O.apply(q))
 
 
-@pytest.mark.timeout(600)
-def test_full_size_2d_config_matches_oracle(lib, orc, inputs):
-    """N = 2^20, 2D log r, n_max 64, eps 1e-8: the benchmarked launch configuration,
-    FP64 against the full oracle product and FP32 against the same."""
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("variant", [0, 1])
+def test_full_size_2d_config_matches_oracle(lib, orc, inputs, variant):
+    """N = 2^20, 2D log r, n_max 64, eps 1e-8: the benchmarked launch configuration, H2* and
+    (H2+H)*, FP64 per phase and in total against the oracle, FP32 against the same total."""
     w = inputs.workload(1)
     pts, q = w.points(), w.rhs()[:, 0]
-    print("building oracle at N=2^20", flush=True)
-    O = orc.Tree(pts, w.kind, w.nmax, w.eps)
-    want = O.apply(q)
+    print(f"building oracle at N=2^20, variant {variant}", flush=True)
+    O = orc.Tree(pts, w.kind, w.nmax, w.eps, variant=variant)
+    near, far, ver = O.apply_parts(q)
     del O
+    want = near + far + ver
     print("building library at N=2^20", flush=True)
-    T = lib.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps)
-    err64 = rel(gpu_apply(T, q), want)
+    T = lib.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps, variant=variant)
+    for mask, part, what in ((lib.PHASE_NEAR, near, "near"), (lib.PHASE_FAR, far, "far"),
+                             (lib.PHASE_VER, ver, "ver"), (lib.PHASE_ALL, want, "total")):
+        e2, em = check64(gpu_apply(T, q, mask), part, what)
+        print(f"  fp64 {what}: {e2:.2e} (max {em:.2e})", flush=True)
     del T
-    T32 = lib.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps, prec=lib.FP32)
-    err32 = rel(gpu_apply(T32, q), want)
-    print(f"full size: fp64 {err64:.2e} fp32 {err32:.2e}", flush=True)
-    assert err64 <= 1e-12
-    assert err32 <= 1e-5
+    T32 = lib.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps, variant=variant, prec=lib.FP32)
+    got32 = gpu_apply(T32, q)
+    err32, em32 = rel(got32, want), relmax(got32, want)
+    print(f"  fp32 total: {err32:.2e} (max {em32:.2e})", flush=True)
+    assert err32 <= 1e-5 and em32 <= 1e-4
+
+
+@pytest.mark.parametrize("d,kind,n,nmax,eps", [(2, 0, 1 << 17, 64, 1e-8), (3, 1, 40000, 64, 1e-6)])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_fp64_matches_oracle_imported_from_the_export(lib, orc, inputs, tmp_path, d, kind, n, nmax, eps, variant):
+    """The library's product against the oracle's MVP run on the library's own export (the
+    oracle's import mode): the comparison holds for whatever tree, pivots and operators the
+    library built, not only while its build takes the oracle's decisions."""
+    print(f"import parity d={d} n={n} variant={variant}", flush=True)
+    pts = inputs.uniform_points(n, d, 4100 + d)
+    q = inputs.normal_rhs(n, 1, 4200 + d)[:, 0]
+    T = lib.build(pts, kind=kind, leaf_size=nmax, eps=eps, variant=variant)
+    path = tmp_path / "rep.h2sx"
+    T.export(path)
+    O = orc.Tree.from_export(path, kind)
+    near, far, ver = O.apply_parts(q)
+    for mask, want, what in ((lib.PHASE_NEAR, near, "near"), (lib.PHASE_FAR, far, "far"),
+                             (lib.PHASE_VER, ver, "ver"), (lib.PHASE_ALL, near + far + ver, "total")):
+        e2, em = check64(gpu_apply(T, q, mask), want, what)
+        print(f"  {what}: {e2:.2e} (max {em:.2e})", flush=True)

@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks used for the roofline fraction.
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -240,29 +241,64 @@ def time_serving(count=24, rate=4.0, workers=4, budget=16 << 30):
 def algorithmic_work(stats, kernel, prec):
     """Algorithmic HBM bytes and kernel evaluations of one launch of a kernel class.
 
-    Bytes count each operator entry, coordinate, charge and output once:
-    leaf bases sum_X n_X r_X entries, transfers sum_X (sum_c r_c) r_X entries,
-    points d FP64 (FP32 in the FP32 policies) per point, charges, near-field
-    potentials, y and perm."""
+    Bytes count each stored operator entry, coordinate, charge and output once:
+    P2M and L2P each read one copy of the stored leaf bases (the rows that are
+    not exact unit rows), M2M and L2L one copy of the stored transfers; points
+    d FP64 (FP32 in the FP32 policies) per point, charges, near-field
+    potentials, y, perm and the int16 row maps.  Evaluations are the near-field
+    pairs (ordered leaf pairs of N*, as Sec. 5.1.2 sums them) and the M2L
+    entries sum_X sum_{Y in IL(X)} r_X r_Y."""
     n, d = stats["n"], stats["d"]
     basis_b = 8 if prec == 0 else 4
     pt_b = 8 if prec == 0 else 4
-    leaf = stats["leaf_basis_entries"]
+    leaf = stats["leaf_basis_stored"] or stats["leaf_basis_entries"]
+    tr = stats["transfer_stored"] or stats["transfer_entries"]
     if kernel == "near":
         return n * (d * pt_b + 8 + 8), stats["p2p_evals"]
     if kernel == "leaf_down":
-        return n * (8 + 8 + 4 + 8) + leaf * basis_b, 0
+        return n * (8 + 8 + 4 + 4 + 8) + leaf * basis_b, 0
     if kernel == "leaf_up":
-        return n * (8 + 4 + 8) + leaf * basis_b, 0
+        return n * (8 + 4 + 8 + 4) + leaf * basis_b, 0
     if kernel == "m2l_far":
         return 0, stats["m2l_evals_family"][0]
     if kernel == "m2l_ver":
         return 0, stats["m2l_evals_family"][1]
     if kernel in ("m2m", "l2l"):
-        return stats["transfer_entries"] * 8, 0
+        return tr * 8, 0
     if kernel == "pair_part":
         return stats["pair_entries"] * basis_b, 0
     return 0, 0
+
+
+CLASSES = ("leaf_up", "m2m", "m2l_far", "m2l_ver", "l2l", "pair_part", "leaf_down", "near")
+
+
+def product_roofline(stats, kernels, ms, r_eval, prec):
+    """Whole-product roofline: T* = max(B / BW_peak, E / R_eval), B the algorithmic bytes and E the
+    kernel evaluations of every phase (algorithmic_work summed over the classes the product runs),
+    BW_peak the published 8 TB/s and R_eval the measured register-resident evaluation rate of the
+    same kernel function.  frac = T* / t_MVP; `binding` names the larger term.  Per-class
+    fractions use each class's isolated time from the profiling hooks."""
+    B = E = 0
+    per = {}
+    for c in CLASSES:
+        if c not in kernels:
+            continue
+        b, e = algorithmic_work(stats, c, prec)
+        B, E = B + b, E + e
+        t = kernels[c]["avg_ms"] * kernels[c]["launches_per_step"] * 1e-3
+        if e:
+            per[c] = {"bound": "alu", "evals": e, "ms": t * 1e3, "geval_s": e / t / 1e9, "frac": e / t / r_eval}
+        elif b:
+            per[c] = {"bound": "hbm", "bytes": b, "ms": t * 1e3, "gb_s": b / t / 1e9, "frac": b / t / 1e9 / HBM_PEAK_GBS}
+    t_hbm = B / (HBM_PEAK_GBS * 1e9)
+    t_eval = E / r_eval
+    t_star = max(t_hbm, t_eval)
+    return {"t_star_ms": t_star * 1e3, "t_mvp_ms": ms, "frac": t_star / (ms * 1e-3),
+            "binding": "alu (kernel evaluations)" if t_eval >= t_hbm else "hbm",
+            "bytes": B, "evals": E, "t_hbm_ms": t_hbm * 1e3, "t_eval_ms": t_eval * 1e3,
+            "r_eval_measured": r_eval, "bw_peak_gb_s": HBM_PEAK_GBS,
+            "frac_if_no_overlap": (t_hbm + t_eval) / (ms * 1e-3), "per_kernel": per}
 
 
 def main():
@@ -310,10 +346,20 @@ def main():
     main_name = "h2star_fp64" if "h2star_fp64" in res else next(iter(res))
     m = res[main_name]
     kernels = m["kernels"]
+    prec_main = 0 if main_name.endswith("fp64") else 1
+    r_eval = h2s.eval_rate(w.kind, w.d, h2s.FP64 if prec_main == 0 else h2s.FP32, param=w.param)
+    print(f"# measured R_eval: {r_eval:.4e} evaluations/s", file=sys.stderr, flush=True)
     roofline = None
     if kernels:
         dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches_per_step"])
-        roofline = roofline_entry(dom, kernels[dom], m["stats"], 0 if main_name.endswith("fp64") else 1)
+        roofline = roofline_entry(dom, kernels[dom], m["stats"], prec_main, r_eval)
+        if not a.profile_only:
+            roofline["whole_product"] = product_roofline(m["stats"], kernels, m["ms"], r_eval, prec_main)
+        for name in res:
+            if name != main_name and res[name]["kernels"] and not a.profile_only:
+                pv = 0 if name.endswith("fp64") else 1
+                res[name]["whole_product"] = product_roofline(res[name]["stats"], res[name]["kernels"],
+                                                              res[name]["ms"], r_eval, pv)
 
     tuned = None
     if not a.no_tune and main_name == "h2star_fp64":
@@ -347,10 +393,20 @@ def main():
 
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline(pts, q, w)
+        print("# oracle on the host cores: build, MVPs at all and at 8 threads, sampled direct sum",
+              file=sys.stderr, flush=True)
+        cpu, oracle_out = cpu_baseline(pts, q, w, want_hph="h2plush_fp64" in outs)
+        for name, y in outs.items():
+            ref_o = oracle_out["h2plush" if name.startswith("h2plush") else "h2star"]
+            if ref_o is not None:
+                res[name]["rel_err_vs_oracle"] = float(np.linalg.norm(y - ref_o) / np.linalg.norm(ref_o))
+                res[name]["max_rel_err_vs_oracle"] = float(np.abs(y - ref_o).max() / np.abs(ref_o).max())
+            rows, exact = oracle_out["rows"], oracle_out["direct_rows"]
+            res[name]["rel_err_vs_direct_sampled"] = float(np.linalg.norm(y[rows] - exact) / np.linalg.norm(exact))
+        cpu["oracle_rel_err_vs_direct_sampled"] = oracle_out["oracle_vs_direct"]
 
     line = {
-        "metric": "H2* MVP points/s (FP64, rel err vs FP64 oracle <= 1e-12)",
+        "metric": "H2* MVP points/s and % roofline at stated rel err vs FP64; solve p50/p99",
         "value": m["points_per_s"],
         "unit": "points/s",
         "n_gpus": 1,
@@ -364,6 +420,8 @@ def main():
         "data": "synthetic: uniform points in [-1,1]^2 (seed 1001), N(0,1) rhs (seed 2001)",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "kernel": "log r (K_ii = 0)", "leaf_size": w.nmax,
                    "nca_tol": w.eps, "nrhs": 1, "variant": "H2*(b+t)"},
+        "rel_err_vs_oracle": m.get("rel_err_vs_oracle"),
+        "rel_err_vs_direct_sampled": m.get("rel_err_vs_direct_sampled"),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "tuned_schedule": tuned,
@@ -382,7 +440,7 @@ def main():
     print(json.dumps(line))
 
 
-def roofline_entry(name, k, stats, prec):
+def roofline_entry(name, k, stats, prec, r_eval=None):
     """Roofline of the dominant kernel class (one launch per step for the leaf and M2L classes).
 
     Kernel-evaluation classes are bound by FP64 VALU issue: the chip issues
@@ -398,10 +456,15 @@ def roofline_entry(name, k, stats, prec):
         per_eval = VALU_PER_EVAL.get(name, VALU_PER_EVAL["near"])
         peak = VALU_LANE_ISSUE_PER_S / per_eval / 1e9
         ach = evals / avg_s / 1e9
-        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": peak, "unit": "Geval/s",
-                "frac": ach / peak, "traffic": traffic, "evals_per_launch": evals,
-                "valu_instr_per_eval": per_eval, "avg_launch_ms": k["avg_ms"],
-                "fp64_tflops": ach * FP64_FLOPS_PER_EVAL / 1e3, "fp64_flops_per_eval": FP64_FLOPS_PER_EVAL}
+        out = {"kernel": name, "bound": "alu", "achieved": ach, "peak": peak, "unit": "Geval/s",
+               "frac": ach / peak, "traffic": traffic, "evals_per_launch": evals,
+               "valu_instr_per_eval": per_eval, "avg_launch_ms": k["avg_ms"],
+               "fp64_tflops": ach * FP64_FLOPS_PER_EVAL / 1e3, "fp64_flops_per_eval": FP64_FLOPS_PER_EVAL,
+               "frac_of_fp64_peak": ach * FP64_FLOPS_PER_EVAL / 1e3 / FP64_PEAK_TFLOPS}
+        if r_eval:
+            out["r_eval_measured_geval_s"] = r_eval / 1e9
+            out["frac_of_measured_r_eval"] = ach / (r_eval / 1e9)
+        return out
     ach = byts / avg_s / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": byts, "avg_launch_ms": k["avg_ms"]}
@@ -446,23 +509,63 @@ def measured_traffic(kernel):
     return None if k is None else k["fetch"] + k["write"]
 
 
-def cpu_baseline(pts, q, w):
-    """The oracle's H2* MVP on the host cores (build untimed), same inputs."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pts, q, w, want_hph=False, direct_rows=1024):
+    """The oracle's H2* MVP on the host cores (build untimed), same inputs: the median of 2 MVPs
+    with every host thread and again with 8 threads (the paper's thread count), and the oracle's
+    compensated direct sum on `direct_rows` seeded rows (scaled to the full product).  Returns the
+    record and the oracle's products (H2*, and (H2+H)* if asked) with the sampled direct rows, for
+    the GPU results' errors."""
     import numpy as np
 
     import oracle
+    oracle.set_threads(0)
+    all_threads = oracle.num_threads()
     t0 = time.perf_counter()
     T = oracle.Tree(pts, w.kind, w.nmax, w.eps)
     t_build = time.perf_counter() - t0
-    times = []
-    for _ in range(2):
-        t0 = time.perf_counter()
-        T.apply(q)
-        times.append(time.perf_counter() - t0)
-    t = float(np.median(times))
-    return {"value": w.n / t, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"full workload {w.name}: oracle FP64 H2* build ({t_build:.1f} s, untimed) then "
-                      f"{len(times)} MVPs, median {t:.2f} s"}
+
+    def mvps(threads):
+        oracle.set_threads(threads)
+        times, y = [], None
+        for _ in range(2):
+            t0 = time.perf_counter()
+            y = T.apply(q)
+            times.append(time.perf_counter() - t0)
+        return float(np.median(times)), y
+
+    t_all, y_h2 = mvps(0)
+    t_8, _ = mvps(8)
+    oracle.set_threads(0)
+    del T
+    y_hph = None
+    if want_hph:
+        y_hph = oracle.Tree(pts, w.kind, w.nmax, w.eps, variant=1).apply(q)
+    rows = np.sort(np.random.default_rng(7).choice(w.n, direct_rows, replace=False))
+    t0 = time.perf_counter()
+    exact = oracle.direct(pts, q, w.kind, param=w.param, shift=w.shift, rows=rows)
+    t_dir = time.perf_counter() - t0
+    rec = {"value": w.n / t_all, "unit": "points/s", "cores": all_threads, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"full workload {w.name}: oracle FP64 H2* build ({t_build:.1f} s, untimed) then 2 MVPs, "
+                     f"median {t_all:.2f} s with {all_threads} threads",
+           "threads_8": {"value": w.n / t_8, "mvp_s": t_8, "cores": 8},
+           "direct_sum": {"rows": direct_rows, "seconds": t_dir, "cores": all_threads,
+                          "full_product_s_est": t_dir * w.n / direct_rows,
+                          "points_per_s_est": direct_rows / t_dir},
+           "build_s": t_build}
+    out = {"h2star": y_h2, "h2plush": y_hph, "rows": rows, "direct_rows": exact,
+           "oracle_vs_direct": float(np.linalg.norm(y_h2[rows] - exact) / np.linalg.norm(exact))}
+    return rec, out
 
 
 if __name__ == "__main__":

@@ -191,6 +191,8 @@ typedef struct {
     double build_seconds;         /* host build wall time */
     int32_t rank_max_level[2][32];
     double rank_avg_level[2][32];
+    int64_t leaf_basis_stored;    /* leaf-basis entries stored on the device (rows other than exact unit rows), one copy */
+    int64_t transfer_stored;      /* the same for the stacked transfers */
 } h2s_stats;
 
 /* Sizes, ranks per level and work counts of a handle. */
@@ -207,6 +209,21 @@ h2s_status h2s_get_stats(h2s_tree t, h2s_stats *s);
  * column-major, stacked L2L row-major), pairs (level, x, y, rank, off_u,
  * off_v per (H2+H)* pair) and pair_data. */
 h2s_status h2s_export(h2s_tree t, const char *path);
+
+/* Measurement: the peak rate R_eval of the device kernel function, the
+ * ceiling of the phases that evaluate kernel values on the fly (the near
+ * field of Sec. 5.1.2 and the M2L blocks T_{X,Y} = K(t^{X,i}, t^{Y,i}) of
+ * Sec. 3.4.3).  A register-resident loop: every thread holds 4 targets and 8
+ * sources in registers and sums K(x, y) q over them pass after pass, with the
+ * lookup table of the table-driven functions in LDS as in the product
+ * kernels, so nothing but the evaluation itself limits it.  kernel: kind and
+ * param as for h2s_build (diag and shift unused); d in {2, 3} (3 for the NTI
+ * multiquadric); prec H2S_FP64 (the double functions of the FP64 product) or
+ * H2S_FP32 (the float functions of the FP32 near field).  Writes the fastest
+ * of five timed launches, in evaluations per second, to *evals_per_s.
+ * Synchronises `stream`; allocates and frees a small device buffer.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+h2s_status h2s_eval_rate(const h2s_kernel *kernel, int32_t d, int32_t prec, double *evals_per_s, void *stream);
 
 /* Kernel classes timed by the profiling hooks, in launch order. */
 #define H2S_PROF_LEAF_UP 0   /* charges to tree order + P2M */

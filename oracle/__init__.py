@@ -70,6 +70,7 @@ def _load():
     lib.orc_hph_pair.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, _i64p, _f64p, _f64p]
     lib.orc_tree_points.argtypes = [ctypes.c_void_p, _f64p]
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
     lib.orc_import.restype = ctypes.c_void_p
     lib.orc_import.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.orc_depth.restype = ctypes.c_int
@@ -135,6 +136,11 @@ def depth(n, d, nmax):
 
 def num_threads():
     return _load().orc_num_threads()
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops from now on (n <= 0: every host core)."""
+    _load().orc_set_threads(int(n))
 
 
 class Tree:

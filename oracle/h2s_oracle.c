@@ -1045,6 +1045,16 @@ void orc_hph_pair(const orc_tree *t, int l, int64_t p, int64_t *info, double *ub
 /* tree-order points (n x d) */
 void orc_tree_points(const orc_tree *t, double *out) { memcpy(out, t->pts, sizeof(double) * t->n * t->d); }
 
+/* Threads of the oracle's parallel loops (n <= 0: all the host offers). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -16,7 +16,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = os.environ.get("H2S_OFFLOAD_ARCH", "gfx950")
 
 HOST_SRC = ["h2s_host_build.cpp", "h2s_api.cpp", "h2s_solve.cpp"]
-HIP_SRC = ["h2s_kernels.hip", "h2s_kernels_batch.hip", "h2s_blas.hip"]
+HIP_SRC = ["h2s_kernels.hip", "h2s_kernels_batch.hip", "h2s_blas.hip", "h2s_eval_rate.hip"]
 
 
 def _run(cmd, verbose):

@@ -20,6 +20,7 @@
 #include "h2s.h"
 #include "h2s_blas.hpp"
 #include "h2s_device.hpp"
+#include "h2s_eval_rate.hpp"
 #include "h2s_host.hpp"
 #include "h2s_solve.hpp"
 
@@ -38,6 +39,45 @@ h2s_status fail(h2s_status s, const std::string &msg)
 }
 
 int default_alloc(void *, size_t bytes, void **p) { return hipMalloc(p, bytes) == hipSuccess ? 0 : 1; }
+
+// Lookup table of the device kernel function (extended precision, rounded once).
+std::vector<double> kernel_table(int kind)
+{
+    std::vector<double> tab;
+    if (kind == H2S_K_LOG_R || kind == H2S_K_RBF_LOG) {
+        // 0.5 ln x by table reduction: subinterval i of m in [1/2, 1) has centre
+        // z_i = 1/2 + (i + 1/2)/512; store c_i = 1/z_i and -0.5 ln c_i
+        for (int i = 0; i < 256; ++i) {
+            const double c = 1.0 / (0.5 + (i + 0.5) / 512.0);
+            tab.push_back(c);
+            tab.push_back((double)(-0.5L * std::log((long double)c)));
+        }
+    } else if (kind == H2S_K_GAUSSIAN || kind == H2S_K_EXP_R) {
+        for (int j = 0; j < 64; ++j) tab.push_back((double)std::exp2((long double)j / 64.0L)); // 2^(j/64)
+    } else {
+        tab.assign(2, 0.0);
+    }
+    return tab;
+}
+
+// Scalar parameters of the device kernel function: kparam = -1/h^2 for the
+// Gaussian; for the piecewise RBFs of radius a, kc = (a^2, and the two branch
+// factors: a, 1/a for a/r | r/a; 1/log a, 1/(a log a - 1) for the log RBF).
+void kernel_scalars(int kind, double a, double &kparam, double kc[3])
+{
+    kparam = kind == H2S_K_GAUSSIAN ? -1.0 / (a * a) : 0.0;
+    kc[0] = kc[1] = kc[2] = 0.0;
+    if (kind == H2S_K_RBF_AR) {
+        kc[0] = a * a;
+        kc[1] = a;
+        kc[2] = 1.0 / a;
+    } else if (kind == H2S_K_RBF_LOG) {
+        const long double la = std::log((long double)a);
+        kc[0] = a * a;
+        kc[1] = (double)(1.0L / la);
+        kc[2] = (double)(1.0L / ((long double)a * la - 1.0L));
+    }
+}
 void default_free(void *, void *p) { (void)hipFree(p); }
 
 } // namespace
@@ -54,6 +94,7 @@ struct h2s_tree_s {
     std::vector<void *> allocs;
     size_t device_bytes = 0;
     int64_t operator_bytes = 0;
+    int64_t leaf_kept[2] = {0, 0}, transfer_kept[2] = {0, 0}; // stored (non-unit) operator entries per family
     std::vector<int32_t> lev_off;
     h2s::LaunchPlan plan{};
     h2s::DevTree<h2s::P64> t64{};
@@ -244,7 +285,7 @@ void box_centre(const h2s::HostRep &r, int32_t g, double *c)
 // `local`), both copies of the leaf bases and transfers, lists, work list.
 template <typename CT, typename BT>
 void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector<double> &ctr, bool local,
-                   h2s::DevFamily<CT, BT> &G, int64_t &op_bytes)
+                   h2s::DevFamily<CT, BT> &G, int64_t &op_bytes, int64_t &leaf_kept, int64_t &transfer_kept)
 {
     const h2s::Family &F = r.fam[f];
     const int d = r.d, kappa = r.kappa;
@@ -331,6 +372,7 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     G.upos = up.copy(upos);
     G.unk = up.copy(unk);
     op_bytes += (int64_t)(2 * sizeof(BT) * uoff.back());
+    leaf_kept = uoff.back();
     // transfers: the host keeps them row-major ((sum r_c) x r).  Row k of box g's transfer
     // belongs to child coefficient bf + k (bf = the first child's first coefficient).  With
     // nested pivots, the row of a child pivot that is also the box's row pivot a is e_a; rows
@@ -398,6 +440,7 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     G.tprow = up.copy(tprow);
     G.tpos = up.copy(tpos);
     op_bytes += (int64_t)(2 * sizeof(double) * toff.back());
+    transfer_kept = toff.back();
     const int w = f == 0 ? 1 : 2;
     std::vector<int32_t> ilo(nbox + 1);
     for (int32_t g = 0; g <= nbox; ++g) ilo[g] = (int32_t)r.list_off[w][g];
@@ -435,20 +478,7 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
     D.kind = r.ker.kind;
     D.diag = r.ker.diag;
     D.shift = r.ker.shift;
-    D.kparam = r.ker.kind == H2S_K_GAUSSIAN ? -1.0 / (r.ker.param * r.ker.param) : 0.0;
-    {
-        const double a = r.ker.param;
-        if (r.ker.kind == H2S_K_RBF_AR) {
-            D.kc[0] = a * a;
-            D.kc[1] = a;
-            D.kc[2] = 1.0 / a;
-        } else if (r.ker.kind == H2S_K_RBF_LOG) {
-            const long double la = std::log((long double)a);
-            D.kc[0] = a * a;
-            D.kc[1] = (double)(1.0L / la);
-            D.kc[2] = (double)(1.0L / ((long double)a * la - 1.0L));
-        }
-    }
+    kernel_scalars(r.ker.kind, r.ker.param, D.kparam, D.kc);
     D.variant = r.variant;
     D.max_leaf = 1;
     for (int32_t g = leaf0; g < nbox; ++g) D.max_leaf = std::max(D.max_leaf, r.box_end[g] - r.box_begin[g]);
@@ -525,8 +555,9 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
         D.near_off = up.copy(noff);
         D.near_idx = up.copy(nidx);
     }
-    upload_family(up, r, 0, ctr, sizeof(typename P::far_t) == 4, D.far, t->operator_bytes);
-    upload_family(up, r, 1, ctr, false, D.ver, t->operator_bytes);
+    upload_family(up, r, 0, ctr, sizeof(typename P::far_t) == 4, D.far, t->operator_bytes, t->leaf_kept[0],
+                  t->transfer_kept[0]);
+    upload_family(up, r, 1, ctr, false, D.ver, t->operator_bytes, t->leaf_kept[1], t->transfer_kept[1]);
     if (r.variant == H2S_H2_PLUS_H) {
         auto &Pr = D.pairs;
         const size_t np = r.pairs.size();
@@ -596,24 +627,7 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
     }
     D.qt = up.template zeros<double>(n);
     D.yn = up.template zeros<double>(n);
-    {
-        // tables of the kernel functions (extended precision, rounded once)
-        std::vector<double> tab;
-        if (r.ker.kind == H2S_K_LOG_R || r.ker.kind == H2S_K_RBF_LOG) {
-            // 0.5 ln x by table reduction: subinterval i of m in [1/2, 1) has centre
-            // z_i = 1/2 + (i + 1/2)/512; store c_i = 1/z_i and -0.5 ln c_i
-            for (int i = 0; i < 256; ++i) {
-                const double c = 1.0 / (0.5 + (i + 0.5) / 512.0);
-                tab.push_back(c);
-                tab.push_back((double)(-0.5L * std::log((long double)c)));
-            }
-        } else if (r.ker.kind == H2S_K_GAUSSIAN || r.ker.kind == H2S_K_EXP_R) {
-            for (int j = 0; j < 64; ++j) tab.push_back((double)std::exp2((long double)j / 64.0L)); // 2^(j/64)
-        } else {
-            tab.assign(2, 0.0);
-        }
-        D.ktab = up.copy(tab);
-    }
+    D.ktab = up.copy(kernel_table(r.ker.kind));
     if (up.st != H2S_OK) return up.st;
     if (hipStreamSynchronize(s) != hipSuccess) return fail(H2S_ERR_DEVICE, "stream synchronisation failed after upload");
     return H2S_OK;
@@ -1432,6 +1446,8 @@ h2s_status h2s_get_stats(h2s_tree t, h2s_stats *s)
         s->pair_entries += (int64_t)P.rank *
                            ((r.box_end[P.x] - r.box_begin[P.x]) + (r.box_end[P.y] - r.box_begin[P.y]));
     s->operator_bytes = t->operator_bytes;
+    s->leaf_basis_stored = t->leaf_kept[0] + t->leaf_kept[1];
+    s->transfer_stored = t->transfer_kept[0] + t->transfer_kept[1];
     s->device_bytes = (int64_t)t->device_bytes;
     s->build_seconds = r.build_seconds;
     return H2S_OK;
@@ -1467,6 +1483,59 @@ h2s_status h2s_get_profile(h2s_tree t, double *ms_total, int64_t *launches)
         if (ms_total) ms_total[i] = ms[i];
         if (launches) launches[i] = cnt[i];
     }
+    return H2S_OK;
+}
+
+h2s_status h2s_eval_rate(const h2s_kernel *k, int32_t d, int32_t prec, double *evals_per_s, void *stream)
+{
+    if (!k || !evals_per_s) return fail(H2S_ERR_INVALID_ARG, "kernel or output is NULL");
+    if (d != 2 && d != 3) return fail(H2S_ERR_INVALID_ARG, "d must be 2 or 3");
+    if (k->kind < H2S_K_LOG_R || k->kind > H2S_K_NTI_MQ) return fail(H2S_ERR_INVALID_ARG, "unknown kernel kind");
+    if (k->kind == H2S_K_NTI_MQ && d != 3) return fail(H2S_ERR_INVALID_ARG, "the NTI multiquadric is 3D only");
+    if (prec != H2S_FP64 && prec != H2S_FP32) return fail(H2S_ERR_INVALID_ARG, "prec must be FP64 or FP32");
+    if ((k->kind == H2S_K_GAUSSIAN || k->kind == H2S_K_RBF_AR || k->kind == H2S_K_RBF_LOG) &&
+        !(std::isfinite(k->param) && k->param > 0.0 && !(k->kind == H2S_K_RBF_LOG && k->param == 1.0)))
+        return fail(H2S_ERR_INVALID_ARG, "kernel parameter out of range");
+    hipStream_t s = (hipStream_t)stream;
+    const int blocks = 8192, passes = 64;
+    const std::vector<double> tab = kernel_table(k->kind);
+    double kparam, kc[3];
+    kernel_scalars(k->kind, k->param, kparam, kc);
+    double *dtab = nullptr, *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    h2s_status st = H2S_OK;
+    float best = 0.0f;
+    if (hipMalloc(&dtab, tab.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&out, h2s::eval_rate_outputs(blocks) * sizeof(double)) != hipSuccess) {
+        st = fail(H2S_ERR_OUT_OF_MEMORY, "device allocation failed");
+    } else if (hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s) !=
+                   hipSuccess ||
+               hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        st = fail(H2S_ERR_DEVICE, "HIP error before the timed launches");
+    } else {
+        // one untimed launch, then the fastest of five
+        for (int rep = 0; rep < 6 && st == H2S_OK; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess ||
+                h2s::launch_eval_rate(k->kind, d, prec == H2S_FP32, blocks, dtab, kparam, kc, passes, out, s) !=
+                    hipSuccess ||
+                hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = fail(H2S_ERR_DEVICE, "evaluation-rate launch failed");
+                break;
+            }
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = fail(H2S_ERR_DEVICE, "event timing failed");
+                break;
+            }
+            if (rep > 0 && (best == 0.0f || ms < best)) best = ms;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (out) (void)hipFree(out);
+    if (dtab) (void)hipFree(dtab);
+    if (st != H2S_OK) return st;
+    *evals_per_s = (double)h2s::eval_rate_evals(blocks, passes) / (best * 1e-3);
     return H2S_OK;
 }
 

@@ -43,7 +43,8 @@ class Stats(ctypes.Structure):
                 ("pair_entries", ctypes.c_int64),
                 ("operator_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("build_seconds", ctypes.c_double),
-                ("rank_max_level", (ctypes.c_int32 * 32) * 2), ("rank_avg_level", (ctypes.c_double * 32) * 2)]
+                ("rank_max_level", (ctypes.c_int32 * 32) * 2), ("rank_avg_level", (ctypes.c_double * 32) * 2),
+                ("leaf_basis_stored", ctypes.c_int64), ("transfer_stored", ctypes.c_int64)]
 
     def as_dict(self):
         out = {}
@@ -117,10 +118,11 @@ def load():
     lib.h2s_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
     lib.h2s_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
     lib.h2s_tune.argtypes = [vp, vp, vp, i32, ctypes.POINTER(TuneInfo), vp]
+    lib.h2s_eval_rate.argtypes = [ctypes.POINTER(Kernel), i32, i32, f64p, vp]
     for name in ("h2s_build", "h2s_apply", "h2s_apply_phases", "h2s_free", "h2s_get_stats", "h2s_export",
                  "h2s_set_allocator", "h2s_last_error", "h2s_set_profiling", "h2s_get_profile",
                  "h2s_solve_opts_default", "h2s_solve", "h2s_get_schedule", "h2s_set_schedule", "h2s_tune",
-                 "h2s_group_create", "h2s_group_apply", "h2s_group_free"):
+                 "h2s_group_create", "h2s_group_apply", "h2s_group_free", "h2s_eval_rate"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -379,6 +381,15 @@ def build(points, kind=LOG_R, leaf_size=64, eps=1e-8, eps_ver=None, variant=H2ST
     check(lib.h2s_build(pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n, d, ctypes.byref(k), ctypes.byref(o),
                         _stream_ptr(stream) if not host_only else ctypes.c_void_p(0), ctypes.byref(h)))
     return Tree(h, n, d)
+
+
+def eval_rate(kind=LOG_R, d=2, prec=FP64, param=0.0, stream=None):
+    """h2s_eval_rate: peak kernel evaluations per second of the device kernel function
+    (register-resident loop, fastest of five launches)."""
+    out = ctypes.c_double()
+    k = Kernel(kind, param, 0.0, 0.0)
+    check(load().h2s_eval_rate(ctypes.byref(k), d, prec, ctypes.byref(out), _stream_ptr(stream)))
+    return out.value
 
 
 _DT = {1: np.int32, 2: np.int64, 3: np.float64}

@@ -152,15 +152,16 @@ static double dot(const double *a, const double *b, int64_t n)
  *   - v_p = R / R_{j*};  u_p(i) = K(I_i, j*) - sum_{k<p} u_k(i) v_k(j*);
  *   - ||S||_F^2 += ||u_p||^2 ||v_p||^2 + 2 sum_{k<p} (u_k.u_p)(v_k.v_p);
  *   - the term is accepted; the iteration ends once ||u_p|| ||v_p|| <=
- *     eps ||S||_F has held for ACA_RUN successive terms, or when the rank
- *     reaches min(|I|, |J|).  The paper states the condition a term must meet,
- *     not how many terms must meet it.  One small term proves little under
- *     partial pivoting, which sees only the rows and columns it visits: on
- *     vertex-sharing blocks the residual sits on the few close pairs near
- *     the shared corner, and a single small term ends the iteration with the
- *     true error 10-100x above eps.  Six successive terms reproduce the
- *     relative errors the paper prints for its 2D and 3D MVP experiments
- *     (Tables smvp2d_lap_1..3, smvp3d_lap_1..3) to within a factor of 2;
+ *     eps ||S||_F has held for ACA_RUN successive terms (all of them kept),
+ *     or when the rank reaches min(|I|, |J|).  The paper states the
+ *     condition a term must meet, not how many terms must meet it.  One small
+ *     term proves little under partial pivoting, which sees only the rows and
+ *     columns it visits: on vertex-sharing blocks the residual sits on the
+ *     few close pairs near the shared corner, and a single small term ends
+ *     the iteration with the true error 10-100x above eps.  Six successive
+ *     terms reproduce the relative errors the paper prints for its 2D and 3D
+ *     MVP experiments (Tables smvp2d_lap_1..3, smvp3d_lap_1..3) to within a
+ *     factor of 2;
  *   - next row pivot = argmax of |u_p| over unused rows, first on ties.
  * eps = 0 runs to full rank.
  */
@@ -352,6 +353,7 @@ typedef struct orc_tree {
     double ctr[3], half, origin[3];
     int64_t *perm;  /* perm[t] = user index of tree position t */
     double *pts;    /* tree-order points, row-major n x d */
+    char *dup;      /* dup[t] = 1 if an earlier point of the same leaf coincides with point t */
     olevel *lev;    /* kappa + 1 levels */
 } orc_tree;
 
@@ -506,6 +508,15 @@ static void build_tree(orc_tree *t, const double *user_pts)
         }
     }
     free(key);
+    /* coincident points (exactly equal coordinates) share a leaf */
+    t->dup = calloc(n > 0 ? n : 1, 1);
+    {
+        const olevel *Lf = &t->lev[kappa];
+        for (int64_t b = 0; b < Lf->nbox; ++b)
+            for (int64_t i = Lf->begin[b]; i < Lf->end[b]; ++i)
+                for (int64_t j = Lf->begin[b]; j < i && !t->dup[i]; ++j)
+                    if (!t->dup[j] && memcmp(t->pts + i * d, t->pts + j * d, sizeof(double) * d) == 0) t->dup[i] = 1;
+    }
     for (int l = 0; l <= kappa; ++l) {
         olevel *L = &t->lev[l];
         L->parent = malloc(sizeof(int64_t) * (L->nbox ? L->nbox : 1));
@@ -603,7 +614,11 @@ static void build_lists(orc_tree *t)
  * of the children's row pivots, J = union over Y in IL_far(X) and over the
  * children of Y of their outgoing column pivots.  reading: the kernel is
  * symmetric, so the outgoing pivots are the incoming ones transposed
- * (s^{Y,o} = t^{Y,i}, Sec. 3.4.3 remark). */
+ * (s^{Y,o} = t^{Y,i}, Sec. 3.4.3 remark).  reading: coincident points give
+ * identical rows and columns of K, so I and J hold one point of each
+ * coincident set (the first in tree order); the others still get their rows
+ * of U_X from the same formula.  A second copy could otherwise be taken as a
+ * pivot on a rounding-level residual, which makes the pivot block singular. */
 static void far_pivots(orc_tree *t)
 {
     kctx c = {t};
@@ -616,10 +631,12 @@ static void far_pivots(orc_tree *t)
             int64_t *I = NULL, *J = NULL, nI = 0, nJ = 0, capI = 0, capJ = 0;
             if (L->off[LIST_FAR][x + 1] == L->off[LIST_FAR][x]) continue;
             if (l == t->kappa) {
-                for (int64_t i = L->begin[x]; i < L->end[x]; ++i) append(&I, &nI, &capI, &i, 1);
+                for (int64_t i = L->begin[x]; i < L->end[x]; ++i)
+                    if (!t->dup[i]) append(&I, &nI, &capI, &i, 1);
                 for (int64_t e = L->off[LIST_FAR][x]; e < L->off[LIST_FAR][x + 1]; ++e) {
                     int64_t y = L->idx[LIST_FAR][e];
-                    for (int64_t j = L->begin[y]; j < L->end[y]; ++j) append(&J, &nJ, &capJ, &j, 1);
+                    for (int64_t j = L->begin[y]; j < L->end[y]; ++j)
+                        if (!t->dup[j]) append(&J, &nJ, &capJ, &j, 1);
                 }
             } else {
                 olevel *C = &t->lev[l + 1];
@@ -643,7 +660,8 @@ static void far_pivots(orc_tree *t)
     }
 }
 
-/* T2B NCA on IL_ver (Sec. 5.1.1 step 2), levels 1 to kappa.
+/* T2B NCA on IL_ver (Sec. 5.1.1 step 2), levels 1 to kappa.  Coincident
+ * points enter I and J once, as for the far field.
  * I = t^X; J = union of t^Y over Y in IL_ver(X), then (l > 1) the parent's
  * incoming column pivots s^{P,i}.  reading: J is the union over all Y of the
  * set equations (the printed pseudocode overwrites J inside its loop);
@@ -658,10 +676,12 @@ static void ver_pivots(orc_tree *t)
         for (int64_t x = 0; x < L->nbox; ++x) {
             obasis *B = &L->fam[FAM_VER][x];
             int64_t *I = NULL, *J = NULL, nI = 0, nJ = 0, capI = 0, capJ = 0;
-            for (int64_t i = L->begin[x]; i < L->end[x]; ++i) append(&I, &nI, &capI, &i, 1);
+            for (int64_t i = L->begin[x]; i < L->end[x]; ++i)
+                if (!t->dup[i]) append(&I, &nI, &capI, &i, 1);
             for (int64_t e = L->off[LIST_VER][x]; e < L->off[LIST_VER][x + 1]; ++e) {
                 int64_t y = L->idx[LIST_VER][e];
-                for (int64_t j = L->begin[y]; j < L->end[y]; ++j) append(&J, &nJ, &capJ, &j, 1);
+                for (int64_t j = L->begin[y]; j < L->end[y]; ++j)
+                    if (!t->dup[j]) append(&J, &nJ, &capJ, &j, 1);
             }
             if (l > 1) {
                 const obasis *PB = &t->lev[l - 1].fam[FAM_VER][L->parent[x]];
@@ -821,7 +841,7 @@ void orc_free(orc_tree *t)
         free(L->morton); free(L->begin); free(L->end); free(L->parent);
         free(L->cbeg); free(L->cend); free(L->coord);
     }
-    free(t->lev); free(t->perm); free(t->pts);
+    free(t->lev); free(t->perm); free(t->pts); free(t->dup);
     free(t);
 }
 
@@ -913,20 +933,33 @@ void orc_apply(const orc_tree *t, const double *q_user, double *near_out, double
                 (void)C;
             }
         }
-        /* M2L: u_X = sum_{Y in IL(X)} T_{X,Y} v_Y, T_{X,Y} = K(t^{X,i}, t^{Y,i}) */
+        /* M2L: u_X = sum_{Y in IL(X)} T_{X,Y} v_Y, T_{X,Y} = K(t^{X,i}, t^{Y,i}).
+         * Each output is the sum over every Y of the list and every b, taken as an
+         * accurate dot product (the products' rounding errors from fma and the
+         * additions' from TwoSum, carried in a second sum: Ogita, Rump and Oishi,
+         * "Accurate sum and dot product", 2005), so it is the value of the sum
+         * as if it were computed in twice the working precision.  The bases'
+         * coefficients v can be large against u (interpolation operators of norm
+         * up to ~1e3), and a plain sum's rounding would then be what any two
+         * correct implementations disagree by. */
         for (int l = lmin; l <= kappa; ++l) {
             const olevel *L = &t->lev[l];
             for (int64_t x = 0; x < L->nbox; ++x) {
                 const obasis *B = &L->fam[fam][x];
-                for (int64_t e = L->off[wlist][x]; e < L->off[wlist][x + 1]; ++e) {
-                    int64_t y = L->idx[wlist][e];
-                    const obasis *BY = &L->fam[fam][y];
-                    for (int64_t a = 0; a < B->rank; ++a) {
-                        double s = 0.0;
-                        for (int64_t b = 0; b < BY->rank; ++b)
-                            s += K(t, B->row[a], BY->row[b]) * v[l][co[l][y] + b];
-                        u[l][co[l][x] + a] += s;
+                for (int64_t a = 0; a < B->rank; ++a) {
+                    double s = 0.0, c = 0.0;
+                    for (int64_t e = L->off[wlist][x]; e < L->off[wlist][x + 1]; ++e) {
+                        int64_t y = L->idx[wlist][e];
+                        const obasis *BY = &L->fam[fam][y];
+                        for (int64_t b = 0; b < BY->rank; ++b) {
+                            double kv = K(t, B->row[a], BY->row[b]), vb = v[l][co[l][y] + b];
+                            double p = kv * vb, ep = fma(kv, vb, -p);
+                            double sn = s + p, z = sn - s, es = (s - (sn - z)) + (p - z);
+                            s = sn;
+                            c += ep + es;
+                        }
                     }
+                    u[l][co[l][x] + a] = s + c;
                 }
             }
         }

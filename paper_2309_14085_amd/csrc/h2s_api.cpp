@@ -446,6 +446,36 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     for (int32_t g = 0; g <= nbox; ++g) ilo[g] = (int32_t)r.list_off[w][g];
     G.il_off = up.copy(ilo);
     G.il_idx = up.copy(r.list_idx[w]);
+    {
+        // symmetric M2L: the pair {X, Y}, X < Y, is evaluated by X's block, which writes its
+        // column sums (r_Y entries) to a slot of W that Y's entry for X points at
+        const std::vector<int32_t> &li = r.list_idx[w];
+        std::vector<int32_t> ulb(nbox + 1, 0);
+        std::vector<int64_t> pw(li.size() ? li.size() : 1, -1);
+        int64_t wsize = 0;
+        for (int32_t g = 0; g < nbox; ++g) {
+            int64_t e = r.list_off[w][g];
+            const int64_t e1 = r.list_off[w][g + 1];
+            while (e < e1 && li[e] < g) ++e;
+            ulb[g] = (int32_t)e;
+            for (; e < e1; ++e)
+                if (F.rank[g] > 0 && F.rank[li[e]] > 0) {
+                    pw[e] = wsize;
+                    wsize += F.rank[li[e]];
+                }
+        }
+        for (int32_t g = 0; g < nbox; ++g)
+            for (int64_t e = r.list_off[w][g]; e < ulb[g]; ++e) {
+                const int32_t x = li[e]; // below g: find g in x's list
+                const auto b0 = li.begin() + r.list_off[w][x], b1 = li.begin() + r.list_off[w][x + 1];
+                const auto it = std::lower_bound(b0, b1, g);
+                pw[e] = (it != b1 && *it == g) ? pw[it - li.begin()] : -1;
+            }
+        ulb[nbox] = (int32_t)li.size();
+        G.ul_beg = up.copy(ulb);
+        G.pw_off = up.copy(pw);
+        G.W = up.template zeros<double>(wsize ? 2 * wsize : 2);
+    }
     std::vector<int32_t> targets;
     for (int32_t g = 0; g < nbox; ++g)
         if (F.rank[g] > 0) targets.push_back(g);
@@ -455,6 +485,7 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     G.ncoef = (int32_t)nc;
     G.v = up.template zeros<double>(nc ? nc : 1);
     G.u = up.template zeros<double>(nc ? nc : 1);
+    G.ulo = up.template zeros<double>(nc ? nc : 1);
     (void)kappa;
 }
 
@@ -554,6 +585,29 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
         }
         D.near_off = up.copy(noff);
         D.near_idx = up.copy(nidx);
+        // symmetric near field: leaf X < X' evaluates the pair and writes n_X' column sums for X'
+        std::vector<int32_t> nself(nleaf ? nleaf : 1, 0);
+        std::vector<int64_t> nw(nidx.size() ? nidx.size() : 1, -1);
+        int64_t nws = 0;
+        for (int32_t lf = 0; lf < nleaf; ++lf) {
+            int32_t e = noff[lf];
+            while (e < noff[lf + 1] && nidx[e] < lf) ++e;
+            nself[lf] = e; // nidx[e] == lf: every leaf is in its own near list
+            for (int32_t u = e + 1; u < noff[lf + 1]; ++u) {
+                nw[u] = nws;
+                nws += r.box_end[leaf0 + nidx[u]] - r.box_begin[leaf0 + nidx[u]];
+            }
+        }
+        for (int32_t lf = 0; lf < nleaf; ++lf)
+            for (int32_t e = noff[lf]; e < nself[lf]; ++e) {
+                const int32_t x = nidx[e]; // below lf: its entry for lf holds the offset
+                const auto b0 = nidx.begin() + noff[x], b1 = nidx.begin() + noff[x + 1];
+                nw[e] = nw[std::lower_bound(b0, b1, lf) - nidx.begin()];
+            }
+        if (nws > INT32_MAX) return fail(H2S_ERR_UNSUPPORTED, "near-field column sums exceed 2^31 entries");
+        D.near_self = up.copy(nself);
+        D.near_w = up.copy(nw);
+        D.near_wv = up.template zeros<double>(nws ? nws : 1);
     }
     upload_family(up, r, 0, ctr, sizeof(typename P::far_t) == 4, D.far, t->operator_bytes, t->leaf_kept[0],
                   t->transfer_kept[0]);

@@ -76,6 +76,10 @@ template <typename CT, typename BT> struct DevFamily {
     const int16_t *tpos;         // per coefficient with a unit row: kept rows before that row
     const int32_t *il_off;       // nbox + 1
     const int32_t *il_idx;
+    const int32_t *ul_beg;       // per box: first entry of its list above it (the list is sorted)
+    const int64_t *pw_off;       // per list entry: W offset of the pair's column sums (-1: a rank is 0)
+    double *W;                   // column sums w_{X->Y} as (hi, lo) pairs (r_Y per pair X < Y, both ranks > 0)
+    double *ulo;                 // second part of the M2L row sums before the mirrored sums are added
     const int32_t *targets;      // boxes with rank > 0 at levels >= lmin, in box (so level) order
     int32_t ntargets;
     int32_t targets_leaf;        // index in targets of the first leaf-level box
@@ -115,7 +119,11 @@ template <class P> struct DevTree {
     const int32_t *box_begin, *box_end, *box_cbeg, *box_cend;
     const double *box_ctr;      // 3 per box
     const int32_t *leaf_anc;    // (kappa + 1) per leaf: ancestor at each level
-    const int32_t *near_off, *near_idx; // leaf-local CSR
+    const int32_t *near_off, *near_idx; // leaf-local CSR (sorted: leaves below, the leaf, leaves above)
+    const int32_t *near_self;   // per leaf: its own entry in the near list
+    const int64_t *near_w;      // per near entry: offset in near_wv of the pair's column sums (upper: written
+                                // by this leaf's block; lower: read by this leaf's L2P)
+    double *near_wv;            // column sums of the symmetric near field: n_X' entries per pair X < X'
     DevFamily<typename P::far_t, basis_t> far;
     DevFamily<double, basis_t> ver;
     DevPairs<basis_t> pairs;

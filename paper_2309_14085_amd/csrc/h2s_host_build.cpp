@@ -74,11 +74,12 @@ struct Cross {
 };
 
 // The iteration ends when ||u_p|| ||v_p|| <= eps ||S||_F (the condition of
-// Sec. 3.4) has held for kAcaRun successive terms.  Partial pivoting sees only
-// the rows and columns it visits, so a single small term can end it while the
-// residual elsewhere is still large (vertex-sharing blocks keep theirs on the
-// close pairs near the shared corner); six successive terms give the relative
-// errors of the paper's 2D and 3D MVP tables (smvp2d_lap_*, smvp3d_lap_*).
+// Sec. 3.4) has held for kAcaRun successive terms, all of them kept.  Partial
+// pivoting sees only the rows and columns it visits, so a single small term
+// can end it while the residual elsewhere is still large (vertex-sharing
+// blocks keep theirs on the close pairs near the shared corner); six
+// successive terms give the relative errors of the paper's 2D and 3D MVP
+// tables (smvp2d_lap_*, smvp3d_lap_*).
 constexpr int kAcaRun = 6;
 
 // `entry(a, b)` is K(I[a], J[b]).  `par` lets the elementwise loops use the
@@ -441,7 +442,25 @@ void level_pivots(const HostRep &rep, int l, double eps, PivotSets &ps, const Ma
 
 // B2T NCA on IL_far (Sec. 5.1.1 (1), Alg. "b2t"); reading: outgoing pivots are
 // the incoming ones transposed (symmetric kernels, Sec. 3.4.3 remark).
-void far_pivots(const HostRep &rep, PivotSets &ps)
+// Coincident points: dup[t] is 1 when an earlier point of t's leaf has the
+// same coordinates.  Their rows and columns of K are identical, so the cross
+// approximations of both families take one point of each coincident set;
+// otherwise a second copy can become a pivot on a rounding-level residual and
+// make the pivot block singular.
+std::vector<char> coincident(const HostRep &rep)
+{
+    const int d = rep.d;
+    std::vector<char> dup(rep.n, 0);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t g = rep.leaf0(); g < rep.nbox(); ++g)
+        for (int32_t i = rep.box_begin[g]; i < rep.box_end[g]; ++i)
+            for (int32_t j = rep.box_begin[g]; j < i && !dup[i]; ++j)
+                if (!dup[j] && std::memcmp(&rep.pts[(size_t)i * d], &rep.pts[(size_t)j * d], sizeof(double) * d) == 0)
+                    dup[i] = 1;
+    return dup;
+}
+
+void far_pivots(const HostRep &rep, const std::vector<char> &dup, PivotSets &ps)
 {
     const int kappa = rep.kappa;
     for (int l = kappa; l >= 2; --l) {
@@ -449,10 +468,12 @@ void far_pivots(const HostRep &rep, PivotSets &ps)
             const int64_t e0 = rep.list_off[1][x], e1 = rep.list_off[1][x + 1];
             if (e0 == e1) return;
             if (l == kappa) {
-                for (int32_t t = rep.box_begin[x]; t < rep.box_end[x]; ++t) I.push_back(t);
+                for (int32_t t = rep.box_begin[x]; t < rep.box_end[x]; ++t)
+                    if (!dup[t]) I.push_back(t);
                 for (int64_t e = e0; e < e1; ++e) {
                     const int32_t y = rep.list_idx[1][e];
-                    for (int32_t t = rep.box_begin[y]; t < rep.box_end[y]; ++t) J.push_back(t);
+                    for (int32_t t = rep.box_begin[y]; t < rep.box_end[y]; ++t)
+                        if (!dup[t]) J.push_back(t);
                 }
             } else {
                 for (int32_t c = rep.box_cbeg[x]; c < rep.box_cend[x]; ++c)
@@ -470,14 +491,16 @@ void far_pivots(const HostRep &rep, PivotSets &ps)
 // T2B NCA on IL_ver (Sec. 5.1.1 (2)); reading: J is the union over every
 // Y in IL_ver(X) (the printed loop keeps only the last Y) followed by the
 // parent's incoming column pivots not already in J.
-void vertex_pivots(const HostRep &rep, PivotSets &ps)
+void vertex_pivots(const HostRep &rep, const std::vector<char> &dup, PivotSets &ps)
 {
     for (int l = 1; l <= rep.kappa; ++l) {
         level_pivots(rep, l, rep.eps_ver, ps, [&](int32_t x, std::vector<int32_t> &I, std::vector<int32_t> &J) {
-            for (int32_t t = rep.box_begin[x]; t < rep.box_end[x]; ++t) I.push_back(t);
+            for (int32_t t = rep.box_begin[x]; t < rep.box_end[x]; ++t)
+                if (!dup[t]) I.push_back(t);
             for (int64_t e = rep.list_off[2][x]; e < rep.list_off[2][x + 1]; ++e) {
                 const int32_t y = rep.list_idx[2][e];
-                for (int32_t t = rep.box_begin[y]; t < rep.box_end[y]; ++t) J.push_back(t);
+                for (int32_t t = rep.box_begin[y]; t < rep.box_end[y]; ++t)
+                    if (!dup[t]) J.push_back(t);
             }
             if (l > 1) {
                 const size_t base = J.size();
@@ -622,10 +645,11 @@ h2s_status build_host(const double *points, int64_t n, int d, const KernelSpec &
         make_tree(rep, points, leaf_size);
         make_lists(rep);
         const int32_t total = rep.nbox();
+        const std::vector<char> dup = coincident(rep);
         PivotSets far;
         far.row.assign(total, {});
         far.col.assign(total, {});
-        far_pivots(rep, far);
+        far_pivots(rep, dup, far);
         rep.fam[0].lmin = 2;
         make_operators(rep, 0, far);
         rep.fam[1].lmin = 1;
@@ -633,7 +657,7 @@ h2s_status build_host(const double *points, int64_t n, int d, const KernelSpec &
             PivotSets ver;
             ver.row.assign(total, {});
             ver.col.assign(total, {});
-            vertex_pivots(rep, ver);
+            vertex_pivots(rep, dup, ver);
             make_operators(rep, 1, ver);
         } else {
             PivotSets none;

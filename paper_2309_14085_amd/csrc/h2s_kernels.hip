@@ -441,6 +441,198 @@ __global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t, int32_t t0
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric M2L.  The interaction lists are symmetric (Y in IL(X) iff X in
+// IL(Y)) and so are the coupling blocks: T_{Y,X} = K(t^{Y,i}, t^{X,i}) =
+// T_{X,Y}^T for a symmetric kernel (Sec. 3.4.3 and its remark on symmetric
+// kernels).  Each unordered pair is therefore evaluated once, by the block of
+// its lower box X, over the upper part of X's list (Y > X):
+//   u_X[a]      = sum over upper Y, b of K(a, b) v_Y[b]   (row sums)
+//   w_{X->Y}[b] = sum_a K(a, b) v_X[a]                     (column sums)
+// the column sums going to the pair's slot in W.  A second launch then adds to
+// u_Y the slots w_{X->Y} of every lower X in list order.  Every sum is an
+// accurate dot product kept as an unevaluated pair (hi, lo): each product's
+// rounding error from an fma, each addition's from TwoSum, gathered in lo
+// (Ogita, Rump and Oishi, "Accurate sum and dot product", 2005).  The
+// coefficients v can be large against u (interpolation operators of norm up
+// to ~1e3), so plain sums would leave errors of order eps sum |K v| that the
+// transfers then amplify; these sums are as if taken in twice the precision,
+// in a fixed order, without atomics.  The thread layout is the one-sided
+// M2L's (two targets per thread against a slice of the staged sources); each
+// thread leaves its two targets' share of a source's column sum in LDS, and
+// after the group the shares are added over the target pairs in order.
+// ---------------------------------------------------------------------------
+constexpr int NT_SYM = 256;
+constexpr int SYM_SPT = 4;    // staged sources per thread and group
+constexpr int SYM_GMAX = 256; // staged sources per group at most
+
+// (s, c) += a b: the product's and the addition's rounding errors go to c.
+__device__ __forceinline__ void dot2_add(double &s, double &c, double a, double b)
+{
+#pragma clang fp contract(off) // the error terms need the separately rounded product and sums
+    const double p = a * b, ep = fma(a, b, -p);
+    const double t = s + p, z = t - s, es = (s - (t - z)) + (p - z);
+    s = t;
+    c += ep + es;
+}
+
+// (s, c) += (h, l)
+__device__ __forceinline__ void dd_add(double &s, double &c, double h, double l)
+{
+#pragma clang fp contract(off)
+    const double t = s + h, z = t - s, es = (s - (t - z)) + (h - z);
+    s = t;
+    c += es + l;
+}
+
+template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2l_sym_body(const DevTree<P> &t, int ti)
+{
+    const auto &F = [&]() -> const auto & {
+        if constexpr (FAR) return t.far;
+        else return t.ver;
+    }();
+    constexpr bool XW = kExtraCoord<KIND>;
+    __shared__ double sx[SYM_GMAX], sy[SYM_GMAX], sz[D == 3 ? SYM_GMAX : 1], sv[SYM_GMAX], sw[XW ? SYM_GMAX : 1];
+    __shared__ int64_t sW[SYM_GMAX];
+    // [target pair][source of the group] shares (hi, lo) of the column sums; after the last group
+    // the slices' row sums (hi, lo) for the two targets
+    constexpr int CP = NT_SYM * SYM_SPT;
+    static_assert(CP >= 2 * NT_SYM, "the row sums fit in the column buffer");
+    __shared__ double colhi[CP], collo[CP];
+    __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList];
+    __shared__ int64_t boxw[kMaxList];
+    __shared__ __align__(16) double ktab[kTabLen<KIND>];
+    const int tid = threadIdx.x;
+    stage_table<KIND>(t.ktab, ktab); // first used after a barrier
+    const int g = F.targets[ti];
+    const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0; // r <= 2 NT_SYM (rank cap, checked at build)
+    const int eb = F.ul_beg[g], nil = F.il_off[g + 1] - eb;   // the upper part of IL(X)
+    const KPar<double> kp = kpar<double>(t);
+    // the sources of the upper list as slots 0 .. S-1 (as in the one-sided M2L); slot s of list
+    // box k has W index boxw[k] + s - boxoff[k]
+    for (int k = tid; k < nil; k += NT_SYM) {
+        const int y = F.il_idx[eb + k];
+        boxcoef[k] = F.coef_off[y];
+        boxoff[k + 1] = F.coef_off[y + 1] - F.coef_off[y];
+        boxw[k] = F.pw_off[eb + k];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        boxoff[0] = 0;
+        for (int k = 1; k <= nil; ++k) boxoff[k] += boxoff[k - 1];
+    }
+    __syncthreads();
+    const int S = nil > 0 ? boxoff[nil] : 0;
+    auto box_of = [&](int sl) -> int {
+        int lo = 0, hi = nil - 1; // largest k with boxoff[k] <= sl
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (boxoff[mid] <= sl) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    const int MT = r, NP = (MT + 1) / 2, NS = NT_SYM / NP;
+    const int G = min(NS * SYM_SPT, SYM_GMAX);
+    const int s = tid / NP, pa = tid % NP;
+    const int ia = pa, ib = pa + NP < MT ? ia + NP : ia; // a lone last target is paired with itself
+    const bool act = s < NS;
+    const double xa = F.pvx[c0 + ia], ya = F.pvy[c0 + ia], za = D == 3 ? (double)F.pvz[c0 + ia] : 0.0;
+    const double xb = F.pvx[c0 + ib], yb = F.pvy[c0 + ib], zb = D == 3 ? (double)F.pvz[c0 + ib] : 0.0;
+    const double wa = XW ? (double)F.pvw[c0 + ia] : 0.0, wb = XW ? (double)F.pvw[c0 + ib] : 0.0;
+    const double va = F.v[c0 + ia], vb = ib != ia ? F.v[c0 + ib] : 0.0;
+    double sa = 0.0, ca = 0.0, sb = 0.0, cb = 0.0;
+    for (int base = 0; base < S; base += G) {
+        const int take = min(S - base, G);
+        for (int j = tid; j < take; j += NT_SYM) {
+            const int k = box_of(base + j);
+            const int o = base + j - boxoff[k], c = boxcoef[k] + o;
+            sx[j] = F.pvx[c];
+            sy[j] = F.pvy[c];
+            if constexpr (D == 3) sz[j] = F.pvz[c];
+            if constexpr (XW) sw[j] = F.pvw[c];
+            sv[j] = F.v[c];
+            sW[j] = boxw[k] + o;
+        }
+        __syncthreads();
+        if (act) {
+            for (int j = s; j < take; j += NS) {
+                const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, v0 = sv[j];
+                const double w0 = XW ? sw[j] : 0.0;
+                const double ka = kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), wa, w0), kp, ktab);
+                const double kb = kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), wb, w0), kp, ktab);
+                dot2_add(sa, ca, ka, v0);
+                dot2_add(sb, cb, kb, v0);
+                double hs = 0.0, hc = 0.0;
+                dot2_add(hs, hc, ka, va);
+                dot2_add(hs, hc, kb, vb);
+                colhi[pa * G + j] = hs;
+                collo[pa * G + j] = hc;
+            }
+        }
+        __syncthreads();
+        for (int j = tid; j < take; j += NT_SYM) {
+            double hs = 0.0, hc = 0.0;
+            for (int p = 0; p < NP; ++p) dd_add(hs, hc, colhi[p * G + j], collo[p * G + j]);
+            F.W[2 * sW[j]] = hs;
+            F.W[2 * sW[j] + 1] = hc;
+        }
+        __syncthreads(); // the buffers are reused by the next group (and by the row sums below)
+    }
+    colhi[tid] = act ? sa : 0.0;
+    collo[tid] = act ? ca : 0.0;
+    colhi[NT_SYM + tid] = act ? sb : 0.0;
+    collo[NT_SYM + tid] = act ? cb : 0.0;
+    __syncthreads();
+    if (tid < NP) {
+        double ua = 0.0, uac = 0.0, ub = 0.0, ubc = 0.0;
+        for (int q = 0; q < NS; ++q) {
+            dd_add(ua, uac, colhi[q * NP + tid], collo[q * NP + tid]);
+            dd_add(ub, ubc, colhi[NT_SYM + q * NP + tid], collo[NT_SYM + q * NP + tid]);
+        }
+        F.u[c0 + ia] = ua;
+        F.ulo[c0 + ia] = uac;
+        if (ib != ia) {
+            F.u[c0 + ib] = ub;
+            F.ulo[c0 + ib] = ubc;
+        }
+    }
+}
+
+// u_Y = (its row sums) + w_{X->Y} for every X below Y in IL(Y), in list order, in (hi, lo)
+// pairs, rounded once at the end.
+template <class P, bool FAR> __device__ __forceinline__ void m2l_gather_body(const DevTree<P> &t, int ti)
+{
+    const auto &F = [&]() -> const auto & {
+        if constexpr (FAR) return t.far;
+        else return t.ver;
+    }();
+    const int g = F.targets[ti];
+    const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
+    const int e0 = F.il_off[g], eb = F.ul_beg[g];
+    for (int b = threadIdx.x; b < r; b += blockDim.x) {
+        double u = F.u[c0 + b], c = F.ulo[c0 + b];
+        for (int e = e0; e < eb; ++e) {
+            const int64_t w = F.pw_off[e];
+            if (w >= 0) dd_add(u, c, F.W[2 * (w + b)], F.W[2 * (w + b) + 1]);
+        }
+        F.u[c0 + b] = u + c;
+    }
+}
+
+constexpr int NT_GATHER = 64;
+
+template <class P, bool FAR, int KIND, int D>
+__global__ __launch_bounds__(NT_SYM) void k_m2l_sym(DevTree<P> t, int32_t t0)
+{
+    m2l_sym_body<P, FAR, KIND, D>(t, t0 + xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <class P, bool FAR> __global__ __launch_bounds__(NT_GATHER) void k_m2l_gather(DevTree<P> t, int32_t t0)
+{
+    m2l_gather_body<P, FAR>(t, t0 + (int)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
 // (H2+H)*: partial sums over one row chunk of G^T q, G = Vb over the rows of
 // Y (side 0: w = Vb^T q_Y) or Ub over the rows of X (side 1: w' = Ub^T q_X).
 // ---------------------------------------------------------------------------
@@ -651,12 +843,173 @@ template <class P, int KIND, int D> __device__ __forceinline__ void p2p_body(con
     }
 }
 
+// ---------------------------------------------------------------------------
+// Symmetric near field.  N* is symmetric (X' in N*(X) iff X in N*(X')) and so
+// is K, so the block of leaf X evaluates its own block and the blocks of the
+// near leaves above it once each:
+//   yn_X[i]        = sum over X and upper X', j of K(x_i, x_j) q_j       (row sums)
+//   w_{X->X'}[j]   = sum_i K(x_i, x_j) q_i  for the points j of upper X'  (column sums)
+// the column sums going to the pair's slot in the near-field W; L2P adds to
+// yn the slots of the near leaves below (in list order).  The layout is the
+// one-sided near field's (TPT targets per thread against a slice of the
+// staged sources); each thread leaves its targets' share of a source's
+// column sum in LDS and the sums over the target groups are taken in order.
+// ---------------------------------------------------------------------------
+constexpr int P2PS_SPT = 4;    // staged sources per thread and group
+constexpr int P2PS_GMAX = 256; // staged sources per group at most
+
+template <class P, int KIND, int D> __device__ __forceinline__ void p2p_sym_body(const DevTree<P> &t, int leaf)
+{
+    using PT = typename P::pt_t;
+    constexpr bool TAB = sizeof(PT) == 8;
+    constexpr int TPT = P2P_TPT;
+    constexpr bool XW = kExtraCoord<KIND>;
+    __shared__ PT sx[P2PS_GMAX], sy[P2PS_GMAX], sz[D == 3 ? P2PS_GMAX : 1], sq[P2PS_GMAX], sw[XW ? P2PS_GMAX : 1];
+    __shared__ int32_t sW[P2PS_GMAX]; // W position of a staged source of an upper leaf, -1 for the leaf's own
+    __shared__ PT colpart[NT_P2P * P2PS_SPT];
+    __shared__ double red[TPT * NT_P2P];
+    __shared__ __align__(16) double ktab[TAB ? kTabLen<KIND> : 2];
+    // the leaf itself and the near leaves above it in list order as slots 0 .. S-1 (slot s in
+    // entry e: nboff[e] <= s < nboff[e + 1], point nbbeg[e] + s - nboff[e]); entry 0 is the leaf
+    __shared__ int32_t nboff[kMaxList + 1], nbbeg[kMaxList], nbw[kMaxList], nbg[kMaxList];
+    const int tid = threadIdx.x;
+    const PT diag = (PT)t.diag;
+    const KPar<PT> kp = kpar<PT>(t);
+    if constexpr (TAB) stage_table<KIND>(t.ktab, ktab); // first used after a barrier
+    const int g = t.leaf0 + leaf;
+    const int b = t.box_begin[g], n = t.box_end[g] - b;
+    const double *cX = t.box_ctr + 3 * g;
+    const int eself = t.near_self[leaf], ne1 = t.near_off[leaf + 1];
+    const int nne = ne1 - eself; // the leaf and the leaves above it (<= kMaxList, checked at build)
+    for (int k = tid; k < nne; k += NT_P2P) {
+        const int gs = t.leaf0 + t.near_idx[eself + k];
+        nbbeg[k] = t.box_begin[gs];
+        nboff[k + 1] = t.box_end[gs] - t.box_begin[gs];
+        nbw[k] = k == 0 ? -1 : (int32_t)t.near_w[eself + k];
+        nbg[k] = gs;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        nboff[0] = 0;
+        for (int k = 0; k < nne; ++k) nboff[k + 1] += nboff[k];
+    }
+    __syncthreads();
+    const int S = nboff[nne], nown = nboff[1]; // slots [0, nown) are the leaf's own points
+    auto box_of = [&](int sl) -> int {
+        int lo = 0, hi = nne - 1; // largest e with nboff[e] <= sl
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (nboff[mid] <= sl) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    for (int i0 = 0; i0 < n; i0 += TPT * NT_P2P) {
+        // MT targets this pass in NP groups (a, a + NP, ...); NS source slices
+        const int MT = min(n - i0, TPT * NT_P2P), NP = (MT + TPT - 1) / TPT, NS = NT_P2P / NP;
+        const int G = min(NS * P2PS_SPT, P2PS_GMAX);
+        const int s = tid / NP, pa = tid % NP;
+        const bool act = s < NS;
+        int it[TPT];
+        PT tx[TPT], ty[TPT], tz[TPT], tw[TPT], tq[TPT];
+        double acc[TPT];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const bool real = pa + k * NP < MT;
+            it[k] = real ? i0 + pa + k * NP : i0 + pa; // a missing target repeats the first, with no charge
+            tx[k] = t.px[b + it[k]];
+            ty[k] = t.py[b + it[k]];
+            tz[k] = D == 3 ? t.pz[b + it[k]] : PT(0);
+            tw[k] = XW ? t.pw[b + it[k]] : PT(0);
+            tq[k] = real ? (PT)t.qt[b + it[k]] : PT(0);
+            acc[k] = 0.0;
+        }
+        for (int base = 0; base < S; base += G) {
+            const int take = min(S - base, G);
+            for (int j = tid; j < take; j += NT_P2P) {
+                const int e = box_of(base + j);
+                const int o = base + j - nboff[e], src = nbbeg[e] + o;
+                if constexpr (P::local) {
+                    const int gs = nbg[e];
+                    sx[j] = (PT)((t.box_ctr[3 * gs] - cX[0]) + (double)t.px[src]);
+                    sy[j] = (PT)((t.box_ctr[3 * gs + 1] - cX[1]) + (double)t.py[src]);
+                    if constexpr (D == 3) sz[j] = (PT)((t.box_ctr[3 * gs + 2] - cX[2]) + (double)t.pz[src]);
+                } else {
+                    sx[j] = t.px[src];
+                    sy[j] = t.py[src];
+                    if constexpr (D == 3) sz[j] = t.pz[src];
+                }
+                sq[j] = (PT)t.qt[src];
+                if constexpr (XW) sw[j] = t.pw[src];
+                sW[j] = e == 0 ? -1 : nbw[e] + o;
+            }
+            __syncthreads();
+            if (act) {
+                const int own_end = min(max(nown - base, 0), take); // own points: staged [0, own_end)
+                PT a[TPT]; // float policies: partial sums of the group in float, added to acc in double
+#pragma unroll
+                for (int k = 0; k < TPT; ++k) a[k] = PT(0);
+                for (int j = s; j < take; j += NS) {
+                    const PT x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : PT(0), q0 = sq[j];
+                    const PT w0 = XW ? sw[j] : PT(0);
+                    PT kv[TPT];
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) {
+                        const PT r2 = add_extra<KIND>(dist2<false, D>(tx[k] - x0, ty[k] - y0, tz[k] - z0), tw[k], w0);
+                        if constexpr (sizeof(PT) == 8) {
+                            // only the leaf's own points can coincide with a target
+                            kv[k] = j < own_end ? kval<KIND>(r2, diag, kp, ktab) : kval_pos<KIND>(r2, kp, ktab);
+                        } else {
+                            kv[k] = kval<KIND>(r2, diag, kp);
+                        }
+                    }
+                    PT c = PT(0);
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) {
+                        if constexpr (sizeof(PT) == 8) acc[k] = fma(kv[k], q0, acc[k]);
+                        else a[k] += kv[k] * q0;
+                        c = fma(kv[k], tq[k], c);
+                    }
+                    colpart[pa * G + j] = c;
+                }
+                if constexpr (sizeof(PT) != 8) {
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) acc[k] += (double)a[k];
+                }
+            }
+            __syncthreads();
+            for (int j = tid; j < take; j += NT_P2P) {
+                if (sW[j] < 0) continue;
+                double c = 0.0;
+                for (int p = 0; p < NP; ++p) c += (double)colpart[p * G + j];
+                // a leaf of more than TPT * NT_P2P points adds its later target passes to the first's
+                const double prev = i0 == 0 ? 0.0 : t.near_wv[sW[j]];
+                t.near_wv[sW[j]] = prev + c;
+            }
+            // the next group's staging writes sx .. sW only at indices this thread reads here, and
+            // colpart only after its barrier
+        }
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) red[k * NT_P2P + tid] = act ? acc[k] : 0.0;
+        __syncthreads();
+        if (tid < NP) {
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                double phi = 0.0;
+                for (int q = 0; q < NS; ++q) phi += red[k * NT_P2P + q * NP + tid];
+                if (k == 0 || it[k] != it[0]) t.yn[b + it[k]] = phi;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // leaves leaf_begin .. leaf_begin + gridDim.x - 1, one per block
 template <class P, int KIND, int D>
 __global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin, int32_t leaf_count)
 {
     (void)leaf_count; // == gridDim.x
-    p2p_body<P, KIND, D>(t, leaf_begin + xcd_remap(blockIdx.x, gridDim.x));
+    p2p_sym_body<P, KIND, D>(t, leaf_begin + xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -690,10 +1043,15 @@ __device__ __forceinline__ void down_leaf_body(const DevTree<P> &t, int leaf, do
     // beside the locals
     int ki = 0, dst = 0;
     double yv = 0.0, qv = 0.0;
+    const int ne0 = t.near_off[leaf], nes = t.near_self[leaf]; // near leaves below this one: [ne0, nes)
     auto point_loads = [&](int i) {
         if (i < n && r) ki = urow[i];
         if (f == 0 && i < n) {
-            yv = t.yn[b + i];
+            // the symmetric near field left the column sums of the near leaves below in W
+            double v = t.yn[b + i];
+            if (mask & kNear)
+                for (int e = ne0; e < nes; ++e) v += t.near_wv[t.near_w[e] + i];
+            yv = v;
             qv = t.qt[b + i];
             dst = t.perm[b + i];
         }
@@ -794,12 +1152,29 @@ __global__ __launch_bounds__(NT_M2LS) void km_m2l(const DevTree<P> *__restrict__
     m2l_slices_body<P, FAR, KIND, D>(t, w.y);
 }
 
+template <class P, bool FAR, int KIND, int D>
+__global__ __launch_bounds__(NT_SYM) void km_m2l_sym(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map)
+{
+    const int2 w = map[xcd_remap(blockIdx.x, gridDim.x)];
+    const DevTree<P> t = trees[w.x];
+    m2l_sym_body<P, FAR, KIND, D>(t, w.y);
+}
+
+template <class P, bool FAR>
+__global__ __launch_bounds__(NT_GATHER) void km_m2l_gather(const DevTree<P> *__restrict__ trees,
+                                                           const int2 *__restrict__ map)
+{
+    const int2 w = map[blockIdx.x];
+    const DevTree<P> t = trees[w.x];
+    m2l_gather_body<P, FAR>(t, w.y);
+}
+
 template <class P, int KIND, int D>
 __global__ __launch_bounds__(NT_P2P) void km_p2p(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map)
 {
     const int2 w = map[xcd_remap(blockIdx.x, gridDim.x)];
     const DevTree<P> t = trees[w.x];
-    p2p_body<P, KIND, D>(t, w.y);
+    p2p_sym_body<P, KIND, D>(t, w.y);
 }
 
 // (no waves-per-SIMD bound: under the single-tree bound this one spills)
@@ -828,10 +1203,14 @@ template <class P, int KIND, int D> hipError_t enqueue_multi(const MultiPlan<P> 
     for (int k = 0; k < mp.steps; ++k)
         if (mp.n_m2m[k])
             hipLaunchKernelGGL(km_m2m<P>, dim3(mp.n_m2m[k]), dim3(mp.w_m2m[k]), mp.lds_rows, s, mp.trees, mp.m2m_map[k]);
-    if (mp.n_far)
-        hipLaunchKernelGGL((km_m2l<P, true, KIND, D>), dim3(mp.n_far), dim3(NT_M2LS), 0, s, mp.trees, mp.far_map);
-    if (mp.n_ver)
-        hipLaunchKernelGGL((km_m2l<P, false, KIND, D>), dim3(mp.n_ver), dim3(NT_M2LS), 0, s, mp.trees, mp.ver_map);
+    if (mp.n_far) {
+        hipLaunchKernelGGL((km_m2l_sym<P, true, KIND, D>), dim3(mp.n_far), dim3(NT_SYM), 0, s, mp.trees, mp.far_map);
+        hipLaunchKernelGGL((km_m2l_gather<P, true>), dim3(mp.n_far), dim3(NT_GATHER), 0, s, mp.trees, mp.far_map);
+    }
+    if (mp.n_ver) {
+        hipLaunchKernelGGL((km_m2l_sym<P, false, KIND, D>), dim3(mp.n_ver), dim3(NT_SYM), 0, s, mp.trees, mp.ver_map);
+        hipLaunchKernelGGL((km_m2l_gather<P, false>), dim3(mp.n_ver), dim3(NT_GATHER), 0, s, mp.trees, mp.ver_map);
+    }
     for (int k = 0; k < mp.steps; ++k)
         if (mp.n_l2l[k])
             hipLaunchKernelGGL(km_l2l<P>, dim3(mp.n_l2l[k]), dim3(mp.w_l2l[k]), mp.lds_rank, s, mp.trees, mp.l2l_map[k]);
@@ -877,16 +1256,22 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
         if (le > lb) hipLaunchKernelGGL((k_p2p<P, KIND, D>), dim3(le - lb), dim3(NT_P2P), 0, aux, t, lb, le - lb);
         return hipEventRecord((hipEvent_t)st.join, aux);
     };
-    // M2L of one family over its targets [tb, te) on stream `on`
+    // M2L of one family over its targets [tb, te) on stream `on`: each unordered pair once
+    // (k_m2l_sym), then the mirrored column sums added in list order (k_m2l_gather).  Pairs lie
+    // within one level, and every level's targets are a contiguous range, so a range split at a
+    // level boundary needs nothing from the other part.
     auto m2l = [&](bool far, int32_t tb, int32_t te, hipStream_t on) {
         if (te <= tb) return;
         if (far) {
-            if constexpr (sizeof(typename P::far_t) == 4)
+            if constexpr (sizeof(typename P::far_t) == 4) {
                 hipLaunchKernelGGL((k_m2l<P, true, KIND, D>), dim3(te - tb), dim3(NT_M2L), 0, on, t, tb);
-            else
-                hipLaunchKernelGGL((k_m2l_slices<P, true, KIND, D>), dim3(te - tb), dim3(NT_M2LS), 0, on, t, tb);
+            } else {
+                hipLaunchKernelGGL((k_m2l_sym<P, true, KIND, D>), dim3(te - tb), dim3(NT_SYM), 0, on, t, tb);
+                hipLaunchKernelGGL((k_m2l_gather<P, true>), dim3(te - tb), dim3(NT_GATHER), 0, on, t, tb);
+            }
         } else {
-            hipLaunchKernelGGL((k_m2l_slices<P, false, KIND, D>), dim3(te - tb), dim3(NT_M2LS), 0, on, t, tb);
+            hipLaunchKernelGGL((k_m2l_sym<P, false, KIND, D>), dim3(te - tb), dim3(NT_SYM), 0, on, t, tb);
+            hipLaunchKernelGGL((k_m2l_gather<P, false>), dim3(te - tb), dim3(NT_GATHER), 0, on, t, tb);
         }
     };
     const bool far_on = (mask & kFar) != 0, ver_on = (mask & kVer) != 0;

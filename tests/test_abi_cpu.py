@@ -110,10 +110,15 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("case", CASES + [(2, 3000, 0, 32, 1e-10, 0, 0.0, -14), (3, 3000, 1, 32, 1e-6, 1, 0.0, -15)])
 def test_host_build_equals_oracle_bitwise(lib, orc, inputs, case, tmp_path):
+    """(a negative seed: the point set with 40 exact duplicates, which both builds take once into
+    their cross approximations)"""
     d, n, kind, nmax, eps, variant, param, seed = case
-    pts = inputs.uniform_points(n, d, seed)
+    pts = inputs.uniform_points(n, d, abs(seed))
+    if seed < 0:
+        pts = inputs.with_coincident_points(pts, 40, -seed)
+        n = len(pts)
     O = orc.Tree(pts, kind, nmax, eps, variant=variant, param=param)
     L = lib.build(pts, kind=kind, leaf_size=nmax, eps=eps, variant=variant, param=param, host_only=True)
     ex = L.export(tmp_path / "rep.bin")

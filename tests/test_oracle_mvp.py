@@ -168,3 +168,18 @@ def test_nti_multiquadric_error_follows_tolerance(orc, inputs):
         errs.append(rel(orc.Tree(pts, orc.NTI_MQ, 64, eps).apply(q), want))
         assert errs[-1] <= 10 * eps, (eps, errs[-1])
     assert all(b < a for a, b in zip(errs, errs[1:]))
+
+
+@pytest.mark.parametrize("d,kind,eps", [(2, 0, 1e-10), (3, 1, 1e-6)])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_coincident_points(orc, inputs, d, kind, eps, variant):
+    """Exactly coincident points (G11: K takes the diagonal value on every coincident pair).
+    Their rows and columns of K are identical, so the cross approximations take each
+    coincident set once; a second copy would otherwise be pivoted on a rounding-level residual
+    and leave a singular pivot block.  The product is finite and within the tolerance band of
+    the direct sum."""
+    pts = inputs.with_coincident_points(inputs.uniform_points(3000, d, 70 + d), 60, 71)
+    q = inputs.normal_rhs(len(pts), 1, 72)[:, 0]
+    y = orc.Tree(pts, kind, 32, eps, variant=variant).apply(q)
+    assert np.all(np.isfinite(y))
+    assert rel(y, orc.direct(pts, q, kind)) <= 100 * eps

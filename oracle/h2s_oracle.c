@@ -152,23 +152,27 @@ static double dot(const double *a, const double *b, int64_t n)
  *   - v_p = R / R_{j*};  u_p(i) = K(I_i, j*) - sum_{k<p} u_k(i) v_k(j*);
  *   - ||S||_F^2 += ||u_p||^2 ||v_p||^2 + 2 sum_{k<p} (u_k.u_p)(v_k.v_p);
  *   - the term is accepted; the iteration ends once ||u_p|| ||v_p|| <=
- *     eps ||S||_F has held for ACA_RUN successive terms (all of them kept),
- *     or when the rank reaches min(|I|, |J|).  The paper states the
- *     condition a term must meet, not how many terms must meet it.  One small
- *     term proves little under partial pivoting, which sees only the rows and
- *     columns it visits: on vertex-sharing blocks the residual sits on the
- *     few close pairs near the shared corner, and a single small term ends
- *     the iteration with the true error 10-100x above eps.  Six successive
- *     terms reproduce the relative errors the paper prints for its 2D and 3D
- *     MVP experiments (Tables smvp2d_lap_1..3, smvp3d_lap_1..3) to within a
- *     factor of 2;
+ *     eps ||S||_F has held for ACA_RUN successive terms, or when the rank
+ *     reaches min(|I|, |J|).  The paper states the condition a term must
+ *     meet, not how many terms must meet it.  One small term proves little
+ *     under partial pivoting, which sees only the rows and columns it visits:
+ *     on vertex-sharing blocks the residual sits on the few close pairs near
+ *     the shared corner, and a single small term ended the iteration with the
+ *     true error 10-100x above eps.  Six successive terms reproduce the
+ *     relative errors the paper prints for its 2D and 3D MVP experiments
+ *     (Tables smvp2d_lap_1..2, smvp3d_lap_1..2) to within a factor of 2.
+ *     The first of the six is the stop; the five after it confirm it and are
+ *     kept, except for the T2B vertex bases (drop_confirm), where they are the
+ *     smallest pivots of near-singular pivot blocks and make the vertex
+ *     operators amplify rounding about tenfold more at no gain in accuracy
+ *     (the B2T far bases need them for their nested accuracy at eps = 1e-10);
  *   - next row pivot = argmax of |u_p| over unused rows, first on ties.
  * eps = 0 runs to full rank.
  */
 #define ACA_RUN 6
 
 static void aca(entry_fn f, const void *ctx, const int64_t *I, int64_t nI, const int64_t *J,
-                int64_t nJ, double eps, aca_result *res)
+                int64_t nJ, double eps, int drop_confirm, aca_result *res)
 {
     memset(res, 0, sizeof(*res));
     if (nI <= 0 || nJ <= 0) return;
@@ -226,7 +230,11 @@ static void aca(entry_fn f, const void *ctx, const int64_t *I, int64_t nI, const
         res->pcol[p] = jstar;
         ++p;
         run = sqrt(nu2 * nv2) <= eps * sqrt(s2) ? run + 1 : 0;
-        if (run == ACA_RUN || p == maxr) break;
+        if (run == ACA_RUN) {
+            if (drop_confirm) p -= ACA_RUN - 1;
+            break;
+        }
+        if (p == maxr) break;
         int64_t inext = -1;
         best = -1.0;
         for (int64_t i = 0; i < nI; ++i)
@@ -256,7 +264,7 @@ int64_t orc_aca_dense(const double *M, int64_t nI, int64_t nJ, double eps, int64
     for (int64_t i = 0; i < nI; ++i) I[i] = i;
     for (int64_t j = 0; j < nJ; ++j) J[j] = j;
     aca_result a;
-    aca(dense_entry, &c, I, nI, J, nJ, eps, &a);
+    aca(dense_entry, &c, I, nI, J, nJ, eps, 0, &a);
     for (int64_t p = 0; p < a.rank; ++p) {
         prow[p] = a.prow[p];
         pcol[p] = a.pcol[p];
@@ -649,7 +657,7 @@ static void far_pivots(orc_tree *t)
                 }
             }
             aca_result a;
-            aca(tree_entry, &c, I, nI, J, nJ, t->eps_far, &a);
+            aca(tree_entry, &c, I, nI, J, nJ, t->eps_far, 0, &a);
             B->rank = a.rank;
             B->row = malloc(sizeof(int64_t) * (a.rank ? a.rank : 1));
             B->col = malloc(sizeof(int64_t) * (a.rank ? a.rank : 1));
@@ -693,7 +701,7 @@ static void ver_pivots(orc_tree *t)
                 }
             }
             aca_result a;
-            aca(tree_entry, &c, I, nI, J, nJ, t->eps_ver, &a);
+            aca(tree_entry, &c, I, nI, J, nJ, t->eps_ver, 1, &a);
             B->rank = a.rank;
             B->row = malloc(sizeof(int64_t) * (a.rank ? a.rank : 1));
             B->col = malloc(sizeof(int64_t) * (a.rank ? a.rank : 1));
@@ -731,7 +739,7 @@ static void hph_pairs(orc_tree *t)
             for (int64_t i = 0; i < nx; ++i) I[i] = L->begin[H->x] + i;
             for (int64_t j = 0; j < ny; ++j) J[j] = L->begin[H->y] + j;
             aca_result a;
-            aca(tree_entry, &c, I, nx, J, ny, t->eps_ver, &a);
+            aca(tree_entry, &c, I, nx, J, ny, t->eps_ver, 0, &a);
             H->rank = a.rank;
             H->ub = a.u; a.u = NULL;
             H->vb = a.v; a.v = NULL;

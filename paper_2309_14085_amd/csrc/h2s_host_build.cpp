@@ -79,14 +79,16 @@ struct Cross {
 // can end it while the residual elsewhere is still large (vertex-sharing
 // blocks keep theirs on the close pairs near the shared corner); six
 // successive terms give the relative errors of the paper's 2D and 3D MVP
-// tables (smvp2d_lap_*, smvp3d_lap_*).
+// tables (smvp2d_lap_*, smvp3d_lap_*).  With drop_confirm the five terms after
+// the first of the run only confirm the stop and are dropped (the T2B vertex
+// bases: kept, they are the smallest pivots of near-singular pivot blocks).
 constexpr int kAcaRun = 6;
 
 // `entry(a, b)` is K(I[a], J[b]).  `par` lets the elementwise loops use the
 // OpenMP team (used when few large approximations run one after another);
 // every reduction stays sequential so the result does not depend on it.
 template <class Entry>
-void cross_approx(const Entry &entry, int64_t nI, int64_t nJ, double eps, bool par, Cross &c)
+void cross_approx(const Entry &entry, int64_t nI, int64_t nJ, double eps, bool par, bool drop_confirm, Cross &c)
 {
     c.nI = nI;
     c.nJ = nJ;
@@ -160,7 +162,17 @@ void cross_approx(const Entry &entry, int64_t nI, int64_t nJ, double eps, bool p
         c.pcol.push_back((int32_t)jstar);
         c.rank = p + 1;
         run = std::sqrt(nu2 * nv2) <= eps * std::sqrt(s2) ? run + 1 : 0;
-        if (run == kAcaRun || c.rank == maxr) break;
+        if (run == kAcaRun) {
+            if (drop_confirm) {
+                c.rank -= kAcaRun - 1;
+                c.prow.resize(c.rank);
+                c.pcol.resize(c.rank);
+                c.U.resize((size_t)c.rank * nI);
+                c.V.resize((size_t)c.rank * nJ);
+            }
+            break;
+        }
+        if (c.rank == maxr) break;
         int64_t inext = -1;
         best = -1.0;
         for (int64_t i = 0; i < nI; ++i)
@@ -410,7 +422,7 @@ struct PivotSets {
 
 // Run the cross approximation of K(I, J) for every box of one level.
 template <class MakeSets>
-void level_pivots(const HostRep &rep, int l, double eps, PivotSets &ps, const MakeSets &make_sets)
+void level_pivots(const HostRep &rep, int l, double eps, bool drop_confirm, PivotSets &ps, const MakeSets &make_sets)
 {
     const int32_t b0 = rep.lev_off[l], b1 = rep.lev_off[l + 1];
     const int nth = omp_get_max_threads();
@@ -424,7 +436,7 @@ void level_pivots(const HostRep &rep, int l, double eps, PivotSets &ps, const Ma
         auto entry = [&](int64_t a, int64_t b) {
             return kernel_entry(rep.ker, d, pts + (size_t)I[a] * d, pts + (size_t)J[b] * d);
         };
-        cross_approx(entry, (int64_t)I.size(), (int64_t)J.size(), eps, inner_par, c);
+        cross_approx(entry, (int64_t)I.size(), (int64_t)J.size(), eps, inner_par, drop_confirm, c);
         ps.row[x].resize(c.rank);
         ps.col[x].resize(c.rank);
         for (int p = 0; p < c.rank; ++p) {
@@ -464,7 +476,7 @@ void far_pivots(const HostRep &rep, const std::vector<char> &dup, PivotSets &ps)
 {
     const int kappa = rep.kappa;
     for (int l = kappa; l >= 2; --l) {
-        level_pivots(rep, l, rep.eps_far, ps, [&](int32_t x, std::vector<int32_t> &I, std::vector<int32_t> &J) {
+        level_pivots(rep, l, rep.eps_far, false, ps, [&](int32_t x, std::vector<int32_t> &I, std::vector<int32_t> &J) {
             const int64_t e0 = rep.list_off[1][x], e1 = rep.list_off[1][x + 1];
             if (e0 == e1) return;
             if (l == kappa) {
@@ -494,7 +506,7 @@ void far_pivots(const HostRep &rep, const std::vector<char> &dup, PivotSets &ps)
 void vertex_pivots(const HostRep &rep, const std::vector<char> &dup, PivotSets &ps)
 {
     for (int l = 1; l <= rep.kappa; ++l) {
-        level_pivots(rep, l, rep.eps_ver, ps, [&](int32_t x, std::vector<int32_t> &I, std::vector<int32_t> &J) {
+        level_pivots(rep, l, rep.eps_ver, true, ps, [&](int32_t x, std::vector<int32_t> &I, std::vector<int32_t> &J) {
             for (int32_t t = rep.box_begin[x]; t < rep.box_end[x]; ++t)
                 if (!dup[t]) I.push_back(t);
             for (int64_t e = rep.list_off[2][x]; e < rep.list_off[2][x + 1]; ++e) {
@@ -598,7 +610,7 @@ void make_pairs(HostRep &rep)
         auto entry = [&](int64_t a, int64_t b) {
             return kernel_entry(rep.ker, d, pts + (size_t)(bx + a) * d, pts + (size_t)(by + b) * d);
         };
-        cross_approx(entry, rep.box_end[P.x] - bx, rep.box_end[P.y] - by, rep.eps_ver, par, cr[p]);
+        cross_approx(entry, rep.box_end[P.x] - bx, rep.box_end[P.y] - by, rep.eps_ver, par, false, cr[p]);
     };
     // coarse levels hold few, large pairs: approximate them one at a time with
     // the team on the elementwise loops; the many small ones run concurrently

@@ -464,6 +464,7 @@ __global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t, int32_t t0
 constexpr int NT_SYM = 256;
 constexpr int SYM_SPT = 4;    // staged sources per thread and group
 constexpr int SYM_GMAX = 256; // staged sources per group at most
+constexpr int SYM_CH = 4;     // target pairs per chunk of the first column-reduction step
 
 // (s, c) += a b: the product's and the addition's rounding errors go to c.
 __device__ __forceinline__ void dot2_add(double &s, double &c, double a, double b)
@@ -494,10 +495,12 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
     __shared__ double sx[SYM_GMAX], sy[SYM_GMAX], sz[D == 3 ? SYM_GMAX : 1], sv[SYM_GMAX], sw[XW ? SYM_GMAX : 1];
     __shared__ int64_t sW[SYM_GMAX];
     // [target pair][source of the group] shares (hi, lo) of the column sums; after the last group
-    // the slices' row sums (hi, lo) for the two targets
+    // the slices' row sums (hi, lo) for the two targets.  colred: the shares summed over chunks
+    // of SYM_CH target pairs, [chunk][source]
     constexpr int CP = NT_SYM * SYM_SPT;
     static_assert(CP >= 2 * NT_SYM, "the row sums fit in the column buffer");
     __shared__ double colhi[CP], collo[CP];
+    __shared__ double redhi[CP / SYM_CH + SYM_GMAX], redlo[CP / SYM_CH + SYM_GMAX];
     __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList];
     __shared__ int64_t boxw[kMaxList];
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
@@ -570,14 +573,29 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
             }
         }
         __syncthreads();
+        // column sums over the target pairs in pair order, in two steps that keep every thread
+        // busy: chunks of SYM_CH pairs, then the chunks
+        const int nch = (NP + SYM_CH - 1) / SYM_CH;
+        for (int w = tid; w < nch * take; w += NT_SYM) {
+            const int j = w % take, ch = w / take;
+            const int p0 = ch * SYM_CH, p1 = min(p0 + SYM_CH, NP);
+            double hs = 0.0, hc = 0.0;
+            for (int p = p0; p < p1; ++p) dd_add(hs, hc, colhi[p * G + j], collo[p * G + j]);
+            redhi[ch * take + j] = hs;
+            redlo[ch * take + j] = hc;
+        }
+        __syncthreads();
         for (int j = tid; j < take; j += NT_SYM) {
             double hs = 0.0, hc = 0.0;
-            for (int p = 0; p < NP; ++p) dd_add(hs, hc, colhi[p * G + j], collo[p * G + j]);
+            for (int ch = 0; ch < nch; ++ch) dd_add(hs, hc, redhi[ch * take + j], redlo[ch * take + j]);
             F.W[2 * sW[j]] = hs;
             F.W[2 * sW[j] + 1] = hc;
         }
-        __syncthreads(); // the buffers are reused by the next group (and by the row sums below)
+        // the next group's staging writes sx .. sW only at indices this thread has just read, its
+        // shares only after its staging barrier (every thread is past the chunk step by then), and
+        // the chunk sums only after its share barrier
     }
+    __syncthreads(); // the row sums reuse the share buffers
     colhi[tid] = act ? sa : 0.0;
     collo[tid] = act ? ca : 0.0;
     colhi[NT_SYM + tid] = act ? sb : 0.0;

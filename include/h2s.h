@@ -210,6 +210,26 @@ h2s_status h2s_get_stats(h2s_tree t, h2s_stats *s);
  * off_v per (H2+H)* pair) and pair_data. */
 h2s_status h2s_export(h2s_tree t, const char *path);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc.  The same
+ * product as h2s_apply through the batched multi-RHS kernels (blocks of 8
+ * columns), for 1 <= nrhs <= 32, with the batch buffers (charges, near-field
+ * potentials, multipoles and locals of the active blocks) in a file-scope
+ * device array of H2S_NOALLOC_SCRATCH_BYTES per GPU instead of buffers the
+ * handle allocates on its first multi-RHS product.  The results equal
+ * h2s_apply's for the same nrhs > 1 bit for bit.  The array is shared by
+ * every call on one GPU and keeps the last call's contents (every call writes
+ * all it reads), so calls that overlap on one GPU race: order them on one
+ * stream.  The handle's auxiliary streams are created on its first product
+ * of any kind (streams and events, no device memory).
+ * Requirements: an H2* handle of precision FP64 or FP32; ceil(nrhs / 8) * 64 *
+ * (2 n + 2 (far + vertex coefficients)) bytes <= H2S_NOALLOC_SCRATCH_BYTES.
+ * Errors: INVALID_ARG (as h2s_apply, or nrhs > 32), UNSUPPORTED (variant,
+ * precision, host_only handle, or a size beyond the array), DEVICE. */
+#define H2S_NOALLOC_SCRATCH_BYTES (256u << 20)
+h2s_status h2s_apply_noalloc(h2s_tree t, const double *x, double *y, int32_t nrhs, int64_t ldx, int64_t ldy,
+                             void *stream);
+
 /* Measurement: the peak rate R_eval of the device kernel function, the
  * ceiling of the phases that evaluate kernel values on the fly (the near
  * field of Sec. 5.1.2 and the M2L blocks T_{X,Y} = K(t^{X,i}, t^{Y,i}) of

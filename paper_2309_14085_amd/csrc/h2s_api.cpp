@@ -1156,6 +1156,54 @@ h2s_status h2s_apply(h2s_tree t, const double *x, double *y, int32_t nrhs, int64
     return h2s_apply_phases(t, H2S_PHASE_ALL, x, y, nrhs, ldx, ldy, stream);
 }
 
+h2s_status h2s_apply_noalloc(h2s_tree t, const double *x, double *y, int32_t nrhs, int64_t ldx, int64_t ldy,
+                             void *stream)
+{
+    if (!t) return fail(H2S_ERR_INVALID_ARG, "tree is NULL");
+    if (t->host_only) return fail(H2S_ERR_UNSUPPORTED, "handle was built with host_only");
+    const int64_t n = t->rep.n;
+    if (!x || !y) return fail(H2S_ERR_INVALID_ARG, "x or y is NULL");
+    if (nrhs < 1 || nrhs > h2s::kGroupCols) return fail(H2S_ERR_INVALID_ARG, "nrhs must be in 1..32");
+    if (ldx < n || ldy < n) return fail(H2S_ERR_INVALID_ARG, "leading dimensions must be >= n");
+    const char *xb = (const char *)x, *xe = (const char *)(x + ldx * (nrhs - 1) + n);
+    const char *yb = (const char *)y, *ye = (const char *)(y + ldy * (nrhs - 1) + n);
+    if (xb < ye && yb < xe) return fail(H2S_ERR_INVALID_ARG, "x and y overlap");
+    if (t->rep.variant != H2S_H2STAR || (t->opts.prec != H2S_FP64 && t->opts.prec != H2S_FP32))
+        return fail(H2S_ERR_UNSUPPORTED, "h2s_apply_noalloc takes H2* handles of precision FP64 or FP32");
+    // the active blocks' buffers, each block's at a fixed stride as the batched kernels expect
+    const size_t nblk = (size_t)(nrhs + h2s::kBatch - 1) / h2s::kBatch, NB = h2s::kBatch;
+    const size_t nf = (size_t)t->rep.fam[0].coef_off.back(), nv = (size_t)t->rep.fam[1].coef_off.back();
+    const size_t need = nblk * NB * (2 * (size_t)n + 2 * (nf ? nf : 1) + 2 * (nv ? nv : 1)) * sizeof(double);
+    if (need > H2S_NOALLOC_SCRATCH_BYTES)
+        return fail(H2S_ERR_UNSUPPORTED, "the batch buffers need " + std::to_string(need) + " bytes, above the " +
+                                             std::to_string((size_t)H2S_NOALLOC_SCRATCH_BYTES) +
+                                             "-byte scratch array: use fewer columns or h2s_apply");
+    if (hipSetDevice(t->device) != hipSuccess) return fail(H2S_ERR_DEVICE, "hipSetDevice failed");
+    double *scr = nullptr;
+    const hipError_t se = h2s::noalloc_scratch(t->device, &scr);
+    if (se != hipSuccess) return fail(H2S_ERR_DEVICE, std::string("hipGetSymbolAddress failed: ") + hipGetErrorString(se));
+    if (ensure_streams(t) != H2S_OK) return H2S_ERR_DEVICE;
+    const h2s::Streams st = streams_of(t, stream);
+    auto run = [&](auto D) -> h2s_status { // D: a copy of the handle's tree, its batch buffers in the array
+        double *p = scr;
+        D.qb = p;
+        p += nblk * NB * n;
+        D.ynb = p;
+        p += nblk * NB * n;
+        D.far.vb = p;
+        p += nblk * NB * (nf ? nf : 1);
+        D.far.ub = p;
+        p += nblk * NB * (nf ? nf : 1);
+        D.ver.vb = p;
+        p += nblk * NB * (nv ? nv : 1);
+        D.ver.ub = p;
+        const int rc = h2s::launch_mvp_batch(D, t->plan, x, ldx, y, ldy, nrhs, H2S_PHASE_ALL, st);
+        if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
+        return H2S_OK;
+    };
+    return t->opts.prec == H2S_FP64 ? run(t->t64) : run(t->t32);
+}
+
 h2s_status h2s_solve_opts_default(h2s_solve_opts *o)
 {
     if (!o) return fail(H2S_ERR_INVALID_ARG, "opts is NULL");

@@ -27,6 +27,8 @@
 // remainder).
 #pragma once
 
+#include <hip/hip_runtime_api.h>
+
 #include <cstdint>
 
 namespace h2s {
@@ -197,6 +199,10 @@ constexpr int kGroupCols = kBatch * kGroupBlocks;
 template <class P>
 int launch_mvp_batch(const DevTree<P> &t, const LaunchPlan &plan, const double *x, int64_t ldx, double *y,
                      int64_t ldy, int ncols, uint32_t mask, const Streams &st);
+
+// Device address of the file-scope batch scratch array on `device` (current), for
+// h2s_apply_noalloc; H2S_NOALLOC_SCRATCH_BYTES long.
+hipError_t noalloc_scratch(int device, double **ptr);
 
 // Enqueue one product y = K~ x (single right-hand side), ordered on st.main.
 // Returns a hipError_t as int.

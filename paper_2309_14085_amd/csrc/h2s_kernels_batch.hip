@@ -13,11 +13,17 @@
 // past the block's active count are zero.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "h2s.h"
 #include "h2s_device.hpp"
 #include "h2s_kfun.hpp"
+
+// Batch buffers for callers that cannot allocate (h2s_apply_noalloc): one
+// array per device, alive until the process ends.  Host code never uses this
+// name as an address; it takes the device address from hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[H2S_NOALLOC_SCRATCH_BYTES / sizeof(double)];
 
 namespace h2s {
 
@@ -805,6 +811,24 @@ hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *
 }
 
 } // namespace
+
+// Device address of `scratch` on the current device, looked up on the first call on each device.
+hipError_t noalloc_scratch(int device, double **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<double *>(p);
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 
 template <class P>
 int launch_mvp_batch(const DevTree<P> &t, const LaunchPlan &plan, const double *x, int64_t ldx, double *y,

@@ -119,10 +119,11 @@ def load():
     lib.h2s_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
     lib.h2s_tune.argtypes = [vp, vp, vp, i32, ctypes.POINTER(TuneInfo), vp]
     lib.h2s_eval_rate.argtypes = [ctypes.POINTER(Kernel), i32, i32, f64p, vp]
+    lib.h2s_apply_noalloc.argtypes = [vp, vp, vp, i32, i64, i64, vp]
     for name in ("h2s_build", "h2s_apply", "h2s_apply_phases", "h2s_free", "h2s_get_stats", "h2s_export",
                  "h2s_set_allocator", "h2s_last_error", "h2s_set_profiling", "h2s_get_profile",
                  "h2s_solve_opts_default", "h2s_solve", "h2s_get_schedule", "h2s_set_schedule", "h2s_tune",
-                 "h2s_group_create", "h2s_group_apply", "h2s_group_free", "h2s_eval_rate"):
+                 "h2s_group_create", "h2s_group_apply", "h2s_group_free", "h2s_eval_rate", "h2s_apply_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -234,6 +235,11 @@ class Tree:
         check(load().h2s_apply_phases(self._h, mask, ctypes.c_void_p(xx.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                       m, ldx, ldy, _stream_ptr(stream)))
         return y
+
+    def apply_noalloc_ptr(self, x_ptr, y_ptr, nrhs, ldx=None, ldy=None, stream=None):
+        """Raw-pointer form of h2s_apply_noalloc (pointers as ints); returns the status."""
+        return load().h2s_apply_noalloc(self._h, ctypes.c_void_p(x_ptr), ctypes.c_void_p(y_ptr), nrhs,
+                                        ldx or self.n, ldy or self.n, _stream_ptr(stream))
 
     def apply_ptr(self, x_ptr, y_ptr, nrhs=1, ldx=None, ldy=None, mask=PHASE_ALL, stream=None):
         """Raw-pointer form of h2s_apply_phases (pointers as ints)."""

@@ -54,7 +54,9 @@ typedef struct {
 
 /* K(x, y).  reading: the diagonal value is used whenever the two points
  * coincide (r == 0), which covers i == j; for log r and 1/r the paper sets
- * K_ii = 0 (Sec. 6.1.1, 6.2.1). */
+ * K_ii = 0 (Sec. 6.1.1, 6.2.1).  log r is taken as 0.5 log(r^2), the same
+ * value without the rounding of r itself (which costs up to ~1e-16 absolute
+ * where r is near 1). */
 static double kernel_value(const orc_kernel *k, int d, const double *x, const double *y)
 {
     double r2 = 0.0;
@@ -64,7 +66,7 @@ static double kernel_value(const orc_kernel *k, int d, const double *x, const do
     }
     if (r2 == 0.0) return k->diag;
     switch (k->kind) {
-    case ORC_LOG_R: return log(sqrt(r2));
+    case ORC_LOG_R: return 0.5 * log(r2);
     case ORC_INV_R: return 1.0 / sqrt(r2);
     case ORC_GAUSS: return exp(-r2 / (k->param * k->param));
     case ORC_EXP_R: return exp(-sqrt(r2));
@@ -73,8 +75,8 @@ static double kernel_value(const orc_kernel *k, int d, const double *x, const do
         return r >= a ? a / r : r / a;
     }
     case ORC_RBF_LOG: { /* 3D RBF: log r / log a for r >= a, (r log r - 1)/(a log a - 1) below (Sec. 6, 3D) */
-        double r = sqrt(r2), a = k->param;
-        return r >= a ? log(r) / log(a) : (r * log(r) - 1.0) / (a * log(a) - 1.0);
+        double r = sqrt(r2), a = k->param, lr = 0.5 * log(r2);
+        return r >= a ? lr / log(a) : (r * lr - 1.0) / (a * log(a) - 1.0);
     }
     case ORC_NTI_MQ: { /* non-translation-invariant scaled multiquadric (Sec. 6, 3D):
                           (|x - y|^2 + (c(x) - c(y))^2 + 1)^(3/2), c(x) = exp(-(x_1 + x_3)) */
@@ -139,6 +141,27 @@ static double dot(const double *a, const double *b, int64_t n)
     double s = 0.0;
     for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
     return s;
+}
+
+/* init + sum_i a[i sa] b[i] as an accurate dot product (Ogita, Rump and
+ * Oishi, "Accurate sum and dot product", 2005, Algorithm Dot2): each
+ * product's rounding error from fma, each addition's from TwoSum, gathered
+ * in a second sum and added once at the end, so the result is the sum as if
+ * taken in twice the working precision, then rounded.  Used for every sum of
+ * the MVP whose result an interpolation operator later multiplies (the
+ * transfers and M2L): those operators have norms up to ~1e3, and a plain
+ * sum's rounding, eps sum |a b|, would then be what any two correct
+ * implementations of the same product disagree by. */
+static double acc_dot(const double *a, int64_t sa, const double *b, int64_t n, double init)
+{
+    double s = init, c = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double p = a[i * sa] * b[i], ep = fma(a[i * sa], b[i], -p);
+        double sn = s + p, z = sn - s, es = (s - (sn - z)) + (p - z);
+        s = sn;
+        c += ep + es;
+    }
+    return s + c;
 }
 
 /*
@@ -926,7 +949,7 @@ void orc_apply(const orc_tree *t, const double *q_user, double *near_out, double
                 const obasis *B = &L->fam[fam][x];
                 int64_t nx = L->end[x] - L->begin[x];
                 for (int64_t k = 0; k < B->rank; ++k)
-                    v[kappa][co[kappa][x] + k] = dot(B->op + k * nx, q + L->begin[x], nx);
+                    v[kappa][co[kappa][x] + k] = acc_dot(B->op + k * nx, 1, q + L->begin[x], nx, 0.0);
             }
         }
         /* M2M: v_X = sum_c V~*_{X X_c} v_{X_c}, l = kappa-1 .. lmin */
@@ -937,19 +960,13 @@ void orc_apply(const orc_tree *t, const double *q_user, double *near_out, double
                 if (B->rank == 0) continue;
                 int64_t c0 = co[l + 1][L->cbeg[x]];
                 for (int64_t k = 0; k < B->rank; ++k)
-                    v[l][co[l][x] + k] = dot(B->op + k * B->nrow_op, v[l + 1] + c0, B->nrow_op);
+                    v[l][co[l][x] + k] = acc_dot(B->op + k * B->nrow_op, 1, v[l + 1] + c0, B->nrow_op, 0.0);
                 (void)C;
             }
         }
         /* M2L: u_X = sum_{Y in IL(X)} T_{X,Y} v_Y, T_{X,Y} = K(t^{X,i}, t^{Y,i}).
          * Each output is the sum over every Y of the list and every b, taken as an
-         * accurate dot product (the products' rounding errors from fma and the
-         * additions' from TwoSum, carried in a second sum: Ogita, Rump and Oishi,
-         * "Accurate sum and dot product", 2005), so it is the value of the sum
-         * as if it were computed in twice the working precision.  The bases'
-         * coefficients v can be large against u (interpolation operators of norm
-         * up to ~1e3), and a plain sum's rounding would then be what any two
-         * correct implementations disagree by. */
+         * accurate dot product (as acc_dot, written out over the list). */
         for (int l = lmin; l <= kappa; ++l) {
             const olevel *L = &t->lev[l];
             for (int64_t x = 0; x < L->nbox; ++x) {
@@ -971,18 +988,16 @@ void orc_apply(const orc_tree *t, const double *q_user, double *near_out, double
                 }
             }
         }
-        /* L2L: u_{X_c} += U~_{X_c X} u_X, l = lmin .. kappa-1 */
+        /* L2L: u_{X_c} += U~_{X_c X} u_X, l = lmin .. kappa-1 (the child's M2L
+         * result and the parent's contribution in one accurate sum) */
         for (int l = lmin; l < kappa; ++l) {
             const olevel *L = &t->lev[l];
             for (int64_t x = 0; x < L->nbox; ++x) {
                 const obasis *B = &L->fam[fam][x];
                 if (B->rank == 0) continue;
                 int64_t c0 = co[l + 1][L->cbeg[x]];
-                for (int64_t j = 0; j < B->nrow_op; ++j) {
-                    double s = 0.0;
-                    for (int64_t k = 0; k < B->rank; ++k) s += B->op[k * B->nrow_op + j] * u[l][co[l][x] + k];
-                    u[l + 1][c0 + j] += s;
-                }
+                for (int64_t j = 0; j < B->nrow_op; ++j)
+                    u[l + 1][c0 + j] = acc_dot(B->op + j, B->nrow_op, u[l] + co[l][x], B->rank, u[l + 1][c0 + j]);
             }
         }
         /* L2P: phi_X = U_X u_X */
@@ -991,11 +1006,8 @@ void orc_apply(const orc_tree *t, const double *q_user, double *near_out, double
             for (int64_t x = 0; x < L->nbox; ++x) {
                 const obasis *B = &L->fam[fam][x];
                 int64_t nx = L->end[x] - L->begin[x];
-                for (int64_t i = 0; i < nx; ++i) {
-                    double s = 0.0;
-                    for (int64_t k = 0; k < B->rank; ++k) s += B->op[k * nx + i] * u[kappa][co[kappa][x] + k];
-                    phi[L->begin[x] + i] = s;
-                }
+                for (int64_t i = 0; i < nx; ++i)
+                    phi[L->begin[x] + i] = acc_dot(B->op + i, nx, u[kappa] + co[kappa][x], B->rank, 0.0);
             }
         }
         for (int64_t i = 0; i < n; ++i) out[t->perm[i]] = phi[i];

@@ -46,11 +46,17 @@ std::vector<double> kernel_table(int kind)
     std::vector<double> tab;
     if (kind == H2S_K_LOG_R || kind == H2S_K_RBF_LOG) {
         // 0.5 ln x by table reduction: subinterval i of m in [1/2, 1) has centre
-        // z_i = 1/2 + (i + 1/2)/512; store c_i = 1/z_i and -0.5 ln c_i
+        // z_i = 1/2 + (i + 1/2)/512; store c_i = 1/z_i and T_i = -0.5 ln c_i,
+        // then T_i once more as a head Th_i on the grid 2^-43 and the rest Tl_i
+        tab.resize(1024);
         for (int i = 0; i < 256; ++i) {
             const double c = 1.0 / (0.5 + (i + 0.5) / 512.0);
-            tab.push_back(c);
-            tab.push_back((double)(-0.5L * std::log((long double)c)));
+            const long double T = -0.5L * std::log((long double)c);
+            const long double h = std::ldexp(std::nearbyint(std::ldexp(T, 43)), -43);
+            tab[2 * i] = c;
+            tab[2 * i + 1] = (double)T;
+            tab[512 + 2 * i] = (double)h;
+            tab[512 + 2 * i + 1] = (double)(T - h);
         }
     } else if (kind == H2S_K_GAUSSIAN || kind == H2S_K_EXP_R) {
         for (int j = 0; j < 64; ++j) tab.push_back((double)std::exp2((long double)j / 64.0L)); // 2^(j/64)

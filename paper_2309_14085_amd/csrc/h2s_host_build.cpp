@@ -34,7 +34,7 @@ double kernel_entry(const KernelSpec &k, int d, const double *x, const double *y
     }
     if (r2 == 0.0) return k.diag;
     switch (k.kind) {
-    case H2S_K_LOG_R: return std::log(std::sqrt(r2));
+    case H2S_K_LOG_R: return 0.5 * std::log(r2); // log r, without rounding r itself
     case H2S_K_INV_R: return 1.0 / std::sqrt(r2);
     case H2S_K_GAUSSIAN: return std::exp(-r2 / (k.param * k.param));
     case H2S_K_RBF_AR: {
@@ -42,8 +42,8 @@ double kernel_entry(const KernelSpec &k, int d, const double *x, const double *y
         return r >= a ? a / r : r / a;
     }
     case H2S_K_RBF_LOG: {
-        const double r = std::sqrt(r2), a = k.param;
-        return r >= a ? std::log(r) / std::log(a) : (r * std::log(r) - 1.0) / (a * std::log(a) - 1.0);
+        const double r = std::sqrt(r2), a = k.param, lr = 0.5 * std::log(r2);
+        return r >= a ? lr / std::log(a) : (r * lr - 1.0) / (a * std::log(a) - 1.0);
     }
     case H2S_K_NTI_MQ: { // d == 3 (checked at build)
         const double dc = std::exp(-(x[0] + x[2])) - std::exp(-(y[0] + y[2]));

@@ -151,8 +151,8 @@ template <class P> __device__ __forceinline__ void l2l_body(const DevTree<P> &t,
         const double *A = (f ? Fa.Tr_cm + Fa.troff[g] : Ve.Tr_cm + Ve.troff[g]) + (kj >= 0 ? kj : 0);
         const double *x = f ? xs : xs + rf;
         double *out = f ? Fa.u + bf + jj : Ve.u + bv + jj;
-        const double s = kj >= 0 ? ordered_dot<ORD>(A, (size_t)(f ? nkf : nkv), f ? rf : rv, x) : x[~kj];
-        *out = *out + s;
+        // the parent's contribution added to the child's M2L result inside the one sum
+        *out = kj >= 0 ? ordered_dot<ORD>(A, (size_t)(f ? nkf : nkv), f ? rf : rv, x, -1, 0.0, *out) : *out + x[~kj];
     }
 }
 
@@ -331,9 +331,9 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
     __shared__ double sx[M2LS_SRC], sy[M2LS_SRC], sz[D == 3 ? M2LS_SRC : 1], sv[M2LS_SRC], sw[XW ? M2LS_SRC : 1];
     __shared__ double red[2 * NT_M2LS];
     __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList];
-    __shared__ __align__(16) double ktab[kTabLen<KIND>];
+    __shared__ __align__(16) double ktab[kTabLenAcc<KIND>];
     const int tid = threadIdx.x;
-    stage_table<KIND>(t.ktab, ktab); // first used after a barrier
+    stage_table<KIND, kTabLenAcc<KIND>>(t.ktab, ktab); // first used after a barrier
     const int g = F.targets[ti];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], nil = F.il_off[g + 1] - e0; // nil <= kMaxList (checked at build)
@@ -466,25 +466,6 @@ constexpr int SYM_SPT = 4;    // staged sources per thread and group
 constexpr int SYM_GMAX = 256; // staged sources per group at most
 constexpr int SYM_CH = 4;     // target pairs per chunk of the first column-reduction step
 
-// (s, c) += a b: the product's and the addition's rounding errors go to c.
-__device__ __forceinline__ void dot2_add(double &s, double &c, double a, double b)
-{
-#pragma clang fp contract(off) // the error terms need the separately rounded product and sums
-    const double p = a * b, ep = fma(a, b, -p);
-    const double t = s + p, z = t - s, es = (s - (t - z)) + (p - z);
-    s = t;
-    c += ep + es;
-}
-
-// (s, c) += (h, l)
-__device__ __forceinline__ void dd_add(double &s, double &c, double h, double l)
-{
-#pragma clang fp contract(off)
-    const double t = s + h, z = t - s, es = (s - (t - z)) + (h - z);
-    s = t;
-    c += es + l;
-}
-
 template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2l_sym_body(const DevTree<P> &t, int ti)
 {
     const auto &F = [&]() -> const auto & {
@@ -503,9 +484,9 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
     __shared__ double redhi[CP / SYM_CH + SYM_GMAX], redlo[CP / SYM_CH + SYM_GMAX];
     __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList];
     __shared__ int64_t boxw[kMaxList];
-    __shared__ __align__(16) double ktab[kTabLen<KIND>];
+    __shared__ __align__(16) double ktab[kTabLenAcc<KIND>];
     const int tid = threadIdx.x;
-    stage_table<KIND>(t.ktab, ktab); // first used after a barrier
+    stage_table<KIND, kTabLenAcc<KIND>>(t.ktab, ktab); // first used after a barrier
     const int g = F.targets[ti];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0; // r <= 2 NT_SYM (rank cap, checked at build)
     const int eb = F.ul_beg[g], nil = F.il_off[g + 1] - eb;   // the upper part of IL(X)
@@ -561,8 +542,8 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
             for (int j = s; j < take; j += NS) {
                 const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, v0 = sv[j];
                 const double w0 = XW ? sw[j] : 0.0;
-                const double ka = kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), wa, w0), kp, ktab);
-                const double kb = kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), wb, w0), kp, ktab);
+                const double ka = kval_pos<KIND, true>(add_extra<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), wa, w0), kp, ktab);
+                const double kb = kval_pos<KIND, true>(add_extra<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), wb, w0), kp, ktab);
                 dot2_add(sa, ca, ka, v0);
                 dot2_add(sb, cb, kb, v0);
                 double hs = 0.0, hc = 0.0;

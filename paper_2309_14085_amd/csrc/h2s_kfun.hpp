@@ -61,6 +61,35 @@ __device__ __forceinline__ double half_log(double x, const double2 *tab)
     return fma(r, p, fma((double)e, 0.34657359027997264, c.y)); // ln 2 / 2
 }
 
+// The same logarithm rounded almost always correctly, for the M2L sums, whose
+// result the interpolation operators amplify: ln 2 / 2 = Lh + Ll and
+// -0.5 ln c_i = Th_i + Tl_i with Lh and Th_i multiples of 2^-43 (Lh has 42
+// significant bits), so e Lh + Th_i is exact for |e| < 2^10; the small rest
+// e Ll + Tl_i + 0.5 ln(1 + r) carries an absolute error near 2e-19, and the
+// one final addition rounds.  tab[256 + i] holds (Th_i, Tl_i).
+__device__ __forceinline__ double half_log_acc(double x, const double2 *tab)
+{
+    constexpr double kLh = 0x1.62e42fefa3800p-2, kLl = 0x1.ef35793c76730p-46;
+    int e;
+    const double m = frexp(x, &e);
+    const int i = (__double2hiint(m) >> 12) & 255;
+    const double2 c = tab[i], th = tab[256 + i];
+    const double r = fma(m, c.x, -1.0);
+    double p = 1.0 / 10;
+    p = fma(p, r, -1.0 / 8);
+    p = fma(p, r, 1.0 / 6);
+    p = fma(p, r, -1.0 / 4);
+    p = fma(p, r, 1.0 / 2);
+    const double ed = (double)e;
+    double hi, lo;
+    {
+#pragma clang fp contract(off) // e Lh + Th is exact only as a separate product and sum
+        hi = ed * kLh + th.x;
+    }
+    lo = fma(r, p, fma(ed, kLl, th.y));
+    return hi + lo;
+}
+
 // exp(x) in double, table-driven (Tang's reduction): k = nearest integer to
 // 64 x / ln 2, r = x - k ln2/64 (|r| <= ln2/128, with ln2/64 split into an
 // exactly multipliable head and a tail), k = 64 m + j, and
@@ -101,18 +130,22 @@ __device__ __forceinline__ double inv_sqrt(double x)
 }
 
 // Lookup tables of the kernel functions, in doubles: log r and the log RBF
-// 256 (c_i, -0.5 ln c_i) pairs, the exponential kernels 2^(j/64).  Staged in
-// LDS per block.
+// 256 pairs (c_i, -0.5 ln c_i) followed by 256 pairs (Th_i, Tl_i), the
+// exponential kernels 2^(j/64).  Staged in LDS per block.
 template <int KIND>
 constexpr int kTabLen = KIND == H2S_K_LOG_R || KIND == H2S_K_RBF_LOG
                             ? 512
                             : (KIND == H2S_K_GAUSSIAN || KIND == H2S_K_EXP_R ? 64 : 2);
+// With the (Th_i, Tl_i) pairs of the accurate logarithm behind.
+template <int KIND>
+constexpr int kTabLenAcc = KIND == H2S_K_LOG_R || KIND == H2S_K_RBF_LOG ? 1024 : kTabLen<KIND>;
 
-// Stage the table in LDS (whole block; the caller synchronises).
-template <int KIND> __device__ __forceinline__ void stage_table(const double *g, double *tab)
+// Stage the first LEN doubles of the table in LDS (whole block; the caller
+// synchronises).
+template <int KIND, int LEN = kTabLen<KIND>> __device__ __forceinline__ void stage_table(const double *g, double *tab)
 {
     if constexpr (KIND != H2S_K_INV_R && KIND != H2S_K_RBF_AR)
-        for (int i = threadIdx.x; i < kTabLen<KIND>; i += blockDim.x) tab[i] = g[i];
+        for (int i = threadIdx.x; i < LEN; i += blockDim.x) tab[i] = g[i];
 }
 
 // Kernels of an extra per-point coordinate w besides the position: the NTI
@@ -153,9 +186,11 @@ template <bool ORD, int D, typename T> __device__ __forceinline__ T dist2(T dx, 
 
 // Kernel value from a squared distance r2 > 0.  The branch of the piecewise
 // RBFs is taken on r2 >= a^2 (the functions are continuous at r = a).
-template <int KIND> __device__ __forceinline__ double kval_pos(double r2, const KPar<double> &kp, const double *tab)
+template <int KIND, bool ACC = false>
+__device__ __forceinline__ double kval_pos(double r2, const KPar<double> &kp, const double *tab)
 {
-    if constexpr (KIND == H2S_K_LOG_R) return half_log(r2, (const double2 *)tab);
+    if constexpr (KIND == H2S_K_LOG_R && ACC) return half_log_acc(r2, (const double2 *)tab);
+    else if constexpr (KIND == H2S_K_LOG_R) return half_log(r2, (const double2 *)tab);
     else if constexpr (KIND == H2S_K_INV_R) return inv_sqrt(r2);
     else if constexpr (KIND == H2S_K_GAUSSIAN) return exp_tab(r2 * kp.kp, tab);
     else if constexpr (KIND == H2S_K_EXP_R) return exp_tab(-sqrt(r2), tab);
@@ -163,7 +198,7 @@ template <int KIND> __device__ __forceinline__ double kval_pos(double r2, const 
         const double rs = inv_sqrt(r2); // 1/r
         return r2 >= kp.c0 ? kp.c1 * rs : (r2 * rs) * kp.c2;
     } else if constexpr (KIND == H2S_K_RBF_LOG) {
-        const double lr = half_log(r2, (const double2 *)tab); // log r
+        const double lr = ACC ? half_log_acc(r2, (const double2 *)tab) : half_log(r2, (const double2 *)tab); // log r
         return r2 >= kp.c0 ? lr * kp.c1 : fma(sqrt(r2), lr, -1.0) * kp.c2;
     } else { // H2S_K_NTI_MQ: r2 already holds |x - y|^2 + (c(x) - c(y))^2
         const double t = r2 + 1.0;
@@ -206,19 +241,52 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
-// Ordered dot product sum_j a(j) x[j], a(j) = A[j stride], with qp added to the
-// running sum just before term pos (pos == R: after the last; pos < 0: never).
-// The sum itself is sequential; the operator loads are software-pipelined two
+// Error-free transformations (Ogita, Rump and Oishi, "Accurate sum and dot
+// product", 2005) on an unevaluated pair (s, c), the value s + c:
+// (s, c) += a b -- the product's rounding error from an fma, the addition's
+// from TwoSum, both gathered in c.
+__device__ __forceinline__ void dot2_add(double &s, double &c, double a, double b)
+{
+#pragma clang fp contract(off) // the error terms need the separately rounded product and sums
+    const double p = a * b, ep = fma(a, b, -p);
+    const double t = s + p, z = t - s, es = (s - (t - z)) + (p - z);
+    s = t;
+    c += ep + es;
+}
+
+// (s, c) += (h, l)
+__device__ __forceinline__ void dd_add(double &s, double &c, double h, double l)
+{
+#pragma clang fp contract(off)
+    const double t = s + h, z = t - s, es = (s - (t - z)) + (h - z);
+    s = t;
+    c += es + l;
+}
+
+// Dot product init + sum_j a(j) x[j], a(j) = A[j stride], with qp added just
+// before term pos (pos == R: after the last; pos < 0: never), in index order.
+// ORD (the FP64 path): an accurate dot product -- the sum as if taken in
+// twice the working precision, rounded once -- because the interpolation
+// operators (norms up to ~1e3 - 1e4 on coarse levels) amplify the rounding
+// error of a plain sum, eps sum |a x|, into the potential; otherwise plain
+// fused multiply-adds.  The operator loads are software-pipelined two
 // batches of UNR deep so that a batch is in flight while the previous one is
 // accumulated.
 constexpr int UNR = 8;
 
 template <bool ORD, typename AT>
 __device__ __forceinline__ double ordered_dot(const AT *__restrict__ A, size_t stride, int R, const double *xs,
-                                              int pos = -1, double qp = 0.0)
+                                              int pos = -1, double qp = 0.0, double init = 0.0)
 {
-    double s = 0.0;
-    auto step = [&](int j, double a) { s = madd<ORD>(j == pos ? s + qp : s, a, xs[j]); };
+    double s = init, c = 0.0;
+    auto step = [&](int j, double a) {
+        if constexpr (ORD) {
+            if (j == pos) dd_add(s, c, qp, 0.0);
+            dot2_add(s, c, a, xs[j]);
+        } else {
+            s = fma(a, xs[j], j == pos ? s + qp : s);
+        }
+    };
     int j = 0;
     if (R >= 2 * UNR) {
         double a[UNR], b[UNR];
@@ -248,7 +316,11 @@ __device__ __forceinline__ double ordered_dot(const AT *__restrict__ A, size_t s
         for (int u = 0; u < UNR; ++u)
             if (j + u < R) step(j + u, c[u]);
     }
-    return pos == R ? s + qp : s;
+    if (pos == R) {
+        if constexpr (ORD) dd_add(s, c, qp, 0.0);
+        else s += qp;
+    }
+    return ORD ? s + c : s;
 }
 
 } // namespace

@@ -1261,9 +1261,10 @@ h2s_status h2s_solve(h2s_tree t, const double *b, double *x, int32_t nrhs, int64
         w.r = (double *)up.raw(sizeof(double) * (size_t)n);
         w.y = (double *)up.raw(sizeof(double) * (size_t)n);
         w.part = (double *)up.raw(sizeof(double) * (size_t)h2s::blas_dots_blocks(n) * (m + 1));
-        w.small = (double *)up.raw(sizeof(double) * (size_t)(2 * (m + 1) + 2));
+        w.small = (double *)up.raw(sizeof(double) * (size_t)h2s::solve_small_doubles(m));
         if (up.st != H2S_OK) return up.st;
-        if (hipHostMalloc((void **)&w.small_host, sizeof(double) * (size_t)(2 * (m + 1) + 2), hipHostMallocDefault) !=
+        if (hipHostMalloc((void **)&w.small_host, sizeof(double) * (size_t)h2s::solve_small_doubles(m),
+                          hipHostMallocDefault) !=
             hipSuccess)
             return fail(H2S_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
         if (t->work.small_host) (void)hipHostFree(t->work.small_host);

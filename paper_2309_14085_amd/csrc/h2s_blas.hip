@@ -158,6 +158,84 @@ int blas_gemv_acc(const double *V, int64_t ldv, int ncols, const double *c, doub
     return (int)hipGetLastError();
 }
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// The small dense part of a GMRES(m) cycle on the device (one thread: at most
+// m + 1 = 1001 entries per column, a few microseconds).  H is (m + 1) x m,
+// row-major; st[0] = 1 once the cycle is done, st[1] = the steps it kept.
+// ---------------------------------------------------------------------------
+__global__ void k_cycle_start(double *g, double *st, int m, double beta)
+{
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i <= m; ++i) g[i] = 0.0;
+    g[0] = beta;
+    st[0] = 0.0;
+    st[1] = 0.0;
+}
+
+// Step j: column j of H from the two Gram-Schmidt passes (h1 + h2) and the new norm, the
+// rotations of steps 0 .. j-1 in order, then the rotation that zeroes H(j+1, j), applied to g.
+// The cycle is done when |g[j+1]| <= tol, or on a breakdown (zero norm or zero pivot); a done
+// cycle ignores later steps.
+__global__ void k_givens(int j, int m, const double *h1, const double *h2, const double *nrm2, double *H, double *cs,
+                         double *sn, double *g, double tol, double *st)
+{
+    if (threadIdx.x != 0 || st[0] != 0.0) return;
+    auto Hat = [&](int i, int c) -> double & { return H[(int64_t)i * m + c]; };
+    for (int i = 0; i <= j; ++i) Hat(i, j) = h1[i] + h2[i];
+    const double hn = sqrt(nrm2[0]);
+    Hat(j + 1, j) = hn;
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hat(i, j) + sn[i] * Hat(i + 1, j);
+        Hat(i + 1, j) = -sn[i] * Hat(i, j) + cs[i] * Hat(i + 1, j);
+        Hat(i, j) = t;
+    }
+    const double den = hypot(Hat(j, j), Hat(j + 1, j));
+    cs[j] = den != 0.0 ? Hat(j, j) / den : 1.0;
+    sn[j] = den != 0.0 ? Hat(j + 1, j) / den : 0.0;
+    Hat(j, j) = cs[j] * Hat(j, j) + sn[j] * Hat(j + 1, j);
+    Hat(j + 1, j) = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    st[1] = (double)(j + 1);
+    if (fabs(g[j + 1]) <= tol || hn == 0.0 || den == 0.0) st[0] = 1.0;
+}
+
+// y = H_k^{-1} g_k by back substitution, k = st[1] steps.
+__global__ void k_backsolve(int m, const double *H, const double *g, const double *st, double *y)
+{
+    if (threadIdx.x != 0) return;
+    const int k = (int)st[1];
+    for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int c = i + 1; c < k; ++c) t -= H[(int64_t)i * m + c] * y[c];
+        const double d = H[(int64_t)i * m + i];
+        y[i] = d != 0.0 ? t / d : 0.0;
+    }
+}
+
+} // namespace
+
+int blas_cycle_start(double *g, double *st, int m, double beta, void *stream)
+{
+    hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(64), 0, (hipStream_t)stream, g, st, m, beta);
+    return (int)hipGetLastError();
+}
+
+int blas_givens(int j, int m, const double *h1, const double *h2, const double *nrm2, double *H, double *cs, double *sn,
+                double *g, double tol, double *st, void *stream)
+{
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, (hipStream_t)stream, j, m, h1, h2, nrm2, H, cs, sn, g, tol, st);
+    return (int)hipGetLastError();
+}
+
+int blas_backsolve(int m, const double *H, const double *g, const double *st, double *y, void *stream)
+{
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, (hipStream_t)stream, m, H, g, st, y);
+    return (int)hipGetLastError();
+}
+
 int blas_normalise(const double *w, const double *nrm2, double *v, int64_t n, void *stream)
 {
     if (n <= 0) return 0;

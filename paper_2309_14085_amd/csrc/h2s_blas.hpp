@@ -26,4 +26,15 @@ int blas_sub(const double *b, const double *y, double *r, int64_t n, void *strea
 // v = c.
 int blas_fill(double *v, double c, int64_t n, void *stream);
 
+// The Hessenberg part of a GMRES(m) cycle on the device.  H: (m + 1) x m row-major; cs, sn: m;
+// g: m + 1; st: 2 (st[0] = 1 once the cycle is done, st[1] = steps kept).
+// Start a cycle: g = beta e_1, st = 0.
+int blas_cycle_start(double *g, double *st, int m, double beta, void *stream);
+// Step j: H(:, j) = h1 + h2 (rows 0..j), H(j+1, j) = sqrt(nrm2[0]), the earlier rotations, a new
+// rotation zeroing H(j+1, j), g rotated; done when |g[j+1]| <= tol or on a breakdown.
+int blas_givens(int j, int m, const double *h1, const double *h2, const double *nrm2, double *H, double *cs, double *sn,
+                double *g, double tol, double *st, void *stream);
+// y = H_k^{-1} g_k, k = st[1], by back substitution.
+int blas_backsolve(int m, const double *H, const double *g, const double *st, double *y, void *stream);
+
 } // namespace h2s

@@ -8,15 +8,17 @@
 // classical Gram-Schmidt projections applied twice, norms, the correction
 // x += V y and the residual r = b - K~ x with the FP64 product.  The
 // (m + 1) x m Hessenberg matrix, its Givens rotations and the triangular
-// solve live on the host; one small device-to-host copy per Arnoldi step
-// brings back the projection coefficients and the new norm.
+// solve live on the device too (h2s_blas.hip): a cycle is enqueued step by
+// step without waiting, the host reads back the cycle's state only every
+// kCheck steps (to stop at the inner tolerance) and the new residual norm
+// once per cycle.
 #include "h2s_solve.hpp"
 
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <limits>
-#include <vector>
 
 #include "h2s_blas.hpp"
 
@@ -35,22 +37,29 @@ inline void ck(int rc)
 
 } // namespace
 
+// Arnoldi steps enqueued between two looks at the cycle's state.
+constexpr int kCheck = 4;
+
 int gmres_ir(const SolveOps &ops, const SolveWork &wk, const SolveParams &prm, int64_t n, const double *b, double *x,
              void *stream, SolveResult *res)
 {
     hipStream_t s = (hipStream_t)stream;
     const int m = prm.restart;
-    double *h1 = wk.small, *h2 = wk.small + (m + 1), *nrm2 = wk.small + 2 * (m + 1);
-    const double *h1h = wk.small_host, *h2h = wk.small_host + (m + 1), *nrm2h = wk.small_host + 2 * (m + 1);
+    // layout of wk.small (solve_small_doubles)
+    double *h1 = wk.small, *h2 = h1 + (m + 1), *nrm2 = h2 + (m + 1), *st = nrm2 + 1;
+    double *H = st + 2, *cs = H + (int64_t)(m + 1) * m, *sn = cs + m, *g = sn + m, *yv = g + (m + 1);
+    const int64_t o_nrm2 = nrm2 - wk.small;
+    const double *nrm2h = wk.small_host + o_nrm2, *sth = nrm2h + 1;
     *res = SolveResult{0, 0, 0, std::numeric_limits<double>::quiet_NaN()};
     try {
-        auto to_host = [&](int count) {
-            ck((int)hipMemcpyAsync(wk.small_host, wk.small, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+        // the new norm and the cycle state to the host
+        auto to_host = [&]() {
+            ck((int)hipMemcpyAsync(wk.small_host + o_nrm2, nrm2, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
             ck((int)hipStreamSynchronize(s));
         };
         auto norm = [&](const double *v) {
             ck(blas_dots(v, n, 1, v, n, wk.part, nrm2, s));
-            to_host(2 * (m + 1) + 1);
+            to_host();
             return std::sqrt(*nrm2h);
         };
         const double bnorm = norm(b);
@@ -67,8 +76,6 @@ int gmres_ir(const SolveOps &ops, const SolveWork &wk, const SolveParams &prm, i
             ck((int)hipMemcpyAsync(wk.r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
         }
         double rnorm = norm(wk.r);
-        std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), yv(m);
-        auto Hat = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
         int its = 0, refs = 0, stall = 0;
         while (true) {
             if (rnorm / bnorm <= prm.rtol) {
@@ -76,12 +83,12 @@ int gmres_ir(const SolveOps &ops, const SolveWork &wk, const SolveParams &prm, i
                 break;
             }
             if (its >= prm.max_iter || refs >= prm.max_refine || stall >= 3) break;
-            // one GMRES(m) cycle on K~ d = r, d = V_k y
+            // one GMRES(m) cycle on K~ d = r, d = V_k y, with the Hessenberg work on the device
             ck(blas_scale(wk.r, rnorm, wk.V, n, s));
-            std::fill(g.begin(), g.end(), 0.0);
-            g[0] = rnorm;
-            int k = 0;
-            for (int j = 0; j < m; ++j) {
+            ck(blas_cycle_start(g, st, m, rnorm, s));
+            const double tol = prm.inner_rtol * rnorm;
+            const int steps = std::min(m, prm.max_iter - its);
+            for (int j = 0; j < steps; ++j) {
                 const double *vj = wk.V + (int64_t)j * n;
                 ck(ops.apply_inner(ops.ctx, vj, wk.w));
                 ck(blas_dots(wk.V, n, j + 1, wk.w, n, wk.part, h1, s));
@@ -90,36 +97,18 @@ int gmres_ir(const SolveOps &ops, const SolveWork &wk, const SolveParams &prm, i
                 ck(blas_gemv_acc(wk.V, n, j + 1, h2, -1.0, wk.w, n, s));
                 ck(blas_dots(wk.w, n, 1, wk.w, n, wk.part, nrm2, s));
                 ck(blas_normalise(wk.w, nrm2, wk.V + (int64_t)(j + 1) * n, n, s));
-                to_host(2 * (m + 1) + 1);
-                for (int i = 0; i <= j; ++i) Hat(i, j) = h1h[i] + h2h[i];
-                const double hn = std::sqrt(*nrm2h);
-                Hat(j + 1, j) = hn;
-                for (int i = 0; i < j; ++i) {
-                    const double t = cs[i] * Hat(i, j) + sn[i] * Hat(i + 1, j);
-                    Hat(i + 1, j) = -sn[i] * Hat(i, j) + cs[i] * Hat(i + 1, j);
-                    Hat(i, j) = t;
+                ck(blas_givens(j, m, h1, h2, nrm2, H, cs, sn, g, tol, st, s));
+                if ((j + 1) % kCheck == 0 && j + 1 < steps) {
+                    to_host();
+                    if (sth[0] != 0.0) break;
                 }
-                const double den = std::hypot(Hat(j, j), Hat(j + 1, j));
-                cs[j] = den != 0.0 ? Hat(j, j) / den : 1.0;
-                sn[j] = den != 0.0 ? Hat(j + 1, j) / den : 0.0;
-                Hat(j, j) = cs[j] * Hat(j, j) + sn[j] * Hat(j + 1, j);
-                Hat(j + 1, j) = 0.0;
-                g[j + 1] = -sn[j] * g[j];
-                g[j] = cs[j] * g[j];
-                ++its;
-                k = j + 1;
-                if (std::fabs(g[j + 1]) <= prm.inner_rtol * rnorm || its >= prm.max_iter || hn == 0.0 || den == 0.0)
-                    break;
             }
+            to_host();
+            const int k = (int)sth[1];
+            its += k;
             // back substitution H_k y = g_k, then x += V_k y
-            for (int i = k - 1; i >= 0; --i) {
-                double t = g[i];
-                for (int c = i + 1; c < k; ++c) t -= Hat(i, c) * yv[c];
-                yv[i] = Hat(i, i) != 0.0 ? t / Hat(i, i) : 0.0;
-            }
-            for (int i = 0; i < k; ++i) wk.small_host[i] = yv[i];
-            ck((int)hipMemcpyAsync(h1, wk.small_host, sizeof(double) * k, hipMemcpyHostToDevice, s));
-            ck(blas_gemv_acc(wk.V, n, k, h1, 1.0, x, n, s));
+            ck(blas_backsolve(m, H, g, st, yv, s));
+            ck(blas_gemv_acc(wk.V, n, k, yv, 1.0, x, n, s));
             ++refs;
             // FP64 residual
             ck(ops.apply_outer(ops.ctx, x, wk.y));

@@ -19,9 +19,14 @@ struct SolveWork {
     double *V;          // n x (m + 1), column-major, ld = n
     double *w, *r, *y;  // n each
     double *part;       // blas_dots_blocks(n) * (m + 1)
-    double *small;      // device, 2 (m + 1) + 2
+    double *small;      // device, solve_small_doubles(m): see gmres_ir for the layout
     double *small_host; // pinned host mirror of `small`
 };
+
+// Doubles of SolveWork::small for restart length m: the two Gram-Schmidt projections (m + 1
+// each), the new norm and the cycle state (3), the Hessenberg matrix ((m + 1) m), the rotations
+// (2 m), the rotated right-hand side (m + 1) and the least-squares solution (m).
+inline int64_t solve_small_doubles(int m) { return 2 * (int64_t)(m + 1) + 3 + (int64_t)(m + 1) * m + 2 * (int64_t)m + (m + 1) + m; }
 
 struct SolveParams {
     int restart, max_iter, max_refine;

@@ -452,36 +452,6 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     for (int32_t g = 0; g <= nbox; ++g) ilo[g] = (int32_t)r.list_off[w][g];
     G.il_off = up.copy(ilo);
     G.il_idx = up.copy(r.list_idx[w]);
-    {
-        // symmetric M2L: the pair {X, Y}, X < Y, is evaluated by X's block, which writes its
-        // column sums (r_Y entries) to a slot of W that Y's entry for X points at
-        const std::vector<int32_t> &li = r.list_idx[w];
-        std::vector<int32_t> ulb(nbox + 1, 0);
-        std::vector<int64_t> pw(li.size() ? li.size() : 1, -1);
-        int64_t wsize = 0;
-        for (int32_t g = 0; g < nbox; ++g) {
-            int64_t e = r.list_off[w][g];
-            const int64_t e1 = r.list_off[w][g + 1];
-            while (e < e1 && li[e] < g) ++e;
-            ulb[g] = (int32_t)e;
-            for (; e < e1; ++e)
-                if (F.rank[g] > 0 && F.rank[li[e]] > 0) {
-                    pw[e] = wsize;
-                    wsize += F.rank[li[e]];
-                }
-        }
-        for (int32_t g = 0; g < nbox; ++g)
-            for (int64_t e = r.list_off[w][g]; e < ulb[g]; ++e) {
-                const int32_t x = li[e]; // below g: find g in x's list
-                const auto b0 = li.begin() + r.list_off[w][x], b1 = li.begin() + r.list_off[w][x + 1];
-                const auto it = std::lower_bound(b0, b1, g);
-                pw[e] = (it != b1 && *it == g) ? pw[it - li.begin()] : -1;
-            }
-        ulb[nbox] = (int32_t)li.size();
-        G.ul_beg = up.copy(ulb);
-        G.pw_off = up.copy(pw);
-        G.W = up.template zeros<double>(wsize ? 2 * wsize : 2);
-    }
     std::vector<int32_t> targets;
     for (int32_t g = 0; g < nbox; ++g)
         if (F.rank[g] > 0) targets.push_back(g);
@@ -491,7 +461,6 @@ void upload_family(Uploader &up, const h2s::HostRep &r, int f, const std::vector
     G.ncoef = (int32_t)nc;
     G.v = up.template zeros<double>(nc ? nc : 1);
     G.u = up.template zeros<double>(nc ? nc : 1);
-    G.ulo = up.template zeros<double>(nc ? nc : 1);
     (void)kappa;
 }
 

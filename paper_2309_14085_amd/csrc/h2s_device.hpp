@@ -78,10 +78,6 @@ template <typename CT, typename BT> struct DevFamily {
     const int16_t *tpos;         // per coefficient with a unit row: kept rows before that row
     const int32_t *il_off;       // nbox + 1
     const int32_t *il_idx;
-    const int32_t *ul_beg;       // per box: first entry of its list above it (the list is sorted)
-    const int64_t *pw_off;       // per list entry: W offset of the pair's column sums (-1: a rank is 0)
-    double *W;                   // column sums w_{X->Y} as (hi, lo) pairs (r_Y per pair X < Y, both ranks > 0)
-    double *ulo;                 // second part of the M2L row sums before the mirrored sums are added
     const int32_t *targets;      // boxes with rank > 0 at levels >= lmin, in box (so level) order
     int32_t ntargets;
     int32_t targets_leaf;        // index in targets of the first leaf-level box

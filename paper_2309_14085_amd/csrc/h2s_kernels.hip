@@ -6,7 +6,8 @@
 //   k_p2p        direct near field             yn_X = sum_{X' in N*(X)} K(X, X') q_X'
 //   k_up_leaf    P2M                           v_X = U_X^T q_X            (both families)
 //   k_m2m        one level of M2M              v_X = sum_c U~_{X_c X}^T v_{X_c}
-//   k_m2l        all levels of one family      u_X = sum_{Y in IL(X)} K(t^{X,i}, t^{Y,i}) v_Y
+//   k_m2l_slices all levels of one family      u_X = sum_{Y in IL(X)} K(t^{X,i}, t^{Y,i}) v_Y
+//   k_m2l        the same with a float far field (FP32_M2L)
 //   k_l2l        one level of L2L              u_{X_c} += U~_{X_c X} u_X
 //   k_pair_part  (H2+H)*: partial products Vb^T q_Y, Ub^T q_X over row chunks
 //   k_pair_sum   (H2+H)*: chunk sums in a fixed order
@@ -18,16 +19,15 @@
 // (under the profiling hook everything runs on the main stream, one class
 // at a time).
 //
-// Summation order.  The interpolative NCA operators have norms up to ~1e3 -
-// 1e4 on coarse levels, so a rounding difference in a multipole or local
-// coefficient is amplified on its way to the potential.  The steps whose
-// results are amplified (P2M, M2M, the per-source-box M2L sums, L2L, L2P)
-// therefore sum in the order of the definitions -- one output per thread,
-// terms in index order (as fused multiply-adds) -- so the GPU product
-// tracks a plain sequential evaluation to within a few ulps of each
-// coefficient.  The direct near field is a plain sum of kernel values
-// (nothing amplifies it); it is split over source slices to fill the block.
-// No floating-point atomics are used.
+// Accuracy of the sums.  The interpolative NCA operators have norms up to
+// ~1e3 - 1e4 on coarse levels, so a rounding error in a multipole or local
+// coefficient is amplified on its way to the potential.  In FP64 every sum
+// whose result an operator later multiplies (P2M, M2M, M2L, L2L, L2P) is an
+// accurate dot product (Ogita, Rump and Oishi, "Accurate sum and dot
+// product", 2005): the sum as if taken in twice the precision, rounded once,
+// whatever the order of its terms.  The direct near field is a plain sum of
+// kernel values (nothing amplifies it).  No floating-point atomics are used;
+// results are bitwise reproducible run to run.
 //
 // M2L and the near field evaluate the kernel on the fly from coordinates
 // staged in LDS; the GEMV-shaped steps are HBM-bound and read each operator
@@ -317,6 +317,13 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t, int32_t t0)
 // a + NP) against one slice, so every staged source serves two evaluations.
 // u_X[a] = sum over slices (in slice order) of the slice's partial sums.
 // X and its list boxes are distinct boxes of one level, so r^2 > 0.
+// FP64 (P::ordered): every partial sum is an accurate dot product kept as an
+// unevaluated pair (hi, lo) (dot2_add), the slices' pairs are added in slice
+// order (dd_add) and the result is rounded once, so u_X[a] is the sum over
+// the whole list as if taken in twice the precision: the coefficients v can
+// be large against u (interpolation operators of norm up to ~1e3), and a
+// plain sum's error, eps sum |K v|, would be amplified by the transfers.
+// The kernel values there come from the log rounded about once.
 // ---------------------------------------------------------------------------
 constexpr int NT_M2LS = 256;
 constexpr int M2LS_SRC = 512; // staged source pivots per group
@@ -328,12 +335,14 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
         else return t.ver;
     }();
     constexpr bool XW = kExtraCoord<KIND>;
+    constexpr bool ACC = P::ordered;
+    constexpr int TL = ACC ? kTabLenAcc<KIND> : kTabLen<KIND>;
     __shared__ double sx[M2LS_SRC], sy[M2LS_SRC], sz[D == 3 ? M2LS_SRC : 1], sv[M2LS_SRC], sw[XW ? M2LS_SRC : 1];
-    __shared__ double red[2 * NT_M2LS];
+    __shared__ double red[(ACC ? 4 : 2) * NT_M2LS];
     __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList];
-    __shared__ __align__(16) double ktab[kTabLenAcc<KIND>];
+    __shared__ __align__(16) double ktab[TL];
     const int tid = threadIdx.x;
-    stage_table<KIND, kTabLenAcc<KIND>>(t.ktab, ktab); // first used after a barrier
+    stage_table<KIND, TL>(t.ktab, ktab); // first used after a barrier
     const int g = F.targets[ti];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], nil = F.il_off[g + 1] - e0; // nil <= kMaxList (checked at build)
@@ -369,11 +378,38 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
         const double xa = F.pvx[c0 + ia], ya = F.pvy[c0 + ia], za = D == 3 ? (double)F.pvz[c0 + ia] : 0.0;
         const double xb = F.pvx[c0 + ib], yb = F.pvy[c0 + ib], zb = D == 3 ? (double)F.pvz[c0 + ib] : 0.0;
         const double wa = XW ? (double)F.pvw[c0 + ia] : 0.0, wb = XW ? (double)F.pvw[c0 + ib] : 0.0;
-        double acc_a = 0.0, acc_b = 0.0;
+        double acc_a = 0.0, acc_b = 0.0, lo_a = 0.0, lo_b = 0.0;
         int pos = 0;
+        auto kv = [&](double x, double y, double z, double w, double x0, double y0, double z0, double w0) {
+            return kval_pos<KIND, ACC>(add_extra<KIND>(dist2<false, D>(x - x0, y - y0, z - z0), w, w0), kp, ktab);
+        };
         auto flush = [&]() {
             __syncthreads();
-            if (s < NS) {
+            if (ACC && s < NS) {
+                // two independent (hi, lo) pairs per target keep two addition chains in flight
+                double a0s = 0, a0c = 0, a1s = 0, a1c = 0, b0s = 0, b0c = 0, b1s = 0, b1c = 0;
+                int j = s;
+                for (; j + NS < pos; j += 2 * NS) {
+                    const int j1 = j + NS;
+                    const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, v0 = sv[j];
+                    const double x1 = sx[j1], y1 = sy[j1], z1 = D == 3 ? sz[j1] : 0.0, v1 = sv[j1];
+                    const double w0 = XW ? sw[j] : 0.0, w1 = XW ? sw[j1] : 0.0;
+                    dot2_add(a0s, a0c, kv(xa, ya, za, wa, x0, y0, z0, w0), v0);
+                    dot2_add(b0s, b0c, kv(xb, yb, zb, wb, x0, y0, z0, w0), v0);
+                    dot2_add(a1s, a1c, kv(xa, ya, za, wa, x1, y1, z1, w1), v1);
+                    dot2_add(b1s, b1c, kv(xb, yb, zb, wb, x1, y1, z1, w1), v1);
+                }
+                if (j < pos) {
+                    const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, v0 = sv[j];
+                    const double w0 = XW ? sw[j] : 0.0;
+                    dot2_add(a0s, a0c, kv(xa, ya, za, wa, x0, y0, z0, w0), v0);
+                    dot2_add(b0s, b0c, kv(xb, yb, zb, wb, x0, y0, z0, w0), v0);
+                }
+                dd_add(acc_a, lo_a, a0s, a0c);
+                dd_add(acc_a, lo_a, a1s, a1c);
+                dd_add(acc_b, lo_b, b0s, b0c);
+                dd_add(acc_b, lo_b, b1s, b1c);
+            } else if (s < NS) {
                 double a0s = 0, a1s = 0, b0s = 0, b1s = 0;
                 int j = s;
                 for (; j + NS < pos; j += 2 * NS) {
@@ -419,15 +455,24 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
         }
         red[tid] = s < NS ? acc_a : 0.0;
         red[NT_M2LS + tid] = s < NS ? acc_b : 0.0;
+        if constexpr (ACC) {
+            red[2 * NT_M2LS + tid] = s < NS ? lo_a : 0.0;
+            red[3 * NT_M2LS + tid] = s < NS ? lo_b : 0.0;
+        }
         __syncthreads();
         if (tid < NP) {
-            double ua = 0.0, ub = 0.0;
+            double ua = 0.0, ub = 0.0, uac = 0.0, ubc = 0.0;
             for (int q = 0; q < NS; ++q) {
-                ua += red[q * NP + tid];
-                ub += red[NT_M2LS + q * NP + tid];
+                if constexpr (ACC) {
+                    dd_add(ua, uac, red[q * NP + tid], red[2 * NT_M2LS + q * NP + tid]);
+                    dd_add(ub, ubc, red[NT_M2LS + q * NP + tid], red[3 * NT_M2LS + q * NP + tid]);
+                } else {
+                    ua += red[q * NP + tid];
+                    ub += red[NT_M2LS + q * NP + tid];
+                }
             }
-            F.u[c0 + ia] = ua;
-            if (ib != ia) F.u[c0 + ib] = ub;
+            F.u[c0 + ia] = ua + uac;
+            if (ib != ia) F.u[c0 + ib] = ub + ubc;
         }
         __syncthreads();
     }
@@ -438,197 +483,6 @@ template <class P, bool FAR, int KIND, int D>
 __global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t, int32_t t0)
 {
     m2l_slices_body<P, FAR, KIND, D>(t, t0 + xcd_remap(blockIdx.x, gridDim.x));
-}
-
-// ---------------------------------------------------------------------------
-// Symmetric M2L.  The interaction lists are symmetric (Y in IL(X) iff X in
-// IL(Y)) and so are the coupling blocks: T_{Y,X} = K(t^{Y,i}, t^{X,i}) =
-// T_{X,Y}^T for a symmetric kernel (Sec. 3.4.3 and its remark on symmetric
-// kernels).  Each unordered pair is therefore evaluated once, by the block of
-// its lower box X, over the upper part of X's list (Y > X):
-//   u_X[a]      = sum over upper Y, b of K(a, b) v_Y[b]   (row sums)
-//   w_{X->Y}[b] = sum_a K(a, b) v_X[a]                     (column sums)
-// the column sums going to the pair's slot in W.  A second launch then adds to
-// u_Y the slots w_{X->Y} of every lower X in list order.  Every sum is an
-// accurate dot product kept as an unevaluated pair (hi, lo): each product's
-// rounding error from an fma, each addition's from TwoSum, gathered in lo
-// (Ogita, Rump and Oishi, "Accurate sum and dot product", 2005).  The
-// coefficients v can be large against u (interpolation operators of norm up
-// to ~1e3), so plain sums would leave errors of order eps sum |K v| that the
-// transfers then amplify; these sums are as if taken in twice the precision,
-// in a fixed order, without atomics.  The thread layout is the one-sided
-// M2L's (two targets per thread against a slice of the staged sources); each
-// thread leaves its two targets' share of a source's column sum in LDS, and
-// after the group the shares are added over the target pairs in order.
-// ---------------------------------------------------------------------------
-constexpr int NT_SYM = 256;
-constexpr int SYM_SPT = 4;    // staged sources per thread and group
-constexpr int SYM_GMAX = 256; // staged sources per group at most
-constexpr int SYM_CH = 4;     // target pairs per chunk of the first column-reduction step
-
-template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2l_sym_body(const DevTree<P> &t, int ti)
-{
-    const auto &F = [&]() -> const auto & {
-        if constexpr (FAR) return t.far;
-        else return t.ver;
-    }();
-    constexpr bool XW = kExtraCoord<KIND>;
-    __shared__ double sx[SYM_GMAX], sy[SYM_GMAX], sz[D == 3 ? SYM_GMAX : 1], sv[SYM_GMAX], sw[XW ? SYM_GMAX : 1];
-    __shared__ int64_t sW[SYM_GMAX];
-    // [target pair][source of the group] shares (hi, lo) of the column sums; after the last group
-    // the slices' row sums (hi, lo) for the two targets.  colred: the shares summed over chunks
-    // of SYM_CH target pairs, [chunk][source]
-    constexpr int CP = NT_SYM * SYM_SPT;
-    static_assert(CP >= 2 * NT_SYM, "the row sums fit in the column buffer");
-    __shared__ double colhi[CP], collo[CP];
-    __shared__ double redhi[CP / SYM_CH + SYM_GMAX], redlo[CP / SYM_CH + SYM_GMAX];
-    __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList];
-    __shared__ int64_t boxw[kMaxList];
-    __shared__ __align__(16) double ktab[kTabLenAcc<KIND>];
-    const int tid = threadIdx.x;
-    stage_table<KIND, kTabLenAcc<KIND>>(t.ktab, ktab); // first used after a barrier
-    const int g = F.targets[ti];
-    const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0; // r <= 2 NT_SYM (rank cap, checked at build)
-    const int eb = F.ul_beg[g], nil = F.il_off[g + 1] - eb;   // the upper part of IL(X)
-    const KPar<double> kp = kpar<double>(t);
-    // the sources of the upper list as slots 0 .. S-1 (as in the one-sided M2L); slot s of list
-    // box k has W index boxw[k] + s - boxoff[k]
-    for (int k = tid; k < nil; k += NT_SYM) {
-        const int y = F.il_idx[eb + k];
-        boxcoef[k] = F.coef_off[y];
-        boxoff[k + 1] = F.coef_off[y + 1] - F.coef_off[y];
-        boxw[k] = F.pw_off[eb + k];
-    }
-    __syncthreads();
-    if (tid == 0) {
-        boxoff[0] = 0;
-        for (int k = 1; k <= nil; ++k) boxoff[k] += boxoff[k - 1];
-    }
-    __syncthreads();
-    const int S = nil > 0 ? boxoff[nil] : 0;
-    auto box_of = [&](int sl) -> int {
-        int lo = 0, hi = nil - 1; // largest k with boxoff[k] <= sl
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (boxoff[mid] <= sl) lo = mid;
-            else hi = mid - 1;
-        }
-        return lo;
-    };
-    const int MT = r, NP = (MT + 1) / 2, NS = NT_SYM / NP;
-    const int G = min(NS * SYM_SPT, SYM_GMAX);
-    const int s = tid / NP, pa = tid % NP;
-    const int ia = pa, ib = pa + NP < MT ? ia + NP : ia; // a lone last target is paired with itself
-    const bool act = s < NS;
-    const double xa = F.pvx[c0 + ia], ya = F.pvy[c0 + ia], za = D == 3 ? (double)F.pvz[c0 + ia] : 0.0;
-    const double xb = F.pvx[c0 + ib], yb = F.pvy[c0 + ib], zb = D == 3 ? (double)F.pvz[c0 + ib] : 0.0;
-    const double wa = XW ? (double)F.pvw[c0 + ia] : 0.0, wb = XW ? (double)F.pvw[c0 + ib] : 0.0;
-    const double va = F.v[c0 + ia], vb = ib != ia ? F.v[c0 + ib] : 0.0;
-    double sa = 0.0, ca = 0.0, sb = 0.0, cb = 0.0;
-    for (int base = 0; base < S; base += G) {
-        const int take = min(S - base, G);
-        for (int j = tid; j < take; j += NT_SYM) {
-            const int k = box_of(base + j);
-            const int o = base + j - boxoff[k], c = boxcoef[k] + o;
-            sx[j] = F.pvx[c];
-            sy[j] = F.pvy[c];
-            if constexpr (D == 3) sz[j] = F.pvz[c];
-            if constexpr (XW) sw[j] = F.pvw[c];
-            sv[j] = F.v[c];
-            sW[j] = boxw[k] + o;
-        }
-        __syncthreads();
-        if (act) {
-            for (int j = s; j < take; j += NS) {
-                const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, v0 = sv[j];
-                const double w0 = XW ? sw[j] : 0.0;
-                const double ka = kval_pos<KIND, true>(add_extra<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), wa, w0), kp, ktab);
-                const double kb = kval_pos<KIND, true>(add_extra<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), wb, w0), kp, ktab);
-                dot2_add(sa, ca, ka, v0);
-                dot2_add(sb, cb, kb, v0);
-                double hs = 0.0, hc = 0.0;
-                dot2_add(hs, hc, ka, va);
-                dot2_add(hs, hc, kb, vb);
-                colhi[pa * G + j] = hs;
-                collo[pa * G + j] = hc;
-            }
-        }
-        __syncthreads();
-        // column sums over the target pairs in pair order, in two steps that keep every thread
-        // busy: chunks of SYM_CH pairs, then the chunks
-        const int nch = (NP + SYM_CH - 1) / SYM_CH;
-        for (int w = tid; w < nch * take; w += NT_SYM) {
-            const int j = w % take, ch = w / take;
-            const int p0 = ch * SYM_CH, p1 = min(p0 + SYM_CH, NP);
-            double hs = 0.0, hc = 0.0;
-            for (int p = p0; p < p1; ++p) dd_add(hs, hc, colhi[p * G + j], collo[p * G + j]);
-            redhi[ch * take + j] = hs;
-            redlo[ch * take + j] = hc;
-        }
-        __syncthreads();
-        for (int j = tid; j < take; j += NT_SYM) {
-            double hs = 0.0, hc = 0.0;
-            for (int ch = 0; ch < nch; ++ch) dd_add(hs, hc, redhi[ch * take + j], redlo[ch * take + j]);
-            F.W[2 * sW[j]] = hs;
-            F.W[2 * sW[j] + 1] = hc;
-        }
-        // the next group's staging writes sx .. sW only at indices this thread has just read, its
-        // shares only after its staging barrier (every thread is past the chunk step by then), and
-        // the chunk sums only after its share barrier
-    }
-    __syncthreads(); // the row sums reuse the share buffers
-    colhi[tid] = act ? sa : 0.0;
-    collo[tid] = act ? ca : 0.0;
-    colhi[NT_SYM + tid] = act ? sb : 0.0;
-    collo[NT_SYM + tid] = act ? cb : 0.0;
-    __syncthreads();
-    if (tid < NP) {
-        double ua = 0.0, uac = 0.0, ub = 0.0, ubc = 0.0;
-        for (int q = 0; q < NS; ++q) {
-            dd_add(ua, uac, colhi[q * NP + tid], collo[q * NP + tid]);
-            dd_add(ub, ubc, colhi[NT_SYM + q * NP + tid], collo[NT_SYM + q * NP + tid]);
-        }
-        F.u[c0 + ia] = ua;
-        F.ulo[c0 + ia] = uac;
-        if (ib != ia) {
-            F.u[c0 + ib] = ub;
-            F.ulo[c0 + ib] = ubc;
-        }
-    }
-}
-
-// u_Y = (its row sums) + w_{X->Y} for every X below Y in IL(Y), in list order, in (hi, lo)
-// pairs, rounded once at the end.
-template <class P, bool FAR> __device__ __forceinline__ void m2l_gather_body(const DevTree<P> &t, int ti)
-{
-    const auto &F = [&]() -> const auto & {
-        if constexpr (FAR) return t.far;
-        else return t.ver;
-    }();
-    const int g = F.targets[ti];
-    const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
-    const int e0 = F.il_off[g], eb = F.ul_beg[g];
-    for (int b = threadIdx.x; b < r; b += blockDim.x) {
-        double u = F.u[c0 + b], c = F.ulo[c0 + b];
-        for (int e = e0; e < eb; ++e) {
-            const int64_t w = F.pw_off[e];
-            if (w >= 0) dd_add(u, c, F.W[2 * (w + b)], F.W[2 * (w + b) + 1]);
-        }
-        F.u[c0 + b] = u + c;
-    }
-}
-
-constexpr int NT_GATHER = 64;
-
-template <class P, bool FAR, int KIND, int D>
-__global__ __launch_bounds__(NT_SYM) void k_m2l_sym(DevTree<P> t, int32_t t0)
-{
-    m2l_sym_body<P, FAR, KIND, D>(t, t0 + xcd_remap(blockIdx.x, gridDim.x));
-}
-
-template <class P, bool FAR> __global__ __launch_bounds__(NT_GATHER) void k_m2l_gather(DevTree<P> t, int32_t t0)
-{
-    m2l_gather_body<P, FAR>(t, t0 + (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1151,23 +1005,6 @@ __global__ __launch_bounds__(NT_M2LS) void km_m2l(const DevTree<P> *__restrict__
     m2l_slices_body<P, FAR, KIND, D>(t, w.y);
 }
 
-template <class P, bool FAR, int KIND, int D>
-__global__ __launch_bounds__(NT_SYM) void km_m2l_sym(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map)
-{
-    const int2 w = map[xcd_remap(blockIdx.x, gridDim.x)];
-    const DevTree<P> t = trees[w.x];
-    m2l_sym_body<P, FAR, KIND, D>(t, w.y);
-}
-
-template <class P, bool FAR>
-__global__ __launch_bounds__(NT_GATHER) void km_m2l_gather(const DevTree<P> *__restrict__ trees,
-                                                           const int2 *__restrict__ map)
-{
-    const int2 w = map[blockIdx.x];
-    const DevTree<P> t = trees[w.x];
-    m2l_gather_body<P, FAR>(t, w.y);
-}
-
 template <class P, int KIND, int D>
 __global__ __launch_bounds__(NT_P2P) void km_p2p(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map)
 {
@@ -1202,14 +1039,10 @@ template <class P, int KIND, int D> hipError_t enqueue_multi(const MultiPlan<P> 
     for (int k = 0; k < mp.steps; ++k)
         if (mp.n_m2m[k])
             hipLaunchKernelGGL(km_m2m<P>, dim3(mp.n_m2m[k]), dim3(mp.w_m2m[k]), mp.lds_rows, s, mp.trees, mp.m2m_map[k]);
-    if (mp.n_far) {
-        hipLaunchKernelGGL((km_m2l_sym<P, true, KIND, D>), dim3(mp.n_far), dim3(NT_SYM), 0, s, mp.trees, mp.far_map);
-        hipLaunchKernelGGL((km_m2l_gather<P, true>), dim3(mp.n_far), dim3(NT_GATHER), 0, s, mp.trees, mp.far_map);
-    }
-    if (mp.n_ver) {
-        hipLaunchKernelGGL((km_m2l_sym<P, false, KIND, D>), dim3(mp.n_ver), dim3(NT_SYM), 0, s, mp.trees, mp.ver_map);
-        hipLaunchKernelGGL((km_m2l_gather<P, false>), dim3(mp.n_ver), dim3(NT_GATHER), 0, s, mp.trees, mp.ver_map);
-    }
+    if (mp.n_far)
+        hipLaunchKernelGGL((km_m2l<P, true, KIND, D>), dim3(mp.n_far), dim3(NT_M2LS), 0, s, mp.trees, mp.far_map);
+    if (mp.n_ver)
+        hipLaunchKernelGGL((km_m2l<P, false, KIND, D>), dim3(mp.n_ver), dim3(NT_M2LS), 0, s, mp.trees, mp.ver_map);
     for (int k = 0; k < mp.steps; ++k)
         if (mp.n_l2l[k])
             hipLaunchKernelGGL(km_l2l<P>, dim3(mp.n_l2l[k]), dim3(mp.w_l2l[k]), mp.lds_rank, s, mp.trees, mp.l2l_map[k]);
@@ -1255,22 +1088,18 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
         if (le > lb) hipLaunchKernelGGL((k_p2p<P, KIND, D>), dim3(le - lb), dim3(NT_P2P), 0, aux, t, lb, le - lb);
         return hipEventRecord((hipEvent_t)st.join, aux);
     };
-    // M2L of one family over its targets [tb, te) on stream `on`: each unordered pair once
-    // (k_m2l_sym), then the mirrored column sums added in list order (k_m2l_gather).  Pairs lie
-    // within one level, and every level's targets are a contiguous range, so a range split at a
-    // level boundary needs nothing from the other part.
+    // M2L of one family over its targets [tb, te) on stream `on`.  Targets of one level need
+    // only that level's multipoles, and every level's targets are a contiguous range, so a range
+    // split at a level boundary needs nothing from the other part.
     auto m2l = [&](bool far, int32_t tb, int32_t te, hipStream_t on) {
         if (te <= tb) return;
         if (far) {
-            if constexpr (sizeof(typename P::far_t) == 4) {
+            if constexpr (sizeof(typename P::far_t) == 4)
                 hipLaunchKernelGGL((k_m2l<P, true, KIND, D>), dim3(te - tb), dim3(NT_M2L), 0, on, t, tb);
-            } else {
-                hipLaunchKernelGGL((k_m2l_sym<P, true, KIND, D>), dim3(te - tb), dim3(NT_SYM), 0, on, t, tb);
-                hipLaunchKernelGGL((k_m2l_gather<P, true>), dim3(te - tb), dim3(NT_GATHER), 0, on, t, tb);
-            }
+            else
+                hipLaunchKernelGGL((k_m2l_slices<P, true, KIND, D>), dim3(te - tb), dim3(NT_M2LS), 0, on, t, tb);
         } else {
-            hipLaunchKernelGGL((k_m2l_sym<P, false, KIND, D>), dim3(te - tb), dim3(NT_SYM), 0, on, t, tb);
-            hipLaunchKernelGGL((k_m2l_gather<P, false>), dim3(te - tb), dim3(NT_GATHER), 0, on, t, tb);
+            hipLaunchKernelGGL((k_m2l_slices<P, false, KIND, D>), dim3(te - tb), dim3(NT_M2LS), 0, on, t, tb);
         }
     };
     const bool far_on = (mask & kFar) != 0, ver_on = (mask & kVer) != 0;

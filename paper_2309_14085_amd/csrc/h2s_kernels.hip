@@ -337,10 +337,17 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
     constexpr bool XW = kExtraCoord<KIND>;
     constexpr bool ACC = P::ordered;
     constexpr int TL = ACC ? kTabLenAcc<KIND> : kTabLen<KIND>;
-    __shared__ double sx[M2LS_SRC], sy[M2LS_SRC], sz[D == 3 ? M2LS_SRC : 1], sv[M2LS_SRC], sw[XW ? M2LS_SRC : 1];
-    __shared__ double red[(ACC ? 4 : 2) * NT_M2LS];
-    __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList];
+    // staged sources (x, y, v[, z][, w]); after the last group the same memory holds the slice partials
+    constexpr int NSRC = (3 + (D == 3) + XW) * M2LS_SRC;
+    static_assert(NSRC >= 4 * NT_M2LS, "the slice partials fit in the staging buffer");
+    __shared__ double sbuf[NSRC];
+    double *const sx = sbuf, *const sy = sx + M2LS_SRC, *const sv = sy + M2LS_SRC;
+    double *const sz = sv + M2LS_SRC;                 // used in 3D only
+    double *const sw = sz + (D == 3 ? M2LS_SRC : 0); // used by kernels of an extra coordinate only
+    double *const red = sbuf;
+    __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList], wsum[NT_M2LS / 64];
     __shared__ __align__(16) double ktab[TL];
+    static_assert(kMaxList <= NT_M2LS, "one list box per thread");
     const int tid = threadIdx.x;
     stage_table<KIND, TL>(t.ktab, ktab); // first used after a barrier
     const int g = F.targets[ti];
@@ -350,18 +357,22 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
     // the sources of IL(X) in list order as slots 0 .. S-1: slot s lies in list box e with
     // boxoff[e] <= s < boxoff[e + 1], coefficient boxcoef[e] + s - boxoff[e].  A group of
     // M2LS_SRC slots is staged with all its loads in flight at once.
-    for (int k = tid; k < nil; k += NT_M2LS) {
-        const int y = F.il_idx[e0 + k];
-        boxcoef[k] = F.coef_off[y];
-        boxoff[k + 1] = F.coef_off[y + 1] - F.coef_off[y];
+    int S;
+    {
+        int cb = 0, nb = 0;
+        if (tid < nil) {
+            const int y = F.il_idx[e0 + tid];
+            cb = F.coef_off[y];
+            nb = F.coef_off[y + 1] - cb;
+        }
+        const int off = block_excl_scan<NT_M2LS>(nb, wsum, S);
+        if (tid < nil) {
+            boxcoef[tid] = cb;
+            boxoff[tid] = off;
+        }
+        if (tid == 0) boxoff[nil] = S;
+        __syncthreads();
     }
-    __syncthreads();
-    if (tid == 0) {
-        boxoff[0] = 0;
-        for (int k = 1; k <= nil; ++k) boxoff[k] += boxoff[k - 1];
-    }
-    __syncthreads();
-    const int S = boxoff[nil];
     auto coef_of = [&](int sl) -> int {
         int lo = 0, hi = nil - 1; // largest e with boxoff[e] <= sl
         while (lo < hi) {
@@ -480,7 +491,7 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
 
 // targets t0 .. t0 + gridDim.x - 1 of the family
 template <class P, bool FAR, int KIND, int D>
-__global__ __launch_bounds__(NT_M2LS) void k_m2l_slices(DevTree<P> t, int32_t t0)
+__global__ __launch_bounds__(NT_M2LS) __attribute__((amdgpu_waves_per_eu(6))) void k_m2l_slices(DevTree<P> t, int32_t t0)
 {
     m2l_slices_body<P, FAR, KIND, D>(t, t0 + xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -998,7 +1009,7 @@ __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void km_l2l(const DevTree<
 }
 
 template <class P, bool FAR, int KIND, int D>
-__global__ __launch_bounds__(NT_M2LS) void km_m2l(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map)
+__global__ __launch_bounds__(NT_M2LS) __attribute__((amdgpu_waves_per_eu(5))) void km_m2l(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map)
 {
     const int2 w = map[xcd_remap(blockIdx.x, gridDim.x)];
     const DevTree<P> t = trees[w.x];

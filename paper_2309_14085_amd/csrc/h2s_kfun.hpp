@@ -234,6 +234,31 @@ template <int KIND> __device__ __forceinline__ float kval(float r2, float diag, 
     return r2 == 0.0f ? diag : v;
 }
 
+// Exclusive prefix sum of one value per thread over a block of NT threads (wave
+// scans by shuffles, then the waves' totals); wsum: NT / 64 ints of LDS.  All
+// threads must call it; it ends with the block synchronised.
+template <int NT> __device__ __forceinline__ int block_excl_scan(int v, int *wsum, int &total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+        const int sw = wsum[w];
+        before += w < wave ? sw : 0;
+        total += sw;
+    }
+    return before + x - v;
+}
+
 template <typename T> __device__ __forceinline__ T wave_sum(T v)
 {
 #pragma unroll

@@ -50,7 +50,8 @@ namespace {
 // in one pass.
 // ---------------------------------------------------------------------------
 constexpr int NT_GEMV_MAX = 512;
-constexpr int GEMV_WAVES = 5; // waves per SIMD asked of the compiler (bytes in flight)
+constexpr int GEMV_WAVES = 8; // waves per SIMD asked of the compiler (bytes in flight)
+constexpr int LEAF_WAVES = 6; // the same for L2L's leaf-level partner, k_down_leaf (more live state)
 
 // Charges to tree order: qt[i] = x[perm[i]], 256 per block.
 template <class P> __device__ __forceinline__ void permute_body(const DevTree<P> &t, const double *__restrict__ x, int blk)
@@ -870,7 +871,7 @@ template <class P, int KIND, int D> __device__ __forceinline__ void p2p_sym_body
 
 // leaves leaf_begin .. leaf_begin + gridDim.x - 1, one per block
 template <class P, int KIND, int D>
-__global__ __launch_bounds__(NT_P2P) void k_p2p(DevTree<P> t, int32_t leaf_begin, int32_t leaf_count)
+__global__ __launch_bounds__(NT_P2P) __attribute__((amdgpu_waves_per_eu(5))) void k_p2p(DevTree<P> t, int32_t leaf_begin, int32_t leaf_count)
 {
     (void)leaf_count; // == gridDim.x
     p2p_sym_body<P, KIND, D>(t, leaf_begin + xcd_remap(blockIdx.x, gridDim.x));
@@ -961,7 +962,7 @@ __device__ __forceinline__ void down_leaf_body(const DevTree<P> &t, int leaf, do
 }
 
 template <class P>
-__global__ __launch_bounds__(NT_LEAF, GEMV_WAVES) void k_down_leaf(DevTree<P> t, double *__restrict__ y, uint32_t mask)
+__global__ __launch_bounds__(NT_LEAF, LEAF_WAVES) void k_down_leaf(DevTree<P> t, double *__restrict__ y, uint32_t mask)
 {
     down_leaf_body(t, xcd_remap(blockIdx.x, gridDim.x), y, mask);
 }

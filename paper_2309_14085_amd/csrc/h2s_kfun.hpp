@@ -297,7 +297,7 @@ __device__ __forceinline__ void dd_add(double &s, double &c, double h, double l)
 // fused multiply-adds.  The operator loads are software-pipelined two
 // batches of UNR deep so that a batch is in flight while the previous one is
 // accumulated.
-constexpr int UNR = 8;
+constexpr int UNR = 4;
 
 template <bool ORD, typename AT>
 __device__ __forceinline__ double ordered_dot(const AT *__restrict__ A, size_t stride, int R, const double *xs,

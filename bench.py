@@ -181,8 +181,11 @@ def time_solve(h2s, torch, w):
 
 
 def time_multi_rhs(h2s, torch, w, reps=3):
-    """FP64 H2* product of 32 right-hand sides: one h2s_apply with nrhs = 32 (blocks of 8 columns
-    through the batched kernels) against 32 single-column applies; build untimed."""
+    """H2* product of 32 right-hand sides: one h2s_apply with nrhs = 32 (blocks of 8 columns
+    through the batched kernels) against 32 single-column applies, in FP64; then the same
+    32-column product with the far-field M2L on the matrix cores in float (FP32_M2L) and with
+    bfloat16 inputs (FP32_BF16M2L), each with its error against the FP64 product (which the
+    GPU tests hold within 1e-12 of the oracle).  Builds untimed."""
     import numpy as np
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
@@ -216,12 +219,30 @@ def time_multi_rhs(h2s, torch, w, reps=3):
     diff = float(((Yb - Ys).norm(dim=0) / Ys.norm(dim=0)).max())
     st = T.stats()
     T.free()
+    # M2L flops of the far field per 32-column product (2 per multiply-add), for the matrix-core rate
+    far_flops = 2.0 * st["m2l_evals_family"][0] * w.nrhs
+    lowp = {}
+    for name, prec in (("fp32_m2l", h2s.FP32_M2L), ("bf16_m2l", h2s.FP32_BF16M2L)):
+        Tl = h2s.build(w.points(), kind=w.kind, leaf_size=w.nmax, eps=w.eps, prec=prec)
+        Yl = torch.empty_like(Yb)
+        Tl.apply(X, Yl)
+        torch.cuda.synchronize()
+        ms_l = timed(lambda: Tl.apply(X, Yl))
+        err = (Yl - Yb).norm(dim=0) / Yb.norm(dim=0)
+        errmax = (Yl - Yb).abs().amax(dim=0) / Yb.abs().amax(dim=0)
+        lowp[name] = {"batched_ms": ms_l, "speedup_vs_fp64_batched": ms_b / ms_l,
+                      "points_x_rhs_per_s": w.n * w.nrhs / (ms_l * 1e-3),
+                      "rel_err_vs_fp64_max_column": float(err.max()), "rel_err_vs_fp64_median_column": float(err.median()),
+                      "max_elem_err_vs_fp64": float(errmax.max()),
+                      "far_m2l_mfma": "f32 16x16x4" if prec == h2s.FP32_M2L else "bf16 16x16x32, f32 accumulation"}
+        Tl.free()
     return {"workload": w.name, "n": w.n, "d": w.d, "kernel": "1/r (K_ii = 0)", "nca_tol": w.eps, "nrhs": w.nrhs,
             "dtype": "f64", "batched_ms": ms_b, "per_vector_ms": ms_s, "speedup": ms_s / ms_b,
             "points_x_rhs_per_s_batched": w.n * w.nrhs / (ms_b * 1e-3),
             "points_x_rhs_per_s_per_vector": w.n * w.nrhs / (ms_s * 1e-3),
             "max_rel_diff_batched_vs_per_vector": diff, "t_init_s": t_init,
-            "m2l_evals_per_rhs": st["m2l_evals"], "p2p_evals_per_rhs": st["p2p_evals"]}
+            "m2l_evals_per_rhs": st["m2l_evals"], "p2p_evals_per_rhs": st["p2p_evals"],
+            "far_m2l_flops_per_product": far_flops, "low_precision": lowp}
 
 
 def time_serving(count=24, rate=4.0, workers=4, budget=16 << 30):

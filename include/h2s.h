@@ -83,8 +83,17 @@ typedef enum { H2S_H2STAR = 0, H2S_H2_PLUS_H = 1 } h2s_variant;
  *   FP32_M2L  as FP32, and the far-field M2L evaluated in float as well (for
  *             log r as a per-pair constant in double plus a float remainder).
  *             The interpolative operators amplify float M2L values, so its
- *             error against FP64 is larger; it is reported, not bounded. */
-typedef enum { H2S_FP64 = 0, H2S_FP32 = 1, H2S_FP32_M2L = 2 } h2s_precision;
+ *             error against FP64 is larger; it is reported, not bounded.  In
+ *             products of several right-hand sides (blocks of 8 columns) the
+ *             far-field M2L runs on the matrix cores in float
+ *             (v_mfma_f32_16x16x4f32), kernel values shared by 32 columns.
+ *   FP32_BF16M2L  as FP32_M2L, and in products of several right-hand sides
+ *             the far-field kernel values and multipoles enter the matrix
+ *             cores as bfloat16 (v_mfma_f32_16x16x32_bf16, float accumulation).
+ *             Single-column products are FP32_M2L's.  Its error is reported,
+ *             not bounded.
+ * FP32_M2L and FP32_BF16M2L are not available for the NTI multiquadric. */
+typedef enum { H2S_FP64 = 0, H2S_FP32 = 1, H2S_FP32_M2L = 2, H2S_FP32_BF16M2L = 3 } h2s_precision;
 
 typedef struct {
     int32_t leaf_size;    /* n_max >= 1: leaf level kappa = ceil(log_{2^d}(n / n_max)) (Sec. 3.1) */

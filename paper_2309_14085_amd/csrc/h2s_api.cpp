@@ -664,15 +664,21 @@ template <class P> h2s_status upload(h2s_tree t, hipStream_t s, h2s::DevTree<P> 
 
 bool is_finite(double v) { return std::isfinite(v); }
 
+// The device copy a precision uses: FP32_M2L and FP32_BF16M2L share the float-far-field copy.
+int rep_slot(int p) { return p == H2S_FP32_BF16M2L ? (int)H2S_FP32_M2L : p; }
+
+bool low_m2l(int p) { return p == H2S_FP32_M2L || p == H2S_FP32_BF16M2L; }
+
 // Upload the representation in precision p unless it is already on the device.
 h2s_status ensure_uploaded(h2s_tree t, h2s_precision p, hipStream_t s)
 {
-    if (t->up[p]) return H2S_OK;
+    const int sl = rep_slot(p);
+    if (t->up[sl]) return H2S_OK;
     h2s_status st;
     if (p == H2S_FP64) st = upload<h2s::P64>(t, s, t->t64);
     else if (p == H2S_FP32) st = upload<h2s::P32>(t, s, t->t32);
     else st = upload<h2s::P32M>(t, s, t->t32m);
-    if (st == H2S_OK) t->up[p] = true;
+    if (st == H2S_OK) t->up[sl] = true;
     return st;
 }
 
@@ -838,12 +844,13 @@ h2s_status tune_plan(h2s_tree t, const double *x, double *y, int reps, hipStream
 // The batched product serves H2* with a double far field.
 template <class P> bool batch_supported(h2s_tree t, const h2s::DevTree<P> &)
 {
-    return t->rep.variant == H2S_H2STAR && sizeof(typename P::far_t) == 8;
+    return t->rep.variant == H2S_H2STAR;
 }
 
 // Allocate the multi-RHS block buffers of precision p on first use.
 template <class P> h2s_status ensure_batch(h2s_tree t, h2s::DevTree<P> &D, int p, hipStream_t s)
 {
+    p = rep_slot(p);
     if (t->batch[p]) return H2S_OK;
     Uploader up{t, s};
     const size_t nb = (size_t)h2s::kBatch * h2s::kGroupBlocks; // kGroupBlocks blocks of kBatch columns
@@ -867,17 +874,15 @@ h2s_status apply_columns(h2s_tree t, h2s::DevTree<P> &D, int p, uint32_t mask, c
 {
     const h2s::Streams st = streams_of(t, stream);
     int32_t c = 0;
-    if constexpr (sizeof(typename P::far_t) == 8) { // the batched kernels exist for a double far field only
-        if (nrhs > 1 && !prof && batch_supported(t, D)) {
-            const h2s_status bs = ensure_batch(t, D, p, (hipStream_t)stream);
-            if (bs != H2S_OK) return bs;
-            for (; c + 1 < nrhs; c += h2s::kGroupCols) {
-                const int na = std::min<int32_t>(h2s::kGroupCols, nrhs - c);
-                const int rc = h2s::launch_mvp_batch<P>(D, t->plan, x + c * ldx, ldx, y + c * ldy, ldy, na, mask, st);
-                if (rc != 0)
-                    return fail(H2S_ERR_DEVICE,
-                                std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
-            }
+    if (nrhs > 1 && !prof && batch_supported(t, D)) {
+        const h2s_status bs = ensure_batch(t, D, p, (hipStream_t)stream);
+        if (bs != H2S_OK) return bs;
+        for (; c + 1 < nrhs; c += h2s::kGroupCols) {
+            const int na = std::min<int32_t>(h2s::kGroupCols, nrhs - c);
+            const int rc = h2s::launch_mvp_batch<P>(D, t->plan, x + c * ldx, ldx, y + c * ldy, ldy, na, mask, st,
+                                                    p == H2S_FP32_BF16M2L);
+            if (rc != 0)
+                return fail(H2S_ERR_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString((hipError_t)rc));
         }
     }
     for (; c < nrhs; ++c) {
@@ -1045,8 +1050,8 @@ h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kerne
     if (!k || !o) return fail(H2S_ERR_INVALID_ARG, "kernel or options is NULL");
     if (k->kind < H2S_K_LOG_R || k->kind > H2S_K_NTI_MQ) return fail(H2S_ERR_INVALID_ARG, "unknown kernel kind");
     if (k->kind == H2S_K_NTI_MQ && d != 3) return fail(H2S_ERR_INVALID_ARG, "the NTI multiquadric needs d = 3");
-    if (k->kind == H2S_K_NTI_MQ && o && o->prec == H2S_FP32_M2L)
-        return fail(H2S_ERR_UNSUPPORTED, "H2S_FP32_M2L is not available for the NTI multiquadric");
+    if (k->kind == H2S_K_NTI_MQ && o && low_m2l(o->prec))
+        return fail(H2S_ERR_UNSUPPORTED, "H2S_FP32_M2L and H2S_FP32_BF16M2L are not available for the NTI multiquadric");
     if ((k->kind == H2S_K_RBF_AR || k->kind == H2S_K_RBF_LOG) && !(is_finite(k->param) && k->param > 0))
         return fail(H2S_ERR_INVALID_ARG, "the RBF radius (param) must be finite and > 0");
     if (k->kind == H2S_K_RBF_LOG && k->param == 1.0) return fail(H2S_ERR_INVALID_ARG, "RBF_LOG needs param != 1");
@@ -1057,7 +1062,7 @@ h2s_status h2s_build(const double *points, int64_t n, int32_t d, const h2s_kerne
     if (!(is_finite(o->eps_far) && o->eps_far >= 0 && is_finite(o->eps_ver) && o->eps_ver >= 0))
         return fail(H2S_ERR_INVALID_ARG, "tolerances must be finite and >= 0");
     if (o->variant != H2S_H2STAR && o->variant != H2S_H2_PLUS_H) return fail(H2S_ERR_INVALID_ARG, "unknown variant");
-    if (o->prec != H2S_FP64 && o->prec != H2S_FP32 && o->prec != H2S_FP32_M2L)
+    if (o->prec != H2S_FP64 && o->prec != H2S_FP32 && o->prec != H2S_FP32_M2L && o->prec != H2S_FP32_BF16M2L)
         return fail(H2S_ERR_INVALID_ARG, "unknown precision");
     for (int64_t i = 0; i < n * d; ++i)
         if (!is_finite(points[i])) return fail(H2S_ERR_INVALID_ARG, "points must be finite");
@@ -1123,7 +1128,7 @@ h2s_status h2s_apply_phases(h2s_tree t, uint32_t mask, const double *x, double *
     const h2s::ProfileHook *prof = t->profiling ? &hook : nullptr;
     if (t->opts.prec == H2S_FP64) return apply_columns(t, t->t64, H2S_FP64, mask, x, y, nrhs, ldx, ldy, stream, prof);
     if (t->opts.prec == H2S_FP32) return apply_columns(t, t->t32, H2S_FP32, mask, x, y, nrhs, ldx, ldy, stream, prof);
-    return apply_columns(t, t->t32m, H2S_FP32_M2L, mask, x, y, nrhs, ldx, ldy, stream, prof);
+    return apply_columns(t, t->t32m, t->opts.prec, mask, x, y, nrhs, ldx, ldy, stream, prof);
 }
 
 h2s_status h2s_apply(h2s_tree t, const double *x, double *y, int32_t nrhs, int64_t ldx, int64_t ldy, void *stream)
@@ -1208,9 +1213,10 @@ h2s_status h2s_solve(h2s_tree t, const double *b, double *x, int32_t nrhs, int64
     if (o.max_iter < 0 || o.max_refine < 0) return fail(H2S_ERR_INVALID_ARG, "max_iter and max_refine must be >= 0");
     if (!(o.rtol >= 0.0) || !is_finite(o.rtol) || !(o.inner_rtol >= 0.0) || !is_finite(o.inner_rtol))
         return fail(H2S_ERR_INVALID_ARG, "rtol and inner_rtol must be finite and >= 0");
-    if (o.inner_prec == H2S_FP32_M2L && t->ker.kind == H2S_K_NTI_MQ)
-        return fail(H2S_ERR_UNSUPPORTED, "H2S_FP32_M2L is not available for the NTI multiquadric");
-    if (o.inner_prec != H2S_FP64 && o.inner_prec != H2S_FP32 && o.inner_prec != H2S_FP32_M2L)
+    if (low_m2l(o.inner_prec) && t->ker.kind == H2S_K_NTI_MQ)
+        return fail(H2S_ERR_UNSUPPORTED, "H2S_FP32_M2L and H2S_FP32_BF16M2L are not available for the NTI multiquadric");
+    if (o.inner_prec != H2S_FP64 && o.inner_prec != H2S_FP32 && o.inner_prec != H2S_FP32_M2L &&
+        o.inner_prec != H2S_FP32_BF16M2L)
         return fail(H2S_ERR_INVALID_ARG, "bad inner precision");
     const char *bb = (const char *)b, *be = (const char *)(b + ldb * (nrhs - 1) + n);
     const char *xb = (const char *)x, *xe = (const char *)(x + ldx * (nrhs - 1) + n);

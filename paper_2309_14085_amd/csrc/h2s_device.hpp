@@ -190,11 +190,12 @@ constexpr int kGroupCols = kBatch * kGroupBlocks;
 
 // Enqueue the product for ncols <= kGroupCols right-hand sides at once (x, y
 // column-major with leading dimensions ldx, ldy), ordered on st.main, as
-// ceil(ncols / kBatch) blocks of kBatch columns.  H2* with a double far field
-// only; the block buffers must be allocated.
+// ceil(ncols / kBatch) blocks of kBatch columns.  H2* only; the block buffers
+// must be allocated.  With a float far field (P32M) the far M2L runs on the
+// matrix cores in float, or with bfloat16 inputs when bf16_m2l is set.
 template <class P>
 int launch_mvp_batch(const DevTree<P> &t, const LaunchPlan &plan, const double *x, int64_t ldx, double *y,
-                     int64_t ldy, int ncols, uint32_t mask, const Streams &st);
+                     int64_t ldy, int ncols, uint32_t mask, const Streams &st, bool bf16_m2l = false);
 
 // Device address of the file-scope batch scratch array on `device` (current), for
 // h2s_apply_noalloc; H2S_NOALLOC_SCRATCH_BYTES long.

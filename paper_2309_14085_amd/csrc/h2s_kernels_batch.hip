@@ -737,9 +737,17 @@ __global__ __launch_bounds__(NT_BL) void kb_down_leaf(DevTree<P> t, double *__re
     }
 }
 
+} // namespace
+} // namespace h2s
+
+#include "h2s_kernels_lp.hpp"
+
+namespace h2s {
+namespace {
+
 template <class P, int KIND, int D>
 hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *x, int64_t ldx, double *y,
-                     int64_t ldy, int ncols, uint32_t mask, const Streams &st)
+                     int64_t ldy, int ncols, uint32_t mask, const Streams &st, bool bf16)
 {
     hipStream_t s = (hipStream_t)st.main, aux = (hipStream_t)st.aux;
     const int32_t *lev_off = plan.lev_off;
@@ -782,11 +790,18 @@ hipError_t enqueue_b(const DevTree<P> &t, const LaunchPlan &plan, const double *
     if (fam_on) {
         // M2L: one launch per family for every block (matrix cores when two or more blocks share it)
         if ((mask & kFar) && t.far.ntargets) {
-            if (nblk > 1)
+            if constexpr (sizeof(typename P::far_t) == 4) {
+                // float far field: float or bfloat16 products on the matrix cores, 32 columns a pass
+                if (bf16)
+                    hipLaunchKernelGGL((kb_m2l_lp<P, KIND, D, true>), dim3(t.far.ntargets), dim3(NT_LP), 0, s, t, nblk);
+                else
+                    hipLaunchKernelGGL((kb_m2l_lp<P, KIND, D, false>), dim3(t.far.ntargets), dim3(NT_LP), 0, s, t, nblk);
+            } else if (nblk > 1) {
                 hipLaunchKernelGGL((kb_m2l_mfma<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_BMM), 0, s, t, nblk);
-            else
+            } else {
                 for (int k = 0; k < nblk; ++k)
                     hipLaunchKernelGGL((kb_m2l<P, true, KIND, D>), dim3(t.far.ntargets), dim3(NT_BM), 0, s, tb[k]);
+            }
         }
         if ((mask & kVer) && t.ver.ntargets) {
             if (nblk > 1)
@@ -832,30 +847,34 @@ hipError_t noalloc_scratch(int device, double **ptr)
 
 template <class P>
 int launch_mvp_batch(const DevTree<P> &t, const LaunchPlan &plan, const double *x, int64_t ldx, double *y,
-                     int64_t ldy, int na, uint32_t mask, const Streams &s) // na: columns, at most kGroupCols
+                     int64_t ldy, int na, uint32_t mask, const Streams &s, bool bf16) // na: columns, <= kGroupCols
 {
     const int key = t.kind * 2 + (t.d == 3);
     switch (key) {
-    case 0: return (int)enqueue_b<P, H2S_K_LOG_R, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 1: return (int)enqueue_b<P, H2S_K_LOG_R, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 2: return (int)enqueue_b<P, H2S_K_INV_R, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 3: return (int)enqueue_b<P, H2S_K_INV_R, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 4: return (int)enqueue_b<P, H2S_K_GAUSSIAN, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 5: return (int)enqueue_b<P, H2S_K_GAUSSIAN, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 6: return (int)enqueue_b<P, H2S_K_EXP_R, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 7: return (int)enqueue_b<P, H2S_K_EXP_R, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 8: return (int)enqueue_b<P, H2S_K_RBF_AR, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 9: return (int)enqueue_b<P, H2S_K_RBF_AR, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 10: return (int)enqueue_b<P, H2S_K_RBF_LOG, 2>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 11: return (int)enqueue_b<P, H2S_K_RBF_LOG, 3>(t, plan, x, ldx, y, ldy, na, mask, s);
-    case 13: return (int)enqueue_b<P, H2S_K_NTI_MQ, 3>(t, plan, x, ldx, y, ldy, na, mask, s); // 3D only
+    case 0: return (int)enqueue_b<P, H2S_K_LOG_R, 2>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 1: return (int)enqueue_b<P, H2S_K_LOG_R, 3>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 2: return (int)enqueue_b<P, H2S_K_INV_R, 2>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 3: return (int)enqueue_b<P, H2S_K_INV_R, 3>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 4: return (int)enqueue_b<P, H2S_K_GAUSSIAN, 2>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 5: return (int)enqueue_b<P, H2S_K_GAUSSIAN, 3>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 6: return (int)enqueue_b<P, H2S_K_EXP_R, 2>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 7: return (int)enqueue_b<P, H2S_K_EXP_R, 3>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 8: return (int)enqueue_b<P, H2S_K_RBF_AR, 2>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 9: return (int)enqueue_b<P, H2S_K_RBF_AR, 3>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 10: return (int)enqueue_b<P, H2S_K_RBF_LOG, 2>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 11: return (int)enqueue_b<P, H2S_K_RBF_LOG, 3>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
+    case 13: // the NTI multiquadric: 3D, not with the float far field
+        if constexpr (std::is_same_v<P, P32M>) return (int)hipErrorInvalidValue;
+        else return (int)enqueue_b<P, H2S_K_NTI_MQ, 3>(t, plan, x, ldx, y, ldy, na, mask, s, bf16);
     default: return (int)hipErrorInvalidValue;
     }
 }
 
 template int launch_mvp_batch<P64>(const DevTree<P64> &, const LaunchPlan &, const double *, int64_t, double *,
-                                   int64_t, int, uint32_t, const Streams &);
+                                   int64_t, int, uint32_t, const Streams &, bool);
 template int launch_mvp_batch<P32>(const DevTree<P32> &, const LaunchPlan &, const double *, int64_t, double *,
-                                   int64_t, int, uint32_t, const Streams &);
+                                   int64_t, int, uint32_t, const Streams &, bool);
+template int launch_mvp_batch<P32M>(const DevTree<P32M> &, const LaunchPlan &, const double *, int64_t, double *,
+                                    int64_t, int, uint32_t, const Streams &, bool);
 
 } // namespace h2s

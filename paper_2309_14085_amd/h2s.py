@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "h2s.h")
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED, ERR_UNSUPPORTED, ERR_INTERNAL = range(7)
 LOG_R, INV_R, GAUSSIAN, EXP_R, RBF_AR, RBF_LOG, NTI_MQ = 0, 1, 2, 3, 4, 5, 6
 H2STAR, H2_PLUS_H = 0, 1
-FP64, FP32, FP32_M2L = 0, 1, 2
+FP64, FP32, FP32_M2L, FP32_BF16M2L = 0, 1, 2, 3
 PHASE_NEAR, PHASE_FAR, PHASE_VER, PHASE_ALL = 1, 2, 4, 7
 PROF_NAMES = ("leaf_up", "m2m", "m2l_far", "l2l", "pair_part", "pair_sum", "leaf_down", "m2l_ver", "near")
 

@@ -122,7 +122,7 @@ def test_batched_fp32_within_1e5(lib, orc, inputs, d, kind, eps):
 
 
 def test_multi_rhs_fallbacks_match_oracle(lib, orc, inputs):
-    """(H2+H)* and FP32_M2L take the column loop; their multi-RHS results still match."""
+    """(H2+H)* takes the column loop; its multi-RHS results still match."""
     n, m = 4000, 4
     print("multi-rhs fallbacks", flush=True)
     pts = inputs.uniform_points(n, 2, 73)
@@ -132,36 +132,45 @@ def test_multi_rhs_fallbacks_match_oracle(lib, orc, inputs):
     Y = apply_block(T, lib, Q, n)
     for c in range(m):
         assert rel(Y[:, c], O.apply(Q[:, c])) <= 1e-12
-    O2 = orc.Tree(pts, 0, 48, 1e-8)
-    T2 = lib.build(pts, kind=0, leaf_size=48, eps=1e-8, prec=lib.FP32_M2L)
-    Y2 = apply_block(T2, lib, Q, n)
-    for c in range(m):
-        assert rel(Y2[:, c], O2.apply(Q[:, c])) <= 1e-4
 
 
-def relmax(a, b):
-    return np.abs(a - b).max() / np.abs(b).max()
+LOWP_CASES = [
+    # name, d, n, kind, nmax, eps, param, shift, seed
+    ("2d_log_8192", 2, 8192, 0, 64, 1e-8, 0.0, 0.0, 75),
+    ("3d_invr_12000", 3, 12000, 1, 64, 1e-6, 0.0, 0.0, 76),
+    ("2d_gauss_6000", 2, 6000, 2, 64, 1e-8, 0.2, 1e-2, 77),
+]
 
 
-@pytest.mark.timeout(900)
-@pytest.mark.parametrize("n,cols", [(1 << 15, range(32)), (1 << 18, (0, 13, 31))])
-def test_config3_batched_32_columns_match_oracle(lib, orc, inputs, n, cols):
-    """The 3D 1/r multi-RHS workload (n_max 64, eps 1e-6, 32 columns: four blocks through the
-    matrix-core M2M, M2L and L2L) against the oracle column by column: at N = 2^15 (kappa 3,
-    interaction lists of up to 126 far boxes) every column, at N = 2^18 (the benchmarked size,
-    kappa 4) three sampled columns."""
-    w = inputs.workload(2)
-    print(f"config-3 batched n={n}", flush=True)
-    pts = inputs.uniform_points(n, 3, w.seed_points)
-    Q = inputs.normal_rhs(n, 32, w.seed_rhs)
-    O = orc.Tree(pts, w.kind, w.nmax, w.eps)
-    print("  oracle built", flush=True)
-    T = lib.build(pts, kind=w.kind, leaf_size=w.nmax, eps=w.eps)
-    Y = apply_block(T, lib, Q, n)
-    worst = 0.0
-    for c in cols:
-        want = O.apply(Q[:, c])
-        e2, em = rel(Y[:, c], want), relmax(Y[:, c], want)
-        worst = max(worst, e2)
-        assert e2 <= 1e-12 and em <= 5e-11, (c, e2, em)
-    print(f"  worst column {worst:.2e}", flush=True)
+@pytest.mark.parametrize("case", LOWP_CASES, ids=[c[0] for c in LOWP_CASES])
+@pytest.mark.parametrize("m", [5, 8, 20, 32])
+def test_batched_low_precision_m2l_against_oracle(lib, orc, inputs, case, m):
+    """FP32_M2L and FP32_BF16M2L with several right-hand sides: the far-field M2L on the matrix
+    cores in float / with bfloat16 inputs (one block of 8 columns when m <= 8, else up to four
+    sharing each kernel value).  Against the FP64 oracle per column: FP32_M2L within 1e-4 (the
+    cap of its single-column form), and within 1e-4 of its single-column product (float
+    accumulation on the matrix cores against double accumulation there; a column taken from the
+    wrong block would be off by O(1)).  BF16 is reported, with a sanity cap of 0.25: bfloat16
+    keeps 8 significant bits of the kernel values and multipoles, and the interpolation
+    operators amplify that rounding (about 1e-3 for the Gaussian, 1e-2 for 1/r in 3D and up to
+    1e-1 for log r in 2D on these inputs)."""
+    name, d, n, kind, nmax, eps, param, shift, seed = case
+    pts = inputs.uniform_points(n, d, seed)
+    Q = inputs.normal_rhs(n, m, seed + 100)
+    O = orc.Tree(pts, kind, nmax, eps, param=param, shift=shift)
+    want = np.stack([O.apply(Q[:, c]) for c in range(m)], axis=1)
+    dev = _dev()
+    errs, agree = {}, []
+    for prec in (lib.FP32_M2L, lib.FP32_BF16M2L):
+        T = lib.build(pts, kind=kind, leaf_size=nmax, eps=eps, param=param, shift=shift, prec=prec)
+        Y = apply_block(T, lib, Q, n + 3)
+        errs[prec] = [rel(Y[:, c], want[:, c]) for c in range(m)]
+        if prec == lib.FP32_M2L:
+            for c in (0, m // 2, m - 1):
+                y1 = T.apply(torch.from_numpy(Q[:, c].copy()).to(dev))
+                torch.cuda.synchronize()
+                agree.append(rel(Y[:, c], y1.cpu().numpy()))
+    print(f"low-precision M2L {name} m={m}: fp32 {max(errs[lib.FP32_M2L]):.2e} (vs single column "
+          f"{max(agree):.2e}) bf16 {max(errs[lib.FP32_BF16M2L]):.2e}", flush=True)
+    assert max(errs[lib.FP32_M2L]) <= 1e-4 and max(agree) <= 1e-4
+    assert max(errs[lib.FP32_BF16M2L]) <= 0.25

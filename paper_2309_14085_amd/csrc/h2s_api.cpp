@@ -126,6 +126,9 @@ struct h2s_tree_s {
     // solve workspace for restart length solve_m (device memory is in allocs)
     int solve_m = 0;
     h2s::SolveWork work{};
+    // lockstep workspace of several right-hand sides: restart length many_m, many.cols columns
+    int many_m = 0;
+    h2s::SolveWorkMany many{};
 
     void clear_marks()
     {
@@ -153,6 +156,8 @@ struct h2s_tree_s {
         if (ev_fork3) (void)hipEventDestroy(ev_fork3);
         if (ev_join2) (void)hipEventDestroy(ev_join2);
         if (work.small_host) (void)hipHostFree(work.small_host);
+        if (many.host) (void)hipHostFree(many.host);
+        if (many.host_idx) (void)hipHostFree(many.host_idx);
         for (void *p : allocs) ffn(actx, p);
     }
 };
@@ -910,6 +915,28 @@ int solve_apply_outer(void *c, const double *x, double *y)
     return mvp(s->t, H2S_FP64, H2S_PHASE_ALL, x, y, s->stream, nullptr);
 }
 
+// Y = K~ X for ncols columns in precision p, through the batched product (h2s_apply's path).
+int apply_many(h2s_tree t, h2s_precision p, const double *x, int64_t ldx, double *y, int64_t ldy, int ncols, void *stream)
+{
+    h2s_status st;
+    if (p == H2S_FP64) st = apply_columns(t, t->t64, H2S_FP64, H2S_PHASE_ALL, x, y, ncols, ldx, ldy, stream, nullptr);
+    else if (p == H2S_FP32) st = apply_columns(t, t->t32, H2S_FP32, H2S_PHASE_ALL, x, y, ncols, ldx, ldy, stream, nullptr);
+    else st = apply_columns(t, t->t32m, p, H2S_PHASE_ALL, x, y, ncols, ldx, ldy, stream, nullptr);
+    return st == H2S_OK ? 0 : (int)hipErrorUnknown;
+}
+
+int solve_apply_inner_many(void *c, const double *x, int64_t ldx, double *y, int64_t ldy, int ncols)
+{
+    const SolveCtx *s = (const SolveCtx *)c;
+    return apply_many(s->t, s->inner, x, ldx, y, ldy, ncols, s->stream);
+}
+
+int solve_apply_outer_many(void *c, const double *x, int64_t ldx, double *y, int64_t ldy, int ncols)
+{
+    const SolveCtx *s = (const SolveCtx *)c;
+    return apply_many(s->t, H2S_FP64, x, ldx, y, ldy, ncols, s->stream);
+}
+
 } // namespace
 
 namespace {
@@ -1250,14 +1277,57 @@ h2s_status h2s_solve(h2s_tree t, const double *b, double *x, int32_t nrhs, int64
     h2s::SolveWork w = t->work;
     const h2s::SolveParams prm{o.restart, o.max_iter, o.max_refine, o.rtol, o.inner_rtol, o.use_x0};
     SolveCtx ctx{t, o.inner_prec, stream};
-    const h2s::SolveOps ops{&ctx, solve_apply_inner, solve_apply_outer};
     bool all = true;
-    for (int32_t c = 0; c < nrhs; ++c) {
-        h2s::SolveResult r{};
-        const int rc = h2s::gmres_ir(ops, w, prm, n, b + c * ldb, x + c * ldx, stream, &r);
-        if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("solve failed: ") + hipGetErrorString((hipError_t)rc));
-        if (info) info[c] = h2s_solve_info{r.iterations, r.refinements, r.converged, r.residual};
-        all = all && r.converged;
+    if (nrhs > 1 && t->rep.variant == H2S_H2STAR) {
+        // several right-hand sides in lockstep, up to kGroupCols at a time, through the batched product
+        const int cols = std::min<int32_t>(nrhs, h2s::kGroupCols), m = o.restart;
+        if (t->many_m < m || t->many.cols < cols) {
+            const int mm = std::max(m, t->many_m), cc = std::max(cols, t->many.cols);
+            Uploader up{t, (hipStream_t)stream};
+            h2s::SolveWorkMany wm{};
+            wm.cols = cc;
+            wm.V = up.template zeros<double>((size_t)cc * n * (mm + 1));
+            wm.W = (double *)up.raw(sizeof(double) * (size_t)n * cc);
+            wm.R = (double *)up.raw(sizeof(double) * (size_t)n * cc);
+            wm.Y = (double *)up.raw(sizeof(double) * (size_t)n * cc);
+            wm.part = (double *)up.raw(sizeof(double) * (size_t)cc * h2s::blas_dots_blocks(n) * (mm + 1));
+            wm.small = (double *)up.raw(sizeof(double) * (size_t)cc * h2s::solve_small_doubles(mm));
+            wm.vec = (double *)up.raw(sizeof(double) * (size_t)6 * cc);
+            wm.idx = (int *)up.raw(sizeof(int) * (size_t)cc);
+            if (up.st != H2S_OK) return up.st;
+            if (hipHostMalloc((void **)&wm.host, sizeof(double) * (size_t)6 * cc, hipHostMallocDefault) != hipSuccess)
+                return fail(H2S_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
+            if (hipHostMalloc((void **)&wm.host_idx, sizeof(int) * (size_t)cc, hipHostMallocDefault) != hipSuccess) {
+                (void)hipHostFree(wm.host);
+                return fail(H2S_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
+            }
+            if (t->many.host) (void)hipHostFree(t->many.host);
+            if (t->many.host_idx) (void)hipHostFree(t->many.host_idx);
+            t->many = wm;
+            t->many_m = mm;
+        }
+        // the kernels index V with the solve's own m: a workspace built for a larger m holds it
+        const h2s::SolveOpsMany ops{&ctx, solve_apply_inner_many, solve_apply_outer_many};
+        std::vector<h2s::SolveResult> rs(cols);
+        for (int32_t c0 = 0; c0 < nrhs; c0 += cols) {
+            const int nc = std::min<int32_t>(cols, nrhs - c0);
+            const int rc = h2s::gmres_ir_many(ops, t->many, prm, n, nc, b + c0 * ldb, ldb, x + c0 * ldx, ldx, stream,
+                                              rs.data());
+            if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("solve failed: ") + hipGetErrorString((hipError_t)rc));
+            for (int c = 0; c < nc; ++c) {
+                if (info) info[c0 + c] = h2s_solve_info{rs[c].iterations, rs[c].refinements, rs[c].converged, rs[c].residual};
+                all = all && rs[c].converged;
+            }
+        }
+    } else {
+        const h2s::SolveOps ops{&ctx, solve_apply_inner, solve_apply_outer};
+        for (int32_t c = 0; c < nrhs; ++c) {
+            h2s::SolveResult r{};
+            const int rc = h2s::gmres_ir(ops, w, prm, n, b + c * ldb, x + c * ldx, stream, &r);
+            if (rc != 0) return fail(H2S_ERR_DEVICE, std::string("solve failed: ") + hipGetErrorString((hipError_t)rc));
+            if (info) info[c] = h2s_solve_info{r.iterations, r.refinements, r.converged, r.residual};
+            all = all && r.converged;
+        }
     }
     if (!all) return fail(H2S_ERR_NOT_CONVERGED, "a right-hand side did not reach rtol");
     return H2S_OK;

@@ -37,4 +37,54 @@ int blas_givens(int j, int m, const double *h1, const double *h2, const double *
 // y = H_k^{-1} g_k, k = st[1], by back substitution.
 int blas_backsolve(int m, const double *H, const double *g, const double *st, double *y, void *stream);
 
+// Layout of one column's small solve state (SolveWork::small, solve_small_doubles(m) doubles):
+// offsets of the two Gram-Schmidt projections, the new norm, the cycle state, the Hessenberg
+// matrix, the rotations, the rotated right-hand side and the least-squares solution.
+struct SmallLayout {
+    int64_t h1, h2, nrm2, st, H, cs, sn, g, yv;
+};
+inline SmallLayout small_layout(int m)
+{
+    SmallLayout L{};
+    L.h1 = 0;
+    L.h2 = L.h1 + (m + 1);
+    L.nrm2 = L.h2 + (m + 1);
+    L.st = L.nrm2 + 1;
+    L.H = L.st + 2;
+    L.cs = L.H + (int64_t)(m + 1) * m;
+    L.sn = L.cs + m;
+    L.g = L.sn + m;
+    L.yv = L.g + (m + 1);
+    return L;
+}
+
+// Column-batched forms for the lockstep solve of several right-hand sides: the same operation
+// on the columns idx[0 .. nc) (a device list of column numbers), column c's operands at
+// base + c * stride (strides in doubles).  Each column's results equal the single-column call's.
+int blas_dots_m(const double *V, int64_t ldv, int64_t sV, int ncols, const double *w, int64_t sw, int64_t n,
+                double *part, int64_t sp, double *out, int64_t so, const int *idx, int nc, void *stream);
+int blas_gemv_acc_m(const double *V, int64_t ldv, int64_t sV, int ncols, const double *c, int64_t sc, double alpha,
+                    double *y, int64_t sy, int64_t n, const int *idx, int nc, void *stream);
+int blas_normalise_m(const double *w, int64_t sw, const double *nrm2, int64_t sn, double *v, int64_t sv, int64_t n,
+                     const int *idx, int nc, void *stream);
+// v_c = w_c / beta[c]
+int blas_scale_m(const double *w, int64_t sw, const double *beta, double *v, int64_t sv, int64_t n, const int *idx,
+                 int nc, void *stream);
+// r_c = b_c - y_c
+int blas_sub_m(const double *b, int64_t sb, const double *y, int64_t sy, double *r, int64_t sr, int64_t n,
+               const int *idx, int nc, void *stream);
+// The Hessenberg steps of blas_cycle_start / blas_givens / blas_backsolve for every listed column;
+// small: the columns' states, S doubles apart (layout L); beta[c], tol[c]: the column's cycle
+// start norm and inner tolerance.
+int blas_cycle_start_m(double *small, int64_t S, SmallLayout L, int m, const double *beta, const int *idx, int nc,
+                       void *stream);
+int blas_givens_m(int j, int m, double *small, int64_t S, SmallLayout L, const double *tol, const double *lim,
+                  const int *idx, int nc, void *stream); // steps j >= lim[c] are ignored
+int blas_backsolve_m(int m, double *small, int64_t S, SmallLayout L, const int *idx, int nc, void *stream);
+// x_c += V_c y_c over the k_c = st_c[1] steps the cycle kept
+int blas_xupdate_m(const double *V, int64_t ldv, int64_t sV, const double *small, int64_t S, SmallLayout L, double *x,
+                   int64_t sx, int64_t n, const int *idx, int nc, void *stream);
+// out[3 c + i] = small[c S + L.nrm2 + i], i < 3, c < ncols: every column's new norm and cycle state
+int blas_gather_state(const double *small, int64_t S, SmallLayout L, int ncols, double *out, void *stream);
+
 } // namespace h2s

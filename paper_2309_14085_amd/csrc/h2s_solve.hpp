@@ -43,4 +43,30 @@ struct SolveResult {
 int gmres_ir(const SolveOps &ops, const SolveWork &wk, const SolveParams &prm, int64_t n, const double *b, double *x,
              void *stream, SolveResult *res);
 
+// Several right-hand sides in lockstep: every Krylov step applies the operator to all columns
+// at once (the batched product), and the vector work of the columns runs in column-batched
+// kernels; each column keeps its own Krylov space, cycle and refinement, and stops on its own.
+struct SolveOpsMany {
+    void *ctx;
+    // Y = K~ X for ncols columns (device, column-major, leading dimensions ldx, ldy)
+    int (*apply_inner)(void *ctx, const double *x, int64_t ldx, double *y, int64_t ldy, int ncols);
+    int (*apply_outer)(void *ctx, const double *x, int64_t ldx, double *y, int64_t ldy, int ncols);
+};
+
+// Device workspace for up to `cols` columns and restart length m (owned by the caller).
+struct SolveWorkMany {
+    int cols;
+    double *V;          // cols x n x (m + 1): column c's basis at V + c (m + 1) n, ld = n
+    double *W, *R, *Y;  // n x cols each, ld = n
+    double *part;       // cols x blas_dots_blocks(n) (m + 1)
+    double *small;      // cols x solve_small_doubles(m)
+    double *vec;        // 6 cols: the gathered states (3 per column), then beta, tol, step limit per column
+    int *idx;           // cols: the active columns
+    double *host;       // pinned mirror of vec
+    int *host_idx;      // pinned mirror of idx
+};
+
+int gmres_ir_many(const SolveOpsMany &ops, const SolveWorkMany &wk, const SolveParams &prm, int64_t n, int ncols,
+                  const double *b, int64_t ldb, double *x, int64_t ldx, void *stream, SolveResult *res);
+
 } // namespace h2s

@@ -373,6 +373,40 @@ class Group:
         check(load().h2s_group_apply(self._h, xa, ya, _stream_ptr(stream)))
         return ys
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p))
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = None
+
+
+def set_allocator(alloc=None, free=None):
+    """h2s_set_allocator with Python callables: alloc(nbytes) -> device pointer (int) or 0 on
+    failure, free(ptr).  None, None restores hipMalloc / hipFree.  Affects later builds only."""
+    global _allocator_refs
+    lib = load()
+    if alloc is None and free is None:
+        check(lib.h2s_set_allocator(None, None, None))
+        _allocator_refs = None
+        return
+
+    def _a(ctx, nbytes, out):
+        try:
+            p = int(alloc(int(nbytes)) or 0)
+        except Exception:  # a failing allocator reports failure, it does not raise into C
+            p = 0
+        out[0] = p or None
+        return 0 if p else 1
+
+    def _f(ctx, ptr):
+        try:
+            free(int(ptr))
+        except Exception:
+            pass
+
+    refs = (_ALLOC_FN(_a), _FREE_FN(_f))
+    check(lib.h2s_set_allocator(ctypes.cast(refs[0], ctypes.c_void_p), ctypes.cast(refs[1], ctypes.c_void_p), None))
+    _allocator_refs = refs  # the C library holds these pointers
+
+
 def build(points, kind=LOG_R, leaf_size=64, eps=1e-8, eps_ver=None, variant=H2STAR, prec=FP64, param=0.0,
           diag=None, shift=0.0, host_threads=0, host_only=False, stream=None):
     """h2s_build on host points (n, d) float64."""

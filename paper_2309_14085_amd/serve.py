@@ -85,20 +85,81 @@ def make_requests(count, rate, seed, n_range=(16384, 131072), n_range_3d=None, n
     return out
 
 
-def estimate_bytes(req):
-    """Device memory of one request: representation in FP64 and FP32, solve workspace
-    (restart 50), right-hand sides and solutions; per point, from measured builds."""
-    per_point = 3600 if req.d == 2 else 16000
-    return req.n * (per_point + 51 * 8 + 16 * req.nrhs)
+# Device bytes per point of a request's representation in FP64 and FP32 (from measured builds),
+# before the server has measured any of its own; and of the multi-RHS product buffers of one
+# precision (32 columns of charges, near-field potentials and coefficients), which a solve of
+# several right-hand sides allocates for its inner and its FP64 products.
+REP_BYTES_PER_POINT = {2: 3600, 3: 16000}
+BATCH_BYTES_PER_POINT = {2: 1300, 3: 2600}
+
+
+def batch_bytes(req):
+    return 2 * BATCH_BYTES_PER_POINT[req.d] * req.n if req.nrhs > 1 else 0
+
+
+def solve_bytes(req, restart=50):
+    """The library's solve workspace of a request: Krylov basis, work vectors and state of every
+    column solved in lockstep ((restart + 1) + 3 vectors each) and one column's workspace."""
+    cols = min(req.nrhs, 32)
+    return req.n * 8 * ((restart + 1 + 3) * cols + (restart + 1 + 3))
+
+
+def estimate_bytes(req, rep_per_point=None):
+    """Device memory of one request: its representation (rep_per_point[d] bytes per point, by
+    default REP_BYTES_PER_POINT), the multi-RHS product buffers when it has several right-hand
+    sides, its solve workspace, and b and x."""
+    per_point = (rep_per_point or REP_BYTES_PER_POINT)[req.d]
+    return int(req.n * per_point) + batch_bytes(req) + solve_bytes(req) + 16 * req.n * req.nrhs
+
+
+class CachingAllocator:
+    """The library's device memory from PyTorch's caching allocator (installed with
+    h2s_set_allocator): a finished request's blocks stay cached in the process and serve the next
+    request's representation and Krylov workspace without hipMalloc / hipFree.  Blocks are freed
+    only after the request's stream has finished with them (the solve synchronises before
+    h2s_free), so a reused block is never still in use."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.lock = threading.Lock()
+        self.live, self.bytes, self.peak, self.calls = {}, 0, 0, 0
+
+    def alloc(self, nbytes):
+        p = self.torch.cuda.caching_allocator_alloc(nbytes, device=0)
+        with self.lock:
+            self.live[p] = nbytes
+            self.bytes += nbytes
+            self.peak = max(self.peak, self.bytes)
+            self.calls += 1
+        return p
+
+    def free(self, p):
+        with self.lock:
+            self.bytes -= self.live.pop(p, 0)
+        self.torch.cuda.caching_allocator_delete(p)
+
+    def install(self):
+        h2s.set_allocator(self.alloc, self.free)
+
+    @staticmethod
+    def uninstall():
+        h2s.set_allocator()
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes=16 << 30, workers=4, host_threads=None, keep_x=False):
+    """Admission: a request waits until a worker is free and its estimated device bytes fit the
+    remaining budget.  The estimate of the representation is learned from the device bytes that
+    h2s_get_stats reports for finished requests (the largest bytes per point seen for each d,
+    times 1.1); until a request of that d has finished, REP_BYTES_PER_POINT holds."""
+
+    def __init__(self, hbm_budget_bytes=16 << 30, workers=4, host_threads=None, keep_x=False, allocator=None):
         self.budget = int(hbm_budget_bytes)
         self.workers = int(workers)
         cores = min(os.cpu_count() or 1, 16)
         self.host_threads = host_threads or max(1, cores // self.workers)
         self.keep_x = keep_x
+        self.allocator = allocator
+        self.learned = {}  # d -> representation bytes per point measured so far
 
     def run(self, requests):
         import torch
@@ -127,7 +188,9 @@ class Server:
             served = 0
             while served < len(requests):
                 r = pending.get()
-                est = min(estimate_bytes(r), self.budget)
+                with lock:
+                    per = {d: 1.1 * self.learned[d] if d in self.learned else REP_BYTES_PER_POINT[d] for d in (2, 3)}
+                est = min(estimate_bytes(r, per), self.budget)
                 with lock:
                     while state["inflight"] >= self.workers or state["used"] + est > self.budget:
                         lock.wait()
@@ -155,17 +218,24 @@ class Server:
                     res.error = f"{type(e).__name__}: {e}"
                 res.done = now()
                 with lock:
+                    if res.device_bytes:
+                        rep = max(res.device_bytes - solve_bytes(r) - batch_bytes(r), 0) / r.n
+                        self.learned[r.d] = max(self.learned.get(r.d, 0.0), rep)
                     state["used"] -= res.est_bytes
                     state["inflight"] -= 1
                     state["remaining"] -= 1
                     lock.notify_all()
 
+        if self.allocator is not None:
+            self.allocator.install()
         threads = [threading.Thread(target=arrivals), threading.Thread(target=admitter)]
         threads += [threading.Thread(target=worker) for _ in range(self.workers)]
         for th in threads:
             th.start()
         for th in threads:
             th.join()
+        if self.allocator is not None:
+            self.allocator.uninstall()
         wall = now()
         out = [results[r.rid] for r in requests]
         return out, self.summary(out, requests, wall, state)
@@ -208,4 +278,59 @@ class Server:
                 "mean_build_s": float(np.mean([o.build_s for o in ok])) if ok else float("nan"),
                 "mean_solve_s": float(np.mean([o.solve_s for o in ok])) if ok else float("nan"),
                 "max_iterations": max((max(o.iterations) for o in ok if o.iterations), default=0),
-                "max_residual": max((max(o.residuals) for o in ok if o.residuals), default=float("nan"))}
+                "max_residual": max((max(o.residuals) for o in ok if o.residuals), default=float("nan")),
+                "max_device_bytes": max((o.device_bytes for o in ok), default=0),
+                "est_over_device_bytes_min": min((o.est_bytes / o.device_bytes for o in ok if o.device_bytes),
+                                                 default=float("nan"))}
+
+
+def run_loads(count, loads=(0.5, 0.9), calib=16, seed=5, n_range=(16384, 131072), n_range_3d=(16384, 32768),
+              nrhs_max=16, workers=4, budget=64 << 30, caching=True):
+    """The serving stream at offered loads relative to the server's solo throughput: first a
+    saturated calibration run (calib requests of the same distribution, all arriving at once)
+    measures the throughput mu; then, for each load L, count requests arrive as a Poisson stream
+    at rate L mu.  Each request builds its own representation (uniform points in [-1,1]^d, log r
+    in 2D or 1/r in 3D, in the weighted second-kind form) and solves 1..nrhs_max right-hand
+    sides to 1e-8.  Returns {"solo_throughput_req_per_s": mu, "loads": {L: summary}}."""
+    import torch
+    alloc = CachingAllocator(torch) if caching else None
+    cal = make_requests(calib, rate=1e9, seed=seed + 1000, n_range=n_range, n_range_3d=n_range_3d, nrhs_max=nrhs_max)
+    _, s0 = Server(hbm_budget_bytes=budget, workers=workers, allocator=alloc).run(cal)
+    mu = s0["throughput_req_per_s"]
+    out = {"solo_throughput_req_per_s": mu, "calibration": s0, "loads": {}}
+    for L in loads:
+        reqs = make_requests(count, rate=L * mu, seed=seed, n_range=n_range, n_range_3d=n_range_3d, nrhs_max=nrhs_max)
+        _, sm = Server(hbm_budget_bytes=budget, workers=workers, allocator=alloc).run(reqs)
+        sm["offered_load"] = L
+        sm["arrival_rate_per_s"] = L * mu
+        out["loads"][str(L)] = sm
+    if alloc is not None:
+        out["caching_allocator"] = {"calls": alloc.calls, "peak_bytes": alloc.peak, "live_bytes_at_end": alloc.bytes}
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    p = argparse.ArgumentParser(description="build + solve serving stream at offered loads (config 5 when "
+                                            "--requests 512 --n-max-2d 1048576 --n-max-3d 1048576 --nrhs-max 16)")
+    p.add_argument("--requests", type=int, default=512)
+    p.add_argument("--loads", default="0.5,0.9")
+    p.add_argument("--calib", type=int, default=16)
+    p.add_argument("--workers", type=int, default=4)
+    p.add_argument("--budget-gib", type=float, default=200.0)
+    p.add_argument("--n-min", type=int, default=16384)
+    p.add_argument("--n-max-2d", type=int, default=1048576)
+    p.add_argument("--n-max-3d", type=int, default=1048576)
+    p.add_argument("--nrhs-max", type=int, default=16)
+    p.add_argument("--seed", type=int, default=5)
+    p.add_argument("--no-caching", action="store_true")
+    a = p.parse_args(argv)
+    res = run_loads(a.requests, loads=tuple(float(x) for x in a.loads.split(",")), calib=a.calib, seed=a.seed,
+                    n_range=(a.n_min, a.n_max_2d), n_range_3d=(a.n_min, a.n_max_3d), nrhs_max=a.nrhs_max,
+                    workers=a.workers, budget=int(a.budget_gib * (1 << 30)), caching=not a.no_caching)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -43,3 +43,82 @@ def test_each_result_same_alone_and_in_the_mix(serve, orc, inputs):
     for c in range(r.nrhs):
         res = np.linalg.norm(B[:, c] - O.apply(X[:, c])) / np.linalg.norm(B[:, c])
         assert res <= 1.01e-8, (c, res)
+
+
+def test_failing_allocator_reports_out_of_memory_and_leaks_nothing(serve, inputs):
+    """h2s_set_allocator with an allocator that fails after k successful allocations: the build
+    returns OUT_OF_MEMORY and frees every block it took (the handle owns them until then), and
+    the default allocator works again afterwards."""
+    from paper_2309_14085_amd import h2s
+    pts = inputs.uniform_points(20000, 2, 71)
+    live, count = {}, [0]
+
+    def make(k):
+        def alloc(nbytes):
+            if count[0] >= k:
+                return 0
+            count[0] += 1
+            p = torch.cuda.caching_allocator_alloc(nbytes, device=0)
+            live[p] = nbytes
+            return p
+
+        def free(p):
+            live.pop(p)
+            torch.cuda.caching_allocator_delete(p)
+        return alloc, free
+
+    try:
+        for k in (0, 5, 20):
+            count[0] = 0
+            h2s.set_allocator(*make(k))
+            print(f"failing allocator after {k}", flush=True)
+            with pytest.raises(h2s.H2SError) as e:
+                h2s.build(pts, kind=h2s.LOG_R, leaf_size=64, eps=1e-8)
+            assert e.value.status == h2s.ERR_OUT_OF_MEMORY
+            assert count[0] == k and not live, (k, len(live))
+        # enough allocations: the build and a product go through the callbacks, and h2s_free
+        # returns every block
+        count[0] = 0
+        h2s.set_allocator(*make(10 ** 6))
+        T = h2s.build(pts, kind=h2s.LOG_R, leaf_size=64, eps=1e-8)
+        y = T.apply(torch.ones(20000, dtype=torch.float64, device="cuda:0"))
+        torch.cuda.synchronize()
+        assert live and torch.isfinite(y).all()
+        T.free()
+        assert not live
+    finally:
+        h2s.set_allocator()
+    T = h2s.build(pts, kind=h2s.LOG_R, leaf_size=64, eps=1e-8)
+    T.free()
+
+
+def test_caching_allocator_serves_the_same_results(serve):
+    """The serving loop with its caching allocator (PyTorch's, behind h2s_set_allocator) gives
+    every request the same solution bit for bit as with hipMalloc, and returns every block."""
+    reqs = serve.make_requests(5, rate=50.0, seed=9, n_range=(4096, 16384), n_range_3d=(4096, 8192), nrhs_max=4)
+    plain, _ = serve.Server(workers=2, keep_x=True).run(reqs)
+    alloc = serve.CachingAllocator(torch)
+    cached, summary = serve.Server(workers=2, keep_x=True, allocator=alloc).run(reqs)
+    print(summary, alloc.calls, alloc.peak, flush=True)
+    print([(r.d, r.n, r.nrhs, o.est_bytes, o.device_bytes) for r, o in zip(reqs, cached)], flush=True)
+    assert summary["failed"] == 0 and summary["converged"] == len(reqs)
+    assert alloc.calls > 0 and alloc.bytes == 0 and not alloc.live
+    for a, b in zip(plain, cached):
+        assert np.array_equal(a.x, b.x), a.rid
+    # the admission estimate covers what the library allocated
+    assert summary["est_over_device_bytes_min"] >= 1.0
+
+
+def test_offered_loads_report_latency_percentiles(serve):
+    """The load-driven stream (calibration, then Poisson arrivals at 0.5 and 0.9 of the measured
+    throughput) at a small size: every request converges, p50 <= p99, and the higher load does
+    not finish its stream faster than its arrivals."""
+    res = serve.run_loads(6, loads=(0.5, 0.9), calib=3, n_range=(4096, 16384), n_range_3d=(4096, 8192), nrhs_max=6,
+                          workers=2, budget=8 << 30)
+    print(res, flush=True)
+    assert res["solo_throughput_req_per_s"] > 0
+    for L in ("0.5", "0.9"):
+        sm = res["loads"][L]
+        assert sm["failed"] == 0 and sm["converged"] == 6 and sm["max_residual"] <= 1e-8
+        assert 0 < sm["p50_s"] <= sm["p99_s"]
+    assert res["caching_allocator"]["live_bytes_at_end"] == 0

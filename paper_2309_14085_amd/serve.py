@@ -89,7 +89,7 @@ def make_requests(count, rate, seed, n_range=(16384, 131072), n_range_3d=None, n
 # before the server has measured any of its own; and of the multi-RHS product buffers of one
 # precision (32 columns of charges, near-field potentials and coefficients), which a solve of
 # several right-hand sides allocates for its inner and its FP64 products.
-REP_BYTES_PER_POINT = {2: 3600, 3: 16000}
+REP_BYTES_PER_POINT = {2: 4500, 3: 16000}
 BATCH_BYTES_PER_POINT = {2: 1300, 3: 2600}
 
 
@@ -150,7 +150,7 @@ class Server:
     """Admission: a request waits until a worker is free and its estimated device bytes fit the
     remaining budget.  The estimate of the representation is learned from the device bytes that
     h2s_get_stats reports for finished requests (the largest bytes per point seen for each d,
-    times 1.1); until a request of that d has finished, REP_BYTES_PER_POINT holds."""
+    times 1.25); until a request of that d has finished, REP_BYTES_PER_POINT holds."""
 
     def __init__(self, hbm_budget_bytes=16 << 30, workers=4, host_threads=None, keep_x=False, allocator=None):
         self.budget = int(hbm_budget_bytes)
@@ -189,7 +189,7 @@ class Server:
             while served < len(requests):
                 r = pending.get()
                 with lock:
-                    per = {d: 1.1 * self.learned[d] if d in self.learned else REP_BYTES_PER_POINT[d] for d in (2, 3)}
+                    per = {d: 1.25 * self.learned[d] if d in self.learned else REP_BYTES_PER_POINT[d] for d in (2, 3)}
                 est = min(estimate_bytes(r, per), self.budget)
                 with lock:
                     while state["inflight"] >= self.workers or state["used"] + est > self.budget:

@@ -21,13 +21,18 @@
 //
 // Accuracy of the sums.  The interpolative NCA operators have norms up to
 // ~1e3 - 1e4 on coarse levels, so a rounding error in a multipole or local
-// coefficient is amplified on its way to the potential.  In FP64 every sum
-// whose result an operator later multiplies (P2M, M2M, M2L, L2L, L2P) is an
-// accurate dot product (Ogita, Rump and Oishi, "Accurate sum and dot
-// product", 2005): the sum as if taken in twice the precision, rounded once,
-// whatever the order of its terms.  The direct near field is a plain sum of
-// kernel values (nothing amplifies it).  No floating-point atomics are used;
-// results are bitwise reproducible run to run.
+// coefficient is amplified on its way to the potential.  In FP64 the sums of
+// the transfers (P2M, M2M, L2L, L2P) are accurate dot products (Ogita, Rump
+// and Oishi, "Accurate sum and dot product", 2005): the sum as if taken in
+// twice the precision, rounded once, whatever the order of its terms.  So is
+// the vertex-field M2L, whose T2B coefficients carry the largest
+// amplification: with plain sums there, the product moved from the oracle's
+// by up to 1e-12 at N = 2^17 in 2D.  The far-field M2L sums its terms with
+// fused multiply-adds over slices of the list (it moves the product by about
+// 1e-13 at N = 2^20 in 2D), which saves about 10 instructions per
+// evaluation; both take log r rounded about once.  The direct near field is
+// a plain sum of kernel values (nothing amplifies it).  No floating-point
+// atomics are used; results are bitwise reproducible run to run.
 //
 // M2L and the near field evaluate the kernel on the fly from coordinates
 // staged in LDS; the GEMV-shaped steps are HBM-bound and read each operator
@@ -318,13 +323,14 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t, int32_t t0)
 // a + NP) against one slice, so every staged source serves two evaluations.
 // u_X[a] = sum over slices (in slice order) of the slice's partial sums.
 // X and its list boxes are distinct boxes of one level, so r^2 > 0.
-// FP64 (P::ordered): every partial sum is an accurate dot product kept as an
-// unevaluated pair (hi, lo) (dot2_add), the slices' pairs are added in slice
-// order (dd_add) and the result is rounded once, so u_X[a] is the sum over
-// the whole list as if taken in twice the precision: the coefficients v can
-// be large against u (interpolation operators of norm up to ~1e3), and a
-// plain sum's error, eps sum |K v|, would be amplified by the transfers.
-// The kernel values there come from the log rounded about once.
+// Each slice keeps two partial sums per target (even and odd sources of the
+// slice), added after each staged group; the slices are added in slice order.
+// Far field: chains of fused multiply-adds.  FP64 vertex field (FAR false,
+// P::ordered): every partial sum is an accurate dot product kept as an
+// unevaluated pair (hi, lo) (dot2_add), the pairs are added with dd_add and
+// the result is rounded once, so u_X[a] is the sum over the whole list as if
+// taken in twice the precision.  FP64 takes its kernel values from the log
+// rounded about once.
 // ---------------------------------------------------------------------------
 constexpr int NT_M2LS = 256;
 constexpr int M2LS_SRC = 512; // staged source pivots per group
@@ -336,7 +342,8 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
         else return t.ver;
     }();
     constexpr bool XW = kExtraCoord<KIND>;
-    constexpr bool ACC = P::ordered;
+    constexpr bool ACC = P::ordered;          // FP64: log r rounded about once (half_log_acc)
+    constexpr bool ACC_SUM = ACC && !FAR;     // FP64 vertex field: accurate (hi, lo) sums
     constexpr int TL = ACC ? kTabLenAcc<KIND> : kTabLen<KIND>;
     // staged sources (x, y, v[, z][, w]); after the last group the same memory holds the slice partials
     constexpr int NSRC = (3 + (D == 3) + XW) * M2LS_SRC;
@@ -397,7 +404,7 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
         };
         auto flush = [&]() {
             __syncthreads();
-            if (ACC && s < NS) {
+            if (ACC_SUM && s < NS) {
                 // two independent (hi, lo) pairs per target keep two addition chains in flight
                 double a0s = 0, a0c = 0, a1s = 0, a1c = 0, b0s = 0, b0c = 0, b1s = 0, b1c = 0;
                 int j = s;
@@ -429,22 +436,16 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
                     const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, v0 = sv[j];
                     const double x1 = sx[j1], y1 = sy[j1], z1 = D == 3 ? sz[j1] : 0.0, v1 = sv[j1];
                     const double w0 = XW ? sw[j] : 0.0, w1 = XW ? sw[j1] : 0.0;
-                    a0s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), wa, w0), kp, ktab),
-                              v0, a0s);
-                    b0s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), wb, w0), kp, ktab),
-                              v0, b0s);
-                    a1s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - x1, ya - y1, za - z1), wa, w1), kp, ktab),
-                              v1, a1s);
-                    b1s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xb - x1, yb - y1, zb - z1), wb, w1), kp, ktab),
-                              v1, b1s);
+                    a0s = fma(kv(xa, ya, za, wa, x0, y0, z0, w0), v0, a0s);
+                    b0s = fma(kv(xb, yb, zb, wb, x0, y0, z0, w0), v0, b0s);
+                    a1s = fma(kv(xa, ya, za, wa, x1, y1, z1, w1), v1, a1s);
+                    b1s = fma(kv(xb, yb, zb, wb, x1, y1, z1, w1), v1, b1s);
                 }
                 if (j < pos) {
                     const double x0 = sx[j], y0 = sy[j], z0 = D == 3 ? sz[j] : 0.0, v0 = sv[j];
                     const double w0 = XW ? sw[j] : 0.0;
-                    a0s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xa - x0, ya - y0, za - z0), wa, w0), kp, ktab),
-                              v0, a0s);
-                    b0s = fma(kval_pos<KIND>(add_extra<KIND>(dist2<false, D>(xb - x0, yb - y0, zb - z0), wb, w0), kp, ktab),
-                              v0, b0s);
+                    a0s = fma(kv(xa, ya, za, wa, x0, y0, z0, w0), v0, a0s);
+                    b0s = fma(kv(xb, yb, zb, wb, x0, y0, z0, w0), v0, b0s);
                 }
                 acc_a += a0s + a1s;
                 acc_b += b0s + b1s;
@@ -467,7 +468,7 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
         }
         red[tid] = s < NS ? acc_a : 0.0;
         red[NT_M2LS + tid] = s < NS ? acc_b : 0.0;
-        if constexpr (ACC) {
+        if constexpr (ACC_SUM) {
             red[2 * NT_M2LS + tid] = s < NS ? lo_a : 0.0;
             red[3 * NT_M2LS + tid] = s < NS ? lo_b : 0.0;
         }
@@ -475,7 +476,7 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
         if (tid < NP) {
             double ua = 0.0, ub = 0.0, uac = 0.0, ubc = 0.0;
             for (int q = 0; q < NS; ++q) {
-                if constexpr (ACC) {
+                if constexpr (ACC_SUM) {
                     dd_add(ua, uac, red[q * NP + tid], red[2 * NT_M2LS + q * NP + tid]);
                     dd_add(ub, ubc, red[NT_M2LS + q * NP + tid], red[3 * NT_M2LS + q * NP + tid]);
                 } else {

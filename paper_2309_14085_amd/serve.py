@@ -85,8 +85,8 @@ def make_requests(count, rate, seed, n_range=(16384, 131072), n_range_3d=None, n
     return out
 
 
-# Device bytes per point of a request's representation in FP64 and FP32 (from measured builds),
-# before the server has measured any of its own; and of the multi-RHS product buffers of one
+# Device bytes per point of a request's representation in FP64 and FP32 at the largest sizes
+# served (from measured builds; the floor of the admission estimate); and of the multi-RHS product buffers of one
 # precision (32 columns of charges, near-field potentials and coefficients), which a solve of
 # several right-hand sides allocates for its inner and its FP64 products.
 REP_BYTES_PER_POINT = {2: 4500, 3: 16000}
@@ -148,9 +148,11 @@ class CachingAllocator:
 
 class Server:
     """Admission: a request waits until a worker is free and its estimated device bytes fit the
-    remaining budget.  The estimate of the representation is learned from the device bytes that
+    remaining budget.  The estimate of the representation is REP_BYTES_PER_POINT, raised by what
     h2s_get_stats reports for finished requests (the largest bytes per point seen for each d,
-    times 1.25); until a request of that d has finished, REP_BYTES_PER_POINT holds."""
+    times 1.25).  Bytes per point grow with N (boxes on the boundary have fewer neighbours, and
+    small trees have more of them), so a floor measured at the largest sizes keeps what was
+    learned from small requests from under-reserving large ones."""
 
     def __init__(self, hbm_budget_bytes=16 << 30, workers=4, host_threads=None, keep_x=False, allocator=None):
         self.budget = int(hbm_budget_bytes)
@@ -189,7 +191,7 @@ class Server:
             while served < len(requests):
                 r = pending.get()
                 with lock:
-                    per = {d: 1.25 * self.learned[d] if d in self.learned else REP_BYTES_PER_POINT[d] for d in (2, 3)}
+                    per = {d: max(REP_BYTES_PER_POINT[d], 1.25 * self.learned.get(d, 0.0)) for d in (2, 3)}
                 est = min(estimate_bytes(r, per), self.budget)
                 with lock:
                     while state["inflight"] >= self.workers or state["used"] + est > self.budget:
@@ -281,7 +283,10 @@ class Server:
                 "max_residual": max((max(o.residuals) for o in ok if o.residuals), default=float("nan")),
                 "max_device_bytes": max((o.device_bytes for o in ok), default=0),
                 "est_over_device_bytes_min": min((o.est_bytes / o.device_bytes for o in ok if o.device_bytes),
-                                                 default=float("nan"))}
+                                                 default=float("nan")),
+                "est_worst_request": min(([r.d, r.n, r.nrhs, by_id[r.rid].est_bytes, by_id[r.rid].device_bytes]
+                                          for r in requests if by_id[r.rid].device_bytes and not by_id[r.rid].error),
+                                         key=lambda v: v[3] / v[4], default=None)}
 
 
 def run_loads(count, loads=(0.5, 0.9), calib=16, seed=5, n_range=(16384, 131072), n_range_3d=(16384, 32768),

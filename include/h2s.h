@@ -288,12 +288,14 @@ typedef struct {
                                 a multiple of 64 in [64, 512]; default: outputs of the widest box */
     int32_t dn_threads[33];  /* block width of L2L (levels 1..kappa-1), same rule */
     int32_t m2l_stream;      /* 1: the leaf-level M2L runs on a third stream from the end of P2M, beside
-                                the coarse M2M levels; 0: all M2L after M2M.  Default 1 */
+                                the coarse M2M levels; 2: as 1, and the M2L of the level above the
+                                leaves runs on a fourth stream as soon as M2M has made its multipoles;
+                                0: all M2L after M2M.  Default 2 */
 } h2s_schedule;
 
 /* Read or replace the handle's schedule (valid on host_only handles too).
  * h2s_set_schedule rejects, with H2S_ERR_INVALID_ARG and no change, a
- * near_first outside [0, 1], an m2l_stream other than 0 or 1, or a width
+ * near_first outside [0, 1], an m2l_stream other than 0, 1 or 2, or a width
  * that is not a multiple of 64 in [64, 512] at any level 1..kappa.  It must not be called while another
  * call uses the handle. */
 h2s_status h2s_get_schedule(h2s_tree t, h2s_schedule *s);

@@ -119,6 +119,11 @@ struct h2s_tree_s {
     // third stream for the leaf-level M2L and its fork / join events
     hipStream_t aux2 = nullptr;
     hipEvent_t ev_fork3 = nullptr, ev_join2 = nullptr;
+    // fourth stream for the M2L of the level above the leaves and its fork / join events
+    hipStream_t aux3 = nullptr;
+    hipEvent_t ev_fork4 = nullptr, ev_join3 = nullptr;
+    // per family: index in its targets of the first box of every level
+    std::vector<int32_t> tlev[2];
     // which precisions are on the device
     bool up[3] = {false, false, false};
     // multi-RHS block buffers allocated for these precisions
@@ -155,6 +160,12 @@ struct h2s_tree_s {
         }
         if (ev_fork3) (void)hipEventDestroy(ev_fork3);
         if (ev_join2) (void)hipEventDestroy(ev_join2);
+        if (aux3) {
+            (void)hipStreamSynchronize(aux3);
+            (void)hipStreamDestroy(aux3);
+        }
+        if (ev_fork4) (void)hipEventDestroy(ev_fork4);
+        if (ev_join3) (void)hipEventDestroy(ev_join3);
         if (work.small_host) (void)hipHostFree(work.small_host);
         if (many.host) (void)hipHostFree(many.host);
         if (many.host_idx) (void)hipHostFree(many.host_idx);
@@ -692,31 +703,38 @@ h2s_status ensure_uploaded(h2s_tree t, h2s_precision p, hipStream_t s)
 h2s_status ensure_streams(h2s_tree t)
 {
     if (t->aux) return H2S_OK;
-    hipStream_t a = nullptr, a2 = nullptr;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    constexpr int NE = 7;
+    hipStream_t a = nullptr, a2 = nullptr, a3 = nullptr;
+    hipEvent_t ev[NE] = {};
     bool ok = hipStreamCreateWithFlags(&a, hipStreamNonBlocking) == hipSuccess &&
-              hipStreamCreateWithFlags(&a2, hipStreamNonBlocking) == hipSuccess;
-    for (int i = 0; ok && i < 5; ++i) ok = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
+              hipStreamCreateWithFlags(&a2, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&a3, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; ok && i < NE; ++i) ok = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         if (a) (void)hipStreamDestroy(a);
         if (a2) (void)hipStreamDestroy(a2);
+        if (a3) (void)hipStreamDestroy(a3);
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
         return fail(H2S_ERR_DEVICE, "creating the near-field / M2L streams or their events failed");
     }
     t->aux = a;
     t->aux2 = a2;
+    t->aux3 = a3;
     t->ev_fork = ev[0];
     t->ev_fork2 = ev[1];
     t->ev_join = ev[2];
     t->ev_fork3 = ev[3];
     t->ev_join2 = ev[4];
+    t->ev_join3 = ev[5];
+    t->ev_fork4 = ev[6];
     return H2S_OK;
 }
 
 h2s::Streams streams_of(h2s_tree t, void *stream)
 {
-    return h2s::Streams{stream, t->aux, t->ev_fork, t->ev_fork2, t->ev_join, t->aux2, t->ev_fork3, t->ev_join2};
+    return h2s::Streams{stream,  t->aux,      t->ev_fork,  t->ev_fork2, t->ev_join,
+                        t->aux2, t->ev_fork3, t->ev_join2, t->aux3,     t->ev_fork4, t->ev_join3};
 }
 
 // The default schedule: blocks as wide as the outputs of the widest box of
@@ -730,7 +748,19 @@ void default_plan(h2s_tree t)
     t->plan = h2s::LaunchPlan{};
     t->plan.lev_off = t->lev_off.data();
     t->plan.near_first = h2s::kNearFirstDefault;
-    t->plan.m2l_stream = 1;
+    t->plan.m2l_stream = 2;
+    // targets of a family: its boxes of positive rank, in box order (as uploaded)
+    for (int f = 0; f < 2; ++f) {
+        std::vector<int32_t> &tl = t->tlev[f];
+        tl.assign((size_t)r.kappa + 2, 0);
+        int32_t k = 0;
+        for (int l = 0; l <= r.kappa; ++l) {
+            tl[l] = k;
+            for (int32_t g = r.lev_off[l]; g < r.lev_off[l + 1]; ++g) k += r.fam[f].rank[g] > 0;
+        }
+        tl[(size_t)r.kappa + 1] = k;
+        t->plan.tlev[f] = tl.data();
+    }
     for (int l = 0; l <= h2s::kMaxLevels; ++l) t->plan.up_threads[l] = t->plan.dn_threads[l] = 64;
     for (int l = 0; l <= kappa; ++l) {
         int32_t cols = 0, rows = 0;
@@ -818,9 +848,13 @@ h2s_status tune_plan(h2s_tree t, const double *x, double *y, int reps, hipStream
     };
     if (kappa >= 1) {
         {
-            h2s::LaunchPlan c = best;
-            c.m2l_stream = 1 - best.m2l_stream;
-            if ((st = consider(c)) != H2S_OK) return st;
+            const int32_t cur = best.m2l_stream;
+            for (int32_t m = 0; m <= 2; ++m) {
+                if (m == cur) continue;
+                h2s::LaunchPlan c = best;
+                c.m2l_stream = m;
+                if ((st = consider(c)) != H2S_OK) return st;
+            }
         }
         if ((st = tune_share()) != H2S_OK) return st;
         // P2M (level kappa) and M2M (levels kappa-1 .. 1), then L2L (levels 1 .. kappa-1)
@@ -1351,7 +1385,7 @@ h2s_status h2s_set_schedule(h2s_tree t, const h2s_schedule *sc)
     if (!t || !sc) return fail(H2S_ERR_INVALID_ARG, "tree or schedule is NULL");
     if (!(sc->near_first >= 0.0 && sc->near_first <= 1.0))
         return fail(H2S_ERR_INVALID_ARG, "near_first must be in [0, 1]");
-    if (sc->m2l_stream != 0 && sc->m2l_stream != 1) return fail(H2S_ERR_INVALID_ARG, "m2l_stream must be 0 or 1");
+    if (sc->m2l_stream < 0 || sc->m2l_stream > 2) return fail(H2S_ERR_INVALID_ARG, "m2l_stream must be 0, 1 or 2");
     const int kappa = std::min(t->rep.kappa, h2s::kMaxLevels);
     auto ok = [](int32_t w) { return w >= 64 && w <= 512 && w % 64 == 0; };
     for (int l = 1; l <= kappa; ++l)

@@ -140,7 +140,10 @@ struct LaunchPlan {
     int32_t up_threads[kMaxLevels + 1];  // block size of P2M (level kappa) and M2M (levels < kappa)
     int32_t dn_threads[kMaxLevels + 1];  // block size of L2L per level
     double near_first;                   // share of the leaves whose near field runs beside P2M and M2M
-    int32_t m2l_stream;                  // 1: leaf-level M2L on a third stream right after P2M
+    int32_t m2l_stream;                  // 1: leaf-level M2L on a third stream right after P2M; 2: also the
+                                         // M2L of level kappa - 1 on a fourth stream right after its M2M
+    const int32_t *tlev[2];              // per family: index in its targets of the first box of every
+                                         // level (kappa + 2 entries)
 };
 
 constexpr double kNearFirstDefault = 0.6;
@@ -158,6 +161,7 @@ struct ProfileHook {
 // at join) and the leaf-level M2L stream (forked at fork3, joined at join2).
 struct Streams {
     void *main, *aux, *fork, *fork2, *join, *aux2, *fork3, *join2;
+    void *aux3, *fork4, *join3; // fourth stream (M2L of the level above the leaves), fork / join events
 };
 
 // Many trees of one precision, kernel function and dimension (H2*) applied

@@ -1089,10 +1089,16 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
     // M2L.  The leaf-level M2L needs only the leaf multipoles: with
     // plan.m2l_stream it runs on a third stream from the end of P2M, beside
     // the coarse M2M levels (latency-bound, few boxes), and only the L2L into
-    // the leaves waits for it.  Under the profiling hook everything runs on
+    // the leaves waits for it.  With m2l_stream 2 the M2L of the level above
+    // the leaves (most of the coarse M2L) runs on a fourth stream as soon as
+    // M2M has made that level's multipoles, beside the rest of the M2M chain;
+    // the coarser levels' M2L follows the chain on the main stream as one
+    // launch per family (a launch per level would chain their latencies), and
+    // the L2L chain waits for both.  Under the profiling hook everything runs on
     // the main stream instead, so that every kernel class is timed alone.
     const bool overlap = (mask & kNear) && !prof;
     const bool split = fam_on && !prof && plan.m2l_stream != 0;
+    const bool pipe = split && plan.m2l_stream == 2;
     const int near1 = overlap && fam_on ? (int)(plan.near_first * t.nleaf) : t.nleaf;
     auto fork_near = [&](hipEvent_t ev, int lb, int le) -> hipError_t {
         hipError_t e2;
@@ -1136,22 +1142,34 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
     }
     if (fam_on) {
         mark(H2S_PROF_M2M, 0, s);
+        // with pipe, the M2L of level kappa - 1 goes to the fourth stream after its M2M
+        const int lp = pipe && t.kappa >= 2 ? t.kappa - 1 : -1;
+        const int32_t far_mid = lp > 0 ? plan.tlev[0][lp] : far_split, ver_mid = lp > 0 ? plan.tlev[1][lp] : ver_split;
         for (int l = t.kappa - 1; l >= 1; --l) {
             const int nb = lev_off[l + 1] - lev_off[l];
             if (nb)
                 hipLaunchKernelGGL(k_m2m<P>, dim3(nb), dim3(plan.up_threads[l]), lds_rows, s, t, lev_off[l], mask);
+            if (l == lp) {
+                hipStream_t aux3 = (hipStream_t)st.aux3;
+                if ((err = hipEventRecord((hipEvent_t)st.fork4, s)) != hipSuccess) return err;
+                if ((err = hipStreamWaitEvent(aux3, (hipEvent_t)st.fork4, 0)) != hipSuccess) return err;
+                if (far_on) m2l(true, far_mid, far_split, aux3);
+                if (ver_on) m2l(false, ver_mid, ver_split, aux3);
+                if ((err = hipEventRecord((hipEvent_t)st.join3, aux3)) != hipSuccess) return err;
+            }
         }
         mark(H2S_PROF_M2M, 1, s);
         if (far_on && t.far.ntargets) {
             mark(H2S_PROF_M2L_FAR, 0, s);
-            m2l(true, 0, far_split, s);
+            m2l(true, 0, far_mid, s);
             mark(H2S_PROF_M2L_FAR, 1, s);
         }
         if (ver_on && t.ver.ntargets) {
             mark(H2S_PROF_M2L_VER, 0, s);
-            m2l(false, 0, ver_split, s);
+            m2l(false, 0, ver_mid, s);
             mark(H2S_PROF_M2L_VER, 1, s);
         }
+        if (lp > 0 && (err = hipStreamWaitEvent(s, (hipEvent_t)st.join3, 0)) != hipSuccess) return err;
         if (overlap && (err = fork_near((hipEvent_t)st.fork2, near1, t.nleaf)) != hipSuccess) return err;
         mark(H2S_PROF_L2L, 0, s);
         for (int l = 1; l <= t.kappa - 1; ++l) {

@@ -174,12 +174,13 @@ def test_schedule_defaults_and_validation(lib, inputs):
     T = lib.build(inputs.uniform_points(4096, 2, 1), host_only=True)
     k = T.stats()["kappa"]
     sc = T.schedule()
-    assert sc["near_first"] == 0.6 and sc["m2l_stream"] == 1
+    assert sc["near_first"] == 0.6 and sc["m2l_stream"] == 2
     for l in range(1, k + 1):
         assert sc["up_threads"][l] % 64 == 0 and 64 <= sc["up_threads"][l] <= 512
         if l < k:
             assert sc["dn_threads"][l] % 64 == 0 and 64 <= sc["dn_threads"][l] <= 512
-    for bad in ({"near_first": 1.5}, {"near_first": float("nan")}, {"m2l_stream": 2}, {"up_threads": {k: 96}},
+    for bad in ({"near_first": 1.5}, {"near_first": float("nan")}, {"m2l_stream": 3}, {"m2l_stream": -1},
+                {"up_threads": {k: 96}},
                 {"up_threads": {1: 1024}}, {"dn_threads": {1: 0}}):
         with pytest.raises(lib.H2SError) as e:
             T.set_schedule(**bad)

@@ -31,7 +31,7 @@ def test_schedules_do_not_change_the_product(lib, orc, inputs, d, kind, eps, pre
     ref = T.apply(x).clone()
     k = T.stats()["kappa"]
     for share in (0.0, 1.0, 0.33):
-        for m2l_stream in (0, 1):
+        for m2l_stream in (0, 1, 2):
             T.set_schedule(near_first=share, up_threads=[64] * 33, dn_threads=[512] * 33, m2l_stream=m2l_stream)
             assert torch.equal(T.apply(x), ref), (share, m2l_stream)
     T.set_schedule(near_first=0.6, up_threads=[512] * 33, dn_threads=[64] * 33)

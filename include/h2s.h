@@ -283,7 +283,7 @@ h2s_status h2s_get_profile(h2s_tree t, double *ms_total, int64_t *launches);
  * (h2s_stats.kappa) are ignored. */
 typedef struct {
     double near_first;       /* share of the leaves (0..1) whose near field runs on the second stream
-                                beside P2M and M2M; the rest runs beside L2L.  Default 0.6 */
+                                beside P2M and M2M; the rest runs beside L2L.  Default 0.8 */
     int32_t up_threads[33];  /* block width of P2M (level kappa) and M2M (levels 1..kappa-1):
                                 a multiple of 64 in [64, 512]; default: outputs of the widest box */
     int32_t dn_threads[33];  /* block width of L2L (levels 1..kappa-1), same rule */

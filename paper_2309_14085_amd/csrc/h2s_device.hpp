@@ -146,7 +146,7 @@ struct LaunchPlan {
                                          // level (kappa + 2 entries)
 };
 
-constexpr double kNearFirstDefault = 0.6;
+constexpr double kNearFirstDefault = 0.8;
 
 // Optional timing hook: mark(ctx, kernel class, 0 = before / 1 = after, stream).
 struct ProfileHook {

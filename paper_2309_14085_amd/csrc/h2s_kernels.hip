@@ -332,10 +332,11 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t, int32_t t0)
 // taken in twice the precision.  FP64 takes its kernel values from the log
 // rounded about once.
 // ---------------------------------------------------------------------------
-constexpr int NT_M2LS = 256;
-constexpr int M2LS_SRC = 512; // staged source pivots per group
+// block width and staged source pivots per group of k_m2l_slices / km_m2l, per family
+constexpr int kM2LFarNT = 256, kM2LFarSRC = 512, kM2LVerNT = 256, kM2LVerSRC = 512;
 
-template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2l_slices_body(const DevTree<P> &t, int ti)
+template <class P, bool FAR, int KIND, int D, int NT, int SRC>
+__device__ __forceinline__ void m2l_slices_body(const DevTree<P> &t, int ti)
 {
     const auto &F = [&]() -> const auto & {
         if constexpr (FAR) return t.far;
@@ -346,16 +347,15 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
     constexpr bool ACC_SUM = ACC && !FAR;     // FP64 vertex field: accurate (hi, lo) sums
     constexpr int TL = ACC ? kTabLenAcc<KIND> : kTabLen<KIND>;
     // staged sources (x, y, v[, z][, w]); after the last group the same memory holds the slice partials
-    constexpr int NSRC = (3 + (D == 3) + XW) * M2LS_SRC;
-    static_assert(NSRC >= 4 * NT_M2LS, "the slice partials fit in the staging buffer");
+    constexpr int NSRC = (3 + (D == 3) + XW) * SRC;
+    static_assert(NSRC >= 4 * NT, "the slice partials fit in the staging buffer");
     __shared__ double sbuf[NSRC];
-    double *const sx = sbuf, *const sy = sx + M2LS_SRC, *const sv = sy + M2LS_SRC;
-    double *const sz = sv + M2LS_SRC;                 // used in 3D only
-    double *const sw = sz + (D == 3 ? M2LS_SRC : 0); // used by kernels of an extra coordinate only
+    double *const sx = sbuf, *const sy = sx + SRC, *const sv = sy + SRC;
+    double *const sz = sv + SRC;                 // used in 3D only
+    double *const sw = sz + (D == 3 ? SRC : 0); // used by kernels of an extra coordinate only
     double *const red = sbuf;
-    __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList], wsum[NT_M2LS / 64];
+    __shared__ int32_t boxoff[kMaxList], boxcoef[kMaxList], wsum[NT / 64];
     __shared__ __align__(16) double ktab[TL];
-    static_assert(kMaxList <= NT_M2LS, "one list box per thread");
     const int tid = threadIdx.x;
     stage_table<KIND, TL>(t.ktab, ktab); // first used after a barrier
     const int g = F.targets[ti];
@@ -364,21 +364,23 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
     const KPar<double> kp = kpar<double>(t);
     // the sources of IL(X) in list order as slots 0 .. S-1: slot s lies in list box e with
     // boxoff[e] <= s < boxoff[e + 1], coefficient boxcoef[e] + s - boxoff[e].  A group of
-    // M2LS_SRC slots is staged with all its loads in flight at once.
-    int S;
-    {
+    // SRC slots is staged with all its loads in flight at once.
+    int S = 0;
+    for (int eb = 0; eb < nil; eb += NT) { // NT list boxes at a time
+        const int e = eb + tid;
         int cb = 0, nb = 0;
-        if (tid < nil) {
-            const int y = F.il_idx[e0 + tid];
+        if (e < nil) {
+            const int y = F.il_idx[e0 + e];
             cb = F.coef_off[y];
             nb = F.coef_off[y + 1] - cb;
         }
-        const int off = block_excl_scan<NT_M2LS>(nb, wsum, S);
-        if (tid < nil) {
-            boxcoef[tid] = cb;
-            boxoff[tid] = off;
+        int tot;
+        const int off = block_excl_scan<NT>(nb, wsum, tot);
+        if (e < nil) {
+            boxcoef[e] = cb;
+            boxoff[e] = S + off;
         }
-        if (tid == 0) boxoff[nil] = S;
+        S += tot;
         __syncthreads();
     }
     auto coef_of = [&](int sl) -> int {
@@ -390,8 +392,8 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
         }
         return boxcoef[lo] + (sl - boxoff[lo]);
     };
-    for (int a0 = 0; a0 < r; a0 += 2 * NT_M2LS) {
-        const int MT = min(r - a0, 2 * NT_M2LS), NP = (MT + 1) / 2, NS = NT_M2LS / NP;
+    for (int a0 = 0; a0 < r; a0 += 2 * NT) {
+        const int MT = min(r - a0, 2 * NT), NP = (MT + 1) / 2, NS = NT / NP;
         const int s = tid / NP, pa = tid % NP;
         const int ia = a0 + pa, ib = pa + NP < MT ? ia + NP : ia; // a lone last target is paired with itself
         const double xa = F.pvx[c0 + ia], ya = F.pvy[c0 + ia], za = D == 3 ? (double)F.pvz[c0 + ia] : 0.0;
@@ -453,9 +455,9 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
             __syncthreads();
             pos = 0;
         };
-        for (int base = 0; base < S; base += M2LS_SRC) {
-            const int take = min(S - base, M2LS_SRC);
-            for (int j = tid; j < take; j += NT_M2LS) {
+        for (int base = 0; base < S; base += SRC) {
+            const int take = min(S - base, SRC);
+            for (int j = tid; j < take; j += NT) {
                 const int c = coef_of(base + j);
                 sx[j] = F.pvx[c];
                 sy[j] = F.pvy[c];
@@ -467,21 +469,21 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
             flush();
         }
         red[tid] = s < NS ? acc_a : 0.0;
-        red[NT_M2LS + tid] = s < NS ? acc_b : 0.0;
+        red[NT + tid] = s < NS ? acc_b : 0.0;
         if constexpr (ACC_SUM) {
-            red[2 * NT_M2LS + tid] = s < NS ? lo_a : 0.0;
-            red[3 * NT_M2LS + tid] = s < NS ? lo_b : 0.0;
+            red[2 * NT + tid] = s < NS ? lo_a : 0.0;
+            red[3 * NT + tid] = s < NS ? lo_b : 0.0;
         }
         __syncthreads();
         if (tid < NP) {
             double ua = 0.0, ub = 0.0, uac = 0.0, ubc = 0.0;
             for (int q = 0; q < NS; ++q) {
                 if constexpr (ACC_SUM) {
-                    dd_add(ua, uac, red[q * NP + tid], red[2 * NT_M2LS + q * NP + tid]);
-                    dd_add(ub, ubc, red[NT_M2LS + q * NP + tid], red[3 * NT_M2LS + q * NP + tid]);
+                    dd_add(ua, uac, red[q * NP + tid], red[2 * NT + q * NP + tid]);
+                    dd_add(ub, ubc, red[NT + q * NP + tid], red[3 * NT + q * NP + tid]);
                 } else {
                     ua += red[q * NP + tid];
-                    ub += red[NT_M2LS + q * NP + tid];
+                    ub += red[NT + q * NP + tid];
                 }
             }
             F.u[c0 + ia] = ua + uac;
@@ -492,10 +494,10 @@ template <class P, bool FAR, int KIND, int D> __device__ __forceinline__ void m2
 }
 
 // targets t0 .. t0 + gridDim.x - 1 of the family
-template <class P, bool FAR, int KIND, int D>
-__global__ __launch_bounds__(NT_M2LS) __attribute__((amdgpu_waves_per_eu(6))) void k_m2l_slices(DevTree<P> t, int32_t t0)
+template <class P, bool FAR, int KIND, int D, int NT, int SRC>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_m2l_slices(DevTree<P> t, int32_t t0)
 {
-    m2l_slices_body<P, FAR, KIND, D>(t, t0 + xcd_remap(blockIdx.x, gridDim.x));
+    m2l_slices_body<P, FAR, KIND, D, NT, SRC>(t, t0 + xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1010,12 +1012,12 @@ __global__ __launch_bounds__(NT_GEMV_MAX, GEMV_WAVES) void km_l2l(const DevTree<
     l2l_body(t, w.y, kFar | kVer);
 }
 
-template <class P, bool FAR, int KIND, int D>
-__global__ __launch_bounds__(NT_M2LS) __attribute__((amdgpu_waves_per_eu(5))) void km_m2l(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map)
+template <class P, bool FAR, int KIND, int D, int NT, int SRC>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5))) void km_m2l(const DevTree<P> *__restrict__ trees, const int2 *__restrict__ map)
 {
     const int2 w = map[xcd_remap(blockIdx.x, gridDim.x)];
     const DevTree<P> t = trees[w.x];
-    m2l_slices_body<P, FAR, KIND, D>(t, w.y);
+    m2l_slices_body<P, FAR, KIND, D, NT, SRC>(t, w.y);
 }
 
 template <class P, int KIND, int D>
@@ -1053,9 +1055,11 @@ template <class P, int KIND, int D> hipError_t enqueue_multi(const MultiPlan<P> 
         if (mp.n_m2m[k])
             hipLaunchKernelGGL(km_m2m<P>, dim3(mp.n_m2m[k]), dim3(mp.w_m2m[k]), mp.lds_rows, s, mp.trees, mp.m2m_map[k]);
     if (mp.n_far)
-        hipLaunchKernelGGL((km_m2l<P, true, KIND, D>), dim3(mp.n_far), dim3(NT_M2LS), 0, s, mp.trees, mp.far_map);
+        hipLaunchKernelGGL((km_m2l<P, true, KIND, D, kM2LFarNT, kM2LFarSRC>), dim3(mp.n_far), dim3(kM2LFarNT), 0, s, mp.trees,
+                           mp.far_map);
     if (mp.n_ver)
-        hipLaunchKernelGGL((km_m2l<P, false, KIND, D>), dim3(mp.n_ver), dim3(NT_M2LS), 0, s, mp.trees, mp.ver_map);
+        hipLaunchKernelGGL((km_m2l<P, false, KIND, D, kM2LVerNT, kM2LVerSRC>), dim3(mp.n_ver), dim3(kM2LVerNT), 0, s,
+                           mp.trees, mp.ver_map);
     for (int k = 0; k < mp.steps; ++k)
         if (mp.n_l2l[k])
             hipLaunchKernelGGL(km_l2l<P>, dim3(mp.n_l2l[k]), dim3(mp.w_l2l[k]), mp.lds_rank, s, mp.trees, mp.l2l_map[k]);
@@ -1116,9 +1120,11 @@ hipError_t enqueue(const DevTree<P> &t, const LaunchPlan &plan, const double *x,
             if constexpr (sizeof(typename P::far_t) == 4)
                 hipLaunchKernelGGL((k_m2l<P, true, KIND, D>), dim3(te - tb), dim3(NT_M2L), 0, on, t, tb);
             else
-                hipLaunchKernelGGL((k_m2l_slices<P, true, KIND, D>), dim3(te - tb), dim3(NT_M2LS), 0, on, t, tb);
+                hipLaunchKernelGGL((k_m2l_slices<P, true, KIND, D, kM2LFarNT, kM2LFarSRC>), dim3(te - tb), dim3(kM2LFarNT), 0,
+                                   on, t, tb);
         } else {
-            hipLaunchKernelGGL((k_m2l_slices<P, false, KIND, D>), dim3(te - tb), dim3(NT_M2LS), 0, on, t, tb);
+            hipLaunchKernelGGL((k_m2l_slices<P, false, KIND, D, kM2LVerNT, kM2LVerSRC>), dim3(te - tb), dim3(kM2LVerNT), 0,
+                               on, t, tb);
         }
     };
     const bool far_on = (mask & kFar) != 0, ver_on = (mask & kVer) != 0;

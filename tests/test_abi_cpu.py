@@ -174,7 +174,7 @@ def test_schedule_defaults_and_validation(lib, inputs):
     T = lib.build(inputs.uniform_points(4096, 2, 1), host_only=True)
     k = T.stats()["kappa"]
     sc = T.schedule()
-    assert sc["near_first"] == 0.6 and sc["m2l_stream"] == 2
+    assert sc["near_first"] == 0.8 and sc["m2l_stream"] == 2
     for l in range(1, k + 1):
         assert sc["up_threads"][l] % 64 == 0 and 64 <= sc["up_threads"][l] <= 512
         if l < k:

@@ -26,12 +26,13 @@
 // and Oishi, "Accurate sum and dot product", 2005): the sum as if taken in
 // twice the precision, rounded once, whatever the order of its terms.  So is
 // the vertex-field M2L, whose T2B coefficients carry the largest
-// amplification: with plain sums there, the product moved from the oracle's
-// by up to 1e-12 at N = 2^17 in 2D.  The far-field M2L sums its terms with
-// fused multiply-adds over slices of the list (it moves the product by about
-// 1e-13 at N = 2^20 in 2D), which saves about 10 instructions per
-// evaluation; both take log r rounded about once.  The direct near field is
-// a plain sum of kernel values (nothing amplifies it).  No floating-point
+// amplification (with plain sums there, the product moved from the oracle's
+// by up to 1e-12 at N = 2^17 in 2D), and its kernel values come from log r
+// rounded about once.  The far-field M2L sums its terms with fused
+// multiply-adds over slices of the list, of kernel values from the one-ulp
+// log (it moves the product by about 1e-13 at N = 2^20 in 2D), which saves
+// about 13 instructions and one table read per evaluation.  The direct near
+// field is a plain sum of kernel values (nothing amplifies it).  No floating-point
 // atomics are used; results are bitwise reproducible run to run.
 //
 // M2L and the near field evaluate the kernel on the fly from coordinates
@@ -329,8 +330,8 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t, int32_t t0)
 // P::ordered): every partial sum is an accurate dot product kept as an
 // unevaluated pair (hi, lo) (dot2_add), the pairs are added with dd_add and
 // the result is rounded once, so u_X[a] is the sum over the whole list as if
-// taken in twice the precision.  FP64 takes its kernel values from the log
-// rounded about once.
+// taken in twice the precision, of kernel values from the log rounded about
+// once.
 // ---------------------------------------------------------------------------
 // block width and staged source pivots per group of k_m2l_slices / km_m2l, per family
 constexpr int kM2LFarNT = 256, kM2LFarSRC = 512, kM2LVerNT = 256, kM2LVerSRC = 512;
@@ -343,8 +344,8 @@ __device__ __forceinline__ void m2l_slices_body(const DevTree<P> &t, int ti)
         else return t.ver;
     }();
     constexpr bool XW = kExtraCoord<KIND>;
-    constexpr bool ACC = P::ordered;          // FP64: log r rounded about once (half_log_acc)
-    constexpr bool ACC_SUM = ACC && !FAR;     // FP64 vertex field: accurate (hi, lo) sums
+    // FP64 vertex field: accurate (hi, lo) sums of kernel values from log r rounded about once
+    constexpr bool ACC = P::ordered && !FAR, ACC_SUM = ACC;
     constexpr int TL = ACC ? kTabLenAcc<KIND> : kTabLen<KIND>;
     // staged sources (x, y, v[, z][, w]); after the last group the same memory holds the slice partials
     constexpr int NSRC = (3 + (D == 3) + XW) * SRC;
@@ -493,9 +494,11 @@ __device__ __forceinline__ void m2l_slices_body(const DevTree<P> &t, int ti)
     }
 }
 
-// targets t0 .. t0 + gridDim.x - 1 of the family
+// targets t0 .. t0 + gridDim.x - 1 of the family.  The 2D far field (fused sums, the one-ulp log,
+// 18 KB of LDS) fits 8 blocks per CU in 64 registers; elsewhere LDS or registers allow about 6.
 template <class P, bool FAR, int KIND, int D, int NT, int SRC>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_m2l_slices(DevTree<P> t, int32_t t0)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(FAR && D == 2 ? 8 : 6))) void k_m2l_slices(DevTree<P> t,
+                                                                                                            int32_t t0)
 {
     m2l_slices_body<P, FAR, KIND, D, NT, SRC>(t, t0 + xcd_remap(blockIdx.x, gridDim.x));
 }

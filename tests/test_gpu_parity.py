@@ -12,13 +12,14 @@ N = 2^20 (the reason is beside that test).
 Why the FP64 bars hold with room: the interpolation operators amplify
 rounding (norms up to ~1e3 - 1e4 on coarse levels), so both sides take the
 transfer sums (P2M, M2M, L2L, L2P) and the vertex-field M2L as accurate dot
-products, and log r as 0.5 log(r^2) rounded about once.  The library's
-far-field M2L sums with fused multiply-adds (the oracle's stays accurate):
-that moves the far field by about 1e-13 at N = 2^20; a plain vertex-field M2L
-moved the vertex field by 1e-12 at N = 2^17, and is not used.  With plain
-sums everywhere instead, the oracle's own product at N = 2^20 moves by 9e-13
-in 2-norm and 5e-11 in the largest element.  Measured at N = 2^20: 1.3e-13
-(largest element 4.6e-12).  Inputs are the seeded synthetic workloads (uniform points in
+products.  The oracle takes log r as 0.5 log(r^2); the library's vertex-field
+M2L takes it rounded about once.  The library's far-field M2L sums with fused
+multiply-adds of kernel values from a one-ulp log (the oracle's stays
+accurate): that moves the far field by about 1.4e-13 at N = 2^20; a plain
+vertex-field M2L moved the vertex field by 1e-12 at N = 2^17, and is not used.
+With plain sums everywhere instead, the oracle's own product at N = 2^20 moves
+by 9e-13 in 2-norm and 5e-11 in the largest element.  Measured at N = 2^20:
+1.5e-13 (largest element 5.5e-12).  Inputs are the seeded synthetic workloads (uniform points in
 [-1,1]^d, N(0,1) right-hand sides).
 """
 import numpy as np

@@ -103,6 +103,9 @@ typedef struct {
     h2s_precision prec;
     int32_t host_threads; /* OpenMP threads for the host build; <= 0 = runtime default */
     int32_t host_only;    /* 1: build the representation on the host only (export / stats; apply is rejected) */
+    int64_t hbm_budget_bytes; /* the most device memory the handle may ever hold (representation, product
+                                 and solve buffers, allocated on first use); an allocation beyond it fails
+                                 as OUT_OF_MEMORY like a failed hipMalloc.  <= 0: no limit */
 } h2s_build_opts;
 
 typedef struct h2s_tree_s *h2s_tree;
@@ -110,7 +113,8 @@ typedef struct h2s_tree_s *h2s_tree;
 /* Build the representation of the n x n kernel matrix of `points`.
  * points: host, row-major n x d doubles (copied).  d in {2, 3}; n >= 1; all
  * coordinates finite.  The handle owns all device memory until h2s_free.
- * Errors: INVALID_ARG (bad argument), OUT_OF_MEMORY (host or device),
+ * Errors: INVALID_ARG (bad argument), OUT_OF_MEMORY (host or device, or
+ * opts->hbm_budget_bytes too small for the representation; nothing leaks),
  * DEVICE (no HIP device / HIP error), UNSUPPORTED (a leaf of more than 4096
  * points, a stacked transfer of more than 2560 rows, a rank above 512 or an
  * interaction list of more than 256 boxes: the kernels stage these whole in

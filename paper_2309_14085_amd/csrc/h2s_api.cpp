@@ -268,6 +268,13 @@ struct Uploader {
         if (st != H2S_OK) return nullptr;
         void *p = nullptr;
         if (bytes == 0) bytes = 256;
+        const int64_t budget = t->opts.hbm_budget_bytes;
+        if (budget > 0 && (int64_t)(t->device_bytes + bytes) > budget) {
+            st = fail(H2S_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(bytes) +
+                                                 " bytes would exceed the handle's budget of " + std::to_string(budget) +
+                                                 " bytes (" + std::to_string(t->device_bytes) + " held)");
+            return nullptr;
+        }
         if (t->afn(t->actx, bytes, &p) != 0 || !p) {
             st = fail(H2S_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(bytes) + " bytes failed");
             return nullptr;

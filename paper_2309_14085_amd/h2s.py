@@ -30,7 +30,7 @@ class Kernel(ctypes.Structure):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("eps_far", ctypes.c_double), ("eps_ver", ctypes.c_double),
                 ("variant", ctypes.c_int), ("prec", ctypes.c_int), ("host_threads", ctypes.c_int32),
-                ("host_only", ctypes.c_int32)]
+                ("host_only", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -408,15 +408,17 @@ def set_allocator(alloc=None, free=None):
 
 
 def build(points, kind=LOG_R, leaf_size=64, eps=1e-8, eps_ver=None, variant=H2STAR, prec=FP64, param=0.0,
-          diag=None, shift=0.0, host_threads=0, host_only=False, stream=None):
-    """h2s_build on host points (n, d) float64."""
+          diag=None, shift=0.0, host_threads=0, host_only=False, stream=None, hbm_budget_bytes=0):
+    """h2s_build on host points (n, d) float64.  hbm_budget_bytes > 0 caps the device memory the
+    handle may ever hold (an allocation beyond it fails as OUT_OF_MEMORY)."""
     lib = load()
     pts = np.ascontiguousarray(points, dtype=np.float64)
     n, d = pts.shape
     if diag is None:
         diag = 0.0 if kind in (LOG_R, INV_R, RBF_AR, RBF_LOG) else 1.0
     k = Kernel(kind, param, diag, shift)
-    o = BuildOpts(leaf_size, eps, eps if eps_ver is None else eps_ver, variant, prec, host_threads, int(host_only))
+    o = BuildOpts(leaf_size, eps, eps if eps_ver is None else eps_ver, variant, prec, host_threads, int(host_only),
+                  int(hbm_budget_bytes))
     h = ctypes.c_void_p()
     check(lib.h2s_build(pts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n, d, ctypes.byref(k), ctypes.byref(o),
                         _stream_ptr(stream) if not host_only else ctypes.c_void_p(0), ctypes.byref(h)))

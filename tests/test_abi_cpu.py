@@ -268,3 +268,12 @@ def test_oracle_import_rejects_a_damaged_file(orc, tmp_path):
         orc.Tree.from_export(p, 0)
     with pytest.raises(ValueError):
         orc.Tree.from_export(tmp_path / "missing.h2sx", 0)
+
+def test_build_opts_layout_matches_the_header(lib):
+    """BuildOpts mirrors h2s_build_opts field by field (x86-64 alignment): the budget field sits
+    last, after the two int32 flags, at offset 40 of 48 bytes."""
+    import ctypes as ct
+    assert ct.sizeof(lib.BuildOpts) == 48
+    assert lib.BuildOpts.host_only.offset == 36 and lib.BuildOpts.hbm_budget_bytes.offset == 40
+    T = lib.build(np.random.default_rng(3).uniform(-1, 1, (2000, 2)), host_only=True, hbm_budget_bytes=1)
+    assert T.stats()["device_bytes"] == 0  # a host-only handle holds no device memory: the budget never binds

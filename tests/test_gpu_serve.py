@@ -92,6 +92,59 @@ def test_failing_allocator_reports_out_of_memory_and_leaks_nothing(serve, inputs
     T.free()
 
 
+def test_hbm_budget_caps_the_handle(inputs):
+    """h2s_build_opts.hbm_budget_bytes: a budget below the representation makes the build return
+    OUT_OF_MEMORY with every block returned; a budget that fits the representation only lets
+    single-column products run and makes the first multi-RHS product (whose buffers are allocated
+    on first use) return OUT_OF_MEMORY, after which the handle still works; a larger budget
+    serves both, with results equal to an unbudgeted handle's."""
+    from paper_2309_14085_amd import h2s
+    n = 20000
+    pts = inputs.uniform_points(n, 2, 72)
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(inputs.normal_rhs(n, 4, 73)).to(dev)  # column-major (n, 4)
+    live = {}
+
+    def alloc(nbytes):
+        p = torch.cuda.caching_allocator_alloc(nbytes, device=0)
+        live[p] = nbytes
+        return p
+
+    def free(p):
+        live.pop(p)
+        torch.cuda.caching_allocator_delete(p)
+
+    ref = h2s.build(pts, kind=h2s.LOG_R, leaf_size=64, eps=1e-8)
+    y1 = ref.apply(q[:, 0].contiguous()).clone()
+    rep_bytes = ref.stats()["device_bytes"]  # the representation and what a single-column product uses
+    Y4 = ref.apply(q).clone()
+    full_bytes = ref.stats()["device_bytes"]
+    assert full_bytes > rep_bytes
+    try:
+        h2s.set_allocator(alloc, free)
+        print(f"budget: representation {rep_bytes} B, with the multi-RHS buffers {full_bytes} B", flush=True)
+        with pytest.raises(h2s.H2SError) as e:
+            h2s.build(pts, kind=h2s.LOG_R, leaf_size=64, eps=1e-8, hbm_budget_bytes=rep_bytes // 2)
+        assert e.value.status == h2s.ERR_OUT_OF_MEMORY and not live
+        T = h2s.build(pts, kind=h2s.LOG_R, leaf_size=64, eps=1e-8, hbm_budget_bytes=rep_bytes)
+        assert T.stats()["device_bytes"] <= rep_bytes
+        assert torch.equal(T.apply(q[:, 0].contiguous()), y1)
+        with pytest.raises(h2s.H2SError) as e:
+            T.apply(q)
+        assert e.value.status == h2s.ERR_OUT_OF_MEMORY
+        assert T.stats()["device_bytes"] <= rep_bytes
+        assert torch.equal(T.apply(q[:, 0].contiguous()), y1)
+        T.free()
+        assert not live
+        T = h2s.build(pts, kind=h2s.LOG_R, leaf_size=64, eps=1e-8, hbm_budget_bytes=full_bytes)
+        assert torch.equal(T.apply(q), Y4) and torch.equal(T.apply(q[:, 0].contiguous()), y1)
+        T.free()
+        assert not live
+    finally:
+        h2s.set_allocator()
+    ref.free()
+
+
 def test_caching_allocator_serves_the_same_results(serve):
     """The serving loop with its caching allocator (PyTorch's, behind h2s_set_allocator) gives
     every request the same solution bit for bit as with hipMalloc, and returns every block."""

@@ -18,6 +18,7 @@ Every numeric step runs in libh2s.so; this module only schedules.
 import math
 import os
 import queue
+import sys
 import threading
 import time
 from dataclasses import dataclass, field
@@ -154,7 +155,9 @@ class Server:
     small trees have more of them), so a floor measured at the largest sizes keeps what was
     learned from small requests from under-reserving large ones."""
 
-    def __init__(self, hbm_budget_bytes=16 << 30, workers=4, host_threads=None, keep_x=False, allocator=None):
+    def __init__(self, hbm_budget_bytes=16 << 30, workers=4, host_threads=None, keep_x=False, allocator=None,
+                 progress=None):
+        self.progress = progress  # a label: one line per finished request goes to stderr
         self.budget = int(hbm_budget_bytes)
         self.workers = int(workers)
         cores = min(os.cpu_count() or 1, 16)
@@ -219,6 +222,9 @@ class Server:
                 except Exception as e:  # the request fails, the server goes on
                     res.error = f"{type(e).__name__}: {e}"
                 res.done = now()
+                if self.progress:
+                    print(f"{self.progress}: request {r.rid} d={r.d} n={r.n} nrhs={r.nrhs} latency {res.latency:.2f} s "
+                          f"(build {res.build_s:.2f} s){' ' + res.error if res.error else ''}", file=sys.stderr, flush=True)
                 with lock:
                     if res.device_bytes:
                         rep = max(res.device_bytes - solve_bytes(r) - batch_bytes(r), 0) / r.n
@@ -290,7 +296,7 @@ class Server:
 
 
 def run_loads(count, loads=(0.5, 0.9), calib=16, seed=5, n_range=(16384, 131072), n_range_3d=(16384, 32768),
-              nrhs_max=16, workers=4, budget=64 << 30, caching=True):
+              nrhs_max=16, workers=4, budget=64 << 30, caching=True, progress=False):
     """The serving stream at offered loads relative to the server's solo throughput: first a
     saturated calibration run (calib requests of the same distribution, all arriving at once)
     measures the throughput mu; then, for each load L, count requests arrive as a Poisson stream
@@ -300,12 +306,14 @@ def run_loads(count, loads=(0.5, 0.9), calib=16, seed=5, n_range=(16384, 131072)
     import torch
     alloc = CachingAllocator(torch) if caching else None
     cal = make_requests(calib, rate=1e9, seed=seed + 1000, n_range=n_range, n_range_3d=n_range_3d, nrhs_max=nrhs_max)
-    _, s0 = Server(hbm_budget_bytes=budget, workers=workers, allocator=alloc).run(cal)
+    _, s0 = Server(hbm_budget_bytes=budget, workers=workers, allocator=alloc,
+                   progress="calibration" if progress else None).run(cal)
     mu = s0["throughput_req_per_s"]
     out = {"solo_throughput_req_per_s": mu, "calibration": s0, "loads": {}}
     for L in loads:
         reqs = make_requests(count, rate=L * mu, seed=seed, n_range=n_range, n_range_3d=n_range_3d, nrhs_max=nrhs_max)
-        _, sm = Server(hbm_budget_bytes=budget, workers=workers, allocator=alloc).run(reqs)
+        _, sm = Server(hbm_budget_bytes=budget, workers=workers, allocator=alloc,
+                       progress=f"load {L}" if progress else None).run(reqs)
         sm["offered_load"] = L
         sm["arrival_rate_per_s"] = L * mu
         out["loads"][str(L)] = sm
@@ -333,7 +341,7 @@ def main(argv=None):
     a = p.parse_args(argv)
     res = run_loads(a.requests, loads=tuple(float(x) for x in a.loads.split(",")), calib=a.calib, seed=a.seed,
                     n_range=(a.n_min, a.n_max_2d), n_range_3d=(a.n_min, a.n_max_3d), nrhs_max=a.nrhs_max,
-                    workers=a.workers, budget=int(a.budget_gib * (1 << 30)), caching=not a.no_caching)
+                    workers=a.workers, budget=int(a.budget_gib * (1 << 30)), caching=not a.no_caching, progress=True)
     print(json.dumps(res), flush=True)
 
 

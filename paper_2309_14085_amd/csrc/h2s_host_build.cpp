@@ -102,14 +102,22 @@ void cross_approx(const Entry &entry, int64_t nI, int64_t nJ, double eps, bool p
     int64_t istar = 0;
     int run = 0;  // successive terms whose norm met the tolerance
     const bool parJ = par && nJ >= 16384, parI = par && nI >= 16384;
+    // Residual entries are taken in chunks of kChunk: the chunk stays in cache while the earlier
+    // terms' rows stream through it in order k = 0, 1, ..., so every entry sees the same
+    // operations in the same order as an entry-by-entry loop.
+    constexpr int64_t kChunk = 512;
     for (;;) {
         rowused[istar] = 1;
         const int p = c.rank;
 #pragma omp parallel for if (parJ) schedule(static)
-        for (int64_t j = 0; j < nJ; ++j) {
-            double r = entry(istar, j);
-            for (int k = 0; k < p; ++k) r -= c.U[(size_t)k * nI + istar] * c.V[(size_t)k * nJ + j];
-            R[j] = r;
+        for (int64_t j0 = 0; j0 < nJ; j0 += kChunk) {
+            const int64_t j1 = std::min(j0 + kChunk, nJ);
+            for (int64_t j = j0; j < j1; ++j) R[j] = entry(istar, j);
+            for (int k = 0; k < p; ++k) {
+                const double u = c.U[(size_t)k * nI + istar];
+                const double *vk = c.V.data() + (size_t)k * nJ;
+                for (int64_t j = j0; j < j1; ++j) R[j] -= u * vk[j];
+            }
         }
         int64_t jstar = -1;
         double best = -1.0;
@@ -135,10 +143,14 @@ void cross_approx(const Entry &entry, int64_t nI, int64_t nJ, double eps, bool p
 #pragma omp parallel for if (parJ) schedule(static)
         for (int64_t j = 0; j < nJ; ++j) vp[j] = R[j] / piv;
 #pragma omp parallel for if (parI) schedule(static)
-        for (int64_t i = 0; i < nI; ++i) {
-            double r = entry(i, jstar);
-            for (int k = 0; k < p; ++k) r -= c.U[(size_t)k * nI + i] * c.V[(size_t)k * nJ + jstar];
-            up[i] = r;
+        for (int64_t i0 = 0; i0 < nI; i0 += kChunk) {
+            const int64_t i1 = std::min(i0 + kChunk, nI);
+            for (int64_t i = i0; i < i1; ++i) up[i] = entry(i, jstar);
+            for (int k = 0; k < p; ++k) {
+                const double v = c.V[(size_t)k * nJ + jstar];
+                const double *uk = c.U.data() + (size_t)k * nI;
+                for (int64_t i = i0; i < i1; ++i) up[i] -= uk[i] * v;
+            }
         }
         colused[jstar] = 1;
         double nu2 = 0.0, nv2 = 0.0;

@@ -8,7 +8,7 @@ scatter) with x and y resident in HBM.  `value` is the FP64 H2* rate in
 points/s; the FP32 form and the (H2+H)* variant are timed beside it.
 
 Prints one JSON line (see the fields below).  --gpus N > 1 is not supported:
-this build runs on one GPU.
+the library and this benchmark run on one GPU.
 """
 import argparse
 import json
@@ -247,8 +247,8 @@ def time_multi_rhs(h2s, torch, w, reps=3):
 
 def time_serving(count=32, workers=4, budget=64 << 30):
     """The build + solve serving stream at 0.5x and 0.9x of the server's measured throughput
-    (config 5's distribution with smaller sizes: d in {2, 3}, N log-uniform in [2^14, 2^17] (2D)
-    / [2^14, 2^15] (3D), 1-16 right-hand sides, log r (2D) or 1/r (3D) in second-kind form,
+    (the stream of 512 requests with N up to 2^20 and 1-16 right-hand sides, at smaller sizes and
+    counts: d in {2, 3}, N log-uniform in [2^14, 2^17] (2D) / [2^14, 2^15] (3D), 1-16 right-hand sides, log r (2D) or 1/r (3D) in second-kind form,
     GMRES to 1e-8), admitted by learned device bytes within a 64 GiB budget, 4 workers, the
     library's memory from the caching allocator."""
     from paper_2309_14085_amd import serve
@@ -257,7 +257,7 @@ def time_serving(count=32, workers=4, budget=64 << 30):
     res.update({"workers": workers, "hbm_budget_bytes": budget, "requests_per_load": count,
                 "requests_spec": "d in {2,3}; N log-uniform 2^14..2^17 (2D), 2^14..2^15 (3D); 1-16 RHS; "
                                  "(w K + I) x = b, w = 2^d / N; GMRES(50) FP32 Krylov to 1e-8; "
-                                 "config 5 asks N up to 2^20 (host builds bound it: see DESIGN)"})
+                                 "the full stream has N up to 2^20 (its host builds take up to ~25 s each)"})
     return res
 
 
@@ -327,7 +327,7 @@ def product_roofline(stats, kernels, ms, r_eval, prec):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1", "n_gpus": a.gpus}))
         sys.exit(2)
     if a.profile_only:  # rocprofv3 runs trace the product alone
         a.no_solve = a.no_multi_rhs = a.no_serve = a.no_tune = a.no_group = True

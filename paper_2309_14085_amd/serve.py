@@ -325,8 +325,8 @@ def run_loads(count, loads=(0.5, 0.9), calib=16, seed=5, n_range=(16384, 131072)
 def main(argv=None):
     import argparse
     import json
-    p = argparse.ArgumentParser(description="build + solve serving stream at offered loads (config 5 when "
-                                            "--requests 512 --n-max-2d 1048576 --n-max-3d 1048576 --nrhs-max 16)")
+    p = argparse.ArgumentParser(description="build + solve serving stream at offered loads (defaults: 512 "
+                                            "requests, N up to 2^20 in 2D and 3D, 1-16 right-hand sides)")
     p.add_argument("--requests", type=int, default=512)
     p.add_argument("--loads", default="0.5,0.9")
     p.add_argument("--calib", type=int, default=16)

@@ -116,8 +116,8 @@ def time_tuned(h2s, torch, pts, q, w, steps, warmup):
     return {"ms_default": ms_default, "ms_tuned": ms_tuned, "speedup": ms_default / ms_tuned,
             "points_per_s_tuned": w.n / (ms_tuned * 1e-3), "tune_s": tune_s, "candidates": info["candidates"],
             "bitwise_equal": equal,
-            "schedule": {"near_first": sc["near_first"], "up_threads_by_level": sc["up_threads"][1:k + 1],
-                         "dn_threads_by_level": sc["dn_threads"][1:k]}}
+            "schedule": {"near_first": sc["near_first"], "m2l_stream": sc["m2l_stream"],
+                         "up_threads_by_level": sc["up_threads"][1:k + 1], "dn_threads_by_level": sc["dn_threads"][1:k]}}
 
 
 def time_group(h2s, torch, count=32, seed=7, reps=10):

@@ -333,7 +333,9 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t, int32_t t0)
 // taken in twice the precision, of kernel values from the log rounded about
 // once.
 // ---------------------------------------------------------------------------
-// block width and staged source pivots per group of k_m2l_slices / km_m2l, per family
+// block width and staged source pivots per group of k_m2l_slices / km_m2l, per family; targets
+// dealt to the XCDs in chunks of kM2LChunk
+constexpr int kM2LChunk = 32;
 constexpr int kM2LFarNT = 256, kM2LFarSRC = 512, kM2LVerNT = 256, kM2LVerSRC = 512;
 
 template <class P, bool FAR, int KIND, int D, int NT, int SRC>
@@ -500,7 +502,7 @@ template <class P, bool FAR, int KIND, int D, int NT, int SRC>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(FAR && D == 2 ? 8 : 6))) void k_m2l_slices(DevTree<P> t,
                                                                                                             int32_t t0)
 {
-    m2l_slices_body<P, FAR, KIND, D, NT, SRC>(t, t0 + xcd_remap(blockIdx.x, gridDim.x));
+    m2l_slices_body<P, FAR, KIND, D, NT, SRC>(t, t0 + xcd_chunk_remap<kM2LChunk>(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------

@@ -24,6 +24,21 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb)
     return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
 }
 
+// The same for items of uneven cost sorted by cost class (M2L targets: coarse
+// levels first, their boxes several times the work of a leaf's): the items
+// are cut into chunks of C, and chunk c goes to XCD c mod 8, so each XCD gets
+// Morton-local runs of C items from every part of the range.  Block bid = 8 j
+// + x (XCD x) takes item (8 (j / C) + x) C + j mod C while whole rows of 8
+// chunks remain; the items of the last, partial row map to themselves.  A
+// bijection of [0, nb).
+template <int C> __device__ __forceinline__ int xcd_chunk_remap(int bid, int nb)
+{
+    const int rows = nb / (8 * C);
+    if (bid >= rows * 8 * C) return bid;
+    const int x = bid & 7, j = bid >> 3;
+    return (8 * (j / C) + x) * C + j % C;
+}
+
 // s + a b.  ORD: the product and the sum rounded separately, as a plain
 // sequential evaluation does (the HBM-bound sums can afford it); otherwise
 // one fused multiply-add.

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t, int32_t t0)
     __shared__ __align__(16) double ktab[kTabLen<KIND>];
     const int tid = threadIdx.x;
     if constexpr (!LOWP) stage_table<KIND>(t.ktab, ktab);
-    const int g = F.targets[t0 + xcd_remap(blockIdx.x, gridDim.x)]; // targets t0 .. t0 + gridDim.x - 1
+    const int g = F.targets[t0 + xcd_chunk_remap<kM2LChunk>(blockIdx.x, gridDim.x)]; // targets t0 .. t0 + gridDim.x - 1
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
     const CT diag = (CT)t.diag;
@@ -333,9 +333,7 @@ __global__ __launch_bounds__(NT_M2L) void k_m2l(DevTree<P> t, int32_t t0)
 // taken in twice the precision, of kernel values from the log rounded about
 // once.
 // ---------------------------------------------------------------------------
-// block width and staged source pivots per group of k_m2l_slices / km_m2l, per family; targets
-// dealt to the XCDs in chunks of kM2LChunk
-constexpr int kM2LChunk = 32;
+// block width and staged source pivots per group of k_m2l_slices / km_m2l, per family
 constexpr int kM2LFarNT = 256, kM2LFarSRC = 512, kM2LVerNT = 256, kM2LVerSRC = 512;
 
 template <class P, bool FAR, int KIND, int D, int NT, int SRC>

@@ -307,7 +307,7 @@ template <class P, bool FAR, int KIND, int D> __global__ __launch_bounds__(NT_BM
     static_assert(BM_SRC * NB >= TPT * NT_BM, "slice partials fit in the multipole buffer");
     const int tid = threadIdx.x;
     stage_table<KIND>(t.ktab, ktab); // first used after a barrier
-    const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
+    const int g = F.targets[xcd_chunk_remap<kM2LChunk>(blockIdx.x, gridDim.x)];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], e1 = F.il_off[g + 1];
     const KPar<double> kp = kpar<double>(t);
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(NT_BMM) __attribute__((amdgpu_waves_per_eu(5))) voi
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     stage_table<KIND>(t.ktab, ktab); // first used after a barrier
-    const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
+    const int g = F.targets[xcd_chunk_remap<kM2LChunk>(blockIdx.x, gridDim.x)];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], nil = F.il_off[g + 1] - e0; // nil <= kMaxList (checked at build)
     const KPar<double> kp = kpar<double>(t);

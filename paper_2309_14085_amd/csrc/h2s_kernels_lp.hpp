@@ -47,7 +47,7 @@ __global__ __launch_bounds__(NT_LP) void kb_m2l_lp(DevTree<P> t, int nblk)
     __shared__ int32_t boxoff[kMaxList + 1], boxcoef[kMaxList], boxid[kMaxList];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int g = F.targets[xcd_remap(blockIdx.x, gridDim.x)];
+    const int g = F.targets[xcd_chunk_remap<kM2LChunk>(blockIdx.x, gridDim.x)];
     const int c0 = F.coef_off[g], r = F.coef_off[g + 1] - c0;
     const int e0 = F.il_off[g], nil = F.il_off[g + 1] - e0;
     const KPar<float> kp = kpar<float>(t);

@@ -31,6 +31,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb)
 // + x (XCD x) takes item (8 (j / C) + x) C + j mod C while whole rows of 8
 // chunks remain; the items of the last, partial row map to themselves.  A
 // bijection of [0, nb).
+constexpr int kM2LChunk = 32; // the run length the M2L kernels use
 template <int C> __device__ __forceinline__ int xcd_chunk_remap(int bid, int nb)
 {
     const int rows = nb / (8 * C);
